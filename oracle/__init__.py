@@ -1,0 +1,7 @@
+"""Plain FP64 CPU oracle of the PeriDEM step -- TEST INFRASTRUCTURE.
+
+Only tests/, the smoke check and the CPU-baseline leg of bench.py may import
+this package.  It shares no code with the GPU library; both read the same
+seeded inputs from paper_2108_07212_amd.workloads.
+"""
+from .oracle import Oracle, build_oracle, oracle_library_path  # noqa: F401

@@ -1,0 +1,467 @@
+"""Seeded synthetic workloads for the PeriDEM step loop.
+
+Geometry and placement only: particle boundary polygons (disk, plus, ring,
+L-shape), nodes on a uniform lattice inside each particle, random sequential
+placement of non-overlapping security disks, and the problem record that both
+the GPU library and the CPU oracle consume.  Nothing here evaluates a force
+law, a stretch, a neighbour set or an integrator step; random numbers that
+the method itself would need are never drawn here.
+
+The paper meshes particles with Gmsh (Sec. 5, last paragraph); here the nodes
+are lattice points of spacing h inside the particle, each with nodal area
+h^2 (in 2-D "volume" means area, Sec. 7 intro).  Shapes follow Sec. 7.2:
+plus-shaped particles with arm half-length R and arm width R/2, rings with
+inner radius R/2, plus an L-shape (union of [0,R]x[0,R/2] and [0,R/2]x[0,R]).
+The initial packing of Sec. 7.1 (jammed security disks from a triangle mesh)
+is replaced by random sequential placement of security disks of radius 1.1 R.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SHAPES = ("disk", "plus", "ring", "lshape")
+
+# enum values shared with the C records (see include/pd.h)
+MICRO_CONST, MICRO_CONIC = 0, 1
+PREC_FP64, PREC_FP32_FORCE = 0, 1
+KN_SELF_CONSISTENT, KN_PAPER_3D = 0, 1
+
+
+# ----------------------------------------------------------------------------
+# shapes (body frame, centroid at the origin)
+# ----------------------------------------------------------------------------
+def _circle(radius: float, nv: int, ccw: bool) -> np.ndarray:
+    ang = 2.0 * np.pi * np.arange(nv) / nv
+    pts = np.stack([radius * np.cos(ang), radius * np.sin(ang)], axis=1)
+    return pts if ccw else pts[::-1].copy()
+
+
+def shape_loops(shape: str, R: float, n_circle: int = 64) -> list:
+    """Boundary loops of a shape: outer loop counter-clockwise, holes clockwise.
+
+    A disk returns no loop: it is convex, so no bond can leave it and no
+    line-of-sight filtering applies (Sec. 5: the non-bond set is empty on
+    convex domains).
+    """
+    if shape == "disk":
+        return []
+    if shape == "plus":
+        b = 0.25 * R  # half of the arm width R/2
+        v = [(R, -b), (R, b), (b, b), (b, R), (-b, R), (-b, b), (-R, b),
+             (-R, -b), (-b, -b), (-b, -R), (b, -R), (b, -b)]
+        return [np.array(v, dtype=np.float64)]
+    if shape == "ring":
+        return [_circle(R, n_circle, True), _circle(0.5 * R, n_circle, False)]
+    if shape == "lshape":
+        h2 = 0.5 * R
+        v = np.array([(0, 0), (R, 0), (R, h2), (h2, h2), (h2, R), (0, R)], dtype=np.float64)
+        # centroid of the union of two rectangles minus their overlap
+        a1, c1 = R * h2, (0.5 * R, 0.5 * h2)
+        a2, c2 = h2 * R, (0.5 * h2, 0.5 * R)
+        a3, c3 = h2 * h2, (0.5 * h2, 0.5 * h2)
+        A = a1 + a2 - a3
+        cx = (a1 * c1[0] + a2 * c2[0] - a3 * c3[0]) / A
+        cy = (a1 * c1[1] + a2 * c2[1] - a3 * c3[1]) / A
+        return [v - np.array([cx, cy])]
+    raise ValueError(f"unknown shape {shape!r}")
+
+
+def shape_area(shape: str, R: float) -> float:
+    if shape == "disk":
+        return math.pi * R * R
+    if shape == "plus":
+        return 1.75 * R * R
+    if shape == "ring":
+        return math.pi * R * R * 0.75
+    if shape == "lshape":
+        return 0.75 * R * R
+    raise ValueError(shape)
+
+
+def _inside_even_odd(px: np.ndarray, py: np.ndarray, loops: list) -> np.ndarray:
+    inside = np.zeros(px.shape, dtype=bool)
+    for lp in loops:
+        a = lp
+        b = np.roll(lp, -1, axis=0)
+        for (ax, ay), (bx, by) in zip(a, b):
+            cond = (ay > py) != (by > py)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                xint = ax + (py - ay) * (bx - ax) / (by - ay)
+            inside ^= cond & (px < xint)
+    return inside
+
+
+def _dist_to_loops(px: np.ndarray, py: np.ndarray, loops: list) -> np.ndarray:
+    d = np.full(px.shape, np.inf)
+    for lp in loops:
+        a = lp
+        b = np.roll(lp, -1, axis=0)
+        for (ax, ay), (bx, by) in zip(a, b):
+            ex, ey = bx - ax, by - ay
+            L2 = ex * ex + ey * ey
+            t = np.clip(((px - ax) * ex + (py - ay) * ey) / L2, 0.0, 1.0)
+            qx, qy = ax + t * ex - px, ay + t * ey - py
+            d = np.minimum(d, np.sqrt(qx * qx + qy * qy))
+    return d
+
+
+def body_nodes(shape: str, R: float, h: float, margin: float = 1e-3) -> np.ndarray:
+    """Lattice points (i h, j h) inside the shape, body frame, row-major order.
+
+    Disk: points with |x| <= R (boundary points included).  Polygonal shapes:
+    points strictly inside with distance to the boundary above margin*h, so
+    that no node sits on the boundary.
+    """
+    n = int(math.ceil(R / h)) + 1
+    ii = np.arange(-n, n + 1)
+    jj, iig = np.meshgrid(ii, ii, indexing="ij")  # row-major: j outer, i inner
+    px = (iig * h).ravel().astype(np.float64)
+    py = (jj * h).ravel().astype(np.float64)
+    if shape == "disk":
+        keep = (iig.ravel() ** 2 + jj.ravel() ** 2) * (h * h) <= R * R * (1.0 + 1e-9)
+    else:
+        loops = shape_loops(shape, R)
+        keep = _inside_even_odd(px, py, loops)
+        keep &= _dist_to_loops(px, py, loops) > margin * h
+    return np.stack([px[keep], py[keep]], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# problem record
+# ----------------------------------------------------------------------------
+@dataclass
+class Material:
+    rho: float = 1200.0
+    bulk_k: float = 2.16e7
+    young_E: float = 0.0  # <= 0: E = 4k/3 (2-D, nu = 1/3)
+    Gc: float = 50.0
+    horizon: float = 0.0
+    micro: int = MICRO_CONST
+
+
+@dataclass
+class Problem:
+    """Everything pd_setup / the oracle need, as numpy arrays (SoA)."""
+    x: np.ndarray
+    y: np.ndarray
+    vol: np.ndarray
+    particle_offset: np.ndarray
+    particle_material: np.ndarray
+    particle_aggregate: np.ndarray
+    materials: list
+    loop_offset: np.ndarray
+    loop_vertex_offset: np.ndarray
+    loop_xy: np.ndarray
+    box: np.ndarray  # [n_aggregates, 4] xlo, xhi, ylo, yhi at t = 0
+    top_wall_speed: np.ndarray  # [n_aggregates], downward, m/s
+    contact_radius: float
+    friction_mu: float
+    damping_ratio: float
+    dt: float
+    gravity: tuple = (0.0, 0.0)
+    kn_mode: int = KN_SELF_CONSISTENT
+    precision: int = PREC_FP64
+    u0x: np.ndarray | None = None
+    u0y: np.ndarray | None = None
+    v0x: np.ndarray | None = None
+    v0y: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.particle_offset.shape[0] - 1)
+
+    @property
+    def n_aggregates(self) -> int:
+        return int(self.box.shape[0])
+
+
+@dataclass
+class Particle:
+    shape: str
+    R: float
+    center: tuple
+    theta: float = 0.0
+    material: int = 0
+    aggregate: int = 0
+    velocity: tuple = (0.0, 0.0)
+    nodes_body: np.ndarray | None = None  # override the lattice (tests)
+    loops_body: list | None = None
+
+
+def assemble(particles: list, h: float, materials: list, box, *, contact_radius: float,
+             friction_mu: float, damping_ratio: float, dt: float, gravity=(0.0, 0.0),
+             top_wall_speed=None, kn_mode: int = KN_SELF_CONSISTENT,
+             precision: int = PREC_FP64, vol: float | None = None, meta=None) -> Problem:
+    """Rotate/translate each particle's lattice and loops into the world frame."""
+    xs, ys, offs, vxs, vys = [], [], [0], [], []
+    loop_off, vert_off, loop_xy = [0], [0], []
+    for p in particles:
+        nb = p.nodes_body if p.nodes_body is not None else body_nodes(p.shape, p.R, h)
+        lps = p.loops_body if p.loops_body is not None else shape_loops(p.shape, p.R)
+        c, s = math.cos(p.theta), math.sin(p.theta)
+        wx = p.center[0] + c * nb[:, 0] - s * nb[:, 1]
+        wy = p.center[1] + s * nb[:, 0] + c * nb[:, 1]
+        xs.append(wx)
+        ys.append(wy)
+        vxs.append(np.full(len(nb), p.velocity[0]))
+        vys.append(np.full(len(nb), p.velocity[1]))
+        offs.append(offs[-1] + len(nb))
+        for lp in lps:
+            lx = p.center[0] + c * lp[:, 0] - s * lp[:, 1]
+            ly = p.center[1] + s * lp[:, 0] + c * lp[:, 1]
+            loop_xy.append(np.stack([lx, ly], axis=1).ravel())
+            vert_off.append(vert_off[-1] + len(lp))
+        loop_off.append(loop_off[-1] + len(lps))
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    box = np.asarray(box, dtype=np.float64).reshape(-1, 4)
+    n_agg = box.shape[0]
+    if top_wall_speed is None:
+        top_wall_speed = np.zeros(n_agg)
+    v0x = np.concatenate(vxs)
+    v0y = np.concatenate(vys)
+    return Problem(
+        x=x, y=y,
+        vol=np.full(x.shape, (h * h) if vol is None else vol, dtype=np.float64),
+        particle_offset=np.asarray(offs, dtype=np.int32),
+        particle_material=np.asarray([p.material for p in particles], dtype=np.int32),
+        particle_aggregate=np.asarray([p.aggregate for p in particles], dtype=np.int32),
+        materials=list(materials),
+        loop_offset=np.asarray(loop_off, dtype=np.int32),
+        loop_vertex_offset=np.asarray(vert_off, dtype=np.int32),
+        loop_xy=(np.concatenate(loop_xy) if loop_xy else np.zeros(0)).astype(np.float64),
+        box=box, top_wall_speed=np.asarray(top_wall_speed, dtype=np.float64).reshape(n_agg),
+        contact_radius=float(contact_radius), friction_mu=float(friction_mu),
+        damping_ratio=float(damping_ratio), dt=float(dt), gravity=tuple(gravity),
+        kn_mode=kn_mode, precision=precision,
+        u0x=None, u0y=None,
+        v0x=v0x if np.any(v0x) else None, v0y=v0y if np.any(v0y) else None,
+        meta=dict(meta or {}, h=h),
+    )
+
+
+# ----------------------------------------------------------------------------
+# placement
+# ----------------------------------------------------------------------------
+def rsa_place(rng: np.random.Generator, radii: np.ndarray, width: float, height: float,
+              x0: float = 0.0, y0: float = 0.0, factor: float = 1.1,
+              max_tries: int = 100_000) -> np.ndarray:
+    """Random sequential placement of non-overlapping security disks.
+
+    Disk k has radius factor*radii[k]; its centre is drawn uniformly in the box
+    shrunk by that radius and rejected while it overlaps an accepted disk.
+    """
+    centers = np.zeros((len(radii), 2))
+    rs = factor * np.asarray(radii)
+    # uniform grid of buckets for the overlap test
+    cell = 2.0 * rs.max() if len(rs) else 1.0
+    nbx = max(1, int(width / cell) + 1)
+    buckets: dict = {}
+    for k, r in enumerate(rs):
+        if 2 * r > width or 2 * r > height:
+            raise ValueError("security disk larger than the box")
+        for _ in range(max_tries):
+            cx = x0 + r + (width - 2 * r) * rng.random()
+            cy = y0 + r + (height - 2 * r) * rng.random()
+            bx, by = int((cx - x0) / cell), int((cy - y0) / cell)
+            ok = True
+            for dbx in (-1, 0, 1):
+                for dby in (-1, 0, 1):
+                    for m in buckets.get((bx + dbx) + nbx * (by + dby), ()):
+                        if (cx - centers[m, 0]) ** 2 + (cy - centers[m, 1]) ** 2 < (r + rs[m]) ** 2:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                centers[k] = (cx, cy)
+                buckets.setdefault(bx + nbx * by, []).append(k)
+                break
+        else:
+            raise RuntimeError(f"placement failed for disk {k}")
+    return centers
+
+
+# ----------------------------------------------------------------------------
+# the configurations
+# ----------------------------------------------------------------------------
+def _material(h: float, micro: int = MICRO_CONST) -> Material:
+    return Material(rho=1200.0, bulk_k=2.16e7, young_E=0.0, Gc=50.0, horizon=3.0 * h, micro=micro)
+
+
+def two_disks(contact_active: bool = False, kn_mode: int = KN_SELF_CONSISTENT,
+              dt: float = 1e-7) -> Problem:
+    """Two disks of radius R = 1 mm, h = R/8, horizon 3h.
+
+    Disk A rests on the floor of a 4R x 8R box with its lowest node at height
+    R_c; disk B starts 0.5R above A moving down at 1 m/s under gravity.  The
+    contact-active variant puts B at a surface gap of R_c + 0.05R and turns
+    gravity off, so that the disks meet within about 500 steps.
+    """
+    R = 1e-3
+    h = R / 8
+    Rc = 0.95 * h
+    yA = R + Rc
+    gap = (Rc + 0.05 * R) if contact_active else 0.5 * R
+    yB = yA + 2 * R + gap
+    parts = [Particle("disk", R, (2 * R, yA)),
+             Particle("disk", R, (2 * R, yB), velocity=(0.0, -1.0))]
+    g = (0.0, 0.0) if contact_active else (0.0, -9.81)
+    return assemble(parts, h, [_material(h)], [0.0, 4 * R, 0.0, 8 * R], contact_radius=Rc,
+                    friction_mu=0.5, damping_ratio=0.8, dt=dt, gravity=g, kn_mode=kn_mode,
+                    meta=dict(name="two_disks_contact" if contact_active else "two_disks",
+                              steps=1000, R=R))
+
+
+def mixed_bed(n_particles: int, h: float, box_w: float, box_h: float, seed: int, *,
+              shapes=("disk", "plus", "ring"), R_range=(0.8e-3, 1.2e-3), gravity=-9.81,
+              top_wall_speed: float = 0.0, dt: float = 1e-7, precision: int = PREC_FP64,
+              aggregate: int = 0, x0: float = 0.0, y0: float = 0.0, rng=None,
+              micro: int = MICRO_CONST, name: str = "mixed_bed") -> tuple:
+    """A bed of mixed shapes in equal shares, placed by security-disk RSA.
+
+    Draw order with numpy default_rng(seed): shape list shuffled, then per
+    particle R ~ U[R_range], theta ~ U[0, 2 pi), then the placement attempts.
+    Returns (particles, box).
+    """
+    rng = np.random.default_rng(seed) if rng is None else rng
+    k = len(shapes)
+    counts = [n_particles // k + (1 if i < n_particles % k else 0) for i in range(k)]
+    kinds = []
+    for s, c in zip(shapes, counts):
+        kinds += [s] * c
+    kinds = [kinds[i] for i in rng.permutation(len(kinds))]
+    Rs = rng.uniform(R_range[0], R_range[1], size=n_particles)
+    th = rng.uniform(0.0, 2 * np.pi, size=n_particles)
+    centers = rsa_place(rng, Rs, box_w, box_h, x0=x0, y0=y0)
+    parts = [Particle(kinds[i], float(Rs[i]), (float(centers[i, 0]), float(centers[i, 1])),
+                      float(th[i]), 0, aggregate) for i in range(n_particles)]
+    box = [x0, x0 + box_w, y0, y0 + box_h]
+    return parts, box
+
+
+def settling(n_particles: int = 100, h: float = 0.0904e-3, gravity: float = -9.81,
+             seed: int = 2, dt: float = 1e-7, precision: int = PREC_FP64) -> Problem:
+    """Plain FP64 settling: equal thirds of disks, plus shapes and rings in a 30R x 60R box."""
+    Rn = 1e-3
+    parts, box = mixed_bed(n_particles, h, 30 * Rn, 60 * Rn, seed)
+    return assemble(parts, h, [_material(h)], box, contact_radius=0.95 * h, friction_mu=0.5,
+                    damping_ratio=0.8, dt=dt, gravity=(0.0, gravity), precision=precision,
+                    meta=dict(name=f"settling_{n_particles}", seed=seed, steps=20000))
+
+
+def compaction(n_particles: int = 500, h: float = 0.070e-3, seed: int = 3,
+               wall_speed: float = 0.1, dt: float = 1e-7, precision: int = PREC_FP64,
+               box_scale: float | None = None) -> Problem:
+    """Compaction: mixed shapes, no gravity, top wall moving down at wall_speed.
+
+    The box keeps the settling bed's fill fraction: 30R x 60R scaled by
+    sqrt(n/100).
+    """
+    Rn = 1e-3
+    sc = math.sqrt(n_particles / 100.0) if box_scale is None else box_scale
+    parts, box = mixed_bed(n_particles, h, 30 * Rn * sc, 60 * Rn * sc, seed)
+    return assemble(parts, h, [_material(h)], box, contact_radius=0.95 * h, friction_mu=0.5,
+                    damping_ratio=0.8, dt=dt, gravity=(0.0, 0.0), precision=precision,
+                    top_wall_speed=[wall_speed],
+                    meta=dict(name=f"compaction_{n_particles}", seed=seed))
+
+
+def batched(n_aggregates: int = 64, h: float = 0.078e-3, seed: int = 4,
+            n_range=(50, 400), dt: float = 1e-7, gravity: float = -9.81,
+            precision: int = PREC_FP32_FORCE) -> Problem:
+    """Independent settling aggregates of uneven size in one problem.
+
+    Aggregate a has n_a ~ U{n_range} particles drawn uniformly from disk, plus
+    and ring, in its own box 30R sqrt(n_a/100) x 60R sqrt(n_a/100); the boxes
+    are laid side by side (they never interact: each aggregate has its own
+    walls and its own cells).
+    """
+    Rn = 1e-3
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=n_aggregates)
+    parts, boxes = [], []
+    xoff = 0.0
+    for a, na in enumerate(ns):
+        sc = math.sqrt(na / 100.0)
+        w, hh = 30 * Rn * sc, 60 * Rn * sc
+        kinds = rng.choice(np.array(["disk", "plus", "ring"]), size=na)
+        Rs = rng.uniform(0.8e-3, 1.2e-3, size=na)
+        th = rng.uniform(0.0, 2 * np.pi, size=na)
+        centers = rsa_place(rng, Rs, w, hh, x0=xoff, y0=0.0)
+        parts += [Particle(str(kinds[i]), float(Rs[i]), (float(centers[i, 0]), float(centers[i, 1])),
+                           float(th[i]), 0, a) for i in range(na)]
+        boxes.append([xoff, xoff + w, 0.0, hh])
+        xoff += w + 10 * Rn
+    return assemble(parts, h, [_material(h)], boxes, contact_radius=0.95 * h, friction_mu=0.5,
+                    damping_ratio=0.8, dt=dt, gravity=(0.0, gravity), precision=precision,
+                    meta=dict(name=f"batched_{n_aggregates}", seed=seed,
+                              particles_per_aggregate=ns.tolist()))
+
+
+def subproblem_aggregate(prob: Problem, a: int) -> Problem:
+    """The nodes, particles and box of aggregate a alone, as a problem of its own."""
+    pa = prob.particle_aggregate
+    sel = np.nonzero(pa == a)[0]
+    p0, p1 = int(sel[0]), int(sel[-1]) + 1
+    assert np.all(np.diff(sel) == 1)
+    n0, n1 = int(prob.particle_offset[p0]), int(prob.particle_offset[p1])
+    l0, l1 = int(prob.loop_offset[p0]), int(prob.loop_offset[p1])
+    v0, v1 = int(prob.loop_vertex_offset[l0]), int(prob.loop_vertex_offset[l1])
+
+    def cut(arr):
+        return None if arr is None else arr[n0:n1].copy()
+
+    return Problem(
+        x=prob.x[n0:n1].copy(), y=prob.y[n0:n1].copy(), vol=prob.vol[n0:n1].copy(),
+        particle_offset=(prob.particle_offset[p0:p1 + 1] - n0).astype(np.int32),
+        particle_material=prob.particle_material[p0:p1].copy(),
+        particle_aggregate=np.zeros(p1 - p0, dtype=np.int32),
+        materials=prob.materials,
+        loop_offset=(prob.loop_offset[p0:p1 + 1] - l0).astype(np.int32),
+        loop_vertex_offset=(prob.loop_vertex_offset[l0:l1 + 1] - v0).astype(np.int32),
+        loop_xy=prob.loop_xy[2 * v0:2 * v1].copy(),
+        box=prob.box[a:a + 1].copy(), top_wall_speed=prob.top_wall_speed[a:a + 1].copy(),
+        contact_radius=prob.contact_radius, friction_mu=prob.friction_mu,
+        damping_ratio=prob.damping_ratio, dt=prob.dt, gravity=prob.gravity,
+        kn_mode=prob.kn_mode, precision=prob.precision,
+        u0x=cut(prob.u0x), u0y=cut(prob.u0y), v0x=cut(prob.v0x), v0y=cut(prob.v0y),
+        meta=dict(prob.meta, aggregate=a),
+    )
+
+
+def single_node_particles(points, velocities, vol: float, box, *, contact_radius: float,
+                          h: float, friction_mu=0.0, damping_ratio=0.0, dt=1e-8,
+                          gravity=(0.0, 0.0), kn_mode=KN_SELF_CONSISTENT,
+                          material: Material | None = None) -> Problem:
+    """Particles of one node each (no bonds): the contact law in isolation."""
+    mat = material or _material(h)
+    parts = [Particle("disk", 0.0, tuple(p), 0.0, velocity=tuple(v),
+                      nodes_body=np.zeros((1, 2)), loops_body=[])
+             for p, v in zip(points, velocities)]
+    return assemble(parts, h, [mat], box, contact_radius=contact_radius,
+                    friction_mu=friction_mu, damping_ratio=damping_ratio, dt=dt,
+                    gravity=gravity, kn_mode=kn_mode, vol=vol)
+
+
+def perturb(prob: Problem, seed: int, du: float = 0.0, dv: float = 0.0) -> Problem:
+    """Add seeded uniform noise of amplitude du to u0 and dv to v0 (test inputs)."""
+    rng = np.random.default_rng(seed)
+    n = prob.n_nodes
+    if du:
+        prob.u0x = (prob.u0x if prob.u0x is not None else 0.0) + du * rng.uniform(-1, 1, n)
+        prob.u0y = (prob.u0y if prob.u0y is not None else 0.0) + du * rng.uniform(-1, 1, n)
+    if dv:
+        prob.v0x = (prob.v0x if prob.v0x is not None else 0.0) + dv * rng.uniform(-1, 1, n)
+        prob.v0y = (prob.v0y if prob.v0y is not None else 0.0) + dv * rng.uniform(-1, 1, n)
+    return prob
