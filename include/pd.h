@@ -1,0 +1,202 @@
+/*
+ * pd.h -- C ABI of libpd: the PeriDEM step loop on an AMD MI355X (gfx950).
+ *
+ * The library advances a 2-D aggregate of deformable particles by the
+ * method of Bhattacharya & Lipton, "Simulating grain shape effects and
+ * damage in granular media using PeriDEM":
+ *   - intra-particle bond-based peridynamic force with irreversible bond
+ *     breaking (Sec. 3, eq. peri, eq. pmb, Table tab:2d-peri, Sec. 3.1);
+ *   - reference bonds restricted to segments that stay inside the particle,
+ *     found once by the extended-boundary and cusp-bisector test of Sec. 5;
+ *   - contact between nodes closer than R_c, found every step through a
+ *     radix-sorted cell list (Algorithm alg:buildtree, inter-particle
+ *     neighbour sets), with short-range repulsion (Sec. 4.1), regularized
+ *     Coulomb friction (Sec. 4.2), normal damping (Sec. 4.3) and self-contact
+ *     between unbonded nodes of one particle (Sec. 4.4);
+ *   - analytic contact with the four walls of a rectangular container whose
+ *     top wall may move down (Sec. 4.5, eq. wall-total);
+ *   - velocity-Verlet integration (Sec. 6.1, Algorithm alg:buildtree).
+ * The problem statement is the initial value problem eq. pdmotion with the
+ * forces of eq. full.
+ *
+ * Conventions
+ *   - SI units per unit thickness: nodal "volume" is an area (m^2), density
+ *     kg/m^3, nodal force N/m (Sec. 7 intro: in 2-D volume means area).
+ *   - Arrays are structure-of-arrays, one double per node unless stated.
+ *   - Every call returns pd_status; no exception crosses the ABI.  After an
+ *     error, pd_last_error() gives a message.  PD_E_NONFINITE and
+ *     PD_E_ESCAPED are sticky until pd_set_state().
+ *   - Ownership: the caller owns every input and may free it when pd_setup
+ *     returns (the library deep-copies to device memory).  The context owns
+ *     all device memory it allocates.  Output buffers are caller-allocated:
+ *     host pointers, or device pointers when on_device = 1.
+ *   - Concurrency: one context is used by one host thread at a time.  Work is
+ *     issued on the stream given at setup (NULL: the legacy default stream).
+ *   - Determinism: sums run in a fixed order (gather only, no floating-point
+ *     atomics), so the same inputs on the same device give bitwise equal
+ *     results for a fixed tuning.
+ */
+#ifndef PD_H
+#define PD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_ctx pd_ctx;
+
+typedef enum {
+    PD_OK = 0,
+    PD_E_INVALID = 1,   /* invalid argument or problem description */
+    PD_E_NOMEM = 2,     /* device or host allocation failed */
+    PD_E_DEVICE = 3,    /* HIP runtime error */
+    PD_E_NONFINITE = 4, /* a displacement or velocity became NaN/Inf */
+    PD_E_ESCAPED = 5,   /* a node went through a wall by R_c or more */
+    PD_E_STATE = 6      /* call not valid in the current state */
+} pd_status;
+
+enum { PD_MICRO_CONST = 0, PD_MICRO_CONIC = 1 };           /* Table tab:2d-peri */
+enum { PD_PREC_FP64 = 0, PD_PREC_FP32_FORCE = 1 };         /* force arithmetic */
+enum { PD_KN_SELF_CONSISTENT = 0, PD_KN_PAPER_3D = 1 };    /* normal contact stiffness */
+
+/* force terms of eq. full, for pd_forces */
+enum {
+    PD_TERM_PD = 1,    /* peridynamic bond force, eq. peri */
+    PD_TERM_SELF = 2,  /* self-contact: repulsion, damping, friction (Sec. 4.4) */
+    PD_TERM_NBR = 4,   /* other particles: repulsion, damping, friction */
+    PD_TERM_WALL = 8,  /* container walls (Sec. 4.5) */
+    PD_TERM_BODY = 16, /* body force rho g */
+    PD_TERM_ALL = 31
+};
+
+typedef struct {
+    double rho;     /* mass density, kg/m^3 */
+    double bulk_k;  /* bulk modulus k, Pa */
+    double young_E; /* Young's modulus; <= 0: E = 2 k (1 - nu) = 4k/3 (nu = 1/3 in 2-D) */
+    double Gc;      /* critical energy release rate, J/m^2 */
+    double horizon; /* peridynamic horizon eps, m */
+    int32_t micro;  /* PD_MICRO_CONST (w = 1) or PD_MICRO_CONIC (w = 1 - |xi|/eps) */
+} pd_material;
+
+typedef struct {
+    int32_t n_nodes, n_particles, n_aggregates, n_materials;
+    const double *x, *y;                /* [n_nodes] reference coordinates */
+    const double *vol;                  /* [n_nodes] nodal area */
+    const int32_t *particle_offset;     /* [n_particles+1]; nodes of a particle are contiguous */
+    const int32_t *particle_material;   /* [n_particles] index into materials */
+    const int32_t *particle_aggregate;  /* [n_particles] or NULL (all 0); aggregates never interact */
+    const pd_material *materials;       /* [n_materials] */
+    const int32_t *loop_offset;         /* [n_particles+1] range of boundary loops per particle */
+    const int32_t *loop_vertex_offset;  /* [n_loops+1] range of vertices per loop */
+    const double *loop_xy;              /* interleaved vertices; outer loop counter-clockwise,
+                                           holes clockwise; a particle with no loop is treated
+                                           as convex (no bond is filtered) */
+    const double *u0x, *u0y, *v0x, *v0y; /* [n_nodes] initial displacement/velocity or NULL (0) */
+    double contact_radius;              /* R_c */
+    double friction_mu;                 /* Coulomb coefficient mu */
+    double damping_ratio;               /* r_d in [0, 1] */
+    int32_t kn_mode;                    /* PD_KN_SELF_CONSISTENT: K_n = c_w / R_c;
+                                           PD_KN_PAPER_3D: K_n = 18 k / (pi eps^5) */
+    const double *box;                  /* [n_aggregates*4] xlo, xhi, ylo, yhi at t = 0 */
+    const double *top_wall_speed;       /* [n_aggregates] downward speed of the top wall, or NULL */
+    double gravity_x, gravity_y;        /* body acceleration g */
+    double dt;                          /* time step */
+    int32_t precision;                  /* PD_PREC_FP64 or PD_PREC_FP32_FORCE */
+    void *hip_stream;                   /* hipStream_t for all work, or NULL */
+} pd_problem;
+
+/* Tuning of the launch configuration; results are identical for every
+ * block size and staging choice, and equal within rounding for every cell
+ * factor (the contact set itself never changes). */
+typedef struct {
+    int32_t block_nodes;  /* nodes per workgroup of the force kernel: 64, 128 or 256 */
+    double cell_factor;   /* cell side / R_c, >= 1 */
+    int32_t use_lds;      /* stage bond partners' coordinates in LDS (1) or read through cache (0) */
+    int32_t use_graph;    /* replay steps as a captured HIP graph (1) or launch directly (0) */
+} pd_tuning;
+
+/* Builds the context: validates the problem, copies it to the device,
+ * computes per-material constants (Table tab:2d-peri; K_n of Sec. 4.1),
+ * builds the reference bonds (Algorithm alg:buildtree, reference neighbour
+ * sets: same particle, |x' - x| < eps) minus the non-bonds of Sec. 5, and
+ * evaluates the forces at t = 0 (applying the break rule) to obtain the
+ * initial acceleration a0 = F / (rho V) + g.
+ * Errors: PD_E_INVALID (empty particle, unordered offsets, dt <= 0,
+ * R_c <= 0, bad material index, node outside its box by R_c or more),
+ * PD_E_NOMEM, PD_E_DEVICE. */
+pd_status pd_setup(const pd_problem *p, pd_ctx **out);
+
+/* Releases all device memory of the context. NULL is allowed. */
+void pd_destroy(pd_ctx *c);
+
+/* Message of the last error on this context (never NULL). */
+const char *pd_last_error(const pd_ctx *c);
+
+/* n_steps iterations of Algorithm alg:buildtree: u += dt v + dt^2/2 a;
+ * contact sets at the new positions; forces with the velocities of the
+ * previous step; a = F / (rho V) + g; v += dt/2 (a_old + a).  Returns after
+ * the work is complete.  Errors: PD_E_NONFINITE, PD_E_ESCAPED (sticky),
+ * PD_E_DEVICE, PD_E_INVALID (n_steps < 0). */
+pd_status pd_step(pd_ctx *c, int64_t n_steps);
+
+/* Force density rho u'' by term (eq. full; nodal force divided by nodal
+ * area) at the current state, summed over the terms in term_mask.  The
+ * break rule is applied to the evaluation but not committed.  fx, fy:
+ * [n_nodes], host or device (on_device = 1). */
+pd_status pd_forces(pd_ctx *c, uint32_t term_mask, double *fx, double *fy, int32_t on_device);
+
+/* Damage of each node (Sec. 3.1): broken bonds / reference bonds, and the
+ * number of broken directed bonds.  phi: [n_nodes] host or device, or NULL. */
+pd_status pd_damage(pd_ctx *c, double *phi, int64_t *n_broken_directed, int32_t on_device);
+
+/* Reference bonds as CSR (directed, columns ascending): row[n_nodes+1],
+ * col[pd_n_bonds()], host memory. */
+int64_t pd_n_bonds(const pd_ctx *c);
+pd_status pd_bonds(pd_ctx *c, int32_t *row, int32_t *col);
+
+/* Contact set at the current positions: unordered pairs (i < j) of nodes of
+ * one aggregate with |p_i - p_j|^2 < R_c^2, sorted by i then j.  Writes at
+ * most cap pairs to host arrays pi, pj; *count receives the set size. */
+pd_status pd_contacts(pd_ctx *c, int32_t *pi, int32_t *pj, int64_t cap, int64_t *count);
+
+/* State copy (host arrays of n_nodes; broken: one byte per directed bond in
+ * CSR order; step: number of steps taken).  Any pointer may be NULL. */
+pd_status pd_get_state(pd_ctx *c, double *ux, double *uy, double *vx, double *vy, double *ax,
+                       double *ay, uint8_t *broken, int64_t *step);
+pd_status pd_set_state(pd_ctx *c, const double *ux, const double *uy, const double *vx,
+                       const double *vy, const double *ax, const double *ay,
+                       const uint8_t *broken, int64_t step);
+
+/* Counters accumulated since setup while counting is on (pd_set_counting):
+ * [0] inter-particle pairs, [1] self-contact pairs, [2] sticking, [3] sliding,
+ * [4] wall regions, [5] coincident pairs skipped, [6] bonds broken (directed),
+ * [7] steps taken. */
+pd_status pd_counters(pd_ctx *c, int64_t out[8]);
+pd_status pd_set_counting(pd_ctx *c, int32_t on);
+
+/* Launch configuration (see pd_tuning). */
+pd_status pd_get_tuning(const pd_ctx *c, pd_tuning *t);
+pd_status pd_set_tuning(pd_ctx *c, const pd_tuning *t);
+
+/* Autotuner: times steps_per_trial steps for each candidate configuration
+ * on a copy of the state (the state is restored afterwards) and keeps the
+ * fastest.  chosen may be NULL. */
+pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
+
+/* Kernel timing: runs n_steps steps with direct launches and records HIP
+ * events on the context's stream around every launch; ms[k] receives the
+ * mean duration per launch of kernel class k and launches[k] the number of
+ * launches per step:
+ *   0 cell keys, 1 radix histogram, 2 radix digit scan, 3 radix scatter,
+ *   4 cell starts, 5 force + integrate.  (n_out >= 6) */
+pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out);
+
+/* Sizes: [0] nodes, [1] directed bonds, [2] padded bond slots, [3] cells,
+ * [4] radix passes, [5] particles, [6] aggregates, [7] max LDS window. */
+pd_status pd_sizes(const pd_ctx *c, int64_t out[8]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

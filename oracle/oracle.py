@@ -92,6 +92,8 @@ def _lib(openmp: bool):
                                              C.c_double, C.c_double]
         L.or_wall_segment.argtypes = [C.c_double, C.c_double, _dp, _dp]
         L.or_wall_corner.argtypes = [C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_wall_segment_gap.argtypes = [C.c_double, C.c_double]
+        L.or_wall_segment_gap.restype = C.c_double
         _LIBS[key] = L
     return _LIBS[key]
 
@@ -227,3 +229,7 @@ def wall_corner(Rc: float, da: float, db: float):
     A, ix, iy = C.c_double(), C.c_double(), C.c_double()
     lib.or_wall_corner(Rc, da, db, C.byref(A), C.byref(ix), C.byref(iy))
     return A.value, ix.value, iy.value
+
+
+def wall_segment_gap(Rc: float, d: float) -> float:
+    return float(_lib(False).or_wall_segment_gap(Rc, d))

@@ -102,14 +102,23 @@ int or_constants(const or_ctx *c, double *out) {
 /* ------------------------------------------------------------------------ */
 /* Sec. 5: a bond is kept iff the closed segment lies in the closed domain   */
 /* ------------------------------------------------------------------------ */
+/* coordinates relative to the particle's first node (the particle frame) */
+static void frame_origin(const or_ctx *c, int p, double *rx, double *ry) {
+    *rx = c->x[c->poff[p]];
+    *ry = c->y[c->poff[p]];
+}
+
+/* point (mx, my), given in the particle frame, inside the closed domain */
 static int point_in_closed_particle(const or_ctx *c, int p, double mx, double my, double tol) {
+    double rx, ry;
+    frame_origin(c, p, &rx, &ry);
     int inside = 0;
     for (int l = c->loff[p]; l < c->loff[p + 1]; ++l) {
         int v0 = c->lvoff[l], v1 = c->lvoff[l + 1], n = v1 - v0;
         for (int k = 0; k < n; ++k) {
-            double Px = c->lxy[2 * (v0 + k)], Py = c->lxy[2 * (v0 + k) + 1];
+            double Px = c->lxy[2 * (v0 + k)] - rx, Py = c->lxy[2 * (v0 + k) + 1] - ry;
             int kn = (k + 1 == n) ? 0 : k + 1;
-            double Qx = c->lxy[2 * (v0 + kn)], Qy = c->lxy[2 * (v0 + kn) + 1];
+            double Qx = c->lxy[2 * (v0 + kn)] - rx, Qy = c->lxy[2 * (v0 + kn) + 1] - ry;
             /* on the boundary (within tol) counts as inside */
             double ex = Qx - Px, ey = Qy - Py, L2 = ex * ex + ey * ey;
             double t = ((mx - Px) * ex + (my - Py) * ey) / L2;
@@ -134,6 +143,12 @@ static int cmp_double(const void *a, const void *b) {
 static int segment_in_particle(const or_ctx *c, int p, double ax, double ay, double bx,
                                double by, double *ts, double tol) {
     if (c->loff[p] == c->loff[p + 1]) return 1; /* no boundary loop given: convex */
+    double ox, oy;
+    frame_origin(c, p, &ox, &oy);
+    ax -= ox;
+    ay -= oy;
+    bx -= ox;
+    by -= oy;
     int nt = 0;
     ts[nt++] = 0.0;
     ts[nt++] = 1.0;
@@ -141,9 +156,9 @@ static int segment_in_particle(const or_ctx *c, int p, double ax, double ay, dou
     for (int l = c->loff[p]; l < c->loff[p + 1]; ++l) {
         int v0 = c->lvoff[l], v1 = c->lvoff[l + 1], n = v1 - v0;
         for (int k = 0; k < n; ++k) {
-            double Px = c->lxy[2 * (v0 + k)], Py = c->lxy[2 * (v0 + k) + 1];
+            double Px = c->lxy[2 * (v0 + k)] - ox, Py = c->lxy[2 * (v0 + k) + 1] - oy;
             int kn = (k + 1 == n) ? 0 : k + 1;
-            double Qx = c->lxy[2 * (v0 + kn)], Qy = c->lxy[2 * (v0 + kn) + 1];
+            double Qx = c->lxy[2 * (v0 + kn)] - ox, Qy = c->lxy[2 * (v0 + kn) + 1] - oy;
             double sx = Qx - Px, sy = Qy - Py, wx = Px - ax, wy = Py - ay;
             double den = rx * sy - ry * sx;
             if (den != 0.0) {
@@ -477,6 +492,32 @@ void or_wall_segment(double Rc, double d, double *area, double *centroid_dist) {
     *centroid_dist = (2.0 / 3.0) * (q * sqrt(q)) / A;
 }
 
+/* Rc |S| - (2/3)(Rc^2 - d^2)^(3/2) = |S| (Rc - |c - p|): the factor of the
+ * single-wall repulsion (Sec. 4.5).  With d = Rc cos(phi/2) it equals
+ * Rc^3 [(phi - sin phi)/2 - (2/3) sin^3(phi/2)], whose Taylor series starts
+ * at phi^5/160; the series avoids the cancellation of the two terms as
+ * d -> Rc, where both vanish. */
+double or_wall_segment_gap(double Rc, double d) {
+    const double phi = 4.0 * asin(sqrt((Rc - d) / (2.0 * Rc)));
+    double h;
+    if (phi < 2.0) {
+        double pw = phi * phi * phi * phi * phi / 120.0, a = 0.5 * 0.5 * 0.5 * 0.5 * 0.5,
+               b = 1.5 * 1.5 * 1.5 * 1.5 * 1.5;
+        h = 0.0;
+        for (int k = 2; k < 18; ++k) {
+            const double ck = -0.5 - 0.5 * a + b / 6.0;
+            h += (k % 2 ? -ck : ck) * pw;
+            pw *= phi * phi / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+            a *= 0.25;
+            b *= 2.25;
+        }
+    } else {
+        const double sh = sin(0.5 * phi);
+        h = 0.5 * (phi - sin(phi)) - (2.0 / 3.0) * sh * sh * sh;
+    }
+    return Rc * Rc * Rc * h;
+}
+
 /* Sec. 4.5: the part of the contact disk beyond two adjacent walls at signed
  * distances da, db (da^2 + db^2 < Rc^2), and its first moments Ix (toward
  * wall a) and Iy (toward wall b) about the node.  Evaluated as the right
@@ -504,17 +545,17 @@ void or_wall_corner(double Rc, double da, double db, double *area, double *Ix, d
     *Iy = At * (db + db + (db + wy)) / 3.0 + ms * ny;
 }
 
-/* one wall region (segment or corner) acting on node i: repulsion toward
- * -e, damping and friction against the region's velocity (wvx, wvy) */
-static void wall_region(const or_ctx *c, int i, double Kn, double A, double dist, double ex,
+/* one wall region (segment or corner) acting on node i: repulsion of
+ * magnitude Frmag along -e (e points from the node toward the region's
+ * centroid), damping and friction against the region's velocity (wvx, wvy);
+ * the region's area A stands for the partner volume */
+static void wall_region(const or_ctx *c, int i, double Kn, double A, double Frmag, double ex,
                         double ey, double wvx, double wvy, const double *vx, const double *vy,
                         double sign, double *fx, double *fy, int64_t *cnt) {
     const double Vi = c->vol[i], rho_i = c->rho_n[i];
-    const double coef = -Kn * (c->Rc - dist); /* F = coef V_i |S| e */
-    const double Frx = coef * Vi * A * ex, Fry = coef * Vi * A * ey;
-    const double Frmag = fabs(coef) * Vi * A;
+    const double Frx = -Frmag * ex, Fry = -Frmag * ey;
     double fdx, fdy;
-    damp_friction(c, rho_i, Vi, A, Kn, ex, ey, vx[i] - wvx, vy[i] - wvy, Frmag, &fdx, &fdy,
+    damp_friction(c, rho_i, Vi, A, Kn, ex, ey, vx[i] - wvx, vy[i] - wvy, fabs(Frmag), &fdx, &fdy,
                   &cnt[2], &cnt[3]);
     *fx += sign * (Frx + fdx);
     *fy += sign * (Fry + fdy);
@@ -539,10 +580,14 @@ static int wall_node(or_ctx *c, int i, double t, const double *vx, const double 
     for (int w = 0; w < 4; ++w) {
         if (!(d[w] > -Rc)) st = OR_E_ESCAPED;
         if (d[w] < Rc && d[w] > -Rc) {
+            /* F = -K_n (Rc - |c_l - p|) V_i |S_l| e_l, with |S_l| (Rc - |c_l - p|)
+             * evaluated without cancellation */
             double A, g;
             or_wall_segment(Rc, d[w], &A, &g);
+            const double Frmag = Kn * c->vol[i] * or_wall_segment_gap(Rc, d[w]);
             if (A > 0.0)
-                wall_region(c, i, Kn, A, g, nx[w], ny[w], 0.0, wv[w], vx, vy, +1.0, &fx, &fy, cnt);
+                wall_region(c, i, Kn, A, Frmag, nx[w], ny[w], 0.0, wv[w], vx, vy, +1.0, &fx, &fy,
+                            cnt);
         }
     }
     /* adjacent pairs: (left, floor), (floor, right), (right, top), (top, left) */
@@ -559,7 +604,8 @@ static int wall_node(or_ctx *c, int i, double t, const double *vx, const double 
             double ex = cx / dist, ey = cy / dist;
             /* corner region moves with the top wall when it borders it */
             double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
-            wall_region(c, i, Kn, A, dist, ex, ey, 0.0, wvy, vx, vy, -1.0, &fx, &fy, cnt);
+            const double Frmag = Kn * (Rc - dist) * c->vol[i] * A;
+            wall_region(c, i, Kn, A, Frmag, ex, ey, 0.0, wvy, vx, vy, -1.0, &fx, &fy, cnt);
         }
     }
     c->F[T_WALL][0][i] = fx;

@@ -18,8 +18,8 @@
  *   - velocity-Verlet time integration (Sec. 6.1, Algorithm alg:buildtree);
  *   - reference bonds restricted to segments inside the particle (Sec. 5),
  *     here by the plain definition (segment contained in the closed domain).
- * Readings of passages the paper leaves open are listed in the design doc and at
- * the function that applies them.
+ * Readings of passages the paper leaves open are stated at the function that
+ * applies them.
  */
 #ifndef PD_ORACLE_H
 #define PD_ORACLE_H
@@ -101,6 +101,8 @@ int or_segment_in_particle(const or_ctx *c, int32_t particle, double ax, double 
 /* wall helpers exposed for tests (closed forms of Sec. 4.5) */
 void or_wall_segment(double Rc, double d, double *area, double *centroid_dist);
 void or_wall_corner(double Rc, double da, double db, double *area, double *Ix, double *Iy);
+/* |S| (Rc - |c - p|) of a single wall at signed distance d */
+double or_wall_segment_gap(double Rc, double d);
 
 #ifdef __cplusplus
 }

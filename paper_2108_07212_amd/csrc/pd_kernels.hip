@@ -1,0 +1,841 @@
+// pd_kernels.hip -- gfx950 kernels of libpd.
+//
+// One pass of the step (Algorithm alg:buildtree of the paper) is:
+//   k_keys     cell key of every node at its advanced position
+//              u + dt v + dt^2/2 a (velocity-Verlet position update);
+//   k_hist / k_digit_scan / k_scatter (x radix passes)
+//              stable LSD radix sort of (cell key, node) with 8-bit digits;
+//              within a wavefront equal digits are ranked with eight ballots;
+//   k_cells    first sorted position of every occupied cell, positions and
+//              particle ids in sorted order, step counter;
+//   k_force    per node, in a fixed order: contact with the nodes of the 3x3
+//              neighbouring cells (repulsion, damping, friction, self-contact),
+//              the four walls and their corners, the peridynamic bonds of its
+//              SELL-64 row (partners staged in LDS), then the velocity-Verlet
+//              velocity update and the advanced displacement.
+// Every sum is a gather in a fixed order: no floating-point atomics, so runs
+// are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "pd_internal.h"
+
+namespace pd {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void advanced_pos(const DevArgs &a, int j, bool adv, double &px,
+                                             double &py, double &ux, double &uy) {
+    ux = a.ux[j];
+    uy = a.uy[j];
+    if (adv) {  // u + dt v + dt^2/2 a, evaluated left to right without contraction
+        ux = (ux + a.dt * a.vx[j]) + a.hdt2 * a.ax[j];
+        uy = (uy + a.dt * a.vy[j]) + a.hdt2 * a.ay[j];
+    }
+    px = a.x[j] + ux;
+    py = a.y[j] + uy;
+}
+
+__device__ __forceinline__ void cell_of(const DevArgs &a, int ag, double px, double py, int &cx,
+                                        int &cy) {
+    const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
+    double fx = floor((px - a.agg_gx0[ag]) * a.inv_cell);
+    double fy = floor((py - a.agg_gy0[ag]) * a.inv_cell);
+    fx = fmin(fmax(fx, 0.0), (double)(ncx - 1));  // fmax drops NaN
+    fy = fmin(fmax(fy, 0.0), (double)(ncy - 1));
+    cx = (int)fx;
+    cy = (int)fy;
+}
+
+__device__ __forceinline__ void count(const DevArgs &a, int k, unsigned long long v = 1) {
+    if (a.counting && v) atomicAdd(&a.counters[k], v);
+}
+
+// inclusive scan across a 64-lane wavefront
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan over a 256-thread block; returns the block total in *total
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *total,
+                                                       uint32_t *sh /*[4]*/) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t s = sh[q];
+        if (q < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// setup: reference bonds (Algorithm alg:buildtree, reference neighbours) minus
+// the non-bonds of Sec. 5.  A candidate bond is dropped when it properly
+// crosses a barrier segment of its particle: an edge of the boundary pushed
+// outward by delta along the exterior-angle bisectors, or the bisector ray
+// of a non-convex vertex up to its first hit with the boundary.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double cx,
+                                         double cy) {
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+__device__ bool crosses_barrier(double ax, double ay, double bx, double by, const double *seg,
+                                int s0, int s1) {
+    for (int s = s0; s < s1; ++s) {
+        const double cx = seg[4 * s], cy = seg[4 * s + 1], dx = seg[4 * s + 2], dy = seg[4 * s + 3];
+        const double o1 = orient(ax, ay, bx, by, cx, cy), o2 = orient(ax, ay, bx, by, dx, dy);
+        if (!((o1 > 0.0 && o2 < 0.0) || (o1 < 0.0 && o2 > 0.0))) continue;
+        const double o3 = orient(cx, cy, dx, dy, ax, ay), o4 = orient(cx, cy, dx, dy, bx, by);
+        if ((o3 > 0.0 && o4 < 0.0) || (o3 < 0.0 && o4 > 0.0)) return true;
+    }
+    return false;
+}
+
+__global__ void k_bonds_count_w(BondArgs b, int *rowlen) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.N) return;
+    const int p = b.part[i];
+    const double thr2 = b.thr2[b.pmat[p]];
+    const double xi = b.x[i], yi = b.y[i];
+    const double rx = b.x[b.poff[p]], ry = b.y[b.poff[p]];  // particle frame origin
+    const int s0 = b.seg_off[p], s1 = b.seg_off[p + 1];
+    int n = 0;
+    for (int j = b.poff[p]; j < b.poff[p + 1]; ++j) {
+        if (j == i) continue;
+        const double dx = b.x[j] - xi, dy = b.y[j] - yi;
+        const double d2 = dx * dx + dy * dy;
+        if (!(d2 < thr2)) continue;
+        if (s1 > s0 && crosses_barrier(xi - rx, yi - ry, b.x[j] - rx, b.y[j] - ry, b.seg, s0, s1))
+            continue;
+        ++n;
+    }
+    rowlen[i] = n;
+}
+
+__global__ void k_bonds_fill_w(BondArgs b, uint32_t *col, const uint32_t *slice_ptr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.N) return;
+    const int p = b.part[i];
+    const double thr2 = b.thr2[b.pmat[p]];
+    const double xi = b.x[i], yi = b.y[i];
+    const double rx = b.x[b.poff[p]], ry = b.y[b.poff[p]];  // particle frame origin
+    const int s0 = b.seg_off[p], s1 = b.seg_off[p + 1];
+    const uint32_t base = slice_ptr[i >> 6] + (uint32_t)(i & 63);
+    const int W = (int)((slice_ptr[(i >> 6) + 1] - slice_ptr[i >> 6]) / kSlice);
+    int n = 0;
+    for (int j = b.poff[p]; j < b.poff[p + 1] && n < W; ++j) {
+        if (j == i) continue;
+        const double dx = b.x[j] - xi, dy = b.y[j] - yi;
+        const double d2 = dx * dx + dy * dy;
+        if (!(d2 < thr2)) continue;
+        if (s1 > s0 && crosses_barrier(xi - rx, yi - ry, b.x[j] - rx, b.y[j] - ry, b.seg, s0, s1))
+            continue;
+        col[base + (uint32_t)n * kSlice] = (uint32_t)j;
+        ++n;
+    }
+    for (int k = n; k < W; ++k) col[base + (uint32_t)k * kSlice] = (uint32_t)i | kBroken;
+}
+
+// staging window of each force block: [min, max] of its nodes and partners
+__global__ void k_windows(const uint32_t *col, const uint32_t *slice_ptr, const int *rowlen, int N,
+                          int block_nodes, int *win_lo, int *win_hi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint32_t base = slice_ptr[i >> 6] + (uint32_t)(i & 63);
+    int lo = i, hi = i;
+    for (int k = 0; k < rowlen[i]; ++k) {
+        const int j = (int)(col[base + (uint32_t)k * kSlice] & kIndexMask);
+        lo = min(lo, j);
+        hi = max(hi, j);
+    }
+    atomicMin(&win_lo[i / block_nodes], lo);
+    atomicMax(&win_hi[i / block_nodes], hi);
+}
+
+// ---------------------------------------------------------------------------
+// cell keys
+// ---------------------------------------------------------------------------
+__global__ void k_keys(DevArgs a, int adv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double px, py, ux, uy;
+    advanced_pos(a, i, adv != 0, px, py, ux, uy);
+    const int ag = a.pagg[a.part[i]];
+    int cx, cy;
+    cell_of(a, ag, px, py, cx, cy);
+    a.keys[i] = a.agg_cell0[ag] + (uint32_t)cy * (uint32_t)a.agg_ncx[ag] + (uint32_t)cx;
+}
+
+// ---------------------------------------------------------------------------
+// radix sort: histogram, per-digit scan over tiles, stable scatter
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortBlock) void k_hist(const uint32_t *keys, int N, int shift,
+                                                     uint32_t *hist, int G) {
+    __shared__ uint32_t cnt[kRadix];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kSortTile;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int idx = base + r * kSortBlock + threadIdx.x;
+        if (idx < N) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// one block per digit: exclusive scan of the digit's tile counts, digit total
+__global__ __launch_bounds__(kSortBlock) void k_digit_scan(uint32_t *hist, int G,
+                                                           uint32_t *dtotal) {
+    __shared__ uint32_t sh[4];
+    const int d = blockIdx.x;
+    uint32_t carry = 0;
+    for (int s = 0; s < G; s += kSortBlock) {
+        const int k = s + threadIdx.x;
+        const uint32_t v = k < G ? hist[d * G + k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan256(v, &tot, sh);
+        if (k < G) hist[d * G + k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtotal[d] = carry;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_scatter(const uint32_t *kin, const int *vin,
+                                                        uint32_t *kout, int *vout, int N,
+                                                        int shift, const uint32_t *hist, int G,
+                                                        const uint32_t *dtotal) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t wc[4][kRadix];
+    __shared__ uint32_t sh[4];
+    const int t = threadIdx.x, w = t >> 6;
+    uint32_t tot;
+    const uint32_t dbase = block_excl_scan256(dtotal[t], &tot, sh);
+    run[t] = dbase + hist[t * G + blockIdx.x];
+    wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
+    __syncthreads();
+    const uint64_t lt = __lanemask_lt();
+    const int base = blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int idx = base + r * kSortBlock + t;
+        const bool valid = idx < N;
+        const uint32_t key = valid ? kin[idx] : 0u;
+        const int val = valid ? (vin ? vin[idx] : idx) : 0;
+        const uint32_t d = (key >> shift) & (kRadix - 1);
+        // lanes of this wavefront holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wc[q][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cell starts and sorted payload
+// ---------------------------------------------------------------------------
+__global__ void k_cells(DevArgs a, int adv, int advance_step) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (advance_step && k == 0) *a.step += 1;
+    if (k >= a.N) return;
+    const uint32_t key = a.skey[k];
+    if (k == 0 || a.skey[k - 1] != key) a.cell_start[key] = (uint32_t)k;
+    const int j = a.perm[k];
+    double px, py, ux, uy;
+    advanced_pos(a, j, adv != 0, px, py, ux, uy);
+    a.spx[k] = px;
+    a.spy[k] = py;
+    a.spart[k] = a.part[j];
+}
+
+// ---------------------------------------------------------------------------
+// contact laws (Sec. 4.1-4.4) and walls (Sec. 4.5), FP64
+// ---------------------------------------------------------------------------
+// damping (Sec. 4.3) and friction (Sec. 4.2) on node i; e from i toward the
+// partner, vr = v_i - v_partner, Fr = |F_r|, mi = rho_i V_i, Vp = partner
+// volume or wall-region area, Kd = stiffness in beta_d
+__device__ __forceinline__ void damp_fric(const DevArgs &a, double mi, double Vi, double Vp,
+                                          double Kd, double ex, double ey, double vrx, double vry,
+                                          double Fr, double &fx, double &fy) {
+    const double vn = vrx * ex + vry * ey;
+    const double c = 2.0 * a.rd * sqrt(Kd * mi * Vi * Vp);
+    fx = -c * vn * ex;
+    fy = -c * vn * ey;
+    const double vtx = vrx - vn * ex, vty = vry - vn * ey;
+    const double vt = sqrt(vtx * vtx + vty * vty);
+    const double vthr = a.mu * Fr * a.dt / mi;
+    if (vt > vthr) {  // sliding: mu |F_r| against the tangential relative velocity
+        const double g = a.mu * Fr / vt;
+        fx -= g * vtx;
+        fy -= g * vty;
+        count(a, C_SLIP);
+    } else {  // sticking: removes the tangential relative velocity in one step
+        const double g = mi / a.dt;
+        fx -= g * vtx;
+        fy -= g * vty;
+        count(a, C_STICK);
+    }
+}
+
+// phi - sin(phi), series below 0.5
+__device__ __forceinline__ double phi_minus_sin(double phi) {
+    if (phi < 0.5) {
+        const double p2 = phi * phi;
+        double term = phi * p2 * (1.0 / 6.0), s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s += term;
+            term *= -p2 / ((2.0 * k + 4.0) * (2.0 * k + 5.0));
+        }
+        return s;
+    }
+    return phi - sin(phi);
+}
+
+// |S| (Rc - |c - p|) of the circular segment of central angle phi, divided
+// by Rc^3: (phi - sin phi)/2 - (2/3) sin^3(phi/2).  Its Taylor series
+// (leading term phi^5/160) is summed for phi < 2, where the two terms cancel.
+__device__ __forceinline__ double segment_gap(double phi) {
+    if (phi < 2.0) {
+        const double p2 = phi * phi;
+        double pw = p2 * p2 * phi * (1.0 / 120.0);
+        double a5 = 0.03125, b5 = 7.59375;  // 0.5^5, 1.5^5
+        double h = 0.0;
+#pragma unroll
+        for (int k = 2; k < 18; ++k) {
+            const double ck = -0.5 - 0.5 * a5 + b5 * (1.0 / 6.0);
+            h += (k & 1) ? -ck * pw : ck * pw;
+            pw *= p2 / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+            a5 *= 0.25;
+            b5 *= 2.25;
+        }
+        return h;
+    }
+    const double sh = sin(0.5 * phi);
+    return 0.5 * (phi - sin(phi)) - (2.0 / 3.0) * sh * sh * sh;
+}
+
+// one wall region of area A acting on node i: repulsion Fr along -e (e from
+// the node toward the region's centroid), damping and friction against the
+// region's velocity (0, wvy)
+__device__ __forceinline__ void wall_region(const DevArgs &a, double Kn, double A, double Fr,
+                                            double ex, double ey, double wvy, double vxi,
+                                            double vyi, double mi, double Vi, double sign,
+                                            double &fx, double &fy) {
+    double dfx, dfy;
+    damp_fric(a, mi, Vi, A, Kn, ex, ey, vxi, vyi - wvy, fabs(Fr), dfx, dfy);
+    fx += sign * (-Fr * ex + dfx);
+    fy += sign * (-Fr * ey + dfy);
+    count(a, C_WALL);
+}
+
+__device__ void wall_forces(const DevArgs &a, int ag, double px, double py, double vxi,
+                            double vyi, double mi, double Vi, double Kn, double t, double &fx,
+                            double &fy, int &st) {
+    const double Rc = a.Rc;
+    const double vtop = a.vtop[ag];
+    const double d[4] = {px - a.box[4 * ag], a.box[4 * ag + 1] - px, py - a.box[4 * ag + 2],
+                         (a.box[4 * ag + 3] - vtop * t) - py};
+    // quick exit: far from every wall
+    if (d[0] >= Rc && d[1] >= Rc && d[2] >= Rc && d[3] >= Rc) return;
+    const double nx[4] = {-1.0, 1.0, 0.0, 0.0}, ny[4] = {0.0, 0.0, -1.0, 1.0};
+    const double wv[4] = {0.0, 0.0, 0.0, -vtop};
+    for (int w = 0; w < 4; ++w) {
+        if (!(d[w] > -Rc)) st |= kStEscaped;
+        if (d[w] < Rc && d[w] > -Rc) {
+            // circular segment beyond the wall: area (Rc^2/2)(phi - sin phi),
+            // phi = 4 asin(sqrt((Rc - d)/(2 Rc))); centroid (2/3)(Rc^2-d^2)^1.5/A
+            const double phi = 4.0 * asin(sqrt((Rc - d[w]) / (2.0 * Rc)));
+            const double A = 0.5 * Rc * Rc * phi_minus_sin(phi);
+            if (A > 0.0) {
+                // K_n (Rc - |c - p|) V_i |S| without cancellation as d -> Rc
+                const double Fr = Kn * Vi * (Rc * Rc * Rc * segment_gap(phi));
+                wall_region(a, Kn, A, Fr, nx[w], ny[w], wv[w], vxi, vyi, mi, Vi, 1.0, fx, fy);
+            }
+        }
+    }
+    // corners: (left, floor), (floor, right), (right, top), (top, left)
+    const int pa[4] = {0, 2, 1, 3}, pb[4] = {2, 1, 3, 0};
+    for (int k = 0; k < 4; ++k) {
+        const int wa = pa[k], wb = pb[k];
+        const double da = d[wa], db = d[wb];
+        if (!(da > -Rc && db > -Rc && da * da + db * db < Rc * Rc)) continue;
+        // triangle (da,db)-(x2,db)-(da,y1) plus the circular segment on its hypotenuse
+        const double x2 = sqrt((Rc - db) * (Rc + db)), y1 = sqrt((Rc - da) * (Rc + da));
+        const double D = (Rc - da) * (Rc + da) - db * db;
+        const double wx = da > 0.0 ? D / (x2 + da) : x2 - da;
+        const double wy = db > 0.0 ? D / (y1 + db) : y1 - db;
+        const double At = 0.5 * wx * wy;
+        const double chord = sqrt(wx * wx + wy * wy);
+        const double half = asin(chord / (2.0 * Rc));
+        const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
+        const double sh = sin(half);
+        const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
+        const double A = At + As;
+        if (!(A > 0.0)) continue;
+        const double Ix = At * (da + (da + wx) + da) / 3.0 + ms * (wy / chord);
+        const double Iy = At * (db + db + (db + wy)) / 3.0 + ms * (wx / chord);
+        const double cx = (Ix * nx[wa] + Iy * nx[wb]) / A, cy = (Ix * ny[wa] + Iy * ny[wb]) / A;
+        const double dist = sqrt(cx * cx + cy * cy);
+        const double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
+        const double Fr = Kn * (Rc - dist) * Vi * A;
+        wall_region(a, Kn, A, Fr, cx / dist, cy / dist, wvy, vxi, vyi, mi, Vi, -1.0, fx, fy);
+    }
+}
+
+// bond (i, j) is in the reference set and intact (scan of i's own row)
+__device__ __forceinline__ bool bonded_intact(const DevArgs &a, int i, int j) {
+    const uint32_t base = a.slice_ptr[i >> 6] + (uint32_t)(i & 63);
+    const int n = a.rowlen[i];
+    for (int k = 0; k < n; ++k) {
+        const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+        const int jj = (int)(e & kIndexMask);
+        if (jj == j) return (e & kBroken) == 0;
+        if (jj > j) break;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// the force kernel
+// ---------------------------------------------------------------------------
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
+    extern __shared__ double lds[];
+    double *Sx = lds, *Sy = lds + lds_cap, *Spx = lds + 2 * lds_cap, *Spy = lds + 3 * lds_cap,
+           *Sv = lds + 4 * lds_cap;
+    constexpr bool adv = (MODE == M_STEP);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lo = 0;
+    bool staged = false;
+    if (a.use_lds) {
+        lo = a.win_lo[blockIdx.x];
+        const int cnt = a.win_hi[blockIdx.x] - lo + 1;
+        staged = cnt > 0 && cnt <= lds_cap;
+        if (staged) {
+            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+                const int j = lo + k;
+                double px, py, ux, uy;
+                advanced_pos(a, j, adv, px, py, ux, uy);
+                Sx[k] = a.x[j];
+                Sy[k] = a.y[j];
+                Spx[k] = px;
+                Spy[k] = py;
+                Sv[k] = a.vol[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (i >= a.N) return;
+
+    const double xi = a.x[i], yi = a.y[i];
+    double pxi, pyi, uxi, uyi;
+    advanced_pos(a, i, adv, pxi, pyi, uxi, uyi);
+    const double vxi = a.vx[i], vyi = a.vy[i];  // velocities of the previous step
+    const double Vi = a.vol[i], mi = a.mass[i];
+    const int pi = a.part[i];
+    const int mt = a.pmat[pi];
+    const int ag = a.pagg[pi];
+    const MatConst mc = a.mat[mt];
+    const double t = (double)(*a.step) * a.dt;  // wall time of this evaluation
+    int st = 0;
+
+    // ---- contact: nodes of the 3 x 3 neighbouring cells -------------------
+    R fsx = 0, fsy = 0, fnx = 0, fny = 0;
+    {
+        int cx, cy;
+        cell_of(a, ag, pxi, pyi, cx, cy);
+        const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
+        const uint32_t c0 = a.agg_cell0[ag];
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = cy + dy;
+            if (yy < 0 || yy >= ncy) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = cx + dx;
+                if (xx < 0 || xx >= ncx) continue;
+                const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
+                const uint32_t s = a.cell_start[c];
+                if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
+                for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
+                    const int j = a.perm[k];
+                    if (j == i) continue;
+                    const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
+                    const double r2 = ddx * ddx + ddy * ddy;
+                    if (!(r2 < a.Rc2)) continue;
+                    if (r2 == 0.0) {
+                        count(a, C_COINC);
+                        continue;
+                    }
+                    const int pj = a.spart[k];
+                    const bool same = (pj == pi);
+                    if (same && bonded_intact(a, i, j)) continue;
+                    const double d = sqrt(r2);
+                    const double ex = ddx / d, ey = ddy / d;
+                    const double Vj = a.vol[j];
+                    double coef, Kd;
+                    if (!same) {
+                        const double Ka = mc.Kn, Kb = a.mat[a.pmat[pj]].Kn;
+                        const double Kn = (2.0 * Ka * Kb) / (Ka + Kb);
+                        coef = -Kn * (a.Rc - d);
+                        Kd = Kn;
+                        count(a, C_INTER);
+                    } else {
+                        const double X = a.x[j] - xi, Y = a.y[j] - yi;
+                        const double L = sqrt(X * X + Y * Y);
+                        if (L < a.Rc)
+                            coef = (d < L) ? mc.cw * (d - L) / L : 0.0;
+                        else
+                            coef = mc.cw * (d - a.Rc) / a.Rc;
+                        Kd = mc.Kd_self;
+                        count(a, C_SELF);
+                    }
+                    const double Frx = coef * Vi * Vj * ex, Fry = coef * Vi * Vj * ey;
+                    const double Fr = fabs(coef) * Vi * Vj;
+                    double dfx, dfy;
+                    damp_fric(a, mi, Vi, Vj, Kd, ex, ey, vxi - a.vx[j], vyi - a.vy[j], Fr, dfx, dfy);
+                    if (same) {
+                        fsx += (R)(Frx + dfx);
+                        fsy += (R)(Fry + dfy);
+                    } else {
+                        fnx += (R)(Frx + dfx);
+                        fny += (R)(Fry + dfy);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- walls ---------------------------------------------------------------
+    double fwx = 0.0, fwy = 0.0;
+    wall_forces(a, ag, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+
+    // ---- peridynamic bonds (SELL-64 row, columns ascending) ------------------
+    R fpx = 0, fpy = 0;
+    {
+        const uint32_t sl = (uint32_t)i >> 6;
+        const uint32_t base = a.slice_ptr[sl] + (uint32_t)(i & 63);
+        const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+        const double cw = mc.cw, s0 = mc.s0, eps = mc.eps;
+        const bool conic = mc.conic != 0;
+        unsigned long long nbrk = 0;
+        for (int k = 0; k < W; ++k) {
+            const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+            if (e & kBroken) continue;
+            const int j = (int)e;
+            double xj, yj, pxj, pyj, Vj;
+            if (staged) {
+                const int q = j - lo;
+                xj = Sx[q];
+                yj = Sy[q];
+                pxj = Spx[q];
+                pyj = Spy[q];
+                Vj = Sv[q];
+            } else {
+                double ux, uy;
+                advanced_pos(a, j, adv, pxj, pyj, ux, uy);
+                xj = a.x[j];
+                yj = a.y[j];
+                Vj = a.vol[j];
+            }
+            bool brk;
+            R f, DXr, DYr, lr;
+            if constexpr (sizeof(R) == 8) {
+                const double X = xj - xi, Y = yj - yi;
+                const double l0 = sqrt(X * X + Y * Y);
+                const double DX = pxj - pxi, DY = pyj - pyi;
+                const double l = sqrt(DX * DX + DY * DY);
+                const double s = (l - l0) / l0;
+                brk = fabs(s) > s0;
+                const double w = conic ? 1.0 - l0 / eps : 1.0;
+                f = cw * w * s * Vi * Vj;
+                DXr = DX;
+                DYr = DY;
+                lr = l;
+            } else {
+                const float X = (float)(xj - xi), Y = (float)(yj - yi);
+                const float l0 = __builtin_amdgcn_sqrtf(X * X + Y * Y);
+                const float DX = (float)(pxj - pxi), DY = (float)(pyj - pyi);
+                const float l = __builtin_amdgcn_sqrtf(DX * DX + DY * DY);
+                const float s = (l - l0) * __builtin_amdgcn_rcpf(l0);
+                brk = false;
+                // near or beyond s0 the break decision is taken in FP64
+                if (fabsf(s) > (float)(s0 - 2e-6)) {
+                    const double Xd = xj - xi, Yd = yj - yi;
+                    const double l0d = sqrt(Xd * Xd + Yd * Yd);
+                    const double DXd = pxj - pxi, DYd = pyj - pyi;
+                    const double ld = sqrt(DXd * DXd + DYd * DYd);
+                    brk = fabs((ld - l0d) / l0d) > s0;
+                }
+                const float w = conic ? 1.0f - l0 / (float)eps : 1.0f;
+                f = (float)cw * w * s * (float)Vi * (float)Vj;
+                DXr = DX;
+                DYr = DY;
+                lr = l;
+            }
+            if (brk) {  // Sec. 3.1: broken for good
+                if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
+                ++nbrk;
+                continue;
+            }
+            if constexpr (sizeof(R) == 8) {
+                fpx += f * DXr / lr;
+                fpy += f * DYr / lr;
+            } else {
+                const R g = f * __builtin_amdgcn_rcpf(lr);
+                fpx += g * DXr;
+                fpy += g * DYr;
+            }
+        }
+        if (MODE != M_FORCES) count(a, C_BROKEN, nbrk);
+    }
+
+    // ---- outputs ---------------------------------------------------------------
+    const double Fx = (((double)fpx + (double)fsx) + (double)fnx) + fwx;
+    const double Fy = (((double)fpy + (double)fsy) + (double)fny) + fwy;
+    if (MODE == M_FORCES) {
+        const int N = a.N;
+        double *T = a.terms;
+        T[0 * N + i] = (double)fpx / Vi;
+        T[1 * N + i] = (double)fpy / Vi;
+        T[2 * N + i] = (double)fsx / Vi;
+        T[3 * N + i] = (double)fsy / Vi;
+        T[4 * N + i] = (double)fnx / Vi;
+        T[5 * N + i] = (double)fny / Vi;
+        T[6 * N + i] = fwx / Vi;
+        T[7 * N + i] = fwy / Vi;
+        T[8 * N + i] = mi * a.gx / Vi;
+        T[9 * N + i] = mi * a.gy / Vi;
+    } else {
+        const double axn = Fx / mi + a.gx, ayn = Fy / mi + a.gy;
+        a.ax_o[i] = axn;
+        a.ay_o[i] = ayn;
+        if (MODE == M_STEP) {
+            const double vxn = vxi + a.hdt * (a.ax[i] + axn);
+            const double vyn = vyi + a.hdt * (a.ay[i] + ayn);
+            a.vx_o[i] = vxn;
+            a.vy_o[i] = vyn;
+            a.ux_o[i] = uxi;
+            a.uy_o[i] = uyi;
+            if (!(isfinite(uxi) && isfinite(uyi) && isfinite(vxn) && isfinite(vyn)))
+                st |= kStNonfinite;
+        }
+    }
+    if (st) atomicOr(a.status, st);
+}
+
+// ---------------------------------------------------------------------------
+// outputs
+// ---------------------------------------------------------------------------
+__global__ void k_sum_terms(DevArgs a, uint32_t mask, double *fx, double *fy) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double sx = 0.0, sy = 0.0;
+    for (int t = 0; t < 5; ++t)
+        if (mask & (1u << t)) {
+            sx += a.terms[(2 * t) * a.N + i];
+            sy += a.terms[(2 * t + 1) * a.N + i];
+        }
+    fx[i] = sx;
+    fy[i] = sy;
+}
+
+__global__ void k_damage(DevArgs a, double *phi, unsigned long long *nb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = 0, nref = 0;
+    if (i < a.N) {
+        const uint32_t base = a.slice_ptr[i >> 6] + (uint32_t)(i & 63);
+        nref = a.rowlen[i];
+        for (int k = 0; k < nref; ++k) n += (a.col[base + (uint32_t)k * kSlice] & kBroken) ? 1 : 0;
+        if (phi) phi[i] = nref > 0 ? (double)n / (double)nref : 0.0;
+    }
+    // wavefront reduction, one integer atomic per wavefront
+    unsigned long long v = (unsigned long long)n;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(nb, v);
+}
+
+// contact set (pairs i < j) at the current sorted positions
+template <bool FILL>
+__global__ void k_contacts(DevArgs a, int *cnt, const long long *off, int *pi_out, int *pj_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double pxi, pyi, ux, uy;
+    advanced_pos(a, i, false, pxi, pyi, ux, uy);
+    const int ag = a.pagg[a.part[i]];
+    int cx, cy;
+    cell_of(a, ag, pxi, pyi, cx, cy);
+    const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
+    long long w = FILL ? off[i] : 0;
+    int n = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int yy = cy + dy, xx = cx + dx;
+            if (yy < 0 || yy >= ncy || xx < 0 || xx >= ncx) continue;
+            const uint32_t c = a.agg_cell0[ag] + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
+            const uint32_t s = a.cell_start[c];
+            if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
+            for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
+                const int j = a.perm[k];
+                if (j <= i) continue;
+                const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
+                if (ddx * ddx + ddy * ddy < a.Rc2) {
+                    if (FILL) {
+                        pi_out[w] = i;
+                        pj_out[w] = j;
+                        ++w;
+                    }
+                    ++n;
+                }
+            }
+        }
+    if (!FILL) cnt[i] = n;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, hipStream_t s) {
+    if (b.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bonds_count_w, dim3(grid_for(b.N, 128)), dim3(128), 0, s, b, rowlen);
+    return hipGetLastError();
+}
+
+hipError_t launch_bonds_fill(const BondArgs &b, uint32_t *col, const uint32_t *slice_ptr,
+                             hipStream_t s) {
+    if (b.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bonds_fill_w, dim3(grid_for(b.N, 128)), dim3(128), 0, s, b, col,
+                       slice_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_windows(const DevArgs &a, int *win_lo, int *win_hi, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_windows, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a.col, a.slice_ptr,
+                       a.rowlen, a.N, a.block_nodes, win_lo, win_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const DevArgs &a, int adv, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a, adv);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int N,
+                            int shift, uint32_t *hist, uint32_t *dtotal, hipStream_t s,
+                            hipEvent_t *ev) {
+    const int G = (int)grid_for(N, kSortTile);
+    if (ev) hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(k_hist, dim3(G), dim3(kSortBlock), 0, s, kin, N, shift, hist, G);
+    if (ev) hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL(k_digit_scan, dim3(kRadix), dim3(kSortBlock), 0, s, hist, G, dtotal);
+    if (ev) hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL(k_scatter, dim3(G), dim3(kSortBlock), 0, s, kin, vin, kout, vout, N, shift,
+                       hist, G, dtotal);
+    if (ev) hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t s) {
+    const int n = a.N > 0 ? a.N : 1;
+    hipLaunchKernelGGL(k_cells, dim3(grid_for(n, 256)), dim3(256), 0, s, a, adv, advance_step);
+    return hipGetLastError();
+}
+
+int force_lds_cap(int max_win) { return max_win > kMaxLdsNodes ? 0 : max_win; }
+
+hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    const int B = a.block_nodes;
+    const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
+    const dim3 g(grid_for(a.N, B)), b(B);
+    if (precision == PD_PREC_FP64) {
+        if (mode == M_STEP)
+            hipLaunchKernelGGL((k_force<double, M_STEP>), g, b, shm, s, a, lds_cap);
+        else if (mode == M_FORCES)
+            hipLaunchKernelGGL((k_force<double, M_FORCES>), g, b, shm, s, a, lds_cap);
+        else
+            hipLaunchKernelGGL((k_force<double, M_PROLOGUE>), g, b, shm, s, a, lds_cap);
+    } else {
+        if (mode == M_STEP)
+            hipLaunchKernelGGL((k_force<float, M_STEP>), g, b, shm, s, a, lds_cap);
+        else if (mode == M_FORCES)
+            hipLaunchKernelGGL((k_force<float, M_FORCES>), g, b, shm, s, a, lds_cap);
+        else
+            hipLaunchKernelGGL((k_force<float, M_PROLOGUE>), g, b, shm, s, a, lds_cap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_terms(const DevArgs &a, uint32_t mask, double *fx, double *fy,
+                            hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_terms, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a, mask, fx, fy);
+    return hipGetLastError();
+}
+
+hipError_t launch_damage(const DevArgs &a, double *phi, unsigned long long *nb, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_damage, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a, phi, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_contacts_count(const DevArgs &a, int *cnt, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_contacts<false>), dim3(grid_for(a.N, 256)), dim3(256), 0, s, a, cnt,
+                       (const long long *)nullptr, (int *)nullptr, (int *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_contacts_fill(const DevArgs &a, const long long *off, int *pi, int *pj,
+                                hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_contacts<true>), dim3(grid_for(a.N, 256)), dim3(256), 0, s, a,
+                       (int *)nullptr, off, pi, pj);
+    return hipGetLastError();
+}
+
+}  // namespace pd

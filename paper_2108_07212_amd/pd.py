@@ -1,0 +1,273 @@
+"""Python binding of libpd (include/pd.h): argument marshalling only.
+
+Every computation runs in libpd's HIP kernels.  torch supplies device memory
+(outputs with on_device=True) and the stream; it is imported before libpd is
+loaded so that both use the same HIP runtime.  There is no CPU fallback: if
+libpd.so has not been built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpd.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "pd.h")
+
+PD_OK, PD_E_INVALID, PD_E_NOMEM, PD_E_DEVICE, PD_E_NONFINITE, PD_E_ESCAPED, PD_E_STATE = range(7)
+TERM_PD, TERM_SELF, TERM_NBR, TERM_WALL, TERM_BODY, TERM_ALL = 1, 2, 4, 8, 16, 31
+KERNEL_CLASSES = ("keys", "radix_hist", "radix_digit_scan", "radix_scatter", "cells", "force")
+
+
+class PDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libpd status {status}: {msg}")
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("rho", C.c_double), ("bulk_k", C.c_double), ("young_E", C.c_double),
+                ("Gc", C.c_double), ("horizon", C.c_double), ("micro", C.c_int32)]
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_particles", C.c_int32), ("n_aggregates", C.c_int32),
+                ("n_materials", C.c_int32),
+                ("x", _dp), ("y", _dp), ("vol", _dp),
+                ("particle_offset", _ip), ("particle_material", _ip), ("particle_aggregate", _ip),
+                ("materials", C.POINTER(Material)),
+                ("loop_offset", _ip), ("loop_vertex_offset", _ip), ("loop_xy", _dp),
+                ("u0x", _dp), ("u0y", _dp), ("v0x", _dp), ("v0y", _dp),
+                ("contact_radius", C.c_double), ("friction_mu", C.c_double),
+                ("damping_ratio", C.c_double), ("kn_mode", C.c_int32),
+                ("box", _dp), ("top_wall_speed", _dp),
+                ("gravity_x", C.c_double), ("gravity_y", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int32), ("hip_stream", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block_nodes", C.c_int32), ("cell_factor", C.c_double),
+                ("use_lds", C.c_int32), ("use_graph", C.c_int32)]
+
+    def as_dict(self):
+        return dict(block_nodes=self.block_nodes, cell_factor=self.cell_factor,
+                    use_lds=self.use_lds, use_graph=self.use_graph)
+
+
+_lib = None
+
+
+def header_functions() -> list:
+    """Names of the functions include/pd.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pd_[a-z_]+)\s*\(", txt)))
+
+
+def load_library(path: str = LIB_PATH):
+    """dlopen libpd.so after torch (shared HIP runtime).  Raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpd.so not built at {path}: run __graft_entry__.build()")
+    import torch  # noqa: F401  -- HIP runtime first
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    L.pd_setup.argtypes = [C.POINTER(Problem), C.POINTER(vp)]
+    L.pd_destroy.argtypes = [vp]
+    L.pd_destroy.restype = None
+    L.pd_last_error.argtypes = [vp]
+    L.pd_last_error.restype = C.c_char_p
+    L.pd_step.argtypes = [vp, C.c_int64]
+    L.pd_forces.argtypes = [vp, C.c_uint32, vp, vp, C.c_int32]
+    L.pd_damage.argtypes = [vp, vp, C.POINTER(C.c_int64), C.c_int32]
+    L.pd_n_bonds.argtypes = [vp]
+    L.pd_n_bonds.restype = C.c_int64
+    L.pd_bonds.argtypes = [vp, _ip, _ip]
+    L.pd_contacts.argtypes = [vp, _ip, _ip, C.c_int64, C.POINTER(C.c_int64)]
+    L.pd_get_state.argtypes = [vp] + [_dp] * 6 + [C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]
+    L.pd_set_state.argtypes = [vp] + [_dp] * 6 + [C.POINTER(C.c_uint8), C.c_int64]
+    L.pd_counters.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.pd_set_counting.argtypes = [vp, C.c_int32]
+    L.pd_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pd_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pd_autotune.argtypes = [vp, C.c_int32, C.POINTER(Tuning)]
+    L.pd_time_kernels.argtypes = [vp, C.c_int64, _dp, _ip, C.c_int32]
+    L.pd_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    _lib = L
+    return L
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+class PD:
+    """One libpd context over a workloads.Problem."""
+
+    def __init__(self, prob, stream=None, precision=None):
+        import torch
+        self.lib = load_library()
+        self.prob = prob
+        f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        k = self._keep = dict(
+            x=f64(prob.x), y=f64(prob.y), vol=f64(prob.vol), po=i32(prob.particle_offset),
+            pm=i32(prob.particle_material), pa=i32(prob.particle_aggregate),
+            lo=i32(prob.loop_offset), lvo=i32(prob.loop_vertex_offset),
+            lxy=f64(prob.loop_xy) if len(prob.loop_xy) else np.zeros(1),
+            box=f64(prob.box).ravel(), vt=f64(prob.top_wall_speed),
+            u0x=f64(prob.u0x), u0y=f64(prob.u0y), v0x=f64(prob.v0x), v0y=f64(prob.v0y))
+        mats = (Material * len(prob.materials))()
+        for q, m in enumerate(prob.materials):
+            mats[q] = Material(m.rho, m.bulk_k, m.young_E, m.Gc, m.horizon, m.micro)
+        k["mats"] = mats
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        prec = prob.precision if precision is None else precision
+        pr = Problem(prob.n_nodes, prob.n_particles, prob.n_aggregates, len(prob.materials),
+                     _p(k["x"], C.c_double), _p(k["y"], C.c_double), _p(k["vol"], C.c_double),
+                     _p(k["po"], C.c_int32), _p(k["pm"], C.c_int32), _p(k["pa"], C.c_int32), mats,
+                     _p(k["lo"], C.c_int32), _p(k["lvo"], C.c_int32), _p(k["lxy"], C.c_double),
+                     _p(k["u0x"], C.c_double), _p(k["u0y"], C.c_double),
+                     _p(k["v0x"], C.c_double), _p(k["v0y"], C.c_double),
+                     prob.contact_radius, prob.friction_mu, prob.damping_ratio, prob.kn_mode,
+                     _p(k["box"], C.c_double), _p(k["vt"], C.c_double),
+                     prob.gravity[0], prob.gravity[1], prob.dt, prec,
+                     C.c_void_p(stream.cuda_stream))
+        self._pr = pr
+        h = C.c_void_p()
+        st = self.lib.pd_setup(C.byref(pr), C.byref(h))
+        self.h = h
+        if st != PD_OK:
+            self._raise(st)
+        self.N = prob.n_nodes
+
+    def _raise(self, st):
+        msg = self.lib.pd_last_error(self.h).decode() if self.h else ""
+        raise PDError(st, msg)
+
+    def _chk(self, st):
+        if st != PD_OK:
+            self._raise(st)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the four calls of the problem statement ---------------------------
+    def step(self, n: int = 1, check: bool = True) -> int:
+        st = self.lib.pd_step(self.h, int(n))
+        if check and st not in (PD_OK,):
+            self._raise(st)
+        return st
+
+    def forces(self, mask: int = TERM_ALL, device: bool = False):
+        if device:
+            import torch
+            fx = torch.empty(self.N, dtype=torch.float64, device="cuda")
+            fy = torch.empty(self.N, dtype=torch.float64, device="cuda")
+            self._chk(self.lib.pd_forces(self.h, mask, C.c_void_p(fx.data_ptr()),
+                                         C.c_void_p(fy.data_ptr()), 1))
+            return fx, fy
+        fx = np.zeros(self.N)
+        fy = np.zeros(self.N)
+        self._chk(self.lib.pd_forces(self.h, mask, C.c_void_p(fx.ctypes.data),
+                                     C.c_void_p(fy.ctypes.data), 0))
+        return fx, fy
+
+    def damage(self):
+        phi = np.zeros(self.N)
+        nb = C.c_int64()
+        self._chk(self.lib.pd_damage(self.h, C.c_void_p(phi.ctypes.data), C.byref(nb), 0))
+        return phi, nb.value
+
+    # -- inspection ------------------------------------------------------------
+    def bonds(self):
+        nnz = self.lib.pd_n_bonds(self.h)
+        row = np.zeros(self.N + 1, dtype=np.int32)
+        col = np.zeros(max(nnz, 1), dtype=np.int32)
+        self._chk(self.lib.pd_bonds(self.h, _p(row, C.c_int32), _p(col, C.c_int32)))
+        return row, col[:nnz]
+
+    def contacts(self):
+        cnt = C.c_int64()
+        self._chk(self.lib.pd_contacts(self.h, None, None, 0, C.byref(cnt)))
+        n = cnt.value
+        pi = np.zeros(max(n, 1), dtype=np.int32)
+        pj = np.zeros(max(n, 1), dtype=np.int32)
+        self._chk(self.lib.pd_contacts(self.h, _p(pi, C.c_int32), _p(pj, C.c_int32), n, C.byref(cnt)))
+        return pi[:n], pj[:n]
+
+    def get_state(self):
+        arrs = [np.zeros(self.N) for _ in range(6)]
+        nnz = self.lib.pd_n_bonds(self.h)
+        brk = np.zeros(max(nnz, 1), dtype=np.uint8)
+        st = C.c_int64()
+        self._chk(self.lib.pd_get_state(self.h, *[_p(a, C.c_double) for a in arrs],
+                                        _p(brk, C.c_uint8), C.byref(st)))
+        return dict(ux=arrs[0], uy=arrs[1], vx=arrs[2], vy=arrs[3], ax=arrs[4], ay=arrs[5],
+                    broken=brk[:nnz], step=st.value)
+
+    def set_state(self, s):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        arrs = [f(s[k]) for k in ("ux", "uy", "vx", "vy", "ax", "ay")]
+        brk = None if s.get("broken") is None else np.ascontiguousarray(s["broken"], dtype=np.uint8)
+        self._chk(self.lib.pd_set_state(self.h, *[_p(a, C.c_double) for a in arrs],
+                                        _p(brk, C.c_uint8), int(s["step"])))
+
+    def counters(self):
+        out = np.zeros(8, dtype=np.int64)
+        self._chk(self.lib.pd_counters(self.h, _p(out, C.c_int64)))
+        return dict(inter=out[0], self_=out[1], stick=out[2], slip=out[3], wall=out[4],
+                    coincident=out[5], broken=out[6], steps=out[7])
+
+    def set_counting(self, on: bool = True):
+        self._chk(self.lib.pd_set_counting(self.h, 1 if on else 0))
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._chk(self.lib.pd_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self._chk(self.lib.pd_get_tuning(self.h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        self._chk(self.lib.pd_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, steps: int = 20) -> dict:
+        t = Tuning()
+        self._chk(self.lib.pd_autotune(self.h, int(steps), C.byref(t)))
+        return t.as_dict()
+
+    def time_kernels(self, n_steps: int = 10):
+        ms = np.zeros(8)
+        la = np.zeros(8, dtype=np.int32)
+        self._chk(self.lib.pd_time_kernels(self.h, int(n_steps), _p(ms, C.c_double),
+                                           _p(la, C.c_int32), 8))
+        return {k: (float(ms[i]), int(la[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def sizes(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        self._chk(self.lib.pd_sizes(self.h, _p(out, C.c_int64)))
+        keys = ("nodes", "bonds", "slots", "cells", "radix_passes", "particles", "aggregates",
+                "max_window")
+        return {k: int(v) for k, v in zip(keys, out)}

@@ -1,0 +1,319 @@
+"""Parity of the HIP path (libpd through its C ABI) with the FP64 oracle.
+
+Bars: reference bond sets and contact sets bit-exact; per-step forces
+||F_gpu - F_oracle||_inf / ||F_oracle||_inf <= 1e-12 per term; 100-step
+trajectories max|u_gpu - u_oracle| / max|u_oracle| <= 1e-9 (same for v).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2108_07212_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FORCE_TOL = 1e-12
+TRAJ_TOL = 1e-9
+TERMS = (1, 2, 4, 8, 16)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pdmod():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2108_07212_amd import pd
+    pd.load_library()
+    return pd
+
+
+def _bed(n, seed, h=0.12e-3, box=(14e-3, 14e-3), g=(0.0, 0.0), mu=0.5, rd=0.8, dt=1e-7,
+         shapes=("disk", "plus", "ring"), vtop=0.0, precision=W.PREC_FP64):
+    parts, bx = W.mixed_bed(n, h, box[0], box[1], seed, shapes=shapes)
+    return W.assemble(parts, h, [W.Material(horizon=3 * h)], bx, contact_radius=0.95 * h,
+                      friction_mu=mu, damping_ratio=rd, dt=dt, gravity=g,
+                      top_wall_speed=[vtop], precision=precision)
+
+
+def _herd(prob, alpha, seed=0, dv=0.0):
+    """Translate each particle rigidly toward the bed centre so particles
+    overlap (contacts without bond strain); optional random velocities."""
+    cx, cy = prob.x.mean(), prob.y.mean()
+    po = prob.particle_offset
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        s = slice(po[p], po[p + 1])
+        ux[s] = -alpha * (prob.x[s].mean() - cx)
+        uy[s] = -alpha * (prob.y[s].mean() - cy)
+    prob.u0x, prob.u0y = ux, uy
+    if dv:
+        W.perturb(prob, seed, dv=dv)
+    return prob
+
+
+def _relerr(a, b):
+    scale = max(np.abs(b).max(), 1e-300)
+    return np.abs(a - b).max() / scale
+
+
+def _check_forces(g, o, label):
+    worst = 0.0
+    for t in TERMS:
+        gx, gy = g.forces(t)
+        ox, oy = o.forces(t)
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        if scale == 0.0:
+            assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0, (label, t)
+            continue
+        e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
+        worst = max(worst, e)
+        assert e <= FORCE_TOL, (label, t, e)
+    return worst
+
+
+def _check_bonds(g, o, label):
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro), label
+    assert np.array_equal(cg, co), label
+
+
+# ---------------------------------------------------------------------------
+def test_bond_sets_two_disks(pdmod):
+    _say("case: bond sets, two disks")
+    prob = W.two_disks()
+    g = pdmod.PD(prob)
+    o = Oracle(prob)
+    _check_bonds(g, o, "two_disks")
+    assert len(g.bonds()[1]) == 7952
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_bond_sets_mixed_shapes(pdmod, seed):
+    """The extended-boundary / cusp-bisector detector (GPU) gives exactly the
+    plain-definition bond set (oracle) on plus, ring and L shapes."""
+    _say(f"case: bond sets, mixed shapes seed={seed}")
+    prob = _bed(12, seed, shapes=("plus", "ring", "lshape", "disk"))
+    g = pdmod.PD(prob)
+    o = Oracle(prob)
+    _check_bonds(g, o, f"mixed{seed}")
+    assert len(o.bonds()[1]) > 1000
+
+
+def test_bond_sets_lattice_aligned(pdmod):
+    """Unrotated shapes whose corners sit on lattice lines."""
+    _say("case: bond sets, lattice aligned")
+    h = 0.125e-3
+    parts = [W.Particle("plus", 1e-3, (3e-3, 3e-3), 0.0), W.Particle("lshape", 1e-3, (6e-3, 3e-3), 0.0),
+             W.Particle("ring", 1e-3, (3e-3, 6e-3), 0.0), W.Particle("plus", 1e-3, (6e-3, 6e-3), math.pi / 4)]
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], [0, 9e-3, 0, 9e-3],
+                      contact_radius=0.95 * h, friction_mu=0.5, damping_ratio=0.5, dt=1e-7)
+    _check_bonds(pdmod.PD(prob), Oracle(prob), "aligned")
+
+
+def test_forces_t0_two_disks(pdmod):
+    _say("case: forces t0 two disks")
+    prob = W.two_disks()
+    _check_forces(pdmod.PD(prob), Oracle(prob), "two_disks")
+
+
+@pytest.mark.parametrize("seed,alpha", [(3, 0.45), (5, 0.5)])
+def test_forces_contact_active(pdmod, seed, alpha):
+    """Per-step forces with inter-particle contact, self-contact after damage,
+    friction in both regimes, damping and walls, at a herded state."""
+    _say(f"case: forces contact-active seed={seed}")
+    prob = _herd(_bed(10, seed), alpha, seed=seed, dv=0.5)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_counting(True)
+    _check_forces(g, o, f"herd{seed}")
+    pi, pj = g.contacts()
+    qi, qj = o.contacts()
+    assert len(qi) > 100
+    assert np.array_equal(pi, qi) and np.array_equal(pj, qj)
+
+
+def _wall_probe(vtop=0.0, seed=0):
+    """Single-node particles at signed distances -0.8 R_c .. 0.97 R_c from each
+    wall and in each corner zone, with random velocities."""
+    h = 1e-4
+    Rc = 0.95 * h
+    L = 4e-3
+    rng = np.random.default_rng(seed)
+    pts = []
+    for d in np.linspace(-0.8, 0.97, 13) * Rc:
+        s = rng.uniform(0.2, 0.8) * L
+        pts += [(d, s), (L - d, s), (s, d), (s, L - d)]
+    for _ in range(24):
+        da, db = rng.uniform(-0.7, 0.95, 2) * Rc
+        pts += [(da, db), (L - da, db), (L - da, L - db), (da, L - db)]
+    vel = [tuple(v) for v in rng.uniform(-0.5, 0.5, (len(pts), 2))]
+    prob = W.single_node_particles(pts, vel, h * h, [0, L, 0, L], contact_radius=Rc, h=h,
+                                   friction_mu=0.4, damping_ratio=0.6, dt=1e-8)
+    prob.top_wall_speed = np.array([vtop])
+    return prob
+
+
+@pytest.mark.parametrize("vtop", [0.0, 2.0])
+def test_forces_walls_and_corners(pdmod, vtop):
+    """Wall and corner regions (Sec. 4.5) with damping and friction, including
+    a moving top wall evaluated at a later time."""
+    _say(f"case: forces walls vtop={vtop}")
+    prob = _wall_probe(vtop)
+    o = Oracle(prob)
+    g = pdmod.PD(prob)
+    _check_forces(g, o, "walls")
+    if vtop:
+        s = o.get_state()
+        s["step"] = 3  # top wall moved by 3 dt vtop
+        o.set_state(s)
+        g.set_state(s)
+        _check_forces(g, o, "walls-later")
+    wx, wy = o.forces(8)
+    assert np.count_nonzero(wx) + np.count_nonzero(wy) > 100
+
+
+def _traj(g, o, steps):
+    assert g.step(steps, check=False) == o.step(steps)
+    sg, so = g.get_state(), o.get_state()
+    eu = max(_relerr(sg["ux"], so["ux"]), _relerr(sg["uy"], so["uy"]))
+    ev = max(_relerr(sg["vx"], so["vx"]), _relerr(sg["vy"], so["vy"]))
+    return eu, ev, sg, so
+
+
+def test_trajectory_two_disks_100(pdmod):
+    _say("case: trajectory two disks")
+    prob = W.two_disks()
+    g, o = pdmod.PD(prob), Oracle(prob)
+    eu, ev, sg, so = _traj(g, o, 100)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+
+
+def test_trajectory_two_disks_contact_1000(pdmod):
+    """The contact-active two-disk case through first contact (~step 500)."""
+    _say("case: trajectory two disks contact")
+    prob = W.two_disks(contact_active=True)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    for k in range(10):
+        eu, ev, sg, so = _traj(g, o, 100)
+        assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (k, eu, ev)
+    assert o.counters()["inter"] > 0
+    assert np.array_equal(sg["broken"], so["broken"])
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_trajectory_bed_100(pdmod, seed):
+    """A herded bed with gravity 5000 m/s^2: contact, friction, damping,
+    walls and bond breaking over 100 steps."""
+    _say(f"case: trajectory bed seed={seed}")
+    prob = _herd(_bed(10, seed, g=(0.0, -5000.0)), 0.45, seed=seed, dv=0.5)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    eu, ev, sg, so = _traj(g, o, 100)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
+    pg, nbg = g.damage()
+    po, nbo = o.damage()
+    assert nbg == nbo
+    assert np.array_equal(pg, po)
+
+
+def test_damage_after_breaking(pdmod):
+    _say("case: damage")
+    h = 0.125e-3
+    parts = [W.Particle("disk", 1e-3, (3e-3, 3e-3))]
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], [0, 6e-3, 0, 6e-3],
+                      contact_radius=0.95 * h, friction_mu=0, damping_ratio=0, dt=1e-8)
+    prob.u0x = np.zeros(prob.n_nodes)
+    prob.u0x[100] = 12 * h
+    g, o = pdmod.PD(prob), Oracle(prob)
+    pg, nbg = g.damage()
+    po, nbo = o.damage()
+    assert nbg == nbo > 0 and np.array_equal(pg, po)
+
+
+def test_determinism_graph_and_tuning(pdmod):
+    """Bitwise equal results: two runs; graph vs direct launches; every block
+    size and LDS staging choice."""
+    _say("case: determinism")
+    prob = _herd(_bed(10, 21, g=(0.0, -5000.0)), 0.45, seed=21, dv=0.5)
+    ref = None
+    for bn in (256, 128, 64):
+        for lds in (1, 0):
+            for graph in (1, 0):
+                g = pdmod.PD(prob)
+                g.set_tuning(block_nodes=bn, use_lds=lds, use_graph=graph)
+                g.step(37)
+                s = g.get_state()
+                if ref is None:
+                    ref = s
+                else:
+                    for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
+                        assert np.array_equal(ref[k], s[k]), (bn, lds, graph, k)
+
+
+def test_cell_factor_changes_only_rounding(pdmod):
+    _say("case: cell factor")
+    prob = _herd(_bed(10, 22), 0.45, seed=22, dv=0.5)
+    o = Oracle(prob)
+    for cf in (1.0, 1.5, 2.0, 3.0):
+        g = pdmod.PD(prob)
+        g.set_tuning(cell_factor=cf)
+        _check_forces(g, o, f"cf{cf}")
+        assert np.array_equal(g.contacts()[0], o.contacts()[0])
+
+
+def test_checkpoint_restart(pdmod):
+    _say("case: checkpoint")
+    prob = _herd(_bed(8, 23, g=(0.0, -5000.0)), 0.4, seed=23, dv=0.3)
+    a = pdmod.PD(prob)
+    a.step(50)
+    b = pdmod.PD(prob)
+    b.step(25)
+    s = b.get_state()
+    c = pdmod.PD(prob)
+    c.set_state(s)
+    c.step(25)
+    sa, sc = a.get_state(), c.get_state()
+    for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
+        assert np.array_equal(sa[k], sc[k]), k
+
+
+def test_oracle_state_handoff(pdmod):
+    """The GPU continues from an oracle state (and vice versa) with parity."""
+    _say("case: state handoff")
+    prob = _herd(_bed(8, 24, g=(0.0, -5000.0)), 0.45, seed=24, dv=0.3)
+    o = Oracle(prob)
+    o.step(30)
+    g = pdmod.PD(prob)
+    g.set_state(o.get_state())
+    _check_forces(g, o, "handoff")
+    eu, ev, _, _ = _traj(g, o, 50)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL
+
+
+def test_escape_status(pdmod):
+    _say("case: escape")
+    h = 1e-4
+    Rc = 0.95 * h
+    prob = W.single_node_particles([(5e-3, 0.5 * Rc), (5e-3, 5e-3)], [(0, 0.0), (0, 0)], h * h,
+                                   [0, 1e-2, 0, 1e-2], contact_radius=Rc, h=h, dt=1e-8)
+    g = pdmod.PD(prob)
+    s = g.get_state()
+    s["uy"][0] = -2.0 * Rc
+    g.set_state(s)
+    assert g.step(1, check=False) == pdmod.PD_E_ESCAPED
+    assert g.step(1, check=False) == pdmod.PD_E_ESCAPED  # sticky
+
+
+def test_invalid_problem_rejected(pdmod):
+    prob = W.two_disks()
+    prob.dt = -1.0
+    with pytest.raises(pdmod.PDError) as e:
+        pdmod.PD(prob)
+    assert e.value.status == pdmod.PD_E_INVALID

@@ -15,7 +15,8 @@ import pytest
 from scipy import integrate
 
 from oracle import Oracle
-from oracle.oracle import T_ALL, T_BODY, T_NBR, T_PD, T_SELF, T_WALL, wall_corner, wall_segment
+from oracle.oracle import (T_ALL, T_BODY, T_NBR, T_PD, T_SELF, T_WALL, wall_corner, wall_segment,
+                           wall_segment_gap)
 from paper_2108_07212_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -400,6 +401,20 @@ def test_wall_segment_near_contact_radius_is_smooth():
         lead = 4 * math.sqrt(2) / 3 * Rc ** 2 * r ** 1.5  # leading term of the area
         assert A == pytest.approx(lead, rel=2 * r + 1e-12)
         assert g == pytest.approx(Rc, rel=2 * r + 1e-12)
+
+
+@pytest.mark.parametrize("d", [-0.9, -0.3, 0.0, 0.5, 0.9, 0.999, 1 - 1e-6, 1 - 1e-12, 1 - 6e-16])
+def test_wall_repulsion_factor_vs_quadrature(d):
+    """|S| (Rc - |c - p|) = int_S (Rc - X) dA (X toward the wall): the factor of
+    the single-wall repulsion, pinned by direct quadrature, which has no
+    cancellation as d -> Rc."""
+    Rc = 1.0
+    f = lambda X: (Rc - X) * 2 * math.sqrt(max(0.0, Rc * Rc - X * X))
+    q = integrate.quad(f, d, Rc, epsabs=0, epsrel=1e-12, limit=400)[0]
+    assert wall_segment_gap(Rc, d) == pytest.approx(q, rel=1e-9)
+    A, g = wall_segment(Rc, d)
+    if d < 0.99:  # the printed centroid form is well conditioned here
+        assert wall_segment_gap(Rc, d) == pytest.approx(A * (Rc - g), rel=1e-12)
 
 
 @pytest.mark.parametrize("da,db", [(0.0, 0.0), (0.2, 0.3), (0.5, 0.5), (0.6, 0.1), (-0.3, 0.4),
