@@ -106,14 +106,18 @@ typedef struct {
     void *hip_stream;                   /* hipStream_t for all work, or NULL */
 } pd_problem;
 
-/* Tuning of the launch configuration; results are identical for every
- * block size and staging choice, and equal within rounding for every cell
- * factor (the contact set itself never changes). */
+/* Tuning of the launch configuration.  Results are bitwise identical for
+ * every block size, staging and graph choice, and equal within rounding for
+ * every cell factor and skin (the contact set itself never changes: it is
+ * evaluated from exact distances every step). */
 typedef struct {
     int32_t block_nodes;  /* nodes per workgroup of the force kernel: 64, 128 or 256 */
-    double cell_factor;   /* cell side / R_c, >= 1 */
+    double cell_factor;   /* cell side / search radius, >= 1 */
     int32_t use_lds;      /* stage bond partners' coordinates in LDS (1) or read through cache (0) */
     int32_t use_graph;    /* replay steps as a captured HIP graph (1) or launch directly (0) */
+    double skin_factor;   /* contact candidates within R_c (1 + skin_factor) are listed per node
+                             and the list is rebuilt (cell-key radix sort) when a node has moved
+                             half the skin or a bond broke; 0: search the cells every step */
 } pd_tuning;
 
 /* Builds the context: validates the problem, copies it to the device,
@@ -185,16 +189,21 @@ pd_status pd_set_tuning(pd_ctx *c, const pd_tuning *t);
 pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
 
 /* Kernel timing: runs n_steps steps with direct launches and records HIP
- * events on the context's stream around every launch; ms[k] receives the
- * mean duration per launch of kernel class k and launches[k] the number of
- * launches per step:
+ * events on the context's stream; ms[k] receives the mean duration per
+ * launch of kernel class k and launches[k] the number of launches timed:
  *   0 cell keys, 1 radix histogram, 2 radix digit scan, 3 radix scatter,
- *   4 cell starts, 5 force + integrate.  (n_out >= 6) */
+ *   4 cell starts, 5 force + integrate (one per step), 6 candidate-list
+ *   build.
+ * Search kernels are bracketed one by one.  With candidate lists (skin > 0)
+ * the force kernel is timed over runs of up to 64 back-to-back launches
+ * (events at the ends of each run), so its mean excludes event overhead.
+ * (n_out >= 7) */
 pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out);
 
 /* Sizes: [0] nodes, [1] directed bonds, [2] padded bond slots, [3] cells,
- * [4] radix passes, [5] particles, [6] aggregates, [7] max LDS window. */
-pd_status pd_sizes(const pd_ctx *c, int64_t out[8]);
+ * [4] radix passes, [5] particles, [6] aggregates, [7] max LDS window,
+ * [8] candidate-list rebuilds so far, [9] candidate slots per node. */
+pd_status pd_sizes(const pd_ctx *c, int64_t out[10]);
 
 #ifdef __cplusplus
 }

@@ -244,8 +244,17 @@ pd_status build_windows(Ctx &c) {
     return PD_OK;
 }
 
+double list_radius(const Ctx &c) { return c.a.Rc * (1.0 + c.tune.skin_factor); }
+
+void set_list_params(Ctx &c) {
+    const double r = list_radius(c);
+    c.a.Rl2 = r * r;
+    const double m = 0.45 * c.tune.skin_factor * c.a.Rc;  // half the skin, with a margin
+    c.a.move2 = m * m;
+}
+
 pd_status build_grid(Ctx &c, const double *box) {
-    const double cs = c.tune.cell_factor * c.a.Rc;
+    const double cs = c.tune.cell_factor * list_radius(c);
     c.h_gx0.assign(c.A, 0);
     c.h_gy0.assign(c.A, 0);
     c.h_ncx.assign(c.A, 0);
@@ -288,12 +297,48 @@ pd_status build_grid(Ctx &c, const double *box) {
 }
 
 void invalidate_graph(Ctx &c) {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
         if (c.graph[k]) {
             hipGraphExecDestroy(c.graph[k]);
             c.graph[k] = nullptr;
         }
+        if (c.lgraph[k]) {
+            hipGraphExecDestroy(c.lgraph[k]);
+            c.lgraph[k] = nullptr;
+        }
+    }
     c.graph_valid = false;
+}
+
+// list-mode replay: kChunk steps from buffer parity `start`
+hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
+    for (int k = 0; k < n; ++k) {
+        set_state_ptrs(c, (start + k) & 1);
+        c.a.chunk_k = k;
+        hipError_t e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
+        if (e != hipSuccess) return e;
+    }
+    c.a.chunk_k = 0;
+    return hipSuccess;
+}
+
+pd_status ensure_list_graph(Ctx &c) {
+    if (c.lgraph[0] && c.lgraph[1]) return PD_OK;
+    for (int start = 0; start < 2; ++start) {
+        if (c.lgraph[start]) continue;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+        hipError_t e1 = enqueue_list_steps(c, start, kChunk);
+        hipError_t e2 = hipStreamEndCapture(c.stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(c, PD_E_DEVICE, "graph capture failed");
+        }
+        hipError_t e3 = hipGraphInstantiate(&c.lgraph[start], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(c, PD_E_DEVICE, "graph instantiate failed");
+    }
+    return PD_OK;
 }
 
 pd_status ensure_graph(Ctx &c) {
@@ -329,8 +374,7 @@ pd_status read_status(Ctx &c) {
 }
 
 pd_status set_device_step(Ctx &c) {
-    long long s = c.step;
-    HIPCHK(hipMemcpyAsync(c.a.step, &s, sizeof(s), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(launch_set_u64((unsigned long long *)c.a.step, (unsigned long long)c.step, c.stream));
     return PD_OK;
 }
 
@@ -340,6 +384,88 @@ pd_status eval_terms(Ctx &c) {
     HIPCHK(enqueue_search(c, c.cur, 0, 0));
     set_state_ptrs(c, c.cur);
     HIPCHK(launch_force(c.a, c.precision, M_FORCES, lds_cap(c), c.stream));
+    return PD_OK;
+}
+
+pd_status alloc_lists(Ctx &c, int maxc) {
+    if (c.a.clist) {
+        hipFree(c.a.clist);
+        c.owned.erase(std::remove(c.owned.begin(), c.owned.end(), (void *)c.a.clist), c.owned.end());
+        c.a.clist = nullptr;
+    }
+    TRY(dalloc(c, &c.a.clist, (size_t)maxc * c.N));
+    c.a.maxc = maxc;
+    invalidate_graph(c);
+    return PD_OK;
+}
+
+// candidate lists at the advanced positions of the current state: keys, radix
+// sort and cell starts there, then the per-node lists
+pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        HIPCHK(hipMemsetAsync(c.a.overflow, 0, sizeof(int), c.stream));
+        set_state_ptrs(c, c.cur);
+        if (ev) HIPCHK(hipEventRecord(ev[0], c.stream));
+        HIPCHK(launch_keys(c.a, 1, c.stream));
+        if (ev) HIPCHK(hipEventRecord(ev[1], c.stream));
+        HIPCHK(enqueue_sort(c, ev ? ev + 2 : nullptr));
+        const int b = 2 + 4 * c.a.radix_passes;
+        if (ev) HIPCHK(hipEventRecord(ev[b], c.stream));
+        HIPCHK(launch_cells(c.a, 1, 0, c.stream));
+        if (ev) HIPCHK(hipEventRecord(ev[b + 1], c.stream));
+        HIPCHK(launch_build_list(c.a, c.stream));
+        if (ev) HIPCHK(hipEventRecord(ev[b + 2], c.stream));
+        HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
+        int over = 0;
+        HIPCHK(hipMemcpyAsync(&over, c.a.overflow, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        if (over == 0) {
+            c.list_valid = true;
+            ++c.rebuilds;
+            return PD_OK;
+        }
+        int m = c.a.maxc;
+        while (m < over) m *= 2;
+        TRY(alloc_lists(c, m));
+    }
+    return fail(c, PD_E_DEVICE, "candidate lists keep overflowing");
+}
+
+// list-mode steps: replays of up to kChunk steps; a replay stops early when a
+// list goes stale (a node moved half the skin, or a bond broke), then the
+// lists are rebuilt and the remaining steps run
+pd_status step_lists(Ctx &c, int64_t n) {
+    int64_t left = n;
+    while (left > 0) {
+        if (!c.list_valid) TRY(rebuild_lists(c));
+        HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
+        HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
+                              c.stream));
+        const int chunk = (int)std::min<int64_t>(left, kChunk);
+        if (c.tune.use_graph && chunk == kChunk) {
+            TRY(ensure_list_graph(c));
+            HIPCHK(hipGraphLaunch(c.lgraph[c.cur], c.stream));
+        } else {
+            HIPCHK(enqueue_list_steps(c, c.cur, chunk));
+        }
+        unsigned long long inv = 0;
+        int st = 0;
+        HIPCHK(hipMemcpyAsync(&inv, c.a.invalid_step, sizeof(inv), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipMemcpyAsync(&st, c.a.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        int64_t done = chunk;
+        if (inv != ~0ull) {
+            const int64_t lim = (int64_t)inv - 1 - c.step;  // steps that ran
+            done = std::max<int64_t>(0, std::min<int64_t>(chunk, lim));
+        }
+        c.cur = (int)((c.cur + done) & 1);
+        c.step += done;
+        left -= done;
+        if (inv != ~0ull && (int64_t)inv <= c.step + 1) c.list_valid = false;
+        if (st) return read_status(c);
+    }
+    set_state_ptrs(c, c.cur);
+    TRY(set_device_step(c));
     return PD_OK;
 }
 
@@ -571,6 +697,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     a.rowlen = drowlen;
     a.n_slices = S;
     // ---- contact search buffers ----
+    set_list_params(c);
     TRY(build_grid(c, p->box));
     TRY(dalloc(c, &a.keys, N));
     TRY(dalloc(c, &c.keys_alt, N));
@@ -586,6 +713,14 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     TRY(dalloc(c, &a.spy, N));
     TRY(dalloc(c, &a.spart, N));
     TRY(dalloc(c, &a.step, 1));
+    TRY(dalloc(c, &a.step_base, 1));
+    TRY(dalloc(c, &a.invalid_step, 1));
+    TRY(dalloc(c, &a.overflow, 1));
+    TRY(dalloc(c, &a.clist_n, N));
+    TRY(dalloc(c, &a.ubx, N));
+    TRY(dalloc(c, &a.uby, N));
+    TRY(alloc_lists(c, 16));
+    HIPCHK(launch_invalidate(a, ~0ull, c.stream));
     TRY(dalloc(c, &a.status, 1));
     TRY(dalloc(c, &a.counters, C_N));
     HIPCHK(hipMemsetAsync(a.status, 0, sizeof(int), c.stream));
@@ -616,6 +751,10 @@ pd_status pd_step(pd_ctx *ctx, int64_t n) {
     if (n < 0) return fail(c, PD_E_INVALID, "negative step count");
     if (c.status) return (pd_status)c.status;
     if (n == 0) return PD_OK;
+    if (c.tune.skin_factor > 0.0) {
+        TRY(step_lists(c, n));
+        return read_status(c);
+    }
     int64_t left = n;
     if (c.tune.use_graph) {
         TRY(ensure_graph(c));
@@ -805,6 +944,7 @@ pd_status pd_set_state(pd_ctx *ctx, const double *ux, const double *uy, const do
     HIPCHK(hipMemsetAsync(c.a.status, 0, sizeof(int), c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     c.status = 0;
+    c.list_valid = false;
     set_state_ptrs(c, 0);
     return PD_OK;
 }
@@ -840,13 +980,17 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         return fail(c, PD_E_INVALID, "block_nodes must be 64, 128 or 256");
     if (!(t->cell_factor >= 1.0) || t->cell_factor > 64.0)
         return fail(c, PD_E_INVALID, "cell_factor must be in [1, 64]");
+    if (!(t->skin_factor >= 0.0) || t->skin_factor > 16.0)
+        return fail(c, PD_E_INVALID, "skin_factor must be in [0, 16]");
     HIPCHK(hipStreamSynchronize(c.stream));
-    const bool regrid = t->cell_factor != c.tune.cell_factor;
+    const bool regrid = t->cell_factor != c.tune.cell_factor || t->skin_factor != c.tune.skin_factor;
     const bool rewin = t->block_nodes != c.tune.block_nodes;
     c.tune = *t;
     c.tune.use_lds = t->use_lds ? 1 : 0;
     c.tune.use_graph = t->use_graph ? 1 : 0;
     c.a.use_lds = c.tune.use_lds;
+    c.list_valid = false;
+    set_list_params(c);
     if (regrid) {
         std::vector<double> box(4 * (size_t)c.A);
         HIPCHK(hipMemcpy(box.data(), c.a.box, box.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -864,7 +1008,7 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
     return PD_OK;
 }
 
-pd_status pd_sizes(const pd_ctx *ctx, int64_t out[8]) {
+pd_status pd_sizes(const pd_ctx *ctx, int64_t out[10]) {
     if (!ctx || !out) return PD_E_INVALID;
     const Ctx &c = ctx->c;
     out[0] = c.N;
@@ -875,37 +1019,28 @@ pd_status pd_sizes(const pd_ctx *ctx, int64_t out[8]) {
     out[5] = c.P;
     out[6] = c.A;
     out[7] = c.max_win;
+    out[8] = c.rebuilds;
+    out[9] = c.a.maxc;
     return PD_OK;
 }
 
 pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out) {
-    if (!ctx || !ms || n_out < 6 || n_steps < 1) return PD_E_INVALID;
+    if (!ctx || !ms || n_out < 7 || n_steps < 1) return PD_E_INVALID;
     Ctx &c = ctx->c;
     if (c.status) return (pd_status)c.status;
     const int P = c.a.radix_passes;
-    const int nev = 2 + 4 * P + 2 + 2;
-    std::vector<hipEvent_t> ev(nev);
+    const int nev = 2 + 4 * P + 3;
+    std::vector<hipEvent_t> ev(nev), fe(2);
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t s = 0; s < n_steps; ++s) {
-        const int cur = c.cur;
-        set_state_ptrs(c, cur);
-        HIPCHK(hipEventRecord(ev[0], c.stream));
-        HIPCHK(launch_keys(c.a, 1, c.stream));
-        HIPCHK(hipEventRecord(ev[1], c.stream));
-        HIPCHK(enqueue_sort(c, ev.data() + 2));
-        const int b = 2 + 4 * P;
-        HIPCHK(hipEventRecord(ev[b], c.stream));
-        HIPCHK(launch_cells(c.a, 1, 1, c.stream));
-        HIPCHK(hipEventRecord(ev[b + 1], c.stream));
-        set_state_ptrs(c, cur);
-        HIPCHK(hipEventRecord(ev[b + 2], c.stream));
-        HIPCHK(launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream));
-        HIPCHK(hipEventRecord(ev[b + 3], c.stream));
-        HIPCHK(hipEventSynchronize(ev[b + 3]));
+    for (auto &e : fe) HIPCHK(hipEventCreate(&e));
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    int32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    const bool list = c.tune.skin_factor > 0.0;
+    auto add_search = [&](bool with_list) -> pd_status {
         float t;
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
         acc[0] += t;
+        cnt[0] += 1;
         for (int p = 0; p < P; ++p) {
             hipEvent_t *e = ev.data() + 2 + 4 * p;
             HIPCHK(hipEventElapsedTime(&t, e[0], e[1]));
@@ -914,20 +1049,83 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
             acc[2] += t;
             HIPCHK(hipEventElapsedTime(&t, e[2], e[3]));
             acc[3] += t;
+            cnt[1] += 1;
+            cnt[2] += 1;
+            cnt[3] += 1;
         }
+        const int b = 2 + 4 * P;
         HIPCHK(hipEventElapsedTime(&t, ev[b], ev[b + 1]));
         acc[4] += t;
-        HIPCHK(hipEventElapsedTime(&t, ev[b + 2], ev[b + 3]));
-        acc[5] += t;
-        c.cur ^= 1;
-        c.step += 1;
+        cnt[4] += 1;
+        if (with_list) {
+            HIPCHK(hipEventElapsedTime(&t, ev[b + 1], ev[b + 2]));
+            acc[6] += t;
+            cnt[6] += 1;
+        }
+        return PD_OK;
+    };
+    int64_t s = 0;
+    while (s < n_steps) {
+        if (list) {
+            if (!c.list_valid) {
+                TRY(rebuild_lists(c, ev.data()));
+                TRY(add_search(true));
+            }
+            // a run of back-to-back step launches between two events
+            const int run = (int)std::min<int64_t>(n_steps - s, kChunk);
+            HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
+            HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
+                                  c.stream));
+            HIPCHK(hipEventRecord(fe[0], c.stream));
+            HIPCHK(enqueue_list_steps(c, c.cur, run));
+            HIPCHK(hipEventRecord(fe[1], c.stream));
+            unsigned long long inv = 0;
+            HIPCHK(hipMemcpyAsync(&inv, c.a.invalid_step, sizeof(inv), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipStreamSynchronize(c.stream));
+            int64_t done = run;
+            if (inv != ~0ull) done = std::max<int64_t>(0, std::min<int64_t>(run, (int64_t)inv - 1 - c.step));
+            if (done == run) {  // only complete runs time the kernel
+                float t;
+                HIPCHK(hipEventElapsedTime(&t, fe[0], fe[1]));
+                acc[5] += t;
+                cnt[5] += run;
+            }
+            c.cur = (int)((c.cur + done) & 1);
+            c.step += done;
+            s += std::max<int64_t>(done, 1);
+            if (inv != ~0ull && (int64_t)inv <= c.step + 1) c.list_valid = false;
+        } else {
+            set_state_ptrs(c, c.cur);
+            HIPCHK(hipEventRecord(ev[0], c.stream));
+            HIPCHK(launch_keys(c.a, 1, c.stream));
+            HIPCHK(hipEventRecord(ev[1], c.stream));
+            HIPCHK(enqueue_sort(c, ev.data() + 2));
+            const int b = 2 + 4 * P;
+            HIPCHK(hipEventRecord(ev[b], c.stream));
+            HIPCHK(launch_cells(c.a, 1, 1, c.stream));
+            HIPCHK(hipEventRecord(ev[b + 1], c.stream));
+            set_state_ptrs(c, c.cur);
+            HIPCHK(hipEventRecord(fe[0], c.stream));
+            HIPCHK(launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, false));
+            HIPCHK(hipEventRecord(fe[1], c.stream));
+            HIPCHK(hipEventSynchronize(fe[1]));
+            TRY(add_search(false));
+            float t;
+            HIPCHK(hipEventElapsedTime(&t, fe[0], fe[1]));
+            acc[5] += t;
+            cnt[5] += 1;
+            c.cur ^= 1;
+            c.step += 1;
+            ++s;
+        }
     }
     set_state_ptrs(c, c.cur);
+    if (list) TRY(set_device_step(c));
     for (auto &e : ev) hipEventDestroy(e);
-    const int per[6] = {1, P, P, P, 1, 1};
-    for (int k = 0; k < 6; ++k) {
-        ms[k] = acc[k] / (double)(n_steps * per[k]);
-        if (launches) launches[k] = per[k];
+    for (auto &e : fe) hipEventDestroy(e);
+    for (int k = 0; k < 7; ++k) {
+        ms[k] = cnt[k] ? acc[k] / (double)cnt[k] : 0.0;
+        if (launches) launches[k] = cnt[k];
     }
     return read_status(c);
 }
@@ -957,16 +1155,17 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const int blocks[3] = {64, 128, 256};
-    const double cells[3] = {1.0, 1.5, 2.0};
+    const int blocks[3] = {256, 128, 64};
+    const double skins[4] = {0.0, 0.5, 1.0, 2.0};
     pd_status result = PD_OK;
     for (int bi = 0; bi < 3 && result == PD_OK; ++bi)
-        for (int ci = 0; ci < 3 && result == PD_OK; ++ci)
+        for (int ci = 0; ci < 4 && result == PD_OK; ++ci)
             for (int li = 0; li < 2 && result == PD_OK; ++li) {
                 pd_tuning t = base;
                 t.block_nodes = blocks[bi];
-                t.cell_factor = cells[ci];
-                t.use_lds = li;
+                t.cell_factor = 1.0;
+                t.skin_factor = skins[ci];
+                t.use_lds = 1 - li;
                 if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
                 // restore and warm up
                 for (int k = 0; k < 6; ++k)

@@ -12,13 +12,14 @@ namespace pd {
 
 constexpr uint32_t kBroken = 0x80000000u;  // broken bit of a bond slot
 constexpr uint32_t kIndexMask = 0x7fffffffu;
-constexpr int kSlice = 64;                  // SELL slice height = one wavefront
+constexpr int kSlice = 16;                  // SELL slice height: the nodes of one wavefront (4 lanes each)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMaxLdsNodes = 1024;          // staged window limit (nodes)
+constexpr int kChunk = 64;                  // list-mode steps per graph replay
 
 // status bits raised by kernels
 constexpr int kStEscaped = 1;
@@ -79,11 +80,26 @@ struct DevArgs {
     int counting;
     // per-term outputs (M_FORCES): [5][2][N]
     double *terms;
+    // contact candidate lists (pairs within the list radius at build time,
+    // intact bonds excluded), slot k of node i at clist[k * N + i]
+    uint32_t *clist;
+    int *clist_n;
+    float *ubx, *uby;          // displacement at list build
+    int maxc;                  // slots per node
+    double Rl2;                // list radius squared, (R_c + skin)^2
+    double move2;              // |u - u_build|^2 beyond which the list is stale
+    unsigned long long *invalid_step;  // first step whose list is stale
+    long long *step_base;      // steps completed before the current replay
+    int chunk_k;               // index of this launch within the replay
+    int *overflow;             // a node had more candidates than slots
 };
 
 struct Ctx {
     DevArgs a{};
-    pd_tuning tune{256, 1.0, 1, 1};
+    pd_tuning tune{256, 1.0, 1, 1, 1.0};
+    bool list_valid = false;     // candidate lists match the current state
+    int64_t rebuilds = 0;
+    hipGraphExec_t lgraph[2] = {nullptr, nullptr};  // kChunk list-mode steps per parity
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int precision = 0;
@@ -143,7 +159,11 @@ hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout,
                             hipEvent_t *ev);
 hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t s);
 int force_lds_cap(int max_win);
-hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s);
+hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
+                        bool list = false);
+hipError_t launch_build_list(const DevArgs &a, hipStream_t s);
+hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s);
+hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 hipError_t launch_sum_terms(const DevArgs &a, uint32_t mask, double *fx, double *fy, hipStream_t s);
 hipError_t launch_damage(const DevArgs &a, double *phi, unsigned long long *nb, hipStream_t s);
 hipError_t launch_contacts_count(const DevArgs &a, int *cnt, hipStream_t s);

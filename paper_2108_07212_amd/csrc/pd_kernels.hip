@@ -52,6 +52,15 @@ __device__ __forceinline__ void count(const DevArgs &a, int k, unsigned long lon
     if (a.counting && v) atomicAdd(&a.counters[k], v);
 }
 
+// 1/x to full FP64 precision: hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // inclusive scan across a 64-lane wavefront
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -135,8 +144,8 @@ __global__ void k_bonds_fill_w(BondArgs b, uint32_t *col, const uint32_t *slice_
     const double xi = b.x[i], yi = b.y[i];
     const double rx = b.x[b.poff[p]], ry = b.y[b.poff[p]];  // particle frame origin
     const int s0 = b.seg_off[p], s1 = b.seg_off[p + 1];
-    const uint32_t base = slice_ptr[i >> 6] + (uint32_t)(i & 63);
-    const int W = (int)((slice_ptr[(i >> 6) + 1] - slice_ptr[i >> 6]) / kSlice);
+    const uint32_t base = slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
+    const int W = (int)((slice_ptr[i / kSlice + 1] - slice_ptr[i / kSlice]) / kSlice);
     int n = 0;
     for (int j = b.poff[p]; j < b.poff[p + 1] && n < W; ++j) {
         if (j == i) continue;
@@ -156,7 +165,7 @@ __global__ void k_windows(const uint32_t *col, const uint32_t *slice_ptr, const 
                           int block_nodes, int *win_lo, int *win_hi) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const uint32_t base = slice_ptr[i >> 6] + (uint32_t)(i & 63);
+    const uint32_t base = slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
     int lo = i, hi = i;
     for (int k = 0; k < rowlen[i]; ++k) {
         const int j = (int)(col[base + (uint32_t)k * kSlice] & kIndexMask);
@@ -359,22 +368,27 @@ __device__ __forceinline__ void wall_region(const DevArgs &a, double Kn, double 
     count(a, C_WALL);
 }
 
-__device__ void wall_forces(const DevArgs &a, int ag, double px, double py, double vxi,
+// Walls of node i (Sec. 4.5): lane `part` of the node's quad takes wall
+// `part` (left, right, floor, top) and the corner `part` of (left, floor),
+// (floor, right), (right, top), (top, left), whose region is subtracted
+// (inclusion-exclusion, eq. wall-total).
+__device__ void wall_forces(const DevArgs &a, int ag, int part, double px, double py, double vxi,
                             double vyi, double mi, double Vi, double Kn, double t, double &fx,
                             double &fy, int &st) {
     const double Rc = a.Rc;
     const double vtop = a.vtop[ag];
     const double d[4] = {px - a.box[4 * ag], a.box[4 * ag + 1] - px, py - a.box[4 * ag + 2],
                          (a.box[4 * ag + 3] - vtop * t) - py};
+    if (!(d[part] > -Rc)) st |= kStEscaped;
     // quick exit: far from every wall
     if (d[0] >= Rc && d[1] >= Rc && d[2] >= Rc && d[3] >= Rc) return;
     const double nx[4] = {-1.0, 1.0, 0.0, 0.0}, ny[4] = {0.0, 0.0, -1.0, 1.0};
     const double wv[4] = {0.0, 0.0, 0.0, -vtop};
-    for (int w = 0; w < 4; ++w) {
-        if (!(d[w] > -Rc)) st |= kStEscaped;
+    {
+        const int w = part;
         if (d[w] < Rc && d[w] > -Rc) {
             // circular segment beyond the wall: area (Rc^2/2)(phi - sin phi),
-            // phi = 4 asin(sqrt((Rc - d)/(2 Rc))); centroid (2/3)(Rc^2-d^2)^1.5/A
+            // phi = 4 asin(sqrt((Rc - d)/(2 Rc)))
             const double phi = 4.0 * asin(sqrt((Rc - d[w]) / (2.0 * Rc)));
             const double A = 0.5 * Rc * Rc * phi_minus_sin(phi);
             if (A > 0.0) {
@@ -384,38 +398,35 @@ __device__ void wall_forces(const DevArgs &a, int ag, double px, double py, doub
             }
         }
     }
-    // corners: (left, floor), (floor, right), (right, top), (top, left)
     const int pa[4] = {0, 2, 1, 3}, pb[4] = {2, 1, 3, 0};
-    for (int k = 0; k < 4; ++k) {
-        const int wa = pa[k], wb = pb[k];
-        const double da = d[wa], db = d[wb];
-        if (!(da > -Rc && db > -Rc && da * da + db * db < Rc * Rc)) continue;
-        // triangle (da,db)-(x2,db)-(da,y1) plus the circular segment on its hypotenuse
-        const double x2 = sqrt((Rc - db) * (Rc + db)), y1 = sqrt((Rc - da) * (Rc + da));
-        const double D = (Rc - da) * (Rc + da) - db * db;
-        const double wx = da > 0.0 ? D / (x2 + da) : x2 - da;
-        const double wy = db > 0.0 ? D / (y1 + db) : y1 - db;
-        const double At = 0.5 * wx * wy;
-        const double chord = sqrt(wx * wx + wy * wy);
-        const double half = asin(chord / (2.0 * Rc));
-        const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
-        const double sh = sin(half);
-        const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
-        const double A = At + As;
-        if (!(A > 0.0)) continue;
-        const double Ix = At * (da + (da + wx) + da) / 3.0 + ms * (wy / chord);
-        const double Iy = At * (db + db + (db + wy)) / 3.0 + ms * (wx / chord);
-        const double cx = (Ix * nx[wa] + Iy * nx[wb]) / A, cy = (Ix * ny[wa] + Iy * ny[wb]) / A;
-        const double dist = sqrt(cx * cx + cy * cy);
-        const double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
-        const double Fr = Kn * (Rc - dist) * Vi * A;
-        wall_region(a, Kn, A, Fr, cx / dist, cy / dist, wvy, vxi, vyi, mi, Vi, -1.0, fx, fy);
-    }
+    const int wa = pa[part], wb = pb[part];
+    const double da = d[wa], db = d[wb];
+    if (!(da > -Rc && db > -Rc && da * da + db * db < Rc * Rc)) return;
+    // triangle (da,db)-(x2,db)-(da,y1) plus the circular segment on its hypotenuse
+    const double x2 = sqrt((Rc - db) * (Rc + db)), y1 = sqrt((Rc - da) * (Rc + da));
+    const double D = (Rc - da) * (Rc + da) - db * db;
+    const double wx = da > 0.0 ? D / (x2 + da) : x2 - da;
+    const double wy = db > 0.0 ? D / (y1 + db) : y1 - db;
+    const double At = 0.5 * wx * wy;
+    const double chord = sqrt(wx * wx + wy * wy);
+    const double half = asin(chord / (2.0 * Rc));
+    const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
+    const double sh = sin(half);
+    const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
+    const double A = At + As;
+    if (!(A > 0.0)) return;
+    const double Ix = At * (da + (da + wx) + da) / 3.0 + ms * (wy / chord);
+    const double Iy = At * (db + db + (db + wy)) / 3.0 + ms * (wx / chord);
+    const double cx = (Ix * nx[wa] + Iy * nx[wb]) / A, cy = (Ix * ny[wa] + Iy * ny[wb]) / A;
+    const double dist = sqrt(cx * cx + cy * cy);
+    const double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
+    const double Fr = Kn * (Rc - dist) * Vi * A;
+    wall_region(a, Kn, A, Fr, cx / dist, cy / dist, wvy, vxi, vyi, mi, Vi, -1.0, fx, fy);
 }
 
 // bond (i, j) is in the reference set and intact (scan of i's own row)
 __device__ __forceinline__ bool bonded_intact(const DevArgs &a, int i, int j) {
-    const uint32_t base = a.slice_ptr[i >> 6] + (uint32_t)(i & 63);
+    const uint32_t base = a.slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
     const int n = a.rowlen[i];
     for (int k = 0; k < n; ++k) {
         const uint32_t e = a.col[base + (uint32_t)k * kSlice];
@@ -426,16 +437,129 @@ __device__ __forceinline__ bool bonded_intact(const DevArgs &a, int i, int j) {
     return false;
 }
 
+
+// Contact of node i with node j at separation (ddx, ddy) = p_j - p_i,
+// r2 = |p_j - p_i|^2 < R_c^2, r2 > 0: repulsion (Sec. 4.1 for other
+// particles, Sec. 4.4 for unbonded nodes of the same particle), damping and
+// friction.  Accumulates into the self or the inter-particle term.
+template <typename R>
+__device__ __forceinline__ void contact_pair(const DevArgs &a, const MatConst &mc, int i, int j,
+                                             bool same, int pj, double xi, double yi, double ddx,
+                                             double ddy, double r2, double vxi, double vyi,
+                                             double vxj, double vyj, double Vi, double mi,
+                                             R &fsx, R &fsy, R &fnx, R &fny) {
+    const double d = sqrt(r2);
+    const double ex = ddx / d, ey = ddy / d;
+    const double Vj = a.vol[j];
+    double coef, Kd;
+    if (!same) {
+        const double Ka = mc.Kn, Kb = a.mat[a.pmat[pj]].Kn;
+        const double Kn = (2.0 * Ka * Kb) / (Ka + Kb);  // harmonic mean (Sec. 4.1)
+        coef = -Kn * (a.Rc - d);
+        Kd = Kn;
+        count(a, C_INTER);
+    } else {
+        const double X = a.x[j] - xi, Y = a.y[j] - yi;
+        const double L = sqrt(X * X + Y * Y);  // reference distance |xi|
+        if (L < a.Rc)
+            coef = (d < L) ? mc.cw * (d - L) / L : 0.0;
+        else
+            coef = mc.cw * (d - a.Rc) / a.Rc;
+        Kd = mc.Kd_self;
+        count(a, C_SELF);
+    }
+    const double Frx = coef * Vi * Vj * ex, Fry = coef * Vi * Vj * ey;
+    const double Fr = fabs(coef) * Vi * Vj;
+    double dfx, dfy;
+    damp_fric(a, mi, Vi, Vj, Kd, ex, ey, vxi - vxj, vyi - vyj, Fr, dfx, dfy);
+    if (same) {
+        fsx += (R)(Frx + dfx);
+        fsy += (R)(Fry + dfy);
+    } else {
+        fnx += (R)(Frx + dfx);
+        fny += (R)(Fry + dfy);
+    }
+}
+
+// Contact candidate list of every node at its advanced position: nodes of
+// the 3 x 3 neighbouring cells (cell side >= list radius) closer than the
+// list radius, except intact bonds, in cell order.  Also records the
+// displacement at which the list was built.
+__global__ void k_build_list(DevArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double pxi, pyi, uxi, uyi;
+    advanced_pos(a, i, true, pxi, pyi, uxi, uyi);
+    const int pi = a.part[i];
+    const int ag = a.pagg[pi];
+    int cx, cy;
+    cell_of(a, ag, pxi, pyi, cx, cy);
+    const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
+    const uint32_t c0 = a.agg_cell0[ag];
+    int n = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = cy + dy;
+        if (yy < 0 || yy >= ncy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = cx + dx;
+            if (xx < 0 || xx >= ncx) continue;
+            const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
+            const uint32_t s = a.cell_start[c];
+            if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
+            for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
+                const int j = a.perm[k];
+                if (j == i) continue;
+                const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
+                if (!(ddx * ddx + ddy * ddy < a.Rl2)) continue;
+                if (a.spart[k] == pi && bonded_intact(a, i, j)) continue;
+                if (n < a.maxc) a.clist[(size_t)n * a.N + i] = (uint32_t)j;
+                ++n;
+            }
+        }
+    }
+    if (n > a.maxc) {
+        atomicMax(a.overflow, n);
+        n = a.maxc;
+    }
+    a.clist_n[i] = n;
+    a.ubx[i] = (float)uxi;
+    a.uby[i] = (float)uyi;
+}
+
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
 // ---------------------------------------------------------------------------
 // the force kernel
 // ---------------------------------------------------------------------------
-template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
+// sum over the four lanes of a node's quad in a fixed order, (l0 + l1) + (l2 + l3)
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// Four lanes per node: lane `sub` of node i takes the bond slots k = sub,
+// sub + 4, ... of the node's SELL-16 row, every fourth contact candidate, one
+// wall and one corner; the quad then combines its partial sums in a fixed
+// order and lane 0 integrates.  LDS holds the block's window of bond partners
+// (reference and current positions, volumes).
+template <typename R, int MODE, bool LIST>
+__global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     extern __shared__ double lds[];
+    // list mode: this launch computes step sprev + 1 of a replay that started
+    // after step *step_base; once a list has gone stale, that step and every
+    // later one of the replay are no-ops (the check is uniform over the grid)
+    long long sprev = 0;
+    if (LIST) {
+        sprev = *a.step_base + a.chunk_k;
+        if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    }
     double *Sx = lds, *Sy = lds + lds_cap, *Spx = lds + 2 * lds_cap, *Spy = lds + 3 * lds_cap,
            *Sv = lds + 4 * lds_cap;
     constexpr bool adv = (MODE == M_STEP);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x & 3;
+    const int i = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
     int lo = 0;
     bool staged = false;
     if (a.use_lds) {
@@ -456,7 +580,7 @@ __global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
         }
         __syncthreads();
     }
-    if (i >= a.N) return;
+    if (i >= a.N) return;  // whole quads leave together
 
     const double xi = a.x[i], yi = a.y[i];
     double pxi, pyi, uxi, uyi;
@@ -467,91 +591,85 @@ __global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
     const int mt = a.pmat[pi];
     const int ag = a.pagg[pi];
     const MatConst mc = a.mat[mt];
-    const double t = (double)(*a.step) * a.dt;  // wall time of this evaluation
+    // wall time of this evaluation
+    const double t = LIST ? (double)(sprev + 1) * a.dt : (double)(*a.step) * a.dt;
     int st = 0;
 
-    // ---- contact: nodes of the 3 x 3 neighbouring cells -------------------
+    // ---- contact -----------------------------------------------------------
     R fsx = 0, fsy = 0, fnx = 0, fny = 0;
-    {
+    if (LIST) {
+        // candidates listed at the last rebuild (intact bonds excluded)
+        const int nc = a.clist_n[i];
+        for (int q = sub; q < nc; q += 4) {
+            const int j = (int)a.clist[(size_t)q * a.N + i];
+            double pxj, pyj, ux, uy;
+            advanced_pos(a, j, adv, pxj, pyj, ux, uy);
+            const double ddx = pxj - pxi, ddy = pyj - pyi;
+            const double r2 = ddx * ddx + ddy * ddy;
+            if (!(r2 < a.Rc2)) continue;
+            if (r2 == 0.0) {
+                count(a, C_COINC);
+                continue;
+            }
+            const int pj = a.part[j];
+            contact_pair<R>(a, mc, i, j, pj == pi, pj, xi, yi, ddx, ddy, r2, vxi, vyi, a.vx[j],
+                            a.vy[j], Vi, mi, fsx, fsy, fnx, fny);
+        }
+    } else {
+        // nodes of the 3 x 3 neighbouring cells, cells sub, sub + 4, sub + 8
         int cx, cy;
         cell_of(a, ag, pxi, pyi, cx, cy);
         const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
         const uint32_t c0 = a.agg_cell0[ag];
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = cy + dy;
-            if (yy < 0 || yy >= ncy) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = cx + dx;
-                if (xx < 0 || xx >= ncx) continue;
-                const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
-                const uint32_t s = a.cell_start[c];
-                if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
-                for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
-                    const int j = a.perm[k];
-                    if (j == i) continue;
-                    const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
-                    const double r2 = ddx * ddx + ddy * ddy;
-                    if (!(r2 < a.Rc2)) continue;
-                    if (r2 == 0.0) {
-                        count(a, C_COINC);
-                        continue;
-                    }
-                    const int pj = a.spart[k];
-                    const bool same = (pj == pi);
-                    if (same && bonded_intact(a, i, j)) continue;
-                    const double d = sqrt(r2);
-                    const double ex = ddx / d, ey = ddy / d;
-                    const double Vj = a.vol[j];
-                    double coef, Kd;
-                    if (!same) {
-                        const double Ka = mc.Kn, Kb = a.mat[a.pmat[pj]].Kn;
-                        const double Kn = (2.0 * Ka * Kb) / (Ka + Kb);
-                        coef = -Kn * (a.Rc - d);
-                        Kd = Kn;
-                        count(a, C_INTER);
-                    } else {
-                        const double X = a.x[j] - xi, Y = a.y[j] - yi;
-                        const double L = sqrt(X * X + Y * Y);
-                        if (L < a.Rc)
-                            coef = (d < L) ? mc.cw * (d - L) / L : 0.0;
-                        else
-                            coef = mc.cw * (d - a.Rc) / a.Rc;
-                        Kd = mc.Kd_self;
-                        count(a, C_SELF);
-                    }
-                    const double Frx = coef * Vi * Vj * ex, Fry = coef * Vi * Vj * ey;
-                    const double Fr = fabs(coef) * Vi * Vj;
-                    double dfx, dfy;
-                    damp_fric(a, mi, Vi, Vj, Kd, ex, ey, vxi - a.vx[j], vyi - a.vy[j], Fr, dfx, dfy);
-                    if (same) {
-                        fsx += (R)(Frx + dfx);
-                        fsy += (R)(Fry + dfy);
-                    } else {
-                        fnx += (R)(Frx + dfx);
-                        fny += (R)(Fry + dfy);
-                    }
+        for (int c9 = sub; c9 < 9; c9 += 4) {
+            const int yy = cy + c9 / 3 - 1, xx = cx + c9 % 3 - 1;
+            if (yy < 0 || yy >= ncy || xx < 0 || xx >= ncx) continue;
+            const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
+            const uint32_t s = a.cell_start[c];
+            if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
+            for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
+                const int j = a.perm[k];
+                if (j == i) continue;
+                const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
+                const double r2 = ddx * ddx + ddy * ddy;
+                if (!(r2 < a.Rc2)) continue;
+                if (r2 == 0.0) {
+                    count(a, C_COINC);
+                    continue;
                 }
+                const int pj = a.spart[k];
+                const bool same = (pj == pi);
+                if (same && bonded_intact(a, i, j)) continue;  // the bond acts
+                contact_pair<R>(a, mc, i, j, same, pj, xi, yi, ddx, ddy, r2, vxi, vyi, a.vx[j],
+                                a.vy[j], Vi, mi, fsx, fsy, fnx, fny);
             }
         }
     }
 
     // ---- walls ---------------------------------------------------------------
     double fwx = 0.0, fwy = 0.0;
-    wall_forces(a, ag, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+    wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
 
-    // ---- peridynamic bonds (SELL-64 row, columns ascending) ------------------
+    // ---- peridynamic bonds (SELL-16 row, columns ascending) ------------------
+    // Every slot runs the same branch-free arithmetic (padding and broken
+    // slots are masked), so consecutive slots form independent chains the
+    // compiler can interleave.  A bond whose approximate stretch comes within
+    // 1e-10 (FP64) or 2e-6 (FP32) of s0 is re-decided with the exact FP64
+    // stretch (l - l0) / l0 of correctly rounded lengths, so break decisions
+    // are those of plain FP64 arithmetic.
     R fpx = 0, fpy = 0;
+    int nbrk = 0;
     {
-        const uint32_t sl = (uint32_t)i >> 6;
-        const uint32_t base = a.slice_ptr[sl] + (uint32_t)(i & 63);
+        const uint32_t sl = (uint32_t)i / kSlice;
+        const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
         const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
-        const double cw = mc.cw, s0 = mc.s0, eps = mc.eps;
+        const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
         const bool conic = mc.conic != 0;
-        unsigned long long nbrk = 0;
-        for (int k = 0; k < W; ++k) {
+#pragma unroll 2
+        for (int k = sub; k < W; k += 4) {
             const uint32_t e = a.col[base + (uint32_t)k * kSlice];
-            if (e & kBroken) continue;
-            const int j = (int)e;
+            const bool valid = (e & kBroken) == 0;
+            const int j = valid ? (int)e : i;
             double xj, yj, pxj, pyj, Vj;
             if (staged) {
                 const int q = j - lo;
@@ -567,57 +685,62 @@ __global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
                 yj = a.y[j];
                 Vj = a.vol[j];
             }
-            bool brk;
-            R f, DXr, DYr, lr;
+            const double X = xj - xi, Y = yj - yi;
+            const double DX = pxj - pxi, DY = pyj - pyi;
+            bool cand;
+            R g, DXr, DYr;
             if constexpr (sizeof(R) == 8) {
-                const double X = xj - xi, Y = yj - yi;
-                const double l0 = sqrt(X * X + Y * Y);
-                const double DX = pxj - pxi, DY = pyj - pyi;
-                const double l = sqrt(DX * DX + DY * DY);
-                const double s = (l - l0) / l0;
-                brk = fabs(s) > s0;
-                const double w = conic ? 1.0 - l0 / eps : 1.0;
-                f = cw * w * s * Vi * Vj;
+                const double l0 = sqrt(valid ? X * X + Y * Y : 1.0);
+                const double l = sqrt(valid ? DX * DX + DY * DY : 1.0);
+                const double s = (l - l0) * rcp_nr(l0);
+                cand = valid && fabs(s) > s0 * (1.0 - 1e-10);
+                const double w = conic ? 1.0 - l0 * inv_eps : 1.0;
+                const double f = valid ? cw * w * s * Vi * Vj : 0.0;
+                g = f * rcp_nr(l);
                 DXr = DX;
                 DYr = DY;
-                lr = l;
             } else {
-                const float X = (float)(xj - xi), Y = (float)(yj - yi);
-                const float l0 = __builtin_amdgcn_sqrtf(X * X + Y * Y);
-                const float DX = (float)(pxj - pxi), DY = (float)(pyj - pyi);
-                const float l = __builtin_amdgcn_sqrtf(DX * DX + DY * DY);
-                const float s = (l - l0) * __builtin_amdgcn_rcpf(l0);
-                brk = false;
-                // near or beyond s0 the break decision is taken in FP64
-                if (fabsf(s) > (float)(s0 - 2e-6)) {
-                    const double Xd = xj - xi, Yd = yj - yi;
-                    const double l0d = sqrt(Xd * Xd + Yd * Yd);
-                    const double DXd = pxj - pxi, DYd = pyj - pyi;
-                    const double ld = sqrt(DXd * DXd + DYd * DYd);
-                    brk = fabs((ld - l0d) / l0d) > s0;
+                const float Xf = (float)X, Yf = (float)Y, DXf = (float)DX, DYf = (float)DY;
+                const float l0s = valid ? Xf * Xf + Yf * Yf : 1.0f;
+                const float ls = valid ? DXf * DXf + DYf * DYf : 1.0f;
+                const float r0 = __builtin_amdgcn_rsqf(l0s), rl = __builtin_amdgcn_rsqf(ls);
+                const float l0 = l0s * r0, l = ls * rl;
+                const float s = (l - l0) * r0;
+                cand = valid && fabsf(s) > (float)(s0 - 2e-6);
+                const float w = conic ? 1.0f - l0 * (float)inv_eps : 1.0f;
+                const float f = valid ? (float)cw * w * s * (float)Vi * (float)Vj : 0.0f;
+                g = f * rl;
+                DXr = DXf;
+                DYr = DYf;
+            }
+            if (cand) {  // rare: the exact decision (Sec. 3.1, broken for good)
+                const double l0x = sqrt(X * X + Y * Y), lx = sqrt(DX * DX + DY * DY);
+                if (fabs((lx - l0x) / l0x) > s0) {
+                    if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
+                    ++nbrk;
+                    g = 0;
                 }
-                const float w = conic ? 1.0f - l0 / (float)eps : 1.0f;
-                f = (float)cw * w * s * (float)Vi * (float)Vj;
-                DXr = DX;
-                DYr = DY;
-                lr = l;
             }
-            if (brk) {  // Sec. 3.1: broken for good
-                if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
-                ++nbrk;
-                continue;
-            }
-            if constexpr (sizeof(R) == 8) {
-                fpx += f * DXr / lr;
-                fpy += f * DYr / lr;
-            } else {
-                const R g = f * __builtin_amdgcn_rcpf(lr);
-                fpx += g * DXr;
-                fpy += g * DYr;
-            }
+            fpx += g * DXr;
+            fpy += g * DYr;
         }
-        if (MODE != M_FORCES) count(a, C_BROKEN, nbrk);
     }
+
+    // ---- combine the quad ------------------------------------------------------
+    fpx = quad_sum(fpx);
+    fpy = quad_sum(fpy);
+    fsx = quad_sum(fsx);
+    fsy = quad_sum(fsy);
+    fnx = quad_sum(fnx);
+    fny = quad_sum(fny);
+    fwx = quad_sum(fwx);
+    fwy = quad_sum(fwy);
+    nbrk = quad_sum(nbrk);
+    st |= __shfl_xor(st, 1, 64);
+    st |= __shfl_xor(st, 2, 64);
+    if (sub != 0) return;
+    if (MODE != M_FORCES) count(a, C_BROKEN, (unsigned long long)nbrk);
+    if (LIST && nbrk) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
 
     // ---- outputs ---------------------------------------------------------------
     const double Fx = (((double)fpx + (double)fsx) + (double)fnx) + fwx;
@@ -648,6 +771,14 @@ __global__ __launch_bounds__(256) void k_force(DevArgs a, int lds_cap) {
             a.uy_o[i] = uyi;
             if (!(isfinite(uxi) && isfinite(uyi) && isfinite(vxn) && isfinite(vyn)))
                 st |= kStNonfinite;
+            if (LIST) {
+                // the next step's displacement against the one the list was built at
+                const double unx = (uxi + a.dt * vxn) + a.hdt2 * axn;
+                const double uny = (uyi + a.dt * vyn) + a.hdt2 * ayn;
+                const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
+                if (!(ex * ex + ey * ey <= a.move2))
+                    atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+            }
         }
     }
     if (st) atomicOr(a.status, st);
@@ -673,7 +804,7 @@ __global__ void k_damage(DevArgs a, double *phi, unsigned long long *nb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int n = 0, nref = 0;
     if (i < a.N) {
-        const uint32_t base = a.slice_ptr[i >> 6] + (uint32_t)(i & 63);
+        const uint32_t base = a.slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
         nref = a.rowlen[i];
         for (int k = 0; k < nref; ++k) n += (a.col[base + (uint32_t)k * kSlice] & kBroken) ? 1 : 0;
         if (phi) phi[i] = nref > 0 ? (double)n / (double)nref : 0.0;
@@ -787,26 +918,47 @@ hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t
 
 int force_lds_cap(int max_win) { return max_win > kMaxLdsNodes ? 0 : max_win; }
 
-hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s) {
-    if (a.N == 0) return hipSuccess;
-    const int B = a.block_nodes;
-    const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
-    const dim3 g(grid_for(a.N, B)), b(B);
-    if (precision == PD_PREC_FP64) {
-        if (mode == M_STEP)
-            hipLaunchKernelGGL((k_force<double, M_STEP>), g, b, shm, s, a, lds_cap);
-        else if (mode == M_FORCES)
-            hipLaunchKernelGGL((k_force<double, M_FORCES>), g, b, shm, s, a, lds_cap);
+template <typename R>
+static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b, size_t shm,
+                           hipStream_t s, int lds_cap) {
+    if (mode == M_STEP) {
+        if (list)
+            hipLaunchKernelGGL((k_force<R, M_STEP, true>), g, b, shm, s, a, lds_cap);
         else
-            hipLaunchKernelGGL((k_force<double, M_PROLOGUE>), g, b, shm, s, a, lds_cap);
+            hipLaunchKernelGGL((k_force<R, M_STEP, false>), g, b, shm, s, a, lds_cap);
+    } else if (mode == M_FORCES) {
+        hipLaunchKernelGGL((k_force<R, M_FORCES, false>), g, b, shm, s, a, lds_cap);
     } else {
-        if (mode == M_STEP)
-            hipLaunchKernelGGL((k_force<float, M_STEP>), g, b, shm, s, a, lds_cap);
-        else if (mode == M_FORCES)
-            hipLaunchKernelGGL((k_force<float, M_FORCES>), g, b, shm, s, a, lds_cap);
-        else
-            hipLaunchKernelGGL((k_force<float, M_PROLOGUE>), g, b, shm, s, a, lds_cap);
+        hipLaunchKernelGGL((k_force<R, M_PROLOGUE, false>), g, b, shm, s, a, lds_cap);
     }
+}
+
+hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
+                        bool list) {
+    if (a.N == 0) return hipSuccess;
+    const int B = a.block_nodes;  // nodes per workgroup, four lanes each
+    const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
+    const dim3 g(grid_for(a.N, B)), b(4 * B);
+    if (precision == PD_PREC_FP64)
+        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap);
+    else
+        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_list(const DevArgs &a, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_list, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, a.invalid_step, v);
     return hipGetLastError();
 }
 

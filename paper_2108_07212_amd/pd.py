@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pd.h")
 
 PD_OK, PD_E_INVALID, PD_E_NOMEM, PD_E_DEVICE, PD_E_NONFINITE, PD_E_ESCAPED, PD_E_STATE = range(7)
 TERM_PD, TERM_SELF, TERM_NBR, TERM_WALL, TERM_BODY, TERM_ALL = 1, 2, 4, 8, 16, 31
-KERNEL_CLASSES = ("keys", "radix_hist", "radix_digit_scan", "radix_scatter", "cells", "force")
+KERNEL_CLASSES = ("keys", "radix_hist", "radix_digit_scan", "radix_scatter", "cells", "force",
+                  "build_list")
 
 
 class PDError(RuntimeError):
@@ -54,11 +55,11 @@ class Problem(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block_nodes", C.c_int32), ("cell_factor", C.c_double),
-                ("use_lds", C.c_int32), ("use_graph", C.c_int32)]
+                ("use_lds", C.c_int32), ("use_graph", C.c_int32), ("skin_factor", C.c_double)]
 
     def as_dict(self):
         return dict(block_nodes=self.block_nodes, cell_factor=self.cell_factor,
-                    use_lds=self.use_lds, use_graph=self.use_graph)
+                    use_lds=self.use_lds, use_graph=self.use_graph, skin_factor=self.skin_factor)
 
 
 _lib = None
@@ -259,6 +260,7 @@ class PD:
         return t.as_dict()
 
     def time_kernels(self, n_steps: int = 10):
+        """{kernel class: (mean ms per launch, launches over the n_steps steps)}"""
         ms = np.zeros(8)
         la = np.zeros(8, dtype=np.int32)
         self._chk(self.lib.pd_time_kernels(self.h, int(n_steps), _p(ms, C.c_double),
@@ -266,8 +268,8 @@ class PD:
         return {k: (float(ms[i]), int(la[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def sizes(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         self._chk(self.lib.pd_sizes(self.h, _p(out, C.c_int64)))
         keys = ("nodes", "bonds", "slots", "cells", "radix_passes", "particles", "aggregates",
-                "max_window")
+                "max_window", "list_rebuilds", "list_slots")
         return {k: int(v) for k, v in zip(keys, out)}

@@ -237,24 +237,69 @@ def test_damage_after_breaking(pdmod):
     assert nbg == nbo > 0 and np.array_equal(pg, po)
 
 
-def test_determinism_graph_and_tuning(pdmod):
+@pytest.mark.parametrize("skin", [1.0, 0.0])
+def test_determinism_graph_and_tuning(pdmod, skin):
     """Bitwise equal results: two runs; graph vs direct launches; every block
-    size and LDS staging choice."""
-    _say("case: determinism")
+    size and LDS staging choice (for a fixed skin)."""
+    _say(f"case: determinism skin={skin}")
     prob = _herd(_bed(10, 21, g=(0.0, -5000.0)), 0.45, seed=21, dv=0.5)
     ref = None
     for bn in (256, 128, 64):
         for lds in (1, 0):
             for graph in (1, 0):
                 g = pdmod.PD(prob)
-                g.set_tuning(block_nodes=bn, use_lds=lds, use_graph=graph)
-                g.step(37)
+                g.set_tuning(block_nodes=bn, use_lds=lds, use_graph=graph, skin_factor=skin)
+                g.step(137)
                 s = g.get_state()
                 if ref is None:
                     ref = s
                 else:
                     for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
                         assert np.array_equal(ref[k], s[k]), (bn, lds, graph, k)
+
+
+@pytest.mark.parametrize("skin", [0.0, 0.25, 2.0])
+def test_trajectory_skins(pdmod, skin):
+    """Every skin (0: cell search every step) gives the oracle trajectory;
+    a small skin forces many candidate-list rebuilds."""
+    _say(f"case: trajectory skin={skin}")
+    prob = _herd(_bed(10, 13, g=(0.0, -5000.0)), 0.45, seed=13, dv=2.0)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_tuning(skin_factor=skin)
+    eu, ev, sg, so = _traj(g, o, 150)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
+    if skin == 0.25:
+        assert g.sizes()["list_rebuilds"] > 3
+
+
+def test_autotune_keeps_state(pdmod):
+    """The autotuner times candidates on a copy of the state: afterwards the
+    state and the forces are bitwise what they were, and stepping on with the
+    chosen tuning equals a fresh context run with that tuning."""
+    _say("case: autotune")
+    prob = _herd(_bed(10, 14), 0.3, seed=14, dv=0.3)
+    g = pdmod.PD(prob)
+    g.step(10)
+    s0 = g.get_state()
+    f0 = g.forces()
+    best = g.autotune(6)
+    assert best["block_nodes"] in (64, 128, 256)
+    s1 = g.get_state()
+    f1 = g.forces()
+    for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
+        assert np.array_equal(s0[k], s1[k]), k
+    # the chosen cell size may reorder contact sums: equal up to rounding
+    scale = max(np.abs(f0[0]).max(), np.abs(f0[1]).max())
+    assert max(np.abs(f0[0] - f1[0]).max(), np.abs(f0[1] - f1[1]).max()) <= 1e-13 * scale
+    h = pdmod.PD(prob)
+    h.step(10)
+    h.set_tuning(**best)
+    g.step(40)
+    h.step(40)
+    sg, sh = g.get_state(), h.get_state()
+    for k in ("ux", "uy", "vx", "vy", "broken"):
+        assert np.array_equal(sg[k], sh[k]), k
 
 
 def test_cell_factor_changes_only_rounding(pdmod):
@@ -317,3 +362,61 @@ def test_invalid_problem_rejected(pdmod):
     with pytest.raises(pdmod.PDError) as e:
         pdmod.PD(prob)
     assert e.value.status == pdmod.PD_E_INVALID
+
+
+# ---------------------------------------------------------------------------
+# FP32 force accumulation with FP64 state and FP64 break decisions
+# ---------------------------------------------------------------------------
+def _near_critical(seed, scale=1.0, noise=3e-8):
+    """Particles stretched homogeneously so that bond stretches cluster within
+    about 1e-7 of s0: every break decision is a near tie."""
+    h = 0.12e-3
+    parts, box = W.mixed_bed(6, h, 12e-3, 12e-3, seed)
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], box, contact_radius=0.95 * h,
+                      friction_mu=0.5, damping_ratio=0.8, dt=1e-7)
+    s0 = Oracle(prob).constants()["s0"][0]
+    rng = np.random.default_rng(seed)
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    po = prob.particle_offset
+    for p in range(prob.n_particles):
+        sl = slice(po[p], po[p + 1])
+        cx, cy = prob.x[sl].mean(), prob.y[sl].mean()
+        k = s0 * scale * (1.0 + noise * rng.standard_normal(po[p + 1] - po[p]))
+        ux[sl] = k * (prob.x[sl] - cx)
+        uy[sl] = k * (prob.y[sl] - cy)
+    prob.u0x, prob.u0y = ux, uy
+    return prob
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_break_decisions_at_near_ties(pdmod, precision):
+    """With stretches within ~1e-7 of s0, the bonds broken at t = 0 are exactly
+    the oracle's, in FP64 and in the FP32-force mode (FP64 recheck)."""
+    _say(f"case: near-tie breaks precision={precision}")
+    prob = _near_critical(31)
+    o = Oracle(prob)
+    g = pdmod.PD(prob, precision=precision)
+    bo, bg = o.get_state()["broken"], g.get_state()["broken"]
+    assert 0 < bo.sum() < len(bo)  # a genuine mix of broken and intact bonds
+    assert np.array_equal(bo, bg)
+    o.step(3)
+    g.step(3)
+    assert np.array_equal(o.get_state()["broken"], g.get_state()["broken"])
+
+
+def test_fp32_forces_close_to_fp64(pdmod):
+    """FP32 force arithmetic and accumulation: per-term force error against the
+    FP64 oracle at the same state stays at FP32 level (max-norm relative)."""
+    _say("case: fp32 forces")
+    prob = _herd(_bed(10, 33), 0.45, seed=33, dv=0.5)
+    W.perturb(prob, 34, du=2e-6)
+    o = Oracle(prob)
+    g = pdmod.PD(prob, precision=1)
+    for t in TERMS:
+        gx, gy = g.forces(t)
+        ox, oy = o.forces(t)
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        if scale == 0:
+            continue
+        e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
+        assert e < 2e-5, (t, e)
