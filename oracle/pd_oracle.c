@@ -626,10 +626,18 @@ static void pd_node(or_ctx *c, int i) {
         c->brk_eval[k] = 0;
         if (c->broken[k]) continue;
         const int j = c->col[k];
-        const double dx = c->px[j] - c->px[i], dy = c->py[j] - c->py[i];
+        /* bond xi = x' - x, relative displacement eta = u' - u (Sec. 3) */
+        const double X = c->x[j] - c->x[i], Y = c->y[j] - c->y[i];
+        const double ex = c->ux[j] - c->ux[i], ey = c->uy[j] - c->uy[i];
+        const double dx = X + ex, dy = Y + ey; /* xi + eta */
         const double l = sqrt(dx * dx + dy * dy);
-        const double L0 = c->l0[k];
-        const double s = (l - L0) / L0;
+        const double L0 = c->l0[k]; /* |xi| */
+        /* s = (|xi + eta| - |xi|) / |xi|, evaluated as
+         *     eta . (xi + eta + xi) / (|xi| (|xi + eta| + |xi|)),
+         * the same quantity without the cancellation of |xi + eta| - |xi| at
+         * small strain (both evaluations of a bond give the same bits from its
+         * two ends: every factor flips sign exactly) */
+        const double s = (ex * (dx + X) + ey * (dy + Y)) / (L0 * (l + L0));
         if (fabs(s) > s0) { /* Sec. 3.1: broken when |s| exceeds s0 */
             c->brk_eval[k] = 1;
             continue;

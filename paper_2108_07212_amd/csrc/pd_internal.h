@@ -96,7 +96,7 @@ struct DevArgs {
 
 struct Ctx {
     DevArgs a{};
-    pd_tuning tune{256, 1.0, 1, 1, 1.0};
+    pd_tuning tune{64, 1.0, 1, 1, 1.0};
     bool list_valid = false;     // candidate lists match the current state
     int64_t rebuilds = 0;
     hipGraphExec_t lgraph[2] = {nullptr, nullptr};  // kChunk list-mode steps per parity

@@ -61,6 +61,16 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return fma(r, e, r);
 }
 
+// 1/sqrt(x) to full FP64 precision: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsq_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    double e = fma(-hx * r, r, 0.5);
+    r = fma(r, e, r);
+    e = fma(-hx * r, r, 0.5);
+    return fma(r, e, r);
+}
+
 // inclusive scan across a 64-lane wavefront
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -539,64 +549,122 @@ __device__ __forceinline__ T quad_sum(T v) {
     return v;
 }
 
-// Four lanes per node: lane `sub` of node i takes the bond slots k = sub,
-// sub + 4, ... of the node's SELL-16 row, every fourth contact candidate, one
-// wall and one corner; the quad then combines its partial sums in a fixed
-// order and lane 0 integrates.  LDS holds the block's window of bond partners
-// (reference and current positions, volumes).
-template <typename R, int MODE, bool LIST>
-__global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
-    extern __shared__ double lds[];
-    // list mode: this launch computes step sprev + 1 of a replay that started
-    // after step *step_base; once a list has gone stale, that step and every
-    // later one of the replay are no-ops (the check is uniform over the grid)
-    long long sprev = 0;
-    if (LIST) {
-        sprev = *a.step_base + a.chunk_k;
-        if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
-    }
-    double *Sx = lds, *Sy = lds + lds_cap, *Spx = lds + 2 * lds_cap, *Spy = lds + 3 * lds_cap,
-           *Sv = lds + 4 * lds_cap;
+// Bond forces of node i from the slots k = sub, sub + 4, ... of its SELL-16
+// row (lane `sub` of the node's quad).  Every slot runs the same branch-free
+// arithmetic (padding and broken slots are masked), so consecutive slots form
+// independent chains the compiler can interleave.  A bond whose approximate
+// stretch comes within 1e-10 (FP64) or 2e-6 (FP32) of s0 is re-decided with
+// the stretch evaluated in IEEE FP64 (correctly rounded square roots and
+// division), the exact decision of Sec. 3.1.
+template <typename R, int MODE>
+__device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc, int i, int sub,
+                                            bool staged, int lo, const double *Sx,
+                                            const double *Sy, const double *Sux,
+                                            const double *Suy, const double *Sv, double xi,
+                                            double yi, double uxi, double uyi, double Vi, R &fpx,
+                                            R &fpy, int &nbrk) {
     constexpr bool adv = (MODE == M_STEP);
-    const int sub = threadIdx.x & 3;
-    const int i = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
-    int lo = 0;
-    bool staged = false;
-    if (a.use_lds) {
-        lo = a.win_lo[blockIdx.x];
-        const int cnt = a.win_hi[blockIdx.x] - lo + 1;
-        staged = cnt > 0 && cnt <= lds_cap;
-        if (staged) {
-            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-                const int j = lo + k;
-                double px, py, ux, uy;
-                advanced_pos(a, j, adv, px, py, ux, uy);
-                Sx[k] = a.x[j];
-                Sy[k] = a.y[j];
-                Spx[k] = px;
-                Spy[k] = py;
-                Sv[k] = a.vol[j];
+    {
+        const uint32_t sl = (uint32_t)i / kSlice;
+        const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
+        const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+        const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
+        const bool conic = mc.conic != 0;
+        // this lane's slots k = sub + 4 t; their words are fetched in batches of
+        // kBatch before any of them is used, so the loads overlap
+        constexpr int kBatch = 8;
+        for (int k0 = sub; k0 < W; k0 += 4 * kBatch) {
+            uint32_t ev[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                const int k = k0 + 4 * t;
+                ev[t] = k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken;
+            }
+#pragma unroll 2
+            for (int t = 0; t < kBatch; ++t) {
+                const int k = k0 + 4 * t;
+                const uint32_t e = ev[t];
+                const bool valid = (e & kBroken) == 0;
+                const int j = valid ? (int)e : i;
+                double xj, yj, uxj, uyj, Vj;
+                if (staged) {
+                    const int q = j - lo;
+                    xj = Sx[q];
+                    yj = Sy[q];
+                    uxj = Sux[q];
+                    uyj = Suy[q];
+                    Vj = Sv[q];
+                } else {
+                    double pxj, pyj;
+                    advanced_pos(a, j, adv, pxj, pyj, uxj, uyj);
+                    xj = a.x[j];
+                    yj = a.y[j];
+                    Vj = a.vol[j];
+                }
+                // bond xi, relative displacement eta, current bond xi + eta; the
+                // stretch eta.(xi + eta + xi) / (|xi| (|xi + eta| + |xi|)) has no
+                // cancellation at small strain, so refined hardware square roots
+                // give it to a few ulps
+                const double X = xj - xi, Y = yj - yi;
+                const double EX = uxj - uxi, EY = uyj - uyi;
+                const double DX = X + EX, DY = Y + EY;
+                bool cand;
+                R g, DXr, DYr;
+                if constexpr (sizeof(R) == 8) {
+                    const double l0s = valid ? X * X + Y * Y : 1.0;
+                    const double ls = valid ? DX * DX + DY * DY : 1.0;
+                    const double r0 = rsq_nr(l0s), rl = rsq_nr(ls);
+                    const double l0 = l0s * r0, l = ls * rl;
+                    const double num = EX * (DX + X) + EY * (DY + Y);
+                    const double s = num * rcp_nr(l0 * (l + l0));
+                    cand = valid && fabs(s) > s0 * (1.0 - 1e-10);
+                    const double w = conic ? 1.0 - l0 * inv_eps : 1.0;
+                    const double f = valid ? cw * w * s * Vi * Vj : 0.0;
+                    g = f * rl;
+                    DXr = DX;
+                    DYr = DY;
+                } else {
+                    const float Xf = (float)X, Yf = (float)Y, DXf = (float)DX, DYf = (float)DY;
+                    const float EXf = (float)EX, EYf = (float)EY;
+                    const float l0s = valid ? Xf * Xf + Yf * Yf : 1.0f;
+                    const float ls = valid ? DXf * DXf + DYf * DYf : 1.0f;
+                    const float r0 = __builtin_amdgcn_rsqf(l0s), rl = __builtin_amdgcn_rsqf(ls);
+                    const float l0 = l0s * r0, l = ls * rl;
+                    const float num = EXf * (DXf + Xf) + EYf * (DYf + Yf);
+                    const float s = num * __builtin_amdgcn_rcpf(l0 * (l + l0));
+                    cand = valid && fabsf(s) > (float)(s0 - 2e-6);
+                    const float w = conic ? 1.0f - l0 * (float)inv_eps : 1.0f;
+                    const float f = valid ? (float)cw * w * s * (float)Vi * (float)Vj : 0.0f;
+                    g = f * rl;
+                    DXr = DXf;
+                    DYr = DYf;
+                }
+                if (cand) {  // rare: the exact decision (Sec. 3.1, broken for good)
+                    const double l0x = sqrt(X * X + Y * Y), lx = sqrt(DX * DX + DY * DY);
+                    const double sx = (EX * (DX + X) + EY * (DY + Y)) / (l0x * (lx + l0x));
+                    if (fabs(sx) > s0) {
+                        if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
+                        ++nbrk;
+                        g = 0;
+                    }
+                }
+                fpx += g * DXr;
+                fpy += g * DYr;
             }
         }
-        __syncthreads();
     }
-    if (i >= a.N) return;  // whole quads leave together
+}
 
-    const double xi = a.x[i], yi = a.y[i];
-    double pxi, pyi, uxi, uyi;
-    advanced_pos(a, i, adv, pxi, pyi, uxi, uyi);
-    const double vxi = a.vx[i], vyi = a.vy[i];  // velocities of the previous step
-    const double Vi = a.vol[i], mi = a.mass[i];
-    const int pi = a.part[i];
-    const int mt = a.pmat[pi];
-    const int ag = a.pagg[pi];
-    const MatConst mc = a.mat[mt];
-    // wall time of this evaluation
-    const double t = LIST ? (double)(sprev + 1) * a.dt : (double)(*a.step) * a.dt;
-    int st = 0;
-
-    // ---- contact -----------------------------------------------------------
-    R fsx = 0, fsy = 0, fnx = 0, fny = 0;
+// Contact forces of node i (lane `sub` of its quad): with candidate lists
+// (LIST), every fourth listed candidate; otherwise the nodes of the cells
+// sub, sub + 4, sub + 8 of the 3 x 3 neighbourhood.  Pairs closer than R_c
+// act; an intact bond replaces contact between nodes of one particle.
+template <typename R, bool LIST, bool adv>
+__device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst &mc, int i,
+                                               int sub, int pi, int ag, double xi, double yi,
+                                               double pxi, double pyi, double vxi, double vyi,
+                                               double Vi, double mi, R &fsx, R &fsy, R &fnx,
+                                               R &fny) {
     if (LIST) {
         // candidates listed at the last rebuild (intact bonds excluded)
         const int nc = a.clist_n[i];
@@ -645,85 +713,84 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
             }
         }
     }
+}
 
-    // ---- walls ---------------------------------------------------------------
-    double fwx = 0.0, fwy = 0.0;
-    wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
-
-    // ---- peridynamic bonds (SELL-16 row, columns ascending) ------------------
-    // Every slot runs the same branch-free arithmetic (padding and broken
-    // slots are masked), so consecutive slots form independent chains the
-    // compiler can interleave.  A bond whose approximate stretch comes within
-    // 1e-10 (FP64) or 2e-6 (FP32) of s0 is re-decided with the exact FP64
-    // stretch (l - l0) / l0 of correctly rounded lengths, so break decisions
-    // are those of plain FP64 arithmetic.
-    R fpx = 0, fpy = 0;
-    int nbrk = 0;
-    {
-        const uint32_t sl = (uint32_t)i / kSlice;
-        const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
-        const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
-        const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
-        const bool conic = mc.conic != 0;
-#pragma unroll 2
-        for (int k = sub; k < W; k += 4) {
-            const uint32_t e = a.col[base + (uint32_t)k * kSlice];
-            const bool valid = (e & kBroken) == 0;
-            const int j = valid ? (int)e : i;
-            double xj, yj, pxj, pyj, Vj;
-            if (staged) {
-                const int q = j - lo;
-                xj = Sx[q];
-                yj = Sy[q];
-                pxj = Spx[q];
-                pyj = Spy[q];
-                Vj = Sv[q];
-            } else {
-                double ux, uy;
-                advanced_pos(a, j, adv, pxj, pyj, ux, uy);
-                xj = a.x[j];
-                yj = a.y[j];
-                Vj = a.vol[j];
+// Four lanes per node: lane `sub` of node i takes the bond slots k = sub,
+// sub + 4, ... of the node's SELL-16 row, every fourth contact candidate, one
+// wall and one corner; the quad then combines its partial sums in a fixed
+// order and lane 0 integrates.  LDS holds the block's window of bond partners
+// (reference and current positions, volumes).
+template <typename R, int MODE, bool LIST>
+__global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
+    extern __shared__ double lds[];
+    // list mode: this launch computes step sprev + 1 of a replay that started
+    // after step *step_base; once a list has gone stale, that step and every
+    // later one of the replay are no-ops (the check is uniform over the grid)
+    long long sprev = 0;
+    if (LIST) {
+        sprev = *a.step_base + a.chunk_k;
+        if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    }
+    double *Sx = lds, *Sy = lds + lds_cap, *Sux = lds + 2 * lds_cap, *Suy = lds + 3 * lds_cap,
+           *Sv = lds + 4 * lds_cap;
+    constexpr bool adv = (MODE == M_STEP);
+    const int sub = threadIdx.x & 3;
+    const int i = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    int lo = 0;
+    bool staged = false;
+    if (a.use_lds) {
+        lo = a.win_lo[blockIdx.x];
+        const int cnt = a.win_hi[blockIdx.x] - lo + 1;
+        staged = cnt > 0 && cnt <= lds_cap;
+        if (staged) {
+            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+                const int j = lo + k;
+                double px, py, ux, uy;
+                advanced_pos(a, j, adv, px, py, ux, uy);
+                Sx[k] = a.x[j];
+                Sy[k] = a.y[j];
+                Sux[k] = ux;
+                Suy[k] = uy;
+                Sv[k] = a.vol[j];
             }
-            const double X = xj - xi, Y = yj - yi;
-            const double DX = pxj - pxi, DY = pyj - pyi;
-            bool cand;
-            R g, DXr, DYr;
-            if constexpr (sizeof(R) == 8) {
-                const double l0 = sqrt(valid ? X * X + Y * Y : 1.0);
-                const double l = sqrt(valid ? DX * DX + DY * DY : 1.0);
-                const double s = (l - l0) * rcp_nr(l0);
-                cand = valid && fabs(s) > s0 * (1.0 - 1e-10);
-                const double w = conic ? 1.0 - l0 * inv_eps : 1.0;
-                const double f = valid ? cw * w * s * Vi * Vj : 0.0;
-                g = f * rcp_nr(l);
-                DXr = DX;
-                DYr = DY;
-            } else {
-                const float Xf = (float)X, Yf = (float)Y, DXf = (float)DX, DYf = (float)DY;
-                const float l0s = valid ? Xf * Xf + Yf * Yf : 1.0f;
-                const float ls = valid ? DXf * DXf + DYf * DYf : 1.0f;
-                const float r0 = __builtin_amdgcn_rsqf(l0s), rl = __builtin_amdgcn_rsqf(ls);
-                const float l0 = l0s * r0, l = ls * rl;
-                const float s = (l - l0) * r0;
-                cand = valid && fabsf(s) > (float)(s0 - 2e-6);
-                const float w = conic ? 1.0f - l0 * (float)inv_eps : 1.0f;
-                const float f = valid ? (float)cw * w * s * (float)Vi * (float)Vj : 0.0f;
-                g = f * rl;
-                DXr = DXf;
-                DYr = DYf;
-            }
-            if (cand) {  // rare: the exact decision (Sec. 3.1, broken for good)
-                const double l0x = sqrt(X * X + Y * Y), lx = sqrt(DX * DX + DY * DY);
-                if (fabs((lx - l0x) / l0x) > s0) {
-                    if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
-                    ++nbrk;
-                    g = 0;
-                }
-            }
-            fpx += g * DXr;
-            fpy += g * DYr;
         }
+        __syncthreads();
+    }
+    if (i >= a.N) return;  // whole quads leave together
+
+    const double xi = a.x[i], yi = a.y[i];
+    double pxi, pyi, uxi, uyi;
+    advanced_pos(a, i, adv, pxi, pyi, uxi, uyi);
+    const double vxi = a.vx[i], vyi = a.vy[i];  // velocities of the previous step
+    const double Vi = a.vol[i], mi = a.mass[i];
+    const int pi = a.part[i];
+    const int mt = a.pmat[pi];
+    const int ag = a.pagg[pi];
+    const MatConst mc = a.mat[mt];
+    // wall time of this evaluation
+    const double t = LIST ? (double)(sprev + 1) * a.dt : (double)(*a.step) * a.dt;
+    int st = 0;
+
+    R fsx = 0, fsy = 0, fnx = 0, fny = 0, fpx = 0, fpy = 0;
+    double fwx = 0.0, fwy = 0.0;
+    int nbrk = 0;
+    // List mode runs the bond loop first (its contact candidates never
+    // involve intact bonds, so the order does not matter there), which keeps
+    // fewer partial sums live through the loop.  Otherwise contact comes
+    // first, because self-contact needs the bonds intact at the start of the
+    // step and the bond loop commits breaks.
+    if constexpr (LIST) {
+        bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi, Vi,
+                             fpx, fpy, nbrk);
+        contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
+                                     fsx, fsy, fnx, fny);
+        wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+    } else {
+        contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
+                                     fsx, fsy, fnx, fny);
+        wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+        bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi, Vi,
+                             fpx, fpy, nbrk);
     }
 
     // ---- combine the quad ------------------------------------------------------

@@ -465,3 +465,13 @@ def perturb(prob: Problem, seed: int, du: float = 0.0, dv: float = 0.0) -> Probl
         prob.v0x = (prob.v0x if prob.v0x is not None else 0.0) + dv * rng.uniform(-1, 1, n)
         prob.v0y = (prob.v0y if prob.v0y is not None else 0.0) + dv * rng.uniform(-1, 1, n)
     return prob
+
+
+def particle_velocities(prob: Problem, seed: int, vmax: float) -> Problem:
+    """Give every particle a seeded rigid velocity, uniform in [-vmax, vmax]^2."""
+    rng = np.random.default_rng(seed)
+    vel = rng.uniform(-vmax, vmax, size=(prob.n_particles, 2))
+    counts = np.diff(prob.particle_offset)
+    prob.v0x = np.repeat(vel[:, 0], counts)
+    prob.v0y = np.repeat(vel[:, 1], counts)
+    return prob

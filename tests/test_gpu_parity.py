@@ -420,3 +420,51 @@ def test_fp32_forces_close_to_fp64(pdmod):
             continue
         e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
         assert e < 2e-5, (t, e)
+
+
+# ---------------------------------------------------------------------------
+# batched aggregates
+# ---------------------------------------------------------------------------
+def _small_batch(seed=41, n_agg=3):
+    prob = W.batched(n_aggregates=n_agg, h=0.15e-3, seed=seed, n_range=(6, 12), dt=4e-7,
+                     gravity=-5000.0, precision=W.PREC_FP64)
+    return W.particle_velocities(prob, seed, 3.0)
+
+
+def test_batched_aggregates_match_alone(pdmod):
+    """Aggregates of uneven size in one problem evolve as they do alone:
+    bond sets and broken bonds bit-exact, trajectories to 1e-9."""
+    _say("case: batched vs alone")
+    prob = _small_batch()
+    gb = pdmod.PD(prob)
+    gb.step(500)
+    sb = gb.get_state()
+    rb, cb = gb.bonds()
+    n0 = 0
+    b0 = 0
+    for a in range(prob.n_aggregates):
+        sub = W.subproblem_aggregate(prob, a)
+        ga = pdmod.PD(sub)
+        ra, ca = ga.bonds()
+        n1 = n0 + sub.n_nodes
+        assert np.array_equal(cb[rb[n0]:rb[n1]] - n0, ca)
+        ga.step(500)
+        sa = ga.get_state()
+        for k in ("ux", "uy", "vx", "vy"):
+            e = _relerr(sb[k][n0:n1], sa[k])
+            assert e <= TRAJ_TOL, (a, k, e)
+        nb = len(ca)
+        assert np.array_equal(sb["broken"][b0:b0 + nb], sa["broken"])
+        n0, b0 = n1, b0 + nb
+    assert gb.counters()["steps"] == 500
+
+
+def test_batched_oracle_parity(pdmod):
+    _say("case: batched vs oracle")
+    prob = _small_batch(seed=41, n_agg=3)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_counting(True)
+    eu, ev, sg, so = _traj(g, o, 500)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
+    assert g.counters()["inter"] > 0  # the aggregates' particles touch

@@ -661,3 +661,39 @@ def test_two_disks_centre_of_mass_and_pair_balance():
         assert abs(Fx.sum()) <= 1e-12 * scale * 10 + 1e-14 * np.abs(Fx).sum()
         assert abs(Fy.sum()) <= 1e-12 * scale * 10 + 1e-14 * np.abs(Fy).sum()
     assert o.counters()["inter"] > 0
+
+
+@pytest.mark.parametrize("strain", [1e-13, 1e-9, 3e-6, 1e-3, -2e-2, 5e-2])
+def test_bond_stretch_against_exact_arithmetic(strain):
+    """One bond (Sec. 3: s = (|xi + eta| - |xi|) / |xi|): the PD force on a
+    two-node particle matches 50-digit arithmetic to a few ulps at every
+    strain, including strains where |xi + eta| - |xi| cancels."""
+    from decimal import Decimal, getcontext
+    from fractions import Fraction
+    getcontext().prec = 50
+    h = 1e-4
+    nodes = np.array([[0.0, 0.0], [0.8 * h, 0.35 * h]])
+    parts = [W.Particle("disk", h, (2e-3, 2e-3), 0.3, nodes_body=nodes, loops_body=[])]
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], [0, 4e-3, 0, 4e-3],
+                      contact_radius=0.5 * h, friction_mu=0, damping_ratio=0, dt=1e-9)
+    X = prob.x[1] - prob.x[0]
+    Y = prob.y[1] - prob.y[0]
+    # a displacement of node 1 giving the requested stretch, slightly rotated
+    ux1 = strain * X - 0.3 * strain * Y
+    uy1 = strain * Y + 0.3 * strain * X
+    prob.u0x = np.array([0.0, ux1])
+    prob.u0y = np.array([0.0, uy1])
+    o = Oracle(prob)
+    fx, fy = o.forces(T_PD)
+    cw = o.constants()["cw"][0]
+    D = lambda v: Decimal(Fraction(float(v)).numerator) / Decimal(Fraction(float(v)).denominator)
+    Xd, Yd = D(prob.x[1]) - D(prob.x[0]), D(prob.y[1]) - D(prob.y[0])
+    dxd, dyd = Xd + D(ux1), Yd + D(uy1)
+    l0 = (Xd * Xd + Yd * Yd).sqrt()
+    l = (dxd * dxd + dyd * dyd).sqrt()
+    s = (l - l0) / l0
+    fxe = D(cw) * s * D(prob.vol[1]) * dxd / l
+    fye = D(cw) * s * D(prob.vol[1]) * dyd / l
+    assert float(fxe) != 0.0
+    assert fx[0] == pytest.approx(float(fxe), rel=1e-14)
+    assert fy[0] == pytest.approx(float(fye), rel=1e-14)
