@@ -74,6 +74,98 @@ def cpu_baseline(prob, seconds: float, n_pairs: int):
                       f"OpenMP over nodes), {el:.1f} s"}
 
 
+def herd(prob, alpha):
+    """Translate every particle rigidly toward the bed centre by the fraction
+    alpha of its distance: a synthetic packed state with contacts at once."""
+    import numpy as np
+    cx, cy = prob.x.mean(), prob.y.mean()
+    po = prob.particle_offset
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        sl = slice(po[p], po[p + 1])
+        ux[sl] = -alpha * (prob.x[sl].mean() - cx)
+        uy[sl] = -alpha * (prob.y[sl].mean() - cy)
+    prob.u0x, prob.u0y = ux, uy
+    return prob
+
+
+def precision_split(pd, W, torch, steps):
+    """FP32 force arithmetic with FP64 state and FP64 break decisions, on the
+    compaction bed of 500 particles (about 245k nodes) started from a packed
+    state: throughput of both modes, the per-step force error of FP32 against
+    FP64 at identical states, and broken-bond counts after `steps` steps."""
+    import numpy as np
+    prob = herd(W.compaction(), 0.30)
+    prob.top_wall_speed = np.array([0.1])
+    g64 = pd.PD(prob, precision=0)
+    g32 = pd.PD(prob, precision=1)
+    res = {"workload": "compaction_500 (packed start)", "nodes": prob.n_nodes}
+    errs = []
+    for k in range(4):
+        s = g64.get_state()
+        g32.set_state(s)
+        f64 = g64.forces(pd.TERM_ALL)
+        f32 = g32.forces(pd.TERM_ALL)
+        scale = max(np.abs(f64[0]).max(), np.abs(f64[1]).max())
+        errs.append(float(max(np.abs(f32[0] - f64[0]).max(), np.abs(f32[1] - f64[1]).max()) / scale))
+        g64.step(steps // 4)
+    g32b = pd.PD(prob, precision=1)
+    g32b.step(steps)
+    res["force_rel_err_fp32_vs_fp64_max_norm"] = errs
+    res["broken_directed_fp64"] = int(g64.damage()[1])
+    res["broken_directed_fp32"] = int(g32b.damage()[1])
+    for name, g in (("fp64", g64), ("fp32", g32b)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        sps = steps / (time.perf_counter() - t0)
+        n_pairs = g.sizes()["bonds"] // 2
+        res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+                     "force_kernel_ms": g.time_kernels(128)["force"][0]}
+    return res
+
+
+def batched(pd, W, torch, steps):
+    """64 independent settling aggregates of 50-400 particles (about 6.4M
+    nodes) in one problem, FP64 state and FP32 forces: steps/s of the batch,
+    the roofline of its force kernel, and the time of the same 64 aggregates
+    run one after another, each in a context of its own."""
+    prob = W.batched()
+    g = pd.PD(prob)
+    g.step(20)
+    sizes = g.sizes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    sps = steps / (time.perf_counter() - t0)
+    kt = g.time_kernels(128)
+    fb = BYTES_PER_NODE_FORCE * sizes["nodes"] + BYTES_PER_BOND * sizes["bonds"]
+    ach = fb / (kt["force"][0] * 1e-3) / 1e9
+    res = {"workload": "batched_64", "aggregates": prob.n_aggregates, "nodes": sizes["nodes"],
+           "directed_bonds": sizes["bonds"], "steps_per_s": sps,
+           "bond_interactions_per_s": sizes["bonds"] // 2 * sps,
+           "force_kernel": {"mean_launch_ms": kt["force"][0], "bytes_per_launch": fb,
+                            "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS}}
+    del g
+    seq = 0.0
+    sub_steps = max(20, steps // 2)
+    for a in range(prob.n_aggregates):
+        ga = pd.PD(W.subproblem_aggregate(prob, a))
+        ga.step(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ga.step(sub_steps)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t0) / sub_steps
+        del ga
+    res["sequential_ms_per_step"] = 1e3 * seq
+    res["batched_ms_per_step"] = 1e3 / sps
+    res["speedup_vs_sequential"] = seq * sps
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +174,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=500)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--split-steps", type=int, default=400)
+    ap.add_argument("--batched-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
@@ -153,6 +248,10 @@ def main():
                               "note": "same step with the cell-key sort and cell search "
                                       "every step (skin 0)"},
     }
+    del g
+    if not args.no_variants:
+        out["precision_split"] = precision_split(pd, W, torch, args.split_steps)
+        out["batched"] = batched(pd, W, torch, args.batched_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.settling(), args.cpu_seconds, n_pairs)
     print(json.dumps(out), flush=True)
