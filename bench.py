@@ -166,6 +166,20 @@ def batched(pd, W, torch, steps):
     return res
 
 
+def copy_calibration(torch, mib=256, reps=10):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters of a profiler run: the counters of this run divided by
+    `reps` x `mib` MiB give the counter's bytes per true byte."""
+    n = mib * 1024 * 1024
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_calibration": {"bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                                 "copies": reps}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +191,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--split-steps", type=int, default=400)
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--workload", choices=("settling", "compaction", "batched"),
+                    default="settling",
+                    help="settling: the headline line (plus the variants unless "
+                         "--no-variants); compaction / batched: only that variant")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
@@ -191,6 +211,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(torch)), flush=True)
+        return
+    if args.workload == "compaction":
+        print(json.dumps({"precision_split": precision_split(pd, W, torch, args.split_steps)}),
+              flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps({"batched": batched(pd, W, torch, args.batched_steps)}), flush=True)
+        return
     prob = W.settling()
     g = pd.PD(prob)
     sizes = g.sizes()

@@ -1,0 +1,279 @@
+"""FP64 reference of the learned modal closure -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+use this module; the library never imports it.
+
+The paper has no reduced-order model: this follows the project's own
+definition of one, written out plainly (numpy / scipy, float64):
+
+* the linearized bond force of eq. (peri) about the reference configuration
+  gives a stiffness K per particle shape; with the lumped mass M = diag(rho V)
+  the lowest non-rigid solutions of K phi = lambda M phi (three rigid modes
+  excluded), normalised phi^T M phi = 1, are the modes;
+* a particle's deformation is read in its best-fit rotated frame (weighted
+  2-D Procrustes about the mass centroid), projected on the modes
+  (q = Phi^T M u), and its internal force is replaced by M Phi g(q) rotated
+  back, with g(q) = -lambda q (linear closure) or -lambda q + sigma_r
+  MLP(q / sigma_q) (learned closure);
+* the particle moves as a rigid body plus those modes: the external nodal
+  forces are split into total force, torque about the centroid and modal
+  force, and the nodal acceleration is rebuilt from them (Galerkin
+  projection; coupling between the rotation and the modal inertia is left
+  out).
+
+The MLP is 32 -> 256 -> 256 -> 32 with SiLU after the two hidden layers.
+Weights are stored [out][in]; the packed order is W1, b1, W2, b2, W3, b3.
+With bf16=True the forward and backward round the operands of every matrix
+product to bfloat16 (round to nearest even) at the same points as the GPU
+kernels: the normalised input, the weights, the two hidden activations and
+the three back-propagated signals dy, dz2, dz1; sums are exact (float64)
+here, float32 on the GPU.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+N_RIGID = 3
+N_IN = 32
+N_HID = 256
+LAYERS = ((N_HID, N_IN), (N_HID, N_HID), (N_IN, N_HID))  # (out, in) per layer
+N_PARAMS = sum(o * i + o for o, i in LAYERS)
+
+
+# ----------------------------------------------------------------------------
+# shapes, stiffness and modes
+# ----------------------------------------------------------------------------
+def particle_range(prob, p):
+    return int(prob.particle_offset[p]), int(prob.particle_offset[p + 1])
+
+
+def node_masses(prob, p):
+    n0, n1 = particle_range(prob, p)
+    rho = prob.materials[int(prob.particle_material[p])].rho
+    return rho * prob.vol[n0:n1]
+
+
+def reference_frame(prob, p):
+    """Mass centroid and centred reference coordinates of particle p."""
+    n0, n1 = particle_range(prob, p)
+    m = node_masses(prob, p)
+    xy = np.stack([prob.x[n0:n1], prob.y[n0:n1]], axis=1)
+    c0 = (m[:, None] * xy).sum(0) / m.sum()
+    return c0, xy - c0
+
+
+def best_fit_angle(X, Y, m):
+    """Angle of the rotation R minimising sum m |R X - Y|^2 (X, Y centred):
+    R(phi) X . Y = cos(phi) sum m X.Y + sin(phi) sum m X x Y is largest at
+    phi = atan2(sum m X x Y, sum m X.Y)."""
+    cross = (m * (X[:, 0] * Y[:, 1] - X[:, 1] * Y[:, 0])).sum()
+    dot = (m * (X[:, 0] * Y[:, 0] + X[:, 1] * Y[:, 1])).sum()
+    return float(np.arctan2(cross, dot))
+
+
+def rot(phi, V):
+    c, s = np.cos(phi), np.sin(phi)
+    return np.stack([c * V[:, 0] - s * V[:, 1], s * V[:, 0] + c * V[:, 1]], axis=1)
+
+
+def stiffness(prob, p, row, col, cw, horizon, micro):
+    """K of particle p (2n x 2n, dof order x0, y0, x1, y1, ...): the bond
+    force c_w w s V_i V_j e of eq. (peri) with the stretch linearised,
+    s = (u_j - u_i).e / |xi|, gives on node i the force
+    k (e e^T)(u_j - u_i), k = c_w w V_i V_j / |xi|, and K = -dF/du."""
+    n0, n1 = particle_range(prob, p)
+    n = n1 - n0
+    K = np.zeros((2 * n, 2 * n))
+    for i in range(n0, n1):
+        for k in range(row[i], row[i + 1]):
+            j = int(col[k])
+            dx, dy = prob.x[j] - prob.x[i], prob.y[j] - prob.y[i]
+            L = np.hypot(dx, dy)
+            e = np.array([dx / L, dy / L])
+            w = 1.0 if micro == 0 else 1.0 - L / horizon
+            kk = cw * w * prob.vol[i] * prob.vol[j] / L
+            B = kk * np.outer(e, e)
+            a, b = 2 * (i - n0), 2 * (j - n0)
+            K[a:a + 2, a:a + 2] += B
+            K[a:a + 2, b:b + 2] -= B
+    return K
+
+
+def modes(K, m, n_modes=N_IN):
+    """Lowest n_modes non-rigid solutions of K phi = lambda M phi,
+    M = diag(m_0, m_0, m_1, m_1, ...), with phi^T M phi = I (scipy's
+    generalized symmetric eigensolver). Returns (lambda, Phi [2n x n_modes],
+    all eigenvalues)."""
+    M = np.repeat(m, 2)
+    lam, vec = scipy.linalg.eigh(K, np.diag(M))
+    return lam[N_RIGID:N_RIGID + n_modes].copy(), vec[:, N_RIGID:N_RIGID + n_modes].copy(), lam
+
+
+def stretch_bound(prob, p, row, col, Phi):
+    """sigma_k = max over the particle's bonds of |linear stretch of mode k|:
+    for amplitudes q, max |s| <= sum_k |q_k| sigma_k to first order."""
+    n0, n1 = particle_range(prob, p)
+    P = Phi.reshape(n1 - n0, 2, -1)
+    sig = np.zeros(Phi.shape[1])
+    for i in range(n0, n1):
+        for k in range(row[i], row[i + 1]):
+            j = int(col[k])
+            dx, dy = prob.x[j] - prob.x[i], prob.y[j] - prob.y[i]
+            L2 = dx * dx + dy * dy
+            d = P[j - n0] - P[i - n0]
+            sig = np.maximum(sig, np.abs(d[0] * dx + d[1] * dy) / L2)
+    return sig
+
+
+# ----------------------------------------------------------------------------
+# projection of a particle's state
+# ----------------------------------------------------------------------------
+def project(X, m, Phi, y, v, F):
+    """Rigid + modal reading of a particle at positions y, velocities v,
+    external nodal forces F (all [n, 2]); X = template coordinates, centred.
+
+    Returns c (centroid), vc, phi (best-fit angle), I (polar moment about c),
+    Omega (angular velocity from the angular momentum), Ftot, torque,
+    q = Phi^T M u_body and gext = Phi^T f_body, with u_body = R(-phi)(y - c) - X
+    and f_body = R(-phi) F.
+    """
+    M = m.sum()
+    c = (m[:, None] * y).sum(0) / M
+    vc = (m[:, None] * v).sum(0) / M
+    Y = y - c
+    phi = best_fit_angle(X, Y, m)
+    I = (m * (Y ** 2).sum(1)).sum()
+    dv = v - vc
+    Lz = (m * (Y[:, 0] * dv[:, 1] - Y[:, 1] * dv[:, 0])).sum()
+    Ftot = F.sum(0)
+    tau = (Y[:, 0] * F[:, 1] - Y[:, 1] * F[:, 0]).sum()
+    ub = rot(-phi, Y) - X
+    fb = rot(-phi, F)
+    q = Phi.T @ (np.repeat(m, 2) * ub.ravel())
+    gext = Phi.T @ fb.ravel()
+    return dict(c=c, vc=vc, phi=phi, I=I, Omega=Lz / I, Ftot=Ftot, tau=tau, M=M, Y=Y,
+                q=q, gext=gext)
+
+
+def modal_force(Phi, phi, F):
+    """Phi^T R(-phi) F: the modal part of nodal forces F (e.g. the PD force)."""
+    return Phi.T @ rot(-phi, F).ravel()
+
+
+def closure_accel(pr, Phi, qdd, gravity):
+    """Nodal acceleration of a closure particle: translation by Ftot/M,
+    rotation alpha = tau/I about the centroid with the centripetal term of
+    the angular velocity Omega, and the modal acceleration R(phi) Phi qdd,
+    plus the body force."""
+    Y = pr["Y"]
+    alpha = pr["tau"] / pr["I"]
+    Om = pr["Omega"]
+    a = np.empty_like(Y)
+    a[:, 0] = pr["Ftot"][0] / pr["M"] - alpha * Y[:, 1] - Om * Om * Y[:, 0]
+    a[:, 1] = pr["Ftot"][1] / pr["M"] + alpha * Y[:, 0] - Om * Om * Y[:, 1]
+    a += rot(pr["phi"], (Phi @ qdd).reshape(-1, 2))
+    a[:, 0] += gravity[0]
+    a[:, 1] += gravity[1]
+    return a
+
+
+# ----------------------------------------------------------------------------
+# the MLP
+# ----------------------------------------------------------------------------
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    The input is first rounded to float32, as the GPU holds it."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(f)
+    if nan.any():
+        out[nan] = np.nan
+    return out.reshape(np.shape(a))
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def dsilu(z):
+    s = 1.0 / (1.0 + np.exp(-z))
+    return s * (1.0 + z * (1.0 - s))
+
+
+def unpack(params):
+    """Packed float array -> [(W1, b1), (W2, b2), (W3, b3)], W as [out, in]."""
+    params = np.asarray(params, dtype=np.float64)
+    out, k = [], 0
+    for o, i in LAYERS:
+        W = params[k:k + o * i].reshape(o, i)
+        k += o * i
+        b = params[k:k + o]
+        k += o
+        out.append((W, b))
+    assert k == params.size
+    return out
+
+
+def pack(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers])
+
+
+def mlp_forward(params, x, bf16=False):
+    """y = W3 h2 + b3, h2 = silu(W2 h1 + b2), h1 = silu(W1 x + b1); x [B, 32]."""
+    r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    (W1, b1), (W2, b2), (W3, b3) = unpack(params)
+    xb = r(x)
+    z1 = xb @ r(W1).T + b1
+    h1 = r(silu(z1))
+    z2 = h1 @ r(W2).T + b2
+    h2 = r(silu(z2))
+    y = h2 @ r(W3).T + b3
+    return y, dict(x=xb, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def mlp_backward(params, cache, dy, bf16=False):
+    """Gradients of sum(y * dy) with respect to the packed parameters (the
+    chain rule through the three layers), same packing as params."""
+    r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    (W1, b1), (W2, b2), (W3, b3) = unpack(params)
+    dyb = r(dy)
+    gW3 = dyb.T @ cache["h2"]
+    gb3 = np.asarray(dy).sum(0)
+    dz2 = (dyb @ r(W3)) * dsilu(cache["z2"])
+    dz2b = r(dz2)
+    gW2 = dz2b.T @ cache["h1"]
+    gb2 = dz2.sum(0)
+    dz1 = (dz2b @ r(W2)) * dsilu(cache["z1"])
+    dz1b = r(dz1)
+    gW1 = dz1b.T @ cache["x"]
+    gb1 = dz1.sum(0)
+    return pack([(gW1, gb1), (gW2, gb2), (gW3, gb3)])
+
+
+def loss_and_grads(params, q, r, sig_q, sig_r, bf16=False):
+    """Training objective on a batch: mean over samples and outputs of
+    (MLP(q / sigma_q) - r / sigma_r)^2, r = g + lambda q being the part of the
+    modal force the linear closure misses. Returns (loss, gradients)."""
+    x = np.asarray(q, dtype=np.float64) / sig_q
+    t = np.asarray(r, dtype=np.float64) / sig_r
+    y, cache = mlp_forward(params, x, bf16=bf16)
+    d = y - t
+    B = x.shape[0]
+    loss = float((d * d).sum() / (B * N_IN))
+    dy = 2.0 * d / (B * N_IN)
+    return loss, mlp_backward(params, cache, dy, bf16=bf16)
+
+
+def closure_modal_force(q, lam, params=None, sig_q=None, sig_r=None, bf16=True):
+    """g(q) = -lambda q, plus sigma_r MLP(q / sigma_q) for the learned closure;
+    q [B, 32]."""
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    g = -lam * q
+    if params is not None:
+        y, _ = mlp_forward(params, q / sig_q, bf16=bf16)
+        g = g + sig_r * y
+    return g

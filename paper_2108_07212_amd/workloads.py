@@ -475,3 +475,58 @@ def particle_velocities(prob: Problem, seed: int, vmax: float) -> Problem:
     prob.v0x = np.repeat(vel[:, 0], counts)
     prob.v0y = np.repeat(vel[:, 1], counts)
     return prob
+
+
+CLOSURE_SHAPES = ("disk", "plus", "ring", "lshape")
+
+
+def closure_radius(shape: str, h: float, nodes: int) -> float:
+    """The size R at which the shape's lattice holds about `nodes` nodes
+    (area / h^2 = nodes)."""
+    return h * math.sqrt(nodes / shape_area(shape, 1.0))
+
+
+def closure_bed(n_per_shape: int = 500, h: float = 0.08e-3, nodes: int = 400, seed: int = 5,
+                wall_speed: float = 0.1, vmax: float = 0.0, fill_scale: float = 1.0,
+                gravity: float = 0.0, dt: float = 1e-7, shapes=CLOSURE_SHAPES) -> Problem:
+    """Fixed shapes for the modal closure: n_per_shape particles of each shape,
+    every instance of a shape with the same size R (so the same body-frame
+    node set, and one mode basis per shape), random orientation, placed by
+    security-disk RSA in a box 30 x 60 R_mean scaled by sqrt(n/100) x
+    fill_scale, top wall moving down at wall_speed, optional seeded rigid
+    velocities uniform in [-vmax, vmax]^2.
+
+    Draw order with default_rng(seed): shape list shuffled, theta per
+    particle, placement attempts, then the velocities.
+    """
+    rng = np.random.default_rng(seed)
+    Rs = {s: closure_radius(s, h, nodes) for s in shapes}
+    kinds = []
+    for s in shapes:
+        kinds += [s] * n_per_shape
+    kinds = [kinds[i] for i in rng.permutation(len(kinds))]
+    n = len(kinds)
+    th = rng.uniform(0.0, 2 * np.pi, size=n)
+    # security disks bound the particle: the L shape's farthest vertex from
+    # its centroid is beyond R
+    bound = {s: max(np.hypot(lp[:, 0], lp[:, 1]).max() for lp in shape_loops(s, Rs[s]))
+             if shape_loops(s, Rs[s]) else Rs[s] for s in shapes}
+    radii = np.array([bound[k] for k in kinds])
+    Rm = float(np.mean(radii))
+    sc = math.sqrt(n / 100.0) * fill_scale
+    w, hh = 30 * Rm * sc, 60 * Rm * sc
+    centers = rsa_place(rng, radii, w, hh)
+    parts = [Particle(kinds[i], Rs[kinds[i]], (float(centers[i, 0]), float(centers[i, 1])),
+                      float(th[i]), 0, 0) for i in range(n)]
+    prob = assemble(parts, h, [_material(h)], [0.0, w, 0.0, hh], contact_radius=0.95 * h,
+                    friction_mu=0.5, damping_ratio=0.8, dt=dt, gravity=(0.0, gravity),
+                    top_wall_speed=[wall_speed],
+                    meta=dict(name=f"closure_{n}", seed=seed, shapes=list(shapes),
+                              R=Rs, kinds=kinds))
+    prob.meta["shape_of_particle"] = np.array([list(shapes).index(k) for k in kinds], dtype=np.int32)
+    if vmax > 0:
+        vel = rng.uniform(-vmax, vmax, size=(n, 2))
+        counts = np.diff(prob.particle_offset)
+        prob.v0x = np.repeat(vel[:, 0], counts)
+        prob.v0y = np.repeat(vel[:, 1], counts)
+    return prob
