@@ -166,6 +166,131 @@ def batched(pd, W, torch, steps):
     return res
 
 
+def modal_excitation(prob, modes, seed, strain_range):
+    """u0 of every closure particle in its rigid + modal space: R(theta_p) Phi q
+    with seeded q scaled so that the first-order stretch bound sum |q| sigma
+    is uniform in strain_range (input generation: the modes are the
+    library's)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sp = prob.meta["shape_of_particle"]
+    po = prob.particle_offset
+    rho = prob.materials[0].rho
+    first = {}
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        s = int(sp[p])
+        sl = slice(po[p], po[p + 1])
+        m = rho * prob.vol[sl]
+        xy = np.stack([prob.x[sl], prob.y[sl]], axis=1)
+        X = xy - (m[:, None] * xy).sum(0) / m.sum()
+        if s not in first:
+            first[s] = X
+        T = first[s]
+        th = np.arctan2((m * (T[:, 0] * X[:, 1] - T[:, 1] * X[:, 0])).sum(),
+                        (m * (T[:, 0] * X[:, 0] + T[:, 1] * X[:, 1])).sum())
+        phi, lam, sig, nm = modes[s]
+        q = rng.normal(0, 1, 32) / (1.0 + np.arange(32))
+        q[nm:] = 0.0
+        q *= rng.uniform(*strain_range) / (np.abs(q) * sig).sum()
+        u = np.einsum("nkc,k->nc", phi, q)
+        c, sn = np.cos(th), np.sin(th)
+        ux[sl] = c * u[:, 0] - sn * u[:, 1]
+        uy[sl] = sn * u[:, 0] + c * u[:, 1]
+    prob.u0x, prob.u0y = ux, uy
+    return prob
+
+
+def closure(pd, W, torch, steps, train_iters):
+    """The learned modal closure on 2000 particles of four fixed shapes
+    (disk, plus, ring, L; about 390 nodes each, 781 500 nodes) under
+    compaction: snapshots of a plain run train each shape's network on the
+    GPU; then plain, linear-closure and learned-closure runs from another
+    excitation are timed, with the closure checked against the plain bond
+    force every 100 steps."""
+    import numpy as np
+    mk = lambda: W.closure_bed(vmax=0.5)
+    prob = mk()
+    sp = prob.meta["shape_of_particle"]
+    g = pd.PD(prob)
+    t0 = time.perf_counter()
+    g.closure_setup(sp)
+    t_modes = time.perf_counter() - t0
+    modes = {s: g.closure_modes(s) for s in range(4)}
+    del g
+    strain = (0.01, 0.03)
+    train = modal_excitation(mk(), modes, 51, strain)
+    g = pd.PD(train)
+    g.closure_setup(sp)
+    Q, G = [], []
+    for _ in range(200):
+        g.step(5)
+        q, gg = g.closure_snapshot(device=True)
+        Q.append(q)
+        G.append(gg)
+    Q, G = torch.cat(Q), torch.cat(G)
+    _, s_of, _ = g.closure_particles()
+    rows = torch.from_numpy(np.tile(s_of, len(Q) // len(s_of))).cuda()
+    res = {"workload": "closure_2000 (compaction, modal excitation)", "nodes": prob.n_nodes,
+           "particles": prob.n_particles, "modes_setup_s": t_modes,
+           "snapshots_per_shape": int(len(Q) // 4)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params = {}
+    losses = {}
+    for s in range(4):
+        sel = torch.nonzero(rows == s).flatten()
+        L = g.closure_train(s, Q[sel], G[sel], iters=train_iters, batch=1024, lr=2e-3, seed=s)
+        losses[s] = [float(L[:50].mean()), float(L[-50:].mean())]
+        params[s] = g.closure_get(s)
+    torch.cuda.synchronize()
+    res["train_s"] = time.perf_counter() - t0
+    res["train_loss_first_last"] = losses
+    # held-out snapshots: learned vs linear closure against the plain force
+    test = modal_excitation(mk(), modes, 52, strain)
+    gt = pd.PD(test)
+    gt.closure_setup(sp)
+    for s in range(4):
+        gt.closure_load(s, *params[s])
+    e_n = e_l = n2 = 0.0
+    for _ in range(20):
+        gt.step(10)
+        q, gg = gt.closure_snapshot(device=True)
+        for s in range(4):
+            sel = torch.from_numpy(np.nonzero(s_of == s)[0]).cuda()
+            qs, gs = q[sel], gg[sel]
+            gn = gt.closure_forward(s, qs)
+            lam = torch.from_numpy(modes[s][1]).cuda()
+            e_n += float(((gn - gs) ** 2).sum())
+            e_l += float(((-lam * qs - gs) ** 2).sum())
+            n2 += float((gs ** 2).sum())
+    res["heldout_modal_force_err"] = {"learned": (e_n / n2) ** 0.5, "linear": (e_l / n2) ** 0.5}
+    del gt
+    # timed runs from the held-out excitation
+    for name, mode in (("plain", 0), ("linear", 1), ("learned", 2)):
+        gr = pd.PD(modal_excitation(mk(), modes, 52, strain))
+        gr.closure_setup(sp)
+        for s in range(4):
+            gr.closure_load(s, *params[s])
+        gr.closure_enable(mode)
+        gr.step(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gr.step(steps)
+        torch.cuda.synchronize()
+        sps = steps / (time.perf_counter() - t0)
+        st = gr.closure_stats()
+        n_pairs = gr.sizes()["bonds"] // 2
+        res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+                     "active": st["active"], "fallbacks": st["fallbacks"], "checks": st["checks"],
+                     "check_err": st["err"] if mode else None,
+                     "check_err_linear": st["err_linear"] if mode else None}
+        del gr
+    res["speedup_learned_vs_plain"] = res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"]
+    res["speedup_linear_vs_plain"] = res["linear"]["steps_per_s"] / res["plain"]["steps_per_s"]
+    return res
+
+
 def copy_calibration(torch, mib=256, reps=10):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters of a profiler run: the counters of this run divided by
@@ -191,7 +316,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--split-steps", type=int, default=400)
     ap.add_argument("--batched-steps", type=int, default=200)
-    ap.add_argument("--workload", choices=("settling", "compaction", "batched"),
+    ap.add_argument("--closure-steps", type=int, default=1000)
+    ap.add_argument("--train-iters", type=int, default=2000)
+    ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure"),
                     default="settling",
                     help="settling: the headline line (plus the variants unless "
                          "--no-variants); compaction / batched: only that variant")
@@ -220,6 +347,10 @@ def main():
         return
     if args.workload == "batched":
         print(json.dumps({"batched": batched(pd, W, torch, args.batched_steps)}), flush=True)
+        return
+    if args.workload == "closure":
+        print(json.dumps({"closure": closure(pd, W, torch, args.closure_steps, args.train_iters)}),
+              flush=True)
         return
     prob = W.settling()
     g = pd.PD(prob)
@@ -282,6 +413,7 @@ def main():
     if not args.no_variants:
         out["precision_split"] = precision_split(pd, W, torch, args.split_steps)
         out["batched"] = batched(pd, W, torch, args.batched_steps)
+        out["closure"] = closure(pd, W, torch, args.closure_steps, args.train_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.settling(), args.cpu_seconds, n_pairs)
     print(json.dumps(out), flush=True)

@@ -8,14 +8,19 @@
  *     breaking (Sec. 3, eq. peri, eq. pmb, Table tab:2d-peri, Sec. 3.1);
  *   - reference bonds restricted to segments that stay inside the particle,
  *     found once by the extended-boundary and cusp-bisector test of Sec. 5;
- *   - contact between nodes closer than R_c, found every step through a
- *     radix-sorted cell list (Algorithm alg:buildtree, inter-particle
- *     neighbour sets), with short-range repulsion (Sec. 4.1), regularized
+ *   - contact between nodes closer than R_c, evaluated every step from exact
+ *     distances over per-node candidate lists (all pairs within R_c plus a
+ *     skin), which a radix-sorted cell list rebuilds when a node has moved
+ *     half the skin or a bond broke (Algorithm alg:buildtree, inter-particle
+ *     neighbour sets); skin 0 runs the cell search every step.  Short-range
+ *     repulsion (Sec. 4.1), regularized
  *     Coulomb friction (Sec. 4.2), normal damping (Sec. 4.3) and self-contact
  *     between unbonded nodes of one particle (Sec. 4.4);
  *   - analytic contact with the four walls of a rectangular container whose
  *     top wall may move down (Sec. 4.5, eq. wall-total);
- *   - velocity-Verlet integration (Sec. 6.1, Algorithm alg:buildtree).
+ *   - velocity-Verlet integration (Sec. 6.1, Algorithm alg:buildtree);
+ *   - optionally, a learned reduced-order closure of the bond force for
+ *     particles of repeated shapes (pd_closure_*; not part of the paper).
  * The problem statement is the initial value problem eq. pdmotion with the
  * forces of eq. full.
  *
@@ -204,6 +209,97 @@ pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launc
  * [4] radix passes, [5] particles, [6] aggregates, [7] max LDS window,
  * [8] candidate-list rebuilds so far, [9] candidate slots per node. */
 pd_status pd_sizes(const pd_ctx *c, int64_t out[10]);
+
+/* ---------------------------------------------------------------------------
+ * Learned modal closure (an extension: the paper has no reduced-order model).
+ *
+ * Particles that are rigid copies of one shape share that shape's modes: the
+ * lowest K <= 32 non-rigid solutions of K phi = lambda M phi, K the
+ * stiffness of the bond force of eq. (peri) linearised about the shape's
+ * reference configuration, M = diag(rho V), phi^T M phi = 1.  A particle under
+ * the closure is read in its best-fit rotated frame about its mass centroid
+ * (weighted 2-D Procrustes); its modal amplitudes are q = Phi^T M u_body, its
+ * internal force is M Phi g(q) rotated back, with g(q) = -lambda q (linear
+ * closure) or -lambda q + sigma_r MLP(q / sigma_q) (learned closure: a
+ * 32-256-256-32 SiLU network, bfloat16 weights, float32 accumulation on the
+ * matrix cores), and it moves as a rigid body plus those modes: external
+ * nodal forces (contact, walls) give its total force, its torque about the
+ * centroid and the modal force Phi^T f_body, and the nodal accelerations are
+ * rebuilt from them.  Gate, evaluated every step: a particle whose
+ * first-order bound on its largest bond stretch, sum_k |q_k| sigma_k, passes
+ * gate_frac * s0, or whose contact load sum_i |F_i| passes tau_c, returns to
+ * the plain bond force from the next step on.  Every check_every steps (and at
+ * pd_closure_check) all closure particles are checked against the plain bond
+ * force at the current state: a particle whose largest true stretch passes
+ * gate_frac * s0, or whose modal-force error passes err_tol times the larger
+ * of |g_pd| and |lambda q|, returns to the plain bond force.  A particle never
+ * re-enters the closure by itself (pd_closure_enable re-admits all).
+ * The closure runs with candidate lists (tuning skin_factor > 0).
+ * MLP parameters are packed float32 in the order W1 [256][32], b1 [256],
+ * W2 [256][256], b2 [256], W3 [32][256], b3 [32] (weights [out][in]);
+ * 82 464 values per shape.  Modes are [n_nodes][32][2] doubles (mode k of
+ * node i, x then y), zero past the shape's mode count.
+ * ------------------------------------------------------------------------- */
+#define PD_CLOSURE_MODES 32
+#define PD_CLOSURE_PARAMS 82464
+
+/* shape_of_particle[n_particles]: shape id 0..S-1, or -1 (plain bond force
+ * always).  Every particle of a shape must be a rigid copy of the shape's
+ * first particle (same node count and order, same nodal masses); that first
+ * particle's reference configuration defines the modes, computed here.
+ * tau_c[S] (N/m) or NULL; an entry <= 0 takes 0.1 s0 E D (D the shape's
+ * diameter).  Network parameters start at zero, i.e. the linear closure.
+ * The closure starts switched off (pd_closure_enable).  PD_E_INVALID on a
+ * particle that is not a copy of its shape, a shape with more than three
+ * zero-stiffness modes, or more than 1536 nodes. */
+pd_status pd_closure_setup(pd_ctx *c, const int32_t *shape_of_particle, double gate_frac,
+                           const double *tau_c, int32_t check_every, double err_tol);
+/* the shape's modes (host buffers, any may be NULL): n_nodes, mode count,
+ * phi [n_nodes][32][2], lambda [32], sigma [32] (largest linear bond stretch
+ * of each mode) */
+pd_status pd_closure_modes(pd_ctx *c, int32_t shape, int32_t *n_nodes, int32_t *n_modes,
+                           double *phi, double *lam, double *sig);
+/* replace a shape's modes (host phi [n_nodes][32][2], lambda [32]); sigma is
+ * recomputed */
+pd_status pd_closure_set_modes(pd_ctx *c, int32_t shape, const double *phi, const double *lam);
+/* network parameters (host, PD_CLOSURE_PARAMS floats) and the input/output
+ * scales sigma_q, sigma_r [32] (either may be NULL: kept) */
+pd_status pd_closure_load(pd_ctx *c, int32_t shape, const float *params, const float *sig_q,
+                          const float *sig_r);
+pd_status pd_closure_get(pd_ctx *c, int32_t shape, float *params, float *sig_q, float *sig_r);
+/* 0: off (plain bond force everywhere); 1: linear closure; 2: learned
+ * closure.  Switching on admits every closure particle; its state should lie
+ * in its rigid + modal space (an undeformed particle does). */
+pd_status pd_closure_enable(pd_ctx *c, int32_t mode);
+/* Training snapshot at the current state, for every closure particle in the
+ * order of pd_closure_particles: q [Pc][32] and the modal plain bond force
+ * g = Phi^T R^T F_pd [Pc][32] (host or device buffers). */
+pd_status pd_closure_snapshot(pd_ctx *c, double *q, double *g, int32_t on_device);
+/* g = -lambda q + sigma_r MLP(q / sigma_q) for n rows q [n][32] of one shape */
+pd_status pd_closure_forward(pd_ctx *c, int32_t shape, const double *q, double *g, int64_t n,
+                             int32_t on_device);
+/* loss and gradients (host buffers) of one batch: loss = mean over rows and
+ * outputs of (MLP(q / sigma_q) - (g + lambda q) / sigma_r)^2; grads packed as
+ * the parameters */
+pd_status pd_closure_grads(pd_ctx *c, int32_t shape, const double *q, const double *g, int64_t n,
+                           float *grads, double *loss);
+/* train a shape's network on device data q, g [n][32] (samples of
+ * pd_closure_snapshot): sigma_q, sigma_r from the data, Adam, batches drawn
+ * with a counter-based generator from seed, step size lr with cosine decay
+ * over the call; loss_out[iters] (host) or NULL.  A shape trained for the
+ * first time starts from seeded uniform W1, W2 and zero W3 (the linear
+ * closure). */
+pd_status pd_closure_train(pd_ctx *c, int32_t shape, const double *q, const double *g, int64_t n,
+                           int32_t iters, int32_t batch, double lr, uint64_t seed, float *loss_out);
+/* a check against the plain bond force now (see above) */
+pd_status pd_closure_check(pd_ctx *c);
+/* out: closure particles, active now, fallbacks so far, checks so far, last
+ * check's aggregate modal-force error sqrt(sum |g - g_pd|^2 / sum |g_pd|^2)
+ * of the closure in use, the same for the linear closure, particles checked,
+ * shapes */
+pd_status pd_closure_stats(pd_ctx *c, double out[8]);
+/* closure particles in snapshot order: particle index, shape, active flag */
+pd_status pd_closure_particles(pd_ctx *c, int32_t *particle, int32_t *shape, int32_t *active);
 
 #ifdef __cplusplus
 }

@@ -277,3 +277,136 @@ def closure_modal_force(q, lam, params=None, sig_q=None, sig_r=None, bf16=True):
         y, _ = mlp_forward(params, q / sig_q, bf16=bf16)
         g = g + sig_r * y
     return g
+
+
+# ----------------------------------------------------------------------------
+# a time step with closure particles
+# ----------------------------------------------------------------------------
+class ClosureStepper:
+    """Velocity-Verlet steps of a problem in which the particles listed in
+    `shape_of_particle` (>= 0) take their internal force from the closure and
+    move as rigid body + modes, the others by the plain force of the C oracle
+    (Algorithm alg:buildtree).  Forces of every term come from the C oracle at
+    the advanced positions with the previous velocities; the wall is at
+    t_{n+1}.  Gate after each step: a closure particle whose bound
+    sum |q_k| sigma_k passes gate_frac s0 or whose contact load sum |F_i|
+    passes tau_c uses the plain force from the next step on.  Bonds must not
+    break (the C oracle's force evaluation does not commit breaks)."""
+
+    def __init__(self, o, prob, shape_of_particle, modes, s0, tau_c, gate_frac,
+                 params=None, sig_q=None, sig_r=None):
+        from .oracle import T_PD, T_SELF, T_NBR, T_WALL  # noqa: F401
+        self.o, self.prob = o, prob
+        self.sp = np.asarray(shape_of_particle)
+        self.modes = modes            # shape -> (Phi [2n, K], lam [K], sig [K])
+        self.s0, self.tau_c, self.gate = s0, tau_c, gate_frac
+        self.params, self.sig_q, self.sig_r = params, sig_q, sig_r
+        self.templates = {}
+        for s in sorted(set(self.sp[self.sp >= 0].tolist())):
+            pt = int(np.nonzero(self.sp == s)[0][0])
+            self.templates[s] = reference_frame(prob, pt)[1]
+        self.active = self.sp >= 0
+        rho = np.array([prob.materials[int(m)].rho for m in prob.particle_material])
+        self.rho_node = np.repeat(rho, np.diff(prob.particle_offset))
+
+    def _g(self, s, q):
+        Phi, lam, _ = self.modes[s]
+        if self.params is None:
+            return closure_modal_force(q, lam)[0]
+        return closure_modal_force(q, lam, self.params[s], self.sig_q[s], self.sig_r[s])[0]
+
+    def step(self):
+        from .oracle import T_PD, T_SELF, T_NBR, T_WALL
+        o, prob = self.o, self.prob
+        st = o.get_state()
+        dt = prob.dt
+        ux = (st["ux"] + dt * st["vx"]) + (0.5 * dt * dt) * st["ax"]
+        uy = (st["uy"] + dt * st["vy"]) + (0.5 * dt * dt) * st["ay"]
+        tmp = dict(st, ux=ux, uy=uy, step=st["step"] + 1)
+        o.set_state(tmp)
+        fpx, fpy = o.forces(T_PD)
+        fcx, fcy = o.forces(T_SELF | T_NBR | T_WALL)
+        gx, gy = prob.gravity
+        ax = (fpx + fcx) / self.rho_node + gx
+        ay = (fpy + fcy) / self.rho_node + gy
+        gate_off = []
+        for p in np.nonzero(self.active)[0]:
+            s = int(self.sp[p])
+            n0, n1 = particle_range(prob, p)
+            m = node_masses(prob, p)
+            V = prob.vol[n0:n1]
+            Phi, lam, sig = self.modes[s]
+            y = np.stack([prob.x[n0:n1] + ux[n0:n1], prob.y[n0:n1] + uy[n0:n1]], axis=1)
+            v = np.stack([st["vx"][n0:n1], st["vy"][n0:n1]], axis=1)
+            F = np.stack([fcx[n0:n1] * V, fcy[n0:n1] * V], axis=1)
+            pr = project(self.templates[s], m, Phi, y, v, F)
+            qdd = self._g(s, pr["q"]) + pr["gext"]
+            a = closure_accel(pr, Phi, qdd, (gx, gy))
+            ax[n0:n1], ay[n0:n1] = a[:, 0], a[:, 1]
+            strain = float((np.abs(pr["q"]) * sig).sum())
+            load = float(np.sqrt((F ** 2).sum(1)).sum())
+            if strain > self.gate * self.s0[s] or load > self.tau_c[s]:
+                gate_off.append(p)
+        vx = st["vx"] + (0.5 * dt) * (st["ax"] + ax)
+        vy = st["vy"] + (0.5 * dt) * (st["ay"] + ay)
+        o.set_state(dict(st, ux=ux, uy=uy, vx=vx, vy=vy, ax=ax, ay=ay, step=st["step"] + 1))
+        for p in gate_off:
+            self.active[p] = False
+        return gate_off
+
+    def check(self, err_tol):
+        """The periodic check at the current state: modal PD force vs the
+        closure's, per active particle; returns (sum |g - g_pd|^2,
+        sum |g_pd|^2, sum |-lambda q - g_pd|^2, particles that fall back)."""
+        from .oracle import T_PD
+        o, prob = self.o, self.prob
+        st = o.get_state()
+        fpx, fpy = o.forces(T_PD)
+        e2 = n2 = l2 = 0.0
+        out = []
+        for p in np.nonzero(self.active)[0]:
+            s = int(self.sp[p])
+            n0, n1 = particle_range(prob, p)
+            m = node_masses(prob, p)
+            V = prob.vol[n0:n1]
+            Phi, lam, sig = self.modes[s]
+            y = np.stack([prob.x[n0:n1] + st["ux"][n0:n1], prob.y[n0:n1] + st["uy"][n0:n1]], axis=1)
+            z = np.zeros_like(y)
+            F = np.stack([fpx[n0:n1] * V, fpy[n0:n1] * V], axis=1)
+            pr = project(self.templates[s], m, Phi, y, z, F)
+            g_pd = pr["gext"]
+            gh = self._g(s, pr["q"])
+            lq = -lam * pr["q"]
+            de, dn, dl = ((gh - g_pd) ** 2).sum(), (g_pd ** 2).sum(), ((lq - g_pd) ** 2).sum()
+            e2, n2, l2 = e2 + de, n2 + dn, l2 + dl
+            smax = max_stretch(prob, p, st)
+            if smax > self.gate * self.s0[s] or np.sqrt(de) > err_tol * max(np.sqrt(dn), np.linalg.norm(lq)):
+                out.append(p)
+        for p in out:
+            self.active[p] = False
+        return e2, n2, l2, out
+
+
+def max_stretch(prob, p, st, row=None, col=None, _cache={}):
+    """Largest |stretch| over the particle's intact bonds at state st
+    (eq. (peri): s = (|xi + eta| - |xi|) / |xi|), for the check."""
+    key = id(prob)
+    if key not in _cache:
+        from .oracle import Oracle
+        oo = Oracle(prob, contact_mode=1)
+        _cache[key] = oo.bonds()
+    row, col = _cache[key]
+    n0, n1 = particle_range(prob, p)
+    x, y = prob.x, prob.y
+    brk = st.get("broken")
+    best = 0.0
+    for i in range(n0, n1):
+        for k in range(row[i], row[i + 1]):
+            if brk is not None and brk[k]:
+                continue
+            j = int(col[k])
+            X, Y = x[j] - x[i], y[j] - y[i]
+            L = np.hypot(X, Y)
+            l = np.hypot(X + st["ux"][j] - st["ux"][i], Y + st["uy"][j] - st["uy"][i])
+            best = max(best, abs(l - L) / L)
+    return best

@@ -19,15 +19,21 @@ HIP_FLAGS = [
 ]
 
 
+SOURCES = ("pd_kernels.hip", "pd_closure.hip", "pd_host.cpp", "pd_eig.cpp")
+
+
 def build(verbose: bool = False) -> str:
-    objs = []
-    for src in ("pd_kernels.hip", "pd_host.cpp"):
+    objs, procs = [], []
+    for src in SOURCES:
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         cmd = ["hipcc", *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    for pr, cmd in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -1,0 +1,735 @@
+// pd_closure.hip -- kernels of the learned modal closure.
+//
+//   k_cl_project  one workgroup per closure particle: mass centroid, best-fit
+//                 rotation (weighted 2-D Procrustes about the centroid),
+//                 polar moment, angular velocity, total external force and
+//                 torque, modal amplitudes q = Phi^T M u_body and the modal
+//                 external force Phi^T f_body, and the gate quantities
+//   k_mlp_fwd     the 32 -> 256 -> 256 -> 32 SiLU MLP on 16-row blocks, one
+//                 wavefront per block, bfloat16 operands and float32
+//                 accumulation on the matrix cores (v_mfma 16x16x16 bf16),
+//                 hidden activations in LDS
+//   k_cl_apply    one workgroup per closure particle: nodal acceleration of
+//                 the rigid + modal motion, velocity-Verlet velocity update,
+//                 and the per-step gate
+//   k_gemm        strided bf16 GEMM on the matrix cores (training backward)
+//   k_mlp_loss, k_colsum, k_adam, k_mlp_init, k_batch_idx, k_norm_stats:
+//                 the rest of a training iteration
+//
+// The paper has no reduced-order model; the closure replaces the bond force
+// of eq. (peri) for particles far from the break threshold of Sec. 3.1 and
+// under light contact, and the plain bond force stays the fallback and the
+// periodic check.
+#include <math.h>
+
+#include "pd_internal.h"
+
+namespace pd {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float dsilu_f(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// four consecutive bfloat16 values as one MFMA operand
+__device__ __forceinline__ bf16x4 load4(const uint16_t *p) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    bf16x4 r;
+    r[0] = (short)(v.x & 0xffffu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffffu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// sums of NV doubles over a 256-thread workgroup, in a fixed order (wave
+// butterflies, then the four waves in order); every thread gets the sums
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[w * NV + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = ((sh[k] + sh[NV + k]) + sh[2 * NV + k]) + sh[3 * NV + k];
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// list mode: a launch past the first stale step of a replay does nothing (the
+// same rule as the force kernel)
+__device__ __forceinline__ bool replay_stale(const DevArgs &a, bool list) {
+    if (!list) return false;
+    const long long sprev = *a.step_base + a.chunk_k;
+    return (unsigned long long)(sprev + 1) >= *a.invalid_step;
+}
+
+// ---------------------------------------------------------------------------
+// projection on the rigid + modal coordinates
+//
+// mode 0 (step):  positions x + u_o (the advanced displacement the force
+//                 kernel wrote), velocities v (previous step), forces cl_fx/fy
+// mode 1 (check): positions x + u (current state), forces terms[PD] * V, for
+//                 active particles; gext then holds the modal PD force
+// mode 2 (snapshot): as 1, for every closure particle
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int list, int mode) {
+    extern __shared__ double shm[];
+    if (replay_stale(a, list && mode == 0)) return;
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    if (mode < 2 && !a.cl_on[p]) return;
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int t0 = c.toff[s];
+    double *red = shm;               // [4 * 8] reduction scratch
+    double *sub = shm + 32;          // [8][32][2] partial modal sums
+    double *UB = shm + 32 + 512;     // [n] body-frame displacement x, y, force x, y
+    const double *ux = mode == 0 ? a.ux_o : a.ux;
+    const double *uy = mode == 0 ? a.uy_o : a.uy;
+    const int tid = threadIdx.x;
+
+    double v7[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int k = tid; k < n; k += 256) {
+        const int i = n0 + k;
+        const double m = a.mass[i];
+        const double yx = a.x[i] + ux[i], yy = a.y[i] + uy[i];
+        double fx, fy;
+        if (mode == 0) {
+            fx = a.cl_fx[i];
+            fy = a.cl_fy[i];
+        } else {
+            fx = a.terms[i] * a.vol[i];
+            fy = a.terms[a.N + i] * a.vol[i];
+        }
+        v7[0] += m;
+        v7[1] += m * yx;
+        v7[2] += m * yy;
+        v7[3] += m * a.vx[i];
+        v7[4] += m * a.vy[i];
+        v7[5] += fx;
+        v7[6] += fy;
+    }
+    block_sum<7>(v7, red);
+    const double M = v7[0];
+    const double cx = v7[1] / M, cy = v7[2] / M;
+    const double vcx = v7[3] / M, vcy = v7[4] / M;
+
+    double v6[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = tid; k < n; k += 256) {
+        const int i = n0 + k;
+        const double m = a.mass[i];
+        const double Yx = (a.x[i] + ux[i]) - cx, Yy = (a.y[i] + uy[i]) - cy;
+        const double Xx = c.tX[t0 + k], Xy = c.tY[t0 + k];
+        double fx, fy;
+        if (mode == 0) {
+            fx = a.cl_fx[i];
+            fy = a.cl_fy[i];
+        } else {
+            fx = a.terms[i] * a.vol[i];
+            fy = a.terms[a.N + i] * a.vol[i];
+        }
+        const double dvx = a.vx[i] - vcx, dvy = a.vy[i] - vcy;
+        v6[0] += m * (Xx * Yy - Xy * Yx);
+        v6[1] += m * (Xx * Yx + Xy * Yy);
+        v6[2] += m * (Yx * Yx + Yy * Yy);
+        v6[3] += m * (Yx * dvy - Yy * dvx);
+        v6[4] += Yx * fy - Yy * fx;
+        v6[5] += sqrt(fx * fx + fy * fy);
+    }
+    block_sum<6>(v6, red);
+    const double phi = atan2(v6[0], v6[1]);
+    const double cp = cos(phi), sp = sin(phi);
+    const double I = v6[2];
+    // body-frame displacement and force, staged for the modal sums
+    for (int k = tid; k < n; k += 256) {
+        const int i = n0 + k;
+        const double Yx = (a.x[i] + ux[i]) - cx, Yy = (a.y[i] + uy[i]) - cy;
+        double fx, fy;
+        if (mode == 0) {
+            fx = a.cl_fx[i];
+            fy = a.cl_fy[i];
+        } else {
+            fx = a.terms[i] * a.vol[i];
+            fy = a.terms[a.N + i] * a.vol[i];
+        }
+        const double m = a.mass[i];
+        UB[4 * k + 0] = m * ((cp * Yx + sp * Yy) - c.tX[t0 + k]);
+        UB[4 * k + 1] = m * ((-sp * Yx + cp * Yy) - c.tY[t0 + k]);
+        UB[4 * k + 2] = cp * fx + sp * fy;
+        UB[4 * k + 3] = -sp * fx + cp * fy;
+    }
+    __syncthreads();
+    // modal sums: thread (g, k) takes nodes g, g + 8, ... of mode k
+    {
+        const int k = tid & 31, g = tid >> 5;
+        double sq = 0.0, sf = 0.0;
+        const float2 *ph = reinterpret_cast<const float2 *>(c.phi) + (size_t)t0 * kClModes + k;
+        for (int j = g; j < n; j += 8) {
+            const float2 f = ph[(size_t)j * kClModes];
+            sq += (double)f.x * UB[4 * j] + (double)f.y * UB[4 * j + 1];
+            sf += (double)f.x * UB[4 * j + 2] + (double)f.y * UB[4 * j + 3];
+        }
+        sub[(g * 32 + k) * 2] = sq;
+        sub[(g * 32 + k) * 2 + 1] = sf;
+    }
+    __syncthreads();
+    if (tid < 32) {
+        double sq = 0.0, sf = 0.0;
+        for (int g = 0; g < 8; ++g) {
+            sq += sub[(g * 32 + tid) * 2];
+            sf += sub[(g * 32 + tid) * 2 + 1];
+        }
+        c.q[ci * kClModes + tid] = sq;
+        c.gext[ci * kClModes + tid] = sf;
+        // first-order bound of the largest bond stretch, sum_k |q_k| sigma_k
+        double b = fabs(sq) * c.sig[s * kClModes + tid];
+        for (int o = 16; o > 0; o >>= 1) b += __shfl_xor(b, o, 32);
+        if (tid == 0) {
+            double *R = c.red + (size_t)ci * 16;
+            R[R_M] = M;
+            R[R_CX] = cx;
+            R[R_CY] = cy;
+            R[R_VCX] = vcx;
+            R[R_VCY] = vcy;
+            R[R_PHI] = phi;
+            R[R_I] = I;
+            R[R_OM] = v6[3] / I;
+            R[R_FX] = v7[5];
+            R[R_FY] = v7[6];
+            R[R_TAU] = v6[4];
+            R[R_STRAIN] = b;
+            R[R_CONTACT] = v6[5];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nodal accelerations of the rigid + modal motion, velocity update, gate
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list) {
+    __shared__ double qdd[kClModes];
+    __shared__ double R[16];
+    if (replay_stale(a, list)) return;
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    if (!a.cl_on[p]) return;
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int t0 = c.toff[s];
+    const int tid = threadIdx.x;
+    if (tid < kClModes) {
+        const double q = c.q[ci * kClModes + tid];
+        const double g = c.learned ? c.ghat[ci * kClModes + tid] : -c.lam[s * kClModes + tid] * q;
+        qdd[tid] = g + c.gext[ci * kClModes + tid];
+    }
+    if (tid < 16) R[tid] = c.red[(size_t)ci * 16 + tid];
+    __syncthreads();
+    const double M = R[R_M], cx = R[R_CX], cy = R[R_CY];
+    const double cp = cos(R[R_PHI]), sp = sin(R[R_PHI]);
+    const double alpha = R[R_TAU] / R[R_I], om2 = R[R_OM] * R[R_OM];
+    const double atx = R[R_FX] / M + a.gx, aty = R[R_FY] / M + a.gy;
+    int st = 0;
+    bool stale = false;
+    for (int k = tid; k < n; k += 256) {
+        const int i = n0 + k;
+        const double ux = a.ux_o[i], uy = a.uy_o[i];
+        const double Yx = (a.x[i] + ux) - cx, Yy = (a.y[i] + uy) - cy;
+        // modal acceleration in the body frame, sum_k Phi_ik qdd_k
+        const float4 *ph = reinterpret_cast<const float4 *>(c.phi + (size_t)(t0 + k) * 2 * kClModes);
+        double bx = 0.0, by = 0.0;
+#pragma unroll 4
+        for (int m2 = 0; m2 < kClModes / 2; ++m2) {
+            const float4 f = ph[m2];
+            bx += (double)f.x * qdd[2 * m2] + (double)f.z * qdd[2 * m2 + 1];
+            by += (double)f.y * qdd[2 * m2] + (double)f.w * qdd[2 * m2 + 1];
+        }
+        const double axn = ((atx - alpha * Yy) - om2 * Yx) + (cp * bx - sp * by);
+        const double ayn = ((aty + alpha * Yx) - om2 * Yy) + (sp * bx + cp * by);
+        const double vxn = a.vx[i] + a.hdt * (a.ax[i] + axn);
+        const double vyn = a.vy[i] + a.hdt * (a.ay[i] + ayn);
+        a.ax_o[i] = axn;
+        a.ay_o[i] = ayn;
+        a.vx_o[i] = vxn;
+        a.vy_o[i] = vyn;
+        if (!(isfinite(vxn) && isfinite(vyn))) st |= kStNonfinite;
+        if (list) {
+            const double unx = (ux + a.dt * vxn) + a.hdt2 * axn;
+            const double uny = (uy + a.dt * vyn) + a.hdt2 * ayn;
+            const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
+            if (!(ex * ex + ey * ey <= a.move2)) stale = true;
+        }
+    }
+    if (st) atomicOr(a.status, st);
+    if (stale) {
+        const long long sprev = *a.step_base + a.chunk_k;
+        atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+    }
+    __syncthreads();
+    // gate for the next step: a particle whose bound on the bond stretch passes
+    // gate_frac * s0, or whose contact load passes tau_c, goes back to the
+    // plain bond force
+    if (tid == 0 &&
+        (R[R_STRAIN] > c.gate_frac * c.s0[s] || R[R_CONTACT] > c.tau_c[s])) {
+        a.cl_on[p] = 0;
+        atomicAdd(c.fallbacks, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// periodic check against the plain bond force: per particle, the modal force
+// of the closure vs the modal PD force (in c.gext after a mode-1 projection),
+// and the largest true bond stretch (smax per node, from the force kernel)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_check_part(DevArgs a, ClArgs c, double err_tol,
+                                                       double *per) {
+    __shared__ double sh[4];
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    double *out = per + (size_t)ci * 4;
+    if (!a.cl_on[p]) {
+        if (threadIdx.x == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) mx = fmax(mx, a.smax[n0 + k]);
+    mx = block_max(mx, sh);
+    if (threadIdx.x >= 64) return;
+    const int k = threadIdx.x;
+    double e2 = 0, n2 = 0, l2 = 0, q2 = 0;
+    if (k < kClModes) {
+        const double q = c.q[ci * kClModes + k];
+        const double lq = -c.lam[s * kClModes + k] * q;
+        const double gh = c.learned ? c.ghat[ci * kClModes + k] : lq;
+        const double g = c.gext[ci * kClModes + k];
+        e2 = (gh - g) * (gh - g);
+        n2 = g * g;
+        l2 = (lq - g) * (lq - g);
+        q2 = lq * lq;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        e2 += __shfl_xor(e2, o, 64);
+        n2 += __shfl_xor(n2, o, 64);
+        l2 += __shfl_xor(l2, o, 64);
+        q2 += __shfl_xor(q2, o, 64);
+    }
+    if (k == 0) {
+        out[0] = e2;
+        out[1] = n2;
+        out[2] = l2;
+        out[3] = 1.0;
+        const double scale = fmax(sqrt(n2), sqrt(q2));
+        if (mx > c.gate_frac * c.s0[s] || sqrt(e2) > err_tol * scale) {
+            a.cl_on[p] = 0;
+            atomicAdd(c.fallbacks, 1ull);
+        }
+    }
+}
+
+// fixed-order sums of the per-particle check results: stats = [sum e2,
+// sum n2, sum l2, checked particles]
+__global__ __launch_bounds__(256) void k_cl_check_sum(const double *per, int Pc, double *stats) {
+    __shared__ double sh[16];
+    double v[4] = {0, 0, 0, 0};
+    for (int ci = threadIdx.x; ci < Pc; ci += 256)
+        for (int k = 0; k < 4; ++k) v[k] += per[(size_t)ci * 4 + k];
+    block_sum<4>(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) stats[k] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+// the MLP forward: one wavefront per 16-row block.  MFMA operand layout
+// (v_mfma_f32_16x16x16 bf16): lane l holds A[l % 16][4 (l / 16) + t] and
+// B[4 (l / 16) + t][l % 16], t = 0..3, and receives D[4 (l / 16) + t][l % 16].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs m, DevArgs a, int list) {
+    __shared__ uint16_t H1s[4][16 * kClHidden];
+    __shared__ uint16_t H2s[4][16 * kClHidden];
+    if (list && replay_stale(a, true)) return;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int rb = blockIdx.x * 4 + wv;
+    int s = m.shape, first = 16 * rb, cnt = 0;
+    if (rb < m.row_blocks) {
+        if (m.rb_shape) {
+            s = m.rb_shape[rb];
+            first = m.rb_first[rb];
+            cnt = m.rb_count[rb];
+        } else {
+            cnt = min(16, m.rows - first);
+        }
+    }
+    const uint16_t *W = m.wb + (size_t)s * kClParams;
+    const float *Wf = m.wf + (size_t)s * kClParams;
+    uint16_t *H1 = H1s[wv], *H2 = H2s[wv];
+    const int r = l & 15, kq = 4 * (l >> 4);
+    // row r of this lane's A operand
+    const bool rvalid = r < cnt && (!m.on || m.on[m.cpart[first + r]]);
+    const int src = rvalid ? (m.idx ? m.idx[first + r] : first + r) : 0;
+
+    // ---- layer 1: x (16 x 32) W1^T -----------------------------------------
+    bf16x4 ax[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = 16 * ks + kq + t;
+            float xv = 0.0f;
+            if (rvalid) xv = (float)(m.q[(size_t)src * kClModes + col] / (double)m.sig_q[s * kClModes + col]);
+            const uint16_t b = f2bf(xv);
+            ax[ks][t] = (short)b;
+            if (m.xb && rvalid) m.xb[(size_t)(first + r) * kClModes + col] = b;
+        }
+    }
+    for (int j = 0; j < kClHidden / 16; ++j) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int n = 16 * j + r;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x4 b = load4(W + kOffW1 + n * kClModes + 16 * ks + kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax[ks], b, acc, 0, 0, 0);
+        }
+        const float bias = Wf[kOffB1 + n];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = kq + t;
+            const float z = acc[t] + bias;
+            const uint16_t h = f2bf(silu_f(z));
+            H1[row * kClHidden + n] = h;
+            if (m.z1 && row < cnt) {
+                m.z1[(size_t)(first + row) * kClHidden + n] = z;
+                m.h1[(size_t)(first + row) * kClHidden + n] = h;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- layer 2: h1 (16 x 256) W2^T ------------------------------------------
+    {
+        bf16x4 ah[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H1 + r * kClHidden + 16 * ks + kq);
+        for (int j = 0; j < kClHidden / 16; ++j) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int n = 16 * j + r;
+            const uint16_t *wr = W + kOffW2 + (size_t)n * kClHidden + kq;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], load4(wr + 16 * ks), acc, 0, 0, 0);
+            const float bias = Wf[kOffB2 + n];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = kq + t;
+                const float z = acc[t] + bias;
+                const uint16_t h = f2bf(silu_f(z));
+                H2[row * kClHidden + n] = h;
+                if (m.z2 && row < cnt) {
+                    m.z2[(size_t)(first + row) * kClHidden + n] = z;
+                    m.h2[(size_t)(first + row) * kClHidden + n] = h;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- layer 3: h2 (16 x 256) W3^T ------------------------------------------
+    {
+        bf16x4 ah[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
+        for (int j = 0; j < kClModes / 16; ++j) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int n = 16 * j + r;
+            const uint16_t *wr = W + kOffW3 + (size_t)n * kClHidden + kq;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], load4(wr + 16 * ks), acc, 0, 0, 0);
+            const float bias = Wf[kOffB3 + n];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = kq + t;
+                if (row >= cnt) continue;
+                if (m.on && !m.on[m.cpart[first + row]]) continue;
+                const float y = acc[t] + bias;
+                if (m.y) m.y[(size_t)(first + row) * kClModes + n] = y;
+                if (m.g) {
+                    const int sr = m.idx ? m.idx[first + row] : first + row;
+                    const double q = m.q[(size_t)sr * kClModes + n];
+                    m.g[(size_t)(first + row) * kClModes + n] =
+                        -m.lam[s * kClModes + n] * q + (double)m.sig_r[s * kClModes + n] * (double)y;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+// C[M x N] = sum_k A[m][k] B[k][n], bfloat16 operands at arbitrary strides,
+// float32 accumulation; one 16 x 16 tile per wavefront.
+//   epi 0: C = acc
+//   epi 1: C = acc * silu'(Z), and its bfloat16 copy in Cb (back-propagation
+//          through a SiLU layer)
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t *A, long sam,
+                                              long sak, const uint16_t *B, long sbk, long sbn,
+                                              float *C, long ldc, int epi, const float *Z,
+                                              uint16_t *Cb) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int tn = (N + 15) / 16, tm = (M + 15) / 16;
+    const int tile = blockIdx.x * 4 + wv;
+    if (tile >= tn * tm) return;
+    const int m0 = 16 * (tile / tn), n0 = 16 * (tile % tn);
+    const int r = l & 15, kq = 4 * (l >> 4);
+    const int am = m0 + r, bn = n0 + r;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 av, bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + kq + t;
+            av[t] = (short)((am < M && k < K) ? A[(long)am * sam + (long)k * sak] : 0);
+            bv[t] = (short)((bn < N && k < K) ? B[(long)k * sbk + (long)bn * sbn] : 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int mm = m0 + kq + t, nn = n0 + r;
+        if (mm >= M || nn >= N) continue;
+        float v = acc[t];
+        if (epi == 1) {
+            v *= dsilu_f(Z[(long)mm * ldc + nn]);
+            Cb[(long)mm * ldc + nn] = f2bf(v);
+        }
+        C[(long)mm * ldc + nn] = v;
+    }
+}
+
+// dy = 2 (y - r / sigma_r) / (rows * 32), r = g + lambda q of the batch's
+// samples, and the mean squared error (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_mlp_loss(MlpArgs m, const double *g, float *dy,
+                                                  uint16_t *dyb, float *loss) {
+    __shared__ double sh[4];
+    const int s = m.shape;
+    const int total = m.rows * kClModes;
+    const float scale = 2.0f / (float)total;
+    double acc[1] = {0.0};
+    for (int e = threadIdx.x; e < total; e += 256) {
+        const int b = e / kClModes, k = e % kClModes;
+        const int src = m.idx ? m.idx[b] : b;
+        const double q = m.q[(size_t)src * kClModes + k];
+        const double rr = g[(size_t)src * kClModes + k] + m.lam[s * kClModes + k] * q;
+        const float t = (float)(rr / (double)m.sig_r[s * kClModes + k]);
+        const float d = m.y[e] - t;
+        const float v = scale * d;
+        dy[e] = v;
+        dyb[e] = f2bf(v);
+        acc[0] += (double)d * (double)d;
+    }
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) *loss = (float)(acc[0] / total);
+}
+
+// column sums of X [rows][cols] (bias gradients), one thread per column
+__global__ void k_colsum(const float *X, int rows, int cols, float *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.0f;
+    for (int b = 0; b < rows; ++b) s += X[(size_t)b * cols + j];
+    out[j] = s;
+}
+
+__global__ void k_adam(float *w, uint16_t *wb, const float *g, float *mo, float *ve, int n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * mo[i] + (1.0f - b1) * gi;
+    const float vi = b2 * ve[i] + (1.0f - b2) * gi * gi;
+    mo[i] = mi;
+    ve[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+// counter-based uniform in [0, 1): splitmix64 of (seed, index)
+__device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (i + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// W1, W2 uniform with variance 2 / (fan_in + fan_out); W3 and the biases
+// zero, so the untrained closure is the linear one
+__global__ void k_mlp_init(float *w, uint16_t *wb, uint64_t seed) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kClParams) return;
+    float v = 0.0f;
+    if (i < kOffB1) {
+        const double a = sqrt(6.0 / (kClModes + kClHidden));
+        v = (float)(a * (2.0 * hash_u01(seed, (uint64_t)i) - 1.0));
+    } else if (i >= kOffW2 && i < kOffB2) {
+        const double a = sqrt(6.0 / (kClHidden + kClHidden));
+        v = (float)(a * (2.0 * hash_u01(seed, (uint64_t)i) - 1.0));
+    }
+    w[i] = v;
+    wb[i] = f2bf(v);
+}
+
+__global__ void k_batch_idx(int *idx, int rows, int64_t n, uint64_t seed, int64_t it) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= rows) return;
+    const double u = hash_u01(seed ^ (0x5851f42d4c957f2dull * (uint64_t)(it + 1)), (uint64_t)b);
+    int64_t k = (int64_t)(u * (double)n);
+    idx[b] = (int)(k < n ? k : n - 1);
+}
+
+// sigma_q[k] = rms of q[:, k], sigma_r[k] = rms of (g + lambda q)[:, k]; 1 where zero
+__global__ __launch_bounds__(256) void k_norm_stats(const double *q, const double *g,
+                                                    const double *lam, int64_t n, float *sig_q,
+                                                    float *sig_r) {
+    __shared__ double sh[8];
+    const int k = blockIdx.x;
+    double v[2] = {0.0, 0.0};
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double qq = q[j * kClModes + k];
+        const double rr = g[j * kClModes + k] + lam[k] * qq;
+        v[0] += qq * qq;
+        v[1] += rr * rr;
+    }
+    block_sum<2>(v, sh);
+    if (threadIdx.x == 0) {
+        const double a = sqrt(v[0] / (double)n), b = sqrt(v[1] / (double)n);
+        sig_q[k] = a > 0.0 ? (float)a : 1.0f;
+        sig_r[k] = b > 0.0 ? (float)b : 1.0f;
+    }
+}
+
+__global__ void k_f32_to_bf16(const float *x, uint16_t *y, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static size_t project_lds(const ClArgs &c, int max_n) {
+    (void)c;
+    return (size_t)(32 + 512 + 4 * max_n) * sizeof(double);
+}
+
+hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int mode, int max_n,
+                             hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    // the buffers each mode reads
+    if (mode == 0 ? !(a.cl_on && a.cl_fx && a.cl_fy) : !a.terms) return hipErrorInvalidValue;
+    if (mode == 1 && !a.cl_on) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cl_project, dim3(c.Pc), dim3(256), project_lds(c, max_n), s, a, c,
+                       list ? 1 : 0, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!a.cl_on) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cl_apply, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,
+                           double *stats, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!a.cl_on || !a.smax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cl_check_part, dim3(c.Pc), dim3(256), 0, s, a, c, err_tol, per);
+    hipLaunchKernelGGL(k_cl_check_sum, dim3(1), dim3(256), 0, s, per, c.Pc, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s) {
+    if (m.row_blocks <= 0) return hipSuccess;
+    if (m.on && !m.cpart) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((m.row_blocks + 3) / 4), dim3(256), 0, s, m, a,
+                       list ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16(int M, int N, int K, const uint16_t *A, long sam, long sak,
+                            const uint16_t *B, long sbk, long sbn, float *C, long ldc, int epi,
+                            const float *Z, uint16_t *Cb, hipStream_t s) {
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    hipLaunchKernelGGL(k_gemm, dim3((tiles + 3) / 4), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk,
+                       sbn, C, ldc, epi, Z, Cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss(const MlpArgs &m, const double *g, float *dy, uint16_t *dyb, float *loss,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, m, g, dy, dyb, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *X, int rows, int cols, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256), dim3(256), 0, s, X, rows, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, uint16_t *wb, const float *g, float *m, float *v, int n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, wb, g, m, v, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(float *w, uint16_t *wb, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_init, dim3((kClParams + 255) / 256), dim3(256), 0, s, w, wb, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_idx(int *idx, int rows, int64_t n, uint64_t seed, int64_t it, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_idx, dim3((rows + 255) / 256), dim3(256), 0, s, idx, rows, n, seed, it);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_stats(const double *q, const double *g, const double *lam, int64_t n,
+                             float *sig_q, float *sig_r, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_stats, dim3(kClModes), dim3(256), 0, s, q, g, lam, n, sig_q, sig_r);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace pd

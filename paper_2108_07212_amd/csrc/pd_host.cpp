@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -297,6 +298,8 @@ pd_status build_grid(Ctx &c, const double *box) {
 }
 
 void invalidate_graph(Ctx &c) {
+    for (auto &kv : c.lgraph_n) hipGraphExecDestroy(kv.second);
+    c.lgraph_n.clear();
     for (int k = 0; k < 2; ++k) {
         if (c.graph[k]) {
             hipGraphExecDestroy(c.graph[k]);
@@ -310,34 +313,64 @@ void invalidate_graph(Ctx &c) {
     c.graph_valid = false;
 }
 
-// list-mode replay: kChunk steps from buffer parity `start`
+// the closure's kernels after the force kernel of one step: projection of
+// the closure particles, the MLP (learned closure), nodal accelerations
+hipError_t enqueue_closure(Ctx &c, bool list) {
+    if (c.cl.mode == 0) return hipSuccess;
+    hipError_t e = launch_cl_project(c.a, c.cl.ca, list, 0, c.cl.max_n, c.stream);
+    if (e != hipSuccess) return e;
+    if (c.cl.mode == 2) {
+        e = launch_mlp_forward(c.cl.ma, c.a, list, c.stream);
+        if (e != hipSuccess) return e;
+    }
+    return launch_cl_apply(c.a, c.cl.ca, list, c.stream);
+}
+
+// list-mode replay: n steps from buffer parity `start`
 hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
     for (int k = 0; k < n; ++k) {
         set_state_ptrs(c, (start + k) & 1);
         c.a.chunk_k = k;
         hipError_t e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
         if (e != hipSuccess) return e;
+        e = enqueue_closure(c, true);
+        if (e != hipSuccess) return e;
     }
     c.a.chunk_k = 0;
     return hipSuccess;
 }
 
-pd_status ensure_list_graph(Ctx &c) {
-    if (c.lgraph[0] && c.lgraph[1]) return PD_OK;
-    for (int start = 0; start < 2; ++start) {
-        if (c.lgraph[start]) continue;
-        hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
-        hipError_t e1 = enqueue_list_steps(c, start, kChunk);
-        hipError_t e2 = hipStreamEndCapture(c.stream, &g);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-            if (g) hipGraphDestroy(g);
-            return fail(c, PD_E_DEVICE, "graph capture failed");
-        }
-        hipError_t e3 = hipGraphInstantiate(&c.lgraph[start], g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e3 != hipSuccess) return fail(c, PD_E_DEVICE, "graph instantiate failed");
+pd_status capture_list_graph(Ctx &c, int start, int n, hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+    hipError_t e1 = enqueue_list_steps(c, start, n);
+    hipError_t e2 = hipStreamEndCapture(c.stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(c, PD_E_DEVICE, "graph capture failed");
     }
+    hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(c, PD_E_DEVICE, "graph instantiate failed");
+    return PD_OK;
+}
+
+pd_status ensure_list_graph(Ctx &c) {
+    for (int start = 0; start < 2; ++start)
+        if (!c.lgraph[start]) TRY(capture_list_graph(c, start, kChunk, &c.lgraph[start]));
+    return PD_OK;
+}
+
+// a replay of n < kChunk steps (between periodic closure checks), captured once
+pd_status list_graph_n(Ctx &c, int start, int n, hipGraphExec_t *out) {
+    const long key = (long)start * 1000000L + n;
+    auto it = c.lgraph_n.find(key);
+    if (it == c.lgraph_n.end()) {
+        hipGraphExec_t g = nullptr;
+        TRY(capture_list_graph(c, start, n, &g));
+        it = c.lgraph_n.emplace(key, g).first;
+    }
+    *out = it->second;
     return PD_OK;
 }
 
@@ -434,17 +467,32 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
 // list-mode steps: replays of up to kChunk steps; a replay stops early when a
 // list goes stale (a node moved half the skin, or a bond broke), then the
 // lists are rebuilt and the remaining steps run
+pd_status closure_check(Ctx &c);
+
 pd_status step_lists(Ctx &c, int64_t n) {
     int64_t left = n;
     while (left > 0) {
+        // the closure's periodic check against the plain bond force
+        if (c.cl.mode && c.cl.check_every > 0 && c.step % c.cl.check_every == 0 &&
+            c.step != c.cl.last_check_step) {
+            TRY(closure_check(c));
+            c.cl.last_check_step = c.step;
+        }
         if (!c.list_valid) TRY(rebuild_lists(c));
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
                               c.stream));
-        const int chunk = (int)std::min<int64_t>(left, kChunk);
+        int64_t lim = std::min<int64_t>(left, kChunk);
+        if (c.cl.mode && c.cl.check_every > 0)
+            lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
+        const int chunk = (int)lim;
         if (c.tune.use_graph && chunk == kChunk) {
             TRY(ensure_list_graph(c));
             HIPCHK(hipGraphLaunch(c.lgraph[c.cur], c.stream));
+        } else if (c.tune.use_graph && c.cl.mode) {
+            hipGraphExec_t g = nullptr;
+            TRY(list_graph_n(c, c.cur, chunk, &g));
+            HIPCHK(hipGraphLaunch(g, c.stream));
         } else {
             HIPCHK(enqueue_list_steps(c, c.cur, chunk));
         }
@@ -466,6 +514,458 @@ pd_status step_lists(Ctx &c, int64_t n) {
     }
     set_state_ptrs(c, c.cur);
     TRY(set_device_step(c));
+    return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// modal closure (host side)
+// ---------------------------------------------------------------------------
+void dfree(Ctx &c, void *p) {
+    if (!p) return;
+    hipFree(p);
+    c.owned.erase(std::remove(c.owned.begin(), c.owned.end(), p), c.owned.end());
+}
+
+// Young's modulus behind a micromodulus (Table tab:2d-peri, nu = 1/3)
+double young_of(const MatConst &m) {
+    const double e3 = m.eps * m.eps * m.eps;
+    return m.conic ? m.cw * kPi * e3 * (2.0 / 3.0) / 24.0 : m.cw * kPi * e3 * (2.0 / 3.0) / 6.0;
+}
+
+// the reference bonds (both directions) of the particle p, local indices
+pd_status particle_bonds(Ctx &c, int p, std::vector<std::pair<int, int>> &out) {
+    const int n0 = c.h_poff[p], n1 = c.h_poff[p + 1];
+    const int sl0 = n0 / kSlice, sl1 = (n1 - 1) / kSlice + 1;
+    const uint32_t w0 = c.h_slice_ptr[sl0], w1 = c.h_slice_ptr[sl1];
+    std::vector<uint32_t> col(w1 - w0);
+    HIPCHK(hipMemcpyAsync(col.data(), c.a.col + w0, (w1 - w0) * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    out.clear();
+    for (int i = n0; i < n1; ++i) {
+        const int sl = i / kSlice;
+        const uint32_t base = c.h_slice_ptr[sl] - w0 + (uint32_t)(i % kSlice);
+        const int W = (int)((c.h_slice_ptr[sl + 1] - c.h_slice_ptr[sl]) / kSlice);
+        for (int k = 0; k < W; ++k) {
+            const int j = (int)(col[base + (uint32_t)k * kSlice] & kIndexMask);
+            if (j == i) continue;  // padding
+            if (j < n0 || j >= n1) return fail(c, PD_E_STATE, "bond leaves its particle");
+            out.emplace_back(i - n0, j - n0);
+        }
+    }
+    return PD_OK;
+}
+
+// largest linear stretch of each mode over the template's bonds
+void mode_stretch_bound(const ClState &L, int s, const std::vector<double> &X,
+                        const std::vector<double> &Y, double *sig) {
+    const std::vector<double> &ph = L.h_phi[s];
+    for (int k = 0; k < kClModes; ++k) sig[k] = 0.0;
+    for (const auto &b : L.h_tbonds[s]) {
+        const int i = b.first, j = b.second;
+        const double dx = X[j] - X[i], dy = Y[j] - Y[i];
+        const double L2 = dx * dx + dy * dy;
+        for (int k = 0; k < kClModes; ++k) {
+            const double ex = ph[(j * kClModes + k) * 2] - ph[(i * kClModes + k) * 2];
+            const double ey = ph[(j * kClModes + k) * 2 + 1] - ph[(i * kClModes + k) * 2 + 1];
+            sig[k] = std::max(sig[k], fabs(ex * dx + ey * dy) / L2);
+        }
+    }
+}
+
+pd_status upload_shape_modes(Ctx &c, int s) {
+    ClState &L = c.cl;
+    const int n = L.h_shape_n[s];
+    std::vector<float> f((size_t)n * 2 * kClModes);
+    for (size_t k = 0; k < f.size(); ++k) f[k] = (float)L.h_phi[s][k];
+    HIPCHK(hipMemcpyAsync(L.phi + (size_t)L.h_toff[s] * 2 * kClModes, f.data(), f.size() * sizeof(float),
+                          hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(L.lam + s * kClModes, &L.h_lam[s * kClModes], kClModes * sizeof(double),
+                          hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(L.sig + s * kClModes, &L.h_sig[s * kClModes], kClModes * sizeof(double),
+                          hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PD_OK;
+}
+
+// stiffness of the linearised bond force of eq. (peri) about the template's
+// reference configuration, K = -dF/du; the lowest non-rigid solutions of
+// K phi = lambda M phi (M = diag(rho V)), normalised phi^T M phi = 1, each
+// signed so that its largest entry is positive
+pd_status shape_modes(Ctx &c, int s) {
+    ClState &L = c.cl;
+    const int pt = L.h_shape_first[s];
+    const int n0 = c.h_poff[pt], n = L.h_shape_n[s];
+    const MatConst &mc = c.h_mc[c.h_pmat[pt]];
+    TRY(particle_bonds(c, pt, L.h_tbonds[s]));
+    const int D = 2 * n;
+    std::vector<double> K((size_t)D * D, 0.0);
+    for (const auto &b : L.h_tbonds[s]) {
+        const int i = b.first, j = b.second;
+        const double dx = c.h_x[n0 + j] - c.h_x[n0 + i], dy = c.h_y[n0 + j] - c.h_y[n0 + i];
+        const double l = sqrt(dx * dx + dy * dy);
+        const double ex = dx / l, ey = dy / l;
+        const double w = mc.conic ? 1.0 - l / mc.eps : 1.0;
+        const double k = mc.cw * w * c.h_vol[n0 + i] * c.h_vol[n0 + j] / l;
+        const double e[2] = {ex, ey};
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+                K[(size_t)(2 * i + p) * D + 2 * i + q] += k * e[p] * e[q];
+                K[(size_t)(2 * i + p) * D + 2 * j + q] -= k * e[p] * e[q];
+            }
+    }
+    std::vector<double> rs(D);
+    for (int i = 0; i < n; ++i) rs[2 * i] = rs[2 * i + 1] = 1.0 / sqrt(c.h_mass[n0 + i]);
+    for (int r = 0; r < D; ++r)
+        for (int q = 0; q < D; ++q) K[(size_t)r * D + q] *= rs[r] * rs[q];
+    std::vector<double> w;
+    try {
+        sym_eig(K, D, w);
+    } catch (const std::exception &ex) {
+        return fail(c, PD_E_DEVICE, ex.what());
+    }
+    const int nm = std::min(kClModes, D - 3);
+    if (nm < 1 || !(fabs(w[2]) <= 1e-8 * w[3]))
+        return fail(c, PD_E_INVALID, "a closure shape must have exactly three rigid modes");
+    L.h_nmodes[s] = nm;
+    std::vector<double> &ph = L.h_phi[s];
+    ph.assign((size_t)n * 2 * kClModes, 0.0);
+    for (int k = 0; k < nm; ++k) {
+        const int col = 3 + k;
+        double big = 0.0;
+        int at = 0;
+        for (int r = 0; r < D; ++r) {
+            const double v = K[(size_t)r * D + col] * rs[r];
+            if (fabs(v) > fabs(big) * (1.0 + 1e-12)) {
+                big = v;
+                at = r;
+            }
+        }
+        (void)at;
+        const double sg = big < 0.0 ? -1.0 : 1.0;
+        for (int r = 0; r < D; ++r)
+            ph[((size_t)(r / 2) * kClModes + k) * 2 + (r & 1)] = sg * K[(size_t)r * D + col] * rs[r];
+        L.h_lam[s * kClModes + k] = w[col];
+    }
+    for (int k = nm; k < kClModes; ++k) L.h_lam[s * kClModes + k] = 0.0;
+    std::vector<double> X(n), Y(n);
+    for (int i = 0; i < n; ++i) {
+        X[i] = c.h_x[n0 + i];
+        Y[i] = c.h_y[n0 + i];
+    }
+    mode_stretch_bound(L, s, X, Y, &L.h_sig[s * kClModes]);
+    return upload_shape_modes(c, s);
+}
+
+pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const double *tau_c,
+                        int32_t check_every, double err_tol) {
+    ClState &L = c.cl;
+    if (L.ready) return fail(c, PD_E_STATE, "the closure is already set up");
+    if (!sp) return fail(c, PD_E_INVALID, "missing shape_of_particle");
+    if (!(gate_frac > 0.0) || check_every < 0 || !(err_tol > 0.0))
+        return fail(c, PD_E_INVALID, "gate_frac and err_tol must be positive, check_every >= 0");
+    const int P = c.P;
+    int S = 0;
+    for (int p = 0; p < P; ++p) {
+        if (sp[p] < -1) return fail(c, PD_E_INVALID, "shape ids are -1 (none) or >= 0");
+        S = std::max(S, sp[p] + 1);
+    }
+    if (S == 0) return fail(c, PD_E_INVALID, "no particle has a closure shape");
+    L.S = S;
+    L.h_shape_first.assign(S, -1);
+    L.h_shape_n.assign(S, 0);
+    L.h_toff.assign(S, 0);
+    L.h_nmodes.assign(S, 0);
+    L.h_trained.assign(S, 0);
+    L.h_phi.assign(S, {});
+    L.h_tbonds.assign(S, {});
+    L.h_lam.assign((size_t)S * kClModes, 0.0);
+    L.h_sig.assign((size_t)S * kClModes, 0.0);
+    L.adam_t.assign(S, 0);
+    L.h_cpart.clear();
+    L.h_cshape.clear();
+    for (int s = 0; s < S; ++s)
+        for (int p = 0; p < P; ++p)
+            if (sp[p] == s) {
+                if (L.h_shape_first[s] < 0) L.h_shape_first[s] = p;
+                L.h_cpart.push_back(p);
+                L.h_cshape.push_back(s);
+            }
+    for (int s = 0; s < S; ++s)
+        if (L.h_shape_first[s] < 0) return fail(c, PD_E_INVALID, "shape ids must be 0 .. S-1, each used");
+    L.Pc = (int)L.h_cpart.size();
+    // templates: the first particle of each shape, about its mass centroid
+    std::vector<double> tX, tY;
+    L.max_n = 0;
+    for (int s = 0; s < S; ++s) {
+        const int pt = L.h_shape_first[s];
+        const int n0 = c.h_poff[pt], n = c.h_poff[pt + 1] - n0;
+        if (n > kClMaxNodes || n < 3)
+            return fail(c, PD_E_INVALID, "a closure particle has 3 .. 1536 nodes");
+        L.h_shape_n[s] = n;
+        L.h_toff[s] = (int)tX.size();
+        L.max_n = std::max(L.max_n, n);
+        double M = 0, sx = 0, sy = 0;
+        for (int i = n0; i < n0 + n; ++i) {
+            M += c.h_mass[i];
+            sx += c.h_mass[i] * c.h_x[i];
+            sy += c.h_mass[i] * c.h_y[i];
+        }
+        for (int i = n0; i < n0 + n; ++i) {
+            tX.push_back(c.h_x[i] - sx / M);
+            tY.push_back(c.h_y[i] - sy / M);
+        }
+    }
+    // every particle of a shape is its template rotated and translated
+    for (int k = 0; k < L.Pc; ++k) {
+        const int p = L.h_cpart[k], s = L.h_cshape[k];
+        const int n0 = c.h_poff[p], n = c.h_poff[p + 1] - n0;
+        const int t0 = L.h_toff[s], q0 = c.h_poff[L.h_shape_first[s]];
+        if (n != L.h_shape_n[s]) return fail(c, PD_E_INVALID, "particles of one shape differ in node count");
+        double M = 0, sx = 0, sy = 0, rmax = 0;
+        for (int i = 0; i < n; ++i) {
+            if (fabs(c.h_mass[n0 + i] - c.h_mass[q0 + i]) > 1e-12 * c.h_mass[q0 + i])
+                return fail(c, PD_E_INVALID, "particles of one shape differ in nodal mass");
+            M += c.h_mass[n0 + i];
+            sx += c.h_mass[n0 + i] * c.h_x[n0 + i];
+            sy += c.h_mass[n0 + i] * c.h_y[n0 + i];
+            rmax = std::max(rmax, hypot(tX[t0 + i], tY[t0 + i]));
+        }
+        double cr = 0, dt = 0;
+        for (int i = 0; i < n; ++i) {
+            const double Yx = c.h_x[n0 + i] - sx / M, Yy = c.h_y[n0 + i] - sy / M;
+            cr += c.h_mass[n0 + i] * (tX[t0 + i] * Yy - tY[t0 + i] * Yx);
+            dt += c.h_mass[n0 + i] * (tX[t0 + i] * Yx + tY[t0 + i] * Yy);
+        }
+        const double th = atan2(cr, dt), ct = cos(th), st = sin(th);
+        for (int i = 0; i < n; ++i) {
+            const double Yx = c.h_x[n0 + i] - sx / M, Yy = c.h_y[n0 + i] - sy / M;
+            const double rx = ct * tX[t0 + i] - st * tY[t0 + i] - Yx;
+            const double ry = st * tX[t0 + i] + ct * tY[t0 + i] - Yy;
+            if (hypot(rx, ry) > 1e-9 * rmax)
+                return fail(c, PD_E_INVALID, "a particle is not a rigid copy of its shape's first particle");
+        }
+    }
+    // device buffers
+    const size_t Pc = L.Pc;
+    TRY(upload(c, &L.tX, tX.data(), tX.size()));
+    TRY(upload(c, &L.tY, tY.data(), tY.size()));
+    TRY(dalloc(c, &L.phi, tX.size() * 2 * kClModes));
+    TRY(dalloc(c, &L.lam, (size_t)S * kClModes));
+    TRY(dalloc(c, &L.sig, (size_t)S * kClModes));
+    for (int s = 0; s < S; ++s) TRY(shape_modes(c, s));
+    std::vector<double> s0(S), tc(S);
+    for (int s = 0; s < S; ++s) {
+        const int pt = L.h_shape_first[s];
+        const MatConst &mc = c.h_mc[c.h_pmat[pt]];
+        s0[s] = mc.s0;
+        double rmax = 0;
+        for (int i = 0; i < L.h_shape_n[s]; ++i)
+            rmax = std::max(rmax, hypot(tX[L.h_toff[s] + i], tY[L.h_toff[s] + i]));
+        // default contact threshold: the load that strains the particle's
+        // diameter by a tenth of the critical stretch
+        tc[s] = (tau_c && tau_c[s] > 0.0) ? tau_c[s] : 0.1 * mc.s0 * young_of(mc) * 2.0 * rmax;
+    }
+    L.h_tau_c = tc;
+    TRY(upload(c, &L.s0, s0.data(), S));
+    TRY(upload(c, &L.tau_c, tc.data(), S));
+    std::vector<int> zeros(c.P, 0);
+    TRY(upload(c, &L.on, zeros.data(), c.P));
+    int *dcpart, *dcshape;
+    TRY(upload(c, &dcpart, L.h_cpart.data(), Pc));
+    TRY(upload(c, &dcshape, L.h_cshape.data(), Pc));
+    double *red, *q, *gext, *ghat;
+    TRY(dalloc(c, &red, Pc * 16));
+    TRY(dalloc(c, &q, Pc * kClModes));
+    TRY(dalloc(c, &gext, Pc * kClModes));
+    TRY(dalloc(c, &ghat, Pc * kClModes));
+    TRY(dalloc(c, &L.fx, (size_t)c.N));
+    TRY(dalloc(c, &L.fy, (size_t)c.N));
+    TRY(dalloc(c, &L.smax, (size_t)c.N));
+    TRY(dalloc(c, &L.stats, 4));
+    TRY(dalloc(c, &L.per, Pc * 4));
+    TRY(dalloc(c, &L.fallbacks, 1));
+    HIPCHK(hipMemsetAsync(L.fallbacks, 0, sizeof(unsigned long long), c.stream));
+    HIPCHK(hipMemsetAsync(q, 0, Pc * kClModes * sizeof(double), c.stream));
+    // MLP parameters: zero (the linear closure) until loaded or trained
+    TRY(dalloc(c, &L.wf, (size_t)S * kClParams));
+    TRY(dalloc(c, &L.wb, (size_t)S * kClParams));
+    HIPCHK(hipMemsetAsync(L.wf, 0, (size_t)S * kClParams * sizeof(float), c.stream));
+    HIPCHK(hipMemsetAsync(L.wb, 0, (size_t)S * kClParams * sizeof(uint16_t), c.stream));
+    std::vector<float> ones((size_t)S * kClModes, 1.0f);
+    TRY(upload(c, &L.sig_q, ones.data(), ones.size()));
+    TRY(upload(c, &L.sig_r, ones.data(), ones.size()));
+    // 16-row blocks of the MLP, each within one shape
+    L.h_rb_shape.clear();
+    L.h_rb_first.clear();
+    L.h_rb_count.clear();
+    for (int k = 0; k < L.Pc;) {
+        const int s = L.h_cshape[k];
+        int e = k;
+        while (e < L.Pc && L.h_cshape[e] == s && e - k < 16) ++e;
+        L.h_rb_shape.push_back(s);
+        L.h_rb_first.push_back(k);
+        L.h_rb_count.push_back(e - k);
+        k = e;
+    }
+    int *rbs, *rbf, *rbc;
+    TRY(upload(c, &rbs, L.h_rb_shape.data(), L.h_rb_shape.size()));
+    TRY(upload(c, &rbf, L.h_rb_first.data(), L.h_rb_first.size()));
+    TRY(upload(c, &rbc, L.h_rb_count.data(), L.h_rb_count.size()));
+    int *dtoff;
+    TRY(upload(c, &dtoff, L.h_toff.data(), S));
+    HIPCHK(hipStreamSynchronize(c.stream));
+
+    ClArgs &ca = L.ca;
+    ca = ClArgs{};
+    ca.Pc = L.Pc;
+    ca.cpart = dcpart;
+    ca.cshape = dcshape;
+    ca.poff = c.d_poff;
+    ca.toff = dtoff;
+    ca.tX = L.tX;
+    ca.tY = L.tY;
+    ca.phi = L.phi;
+    ca.lam = L.lam;
+    ca.sig = L.sig;
+    ca.s0 = L.s0;
+    ca.tau_c = L.tau_c;
+    ca.gate_frac = gate_frac;
+    ca.learned = 0;
+    ca.red = red;
+    ca.q = q;
+    ca.gext = gext;
+    ca.ghat = ghat;
+    ca.fallbacks = L.fallbacks;
+    MlpArgs &m = L.ma;
+    m = MlpArgs{};
+    m.rows = L.Pc;
+    m.row_blocks = (int)L.h_rb_shape.size();
+    m.rb_shape = rbs;
+    m.rb_first = rbf;
+    m.rb_count = rbc;
+    m.q = q;
+    m.lam = L.lam;
+    m.wb = L.wb;
+    m.wf = L.wf;
+    m.sig_q = L.sig_q;
+    m.sig_r = L.sig_r;
+    m.g = ghat;
+    m.on = L.on;
+    m.cpart = dcpart;
+    L.check_every = check_every;
+    L.err_tol = err_tol;
+    L.ready = true;
+    return PD_OK;
+}
+
+// the periodic check: plain bond forces (and the largest stretch per node)
+// at the current state, the closure's modal force at the same state, and
+// the per-particle fallback
+pd_status closure_check(Ctx &c) {
+    ClState &L = c.cl;
+    // smax stays set for the check kernel, which reads it; the force
+    // kernels of later steps get it cleared
+    c.a.smax = L.smax;
+    pd_status st = eval_terms(c);
+    if (st == PD_OK) {
+        set_state_ptrs(c, c.cur);
+        hipError_t e = launch_cl_project(c.a, L.ca, false, 1, L.max_n, c.stream);
+        if (e == hipSuccess && L.mode == 2) e = launch_mlp_forward(L.ma, c.a, false, c.stream);
+        if (e == hipSuccess) e = launch_cl_check(c.a, L.ca, L.err_tol, L.per, L.stats, c.stream);
+        if (e != hipSuccess) st = fail(c, PD_E_DEVICE, hipGetErrorString(e));
+    }
+    c.a.smax = nullptr;
+    TRY(st);
+    double r[4];
+    HIPCHK(hipMemcpyAsync(r, L.stats, sizeof r, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    ++L.checks;
+    L.last_checked = (int64_t)r[3];
+    L.last_err = r[1] > 0.0 ? sqrt(r[0] / r[1]) : 0.0;
+    L.last_err_linear = r[1] > 0.0 ? sqrt(r[2] / r[1]) : 0.0;
+    return PD_OK;
+}
+
+pd_status cl_training_buffers(Ctx &c, int rows) {
+    ClState &L = c.cl;
+    if (!L.t_m) {
+        TRY(dalloc(c, &L.t_m, (size_t)L.S * kClParams));
+        TRY(dalloc(c, &L.t_v, (size_t)L.S * kClParams));
+        TRY(dalloc(c, &L.t_grad, (size_t)kClParams));
+    }
+    if (L.tcap >= rows) return PD_OK;
+    void *bufs[] = {L.t_y, L.t_z1, L.t_z2, L.t_dy, L.t_dz2, L.t_dz1, L.t_xb, L.t_h1, L.t_h2,
+                    L.t_dyb, L.t_dz2b, L.t_dz1b, L.t_idx};
+    for (void *b : bufs) dfree(c, b);
+    const size_t R = rows;
+    TRY(dalloc(c, &L.t_y, R * kClModes));
+    TRY(dalloc(c, &L.t_z1, R * kClHidden));
+    TRY(dalloc(c, &L.t_z2, R * kClHidden));
+    TRY(dalloc(c, &L.t_dy, R * kClModes));
+    TRY(dalloc(c, &L.t_dz2, R * kClHidden));
+    TRY(dalloc(c, &L.t_dz1, R * kClHidden));
+    TRY(dalloc(c, &L.t_xb, R * kClModes));
+    TRY(dalloc(c, &L.t_h1, R * kClHidden));
+    TRY(dalloc(c, &L.t_h2, R * kClHidden));
+    TRY(dalloc(c, &L.t_dyb, R * kClModes));
+    TRY(dalloc(c, &L.t_dz2b, R * kClHidden));
+    TRY(dalloc(c, &L.t_dz1b, R * kClHidden));
+    TRY(dalloc(c, &L.t_idx, R));
+    L.tcap = rows;
+    return PD_OK;
+}
+
+// loss and gradients of one batch (rows of q, g; idx selects them or null)
+hipError_t cl_grad_batch(Ctx &c, int s, const double *q, const double *g, int rows, const int *idx,
+                         float *loss) {
+    ClState &L = c.cl;
+    MlpArgs m{};
+    m.rows = rows;
+    m.row_blocks = (rows + 15) / 16;
+    m.shape = s;
+    m.idx = idx;
+    m.q = q;
+    m.lam = L.lam;
+    m.wb = L.wb;
+    m.wf = L.wf;
+    m.sig_q = L.sig_q;
+    m.sig_r = L.sig_r;
+    m.y = L.t_y;
+    m.xb = L.t_xb;
+    m.h1 = L.t_h1;
+    m.h2 = L.t_h2;
+    m.z1 = L.t_z1;
+    m.z2 = L.t_z2;
+    hipError_t e = launch_mlp_forward(m, c.a, false, c.stream);
+    if (e == hipSuccess) e = launch_mlp_loss(m, g, L.t_dy, L.t_dyb, loss, c.stream);
+    const uint16_t *W = L.wb + (size_t)s * kClParams;
+    float *G = L.t_grad;
+    const hipStream_t st = c.stream;
+    if (e == hipSuccess)
+        e = launch_gemm_bf16(kClModes, kClHidden, rows, L.t_dyb, 1, kClModes, L.t_h2, kClHidden, 1,
+                             G + kOffW3, kClHidden, 0, nullptr, nullptr, st);
+    if (e == hipSuccess) e = launch_colsum(L.t_dy, rows, kClModes, G + kOffB3, st);
+    if (e == hipSuccess)
+        e = launch_gemm_bf16(rows, kClHidden, kClModes, L.t_dyb, kClModes, 1, W + kOffW3, kClHidden, 1,
+                             L.t_dz2, kClHidden, 1, L.t_z2, L.t_dz2b, st);
+    if (e == hipSuccess)
+        e = launch_gemm_bf16(kClHidden, kClHidden, rows, L.t_dz2b, 1, kClHidden, L.t_h1, kClHidden, 1,
+                             G + kOffW2, kClHidden, 0, nullptr, nullptr, st);
+    if (e == hipSuccess) e = launch_colsum(L.t_dz2, rows, kClHidden, G + kOffB2, st);
+    if (e == hipSuccess)
+        e = launch_gemm_bf16(rows, kClHidden, kClHidden, L.t_dz2b, kClHidden, 1, W + kOffW2, kClHidden,
+                             1, L.t_dz1, kClHidden, 1, L.t_z1, L.t_dz1b, st);
+    if (e == hipSuccess)
+        e = launch_gemm_bf16(kClHidden, kClModes, rows, L.t_dz1b, 1, kClHidden, L.t_xb, kClModes, 1,
+                             G + kOffW1, kClModes, 0, nullptr, nullptr, st);
+    if (e == hipSuccess) e = launch_colsum(L.t_dz1, rows, kClHidden, G + kOffB1, st);
+    return e;
+}
+
+pd_status check_shape(Ctx &c, int s) {
+    if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
+    if (s < 0 || s >= c.cl.S) return fail(c, PD_E_INVALID, "bad shape id");
     return PD_OK;
 }
 
@@ -598,6 +1098,15 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     if (p->top_wall_speed)
         for (int q = 0; q < A; ++q) vtop[q] = p->top_wall_speed[q];
     TRY(upload(c, &dvtop, vtop.data(), A));
+    // kept for the modal-closure setup
+    c.h_x.assign(p->x, p->x + N);
+    c.h_y.assign(p->y, p->y + N);
+    c.h_vol.assign(p->vol, p->vol + N);
+    c.h_mass = mass;
+    c.h_poff.assign(p->particle_offset, p->particle_offset + P + 1);
+    c.h_pmat.assign(p->particle_material, p->particle_material + P);
+    c.h_mc = mc;
+    c.d_poff = dpoff;
     a.x = dx;
     a.y = dy;
     a.vol = dvol;
@@ -982,6 +1491,8 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         return fail(c, PD_E_INVALID, "cell_factor must be in [1, 64]");
     if (!(t->skin_factor >= 0.0) || t->skin_factor > 16.0)
         return fail(c, PD_E_INVALID, "skin_factor must be in [0, 16]");
+    if (c.cl.mode && !(t->skin_factor > 0.0))
+        return fail(c, PD_E_INVALID, "the modal closure runs with candidate lists (skin_factor > 0)");
     HIPCHK(hipStreamSynchronize(c.stream));
     const bool regrid = t->cell_factor != c.tune.cell_factor || t->skin_factor != c.tune.skin_factor;
     const bool rewin = t->block_nodes != c.tune.block_nodes;
@@ -1134,6 +1645,7 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     if (!ctx || steps < 1) return PD_E_INVALID;
     Ctx &c = ctx->c;
     if (c.status) return (pd_status)c.status;
+    if (c.cl.mode) return fail(c, PD_E_STATE, "tune before switching the modal closure on");
     // save the state (device-side copies)
     const size_t nb = c.N * sizeof(double);
     double *save;
@@ -1206,6 +1718,275 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     if (chosen) *chosen = best;
     if (result != PD_OK) return result;
     return s2;
+}
+
+// ---- modal closure ----------------------------------------------------------
+pd_status pd_closure_setup(pd_ctx *ctx, const int32_t *shape_of_particle, double gate_frac,
+                           const double *tau_c, int32_t check_every, double err_tol) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return closure_setup(c, shape_of_particle, gate_frac, tau_c, check_every, err_tol);
+}
+
+pd_status pd_closure_modes(pd_ctx *ctx, int32_t shape, int32_t *n_nodes, int32_t *n_modes,
+                           double *phi, double *lam, double *sig) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    const ClState &L = c.cl;
+    if (n_nodes) *n_nodes = L.h_shape_n[shape];
+    if (n_modes) *n_modes = L.h_nmodes[shape];
+    if (phi) std::copy(L.h_phi[shape].begin(), L.h_phi[shape].end(), phi);
+    if (lam) std::copy(&L.h_lam[shape * kClModes], &L.h_lam[shape * kClModes] + kClModes, lam);
+    if (sig) std::copy(&L.h_sig[shape * kClModes], &L.h_sig[shape * kClModes] + kClModes, sig);
+    return PD_OK;
+}
+
+pd_status pd_closure_set_modes(pd_ctx *ctx, int32_t shape, const double *phi, const double *lam) {
+    if (!ctx || !phi || !lam) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    ClState &L = c.cl;
+    const int n = L.h_shape_n[shape];
+    L.h_phi[shape].assign(phi, phi + (size_t)n * 2 * kClModes);
+    for (int k = 0; k < kClModes; ++k) L.h_lam[shape * kClModes + k] = lam[k];
+    const int pt = L.h_shape_first[shape], n0 = c.h_poff[pt];
+    std::vector<double> X(c.h_x.begin() + n0, c.h_x.begin() + n0 + n);
+    std::vector<double> Y(c.h_y.begin() + n0, c.h_y.begin() + n0 + n);
+    mode_stretch_bound(L, shape, X, Y, &L.h_sig[shape * kClModes]);
+    return upload_shape_modes(c, shape);
+}
+
+pd_status pd_closure_load(pd_ctx *ctx, int32_t shape, const float *params, const float *sig_q,
+                          const float *sig_r) {
+    if (!ctx || !params) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    ClState &L = c.cl;
+    float *w = L.wf + (size_t)shape * kClParams;
+    HIPCHK(hipMemcpyAsync(w, params, kClParams * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(launch_f32_to_bf16(w, L.wb + (size_t)shape * kClParams, kClParams, c.stream));
+    if (sig_q)
+        HIPCHK(hipMemcpyAsync(L.sig_q + shape * kClModes, sig_q, kClModes * sizeof(float),
+                              hipMemcpyHostToDevice, c.stream));
+    if (sig_r)
+        HIPCHK(hipMemcpyAsync(L.sig_r + shape * kClModes, sig_r, kClModes * sizeof(float),
+                              hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    L.h_trained[shape] = 1;
+    return PD_OK;
+}
+
+pd_status pd_closure_get(pd_ctx *ctx, int32_t shape, float *params, float *sig_q, float *sig_r) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    ClState &L = c.cl;
+    if (params)
+        HIPCHK(hipMemcpyAsync(params, L.wf + (size_t)shape * kClParams, kClParams * sizeof(float),
+                              hipMemcpyDeviceToHost, c.stream));
+    if (sig_q)
+        HIPCHK(hipMemcpyAsync(sig_q, L.sig_q + shape * kClModes, kClModes * sizeof(float),
+                              hipMemcpyDeviceToHost, c.stream));
+    if (sig_r)
+        HIPCHK(hipMemcpyAsync(sig_r, L.sig_r + shape * kClModes, kClModes * sizeof(float),
+                              hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PD_OK;
+}
+
+pd_status pd_closure_enable(pd_ctx *ctx, int32_t mode) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
+    if (mode < 0 || mode > 2) return fail(c, PD_E_INVALID, "mode is 0 (off), 1 (linear) or 2 (learned)");
+    if (mode && !(c.tune.skin_factor > 0.0))
+        return fail(c, PD_E_INVALID, "the modal closure runs with candidate lists (skin_factor > 0)");
+    ClState &L = c.cl;
+    HIPCHK(hipStreamSynchronize(c.stream));
+    std::vector<int> on(c.P, 0);
+    if (mode)
+        for (int p : L.h_cpart) on[p] = 1;
+    HIPCHK(hipMemcpyAsync(L.on, on.data(), c.P * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    L.mode = mode;
+    L.ca.learned = mode == 2 ? 1 : 0;
+    c.a.cl_on = mode ? L.on : nullptr;
+    c.a.cl_fx = L.fx;
+    c.a.cl_fy = L.fy;
+    L.last_check_step = c.step;
+    invalidate_graph(c);
+    return PD_OK;
+}
+
+pd_status pd_closure_snapshot(pd_ctx *ctx, double *q, double *g, int32_t on_device) {
+    if (!ctx || !q || !g) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
+    ClState &L = c.cl;
+    TRY(eval_terms(c));
+    set_state_ptrs(c, c.cur);
+    HIPCHK(launch_cl_project(c.a, L.ca, false, 2, L.max_n, c.stream));
+    const size_t nb = (size_t)L.Pc * kClModes * sizeof(double);
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(q, L.ca.q, nb, k, c.stream));
+    HIPCHK(hipMemcpyAsync(g, L.ca.gext, nb, k, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PD_OK;
+}
+
+pd_status pd_closure_forward(pd_ctx *ctx, int32_t shape, const double *q, double *g, int64_t n,
+                             int32_t on_device) {
+    if (!ctx || !q || !g || n < 0 || n > (1 << 24)) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    if (n == 0) return PD_OK;
+    ClState &L = c.cl;
+    const double *dq = q;
+    double *dg = g, *tq = nullptr, *tg = nullptr;
+    const size_t nb = (size_t)n * kClModes * sizeof(double);
+    if (!on_device) {
+        TRY(dalloc(c, &tq, (size_t)n * kClModes));
+        TRY(dalloc(c, &tg, (size_t)n * kClModes));
+        HIPCHK(hipMemcpyAsync(tq, q, nb, hipMemcpyHostToDevice, c.stream));
+        dq = tq;
+        dg = tg;
+    }
+    MlpArgs m{};
+    m.rows = (int)n;
+    m.row_blocks = (int)((n + 15) / 16);
+    m.shape = shape;
+    m.q = dq;
+    m.lam = L.lam;
+    m.wb = L.wb;
+    m.wf = L.wf;
+    m.sig_q = L.sig_q;
+    m.sig_r = L.sig_r;
+    m.g = dg;
+    HIPCHK(launch_mlp_forward(m, c.a, false, c.stream));
+    if (!on_device) HIPCHK(hipMemcpyAsync(g, tg, nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(c, tq);
+    dfree(c, tg);
+    return PD_OK;
+}
+
+pd_status pd_closure_grads(pd_ctx *ctx, int32_t shape, const double *q, const double *g, int64_t n,
+                           float *grads, double *loss) {
+    if (!ctx || !q || !g || !grads || n < 1 || n > (1 << 20)) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    ClState &L = c.cl;
+    TRY(cl_training_buffers(c, (int)n));
+    double *dq, *dg;
+    float *dl;
+    TRY(dalloc(c, &dq, (size_t)n * kClModes));
+    TRY(dalloc(c, &dg, (size_t)n * kClModes));
+    TRY(dalloc(c, &dl, 1));
+    const size_t nb = (size_t)n * kClModes * sizeof(double);
+    HIPCHK(hipMemcpyAsync(dq, q, nb, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(dg, g, nb, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(cl_grad_batch(c, shape, dq, dg, (int)n, nullptr, dl));
+    float lf = 0.0f;
+    HIPCHK(hipMemcpyAsync(grads, L.t_grad, kClParams * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&lf, dl, sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (loss) *loss = lf;
+    dfree(c, dq);
+    dfree(c, dg);
+    dfree(c, dl);
+    return PD_OK;
+}
+
+pd_status pd_closure_train(pd_ctx *ctx, int32_t shape, const double *q, const double *g, int64_t n,
+                           int32_t iters, int32_t batch, double lr, uint64_t seed, float *loss_out) {
+    if (!ctx || !q || !g || n < 1 || iters < 1 || batch < 16 || batch > (1 << 16) || !(lr > 0.0))
+        return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    TRY(check_shape(c, shape));
+    ClState &L = c.cl;
+    TRY(cl_training_buffers(c, batch));
+    float *dl;
+    TRY(dalloc(c, &dl, (size_t)iters));
+    const size_t P = kClParams;
+    float *w = L.wf + shape * P;
+    uint16_t *wb = L.wb + shape * P;
+    float *mo = L.t_m + shape * P, *ve = L.t_v + shape * P;
+    // normalisation from the data: rms of the inputs and of the targets
+    HIPCHK(launch_norm_stats(q, g, L.lam + shape * kClModes, n, L.sig_q + shape * kClModes,
+                             L.sig_r + shape * kClModes, c.stream));
+    if (!L.h_trained[shape]) HIPCHK(launch_mlp_init(w, wb, seed, c.stream));
+    if (L.adam_t[shape] == 0) {
+        HIPCHK(hipMemsetAsync(mo, 0, P * sizeof(float), c.stream));
+        HIPCHK(hipMemsetAsync(ve, 0, P * sizeof(float), c.stream));
+    }
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int it = 0; it < iters; ++it) {
+        HIPCHK(launch_batch_idx(L.t_idx, batch, n, seed, it + L.adam_t[shape], c.stream));
+        HIPCHK(cl_grad_batch(c, shape, q, g, batch, L.t_idx, dl + it));
+        const int64_t t = ++L.adam_t[shape];
+        // cosine decay of the step size over this call
+        const double lrt = 0.5 * lr * (1.0 + cos(kPi * (double)it / (double)iters));
+        const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+        const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+        HIPCHK(launch_adam(w, wb, L.t_grad, mo, ve, kClParams, (float)lrt, b1, b2, 1e-8f, c1, c2,
+                           c.stream));
+    }
+    if (loss_out)
+        HIPCHK(hipMemcpyAsync(loss_out, dl, iters * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(c, dl);
+    L.h_trained[shape] = 1;
+    return PD_OK;
+}
+
+pd_status pd_closure_check(pd_ctx *ctx) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.cl.ready || !c.cl.mode) return fail(c, PD_E_STATE, "the closure is not on");
+    TRY(closure_check(c));
+    c.cl.last_check_step = c.step;
+    return PD_OK;
+}
+
+pd_status pd_closure_stats(pd_ctx *ctx, double out[8]) {
+    if (!ctx || !out) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
+    ClState &L = c.cl;
+    std::vector<int> on(c.P);
+    unsigned long long fb = 0;
+    HIPCHK(hipMemcpyAsync(on.data(), L.on, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&fb, L.fallbacks, sizeof fb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    int act = 0;
+    for (int p : L.h_cpart) act += on[p] ? 1 : 0;
+    out[0] = L.Pc;
+    out[1] = act;
+    out[2] = (double)fb;
+    out[3] = (double)L.checks;
+    out[4] = L.last_err;
+    out[5] = L.last_err_linear;
+    out[6] = (double)L.last_checked;
+    out[7] = L.S;
+    return PD_OK;
+}
+
+pd_status pd_closure_particles(pd_ctx *ctx, int32_t *particle, int32_t *shape, int32_t *active) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
+    ClState &L = c.cl;
+    std::vector<int> on(c.P);
+    HIPCHK(hipMemcpyAsync(on.data(), L.on, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (int k = 0; k < L.Pc; ++k) {
+        if (particle) particle[k] = L.h_cpart[k];
+        if (shape) shape[k] = L.h_cshape[k];
+        if (active) active[k] = on[L.h_cpart[k]];
+    }
+    return PD_OK;
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -92,14 +93,124 @@ struct DevArgs {
     long long *step_base;      // steps completed before the current replay
     int chunk_k;               // index of this launch within the replay
     int *overflow;             // a node had more candidates than slots
+    // modal closure: particles with cl_on[p] != 0 take their internal force
+    // from the closure; the force kernel skips their bonds and leaves their
+    // external (contact + wall) nodal force in cl_fx / cl_fy
+    int *cl_on;                // [P] or null
+    double *cl_fx, *cl_fy;     // [N]
+    // M_FORCES: largest |stretch| over each node's intact bonds, or null
+    double *smax;
+};
+
+// ---- modal closure -----------------------------------------------------------
+constexpr int kClModes = 32;        // modal amplitudes per particle (MLP width in and out)
+constexpr int kClHidden = 256;      // hidden width
+constexpr int kClMaxNodes = 1536;   // nodes per closure particle (projection LDS <= 64 KB)
+constexpr int kClParams = kClHidden * kClModes + kClHidden + kClHidden * kClHidden + kClHidden +
+                          kClModes * kClHidden + kClModes;
+// packed parameter offsets: W1 [256][32], b1, W2 [256][256], b2, W3 [32][256], b3
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kClHidden * kClModes;
+constexpr int kOffW2 = kOffB1 + kClHidden;
+constexpr int kOffB2 = kOffW2 + kClHidden * kClHidden;
+constexpr int kOffW3 = kOffB2 + kClHidden;
+constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
+// per closure particle reduced quantities (red[16 * c + k])
+enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
+       R_N };
+
+struct ClArgs {
+    int Pc;                    // closure particles (sorted by shape)
+    const int *cpart;          // [Pc] particle index
+    const int *cshape;         // [Pc] shape
+    const int *poff;           // [P+1] first node of each particle
+    const int *toff;           // [S] first template node of a shape
+    const double *tX, *tY;     // template coordinates about the mass centroid
+    const float *phi;          // modes: phi[(toff + i) * 64 + 2 k + c]
+    const double *lam;         // [S][32] eigenvalues (0 past the shape's mode count)
+    const double *sig;         // [S][32] linear stretch of each mode, max over bonds
+    const double *s0;          // [S] critical stretch of the shape's material
+    const double *tau_c;       // [S] contact-load threshold of the gate
+    double gate_frac;
+    int learned;               // 0: g = -lambda q; 1: -lambda q + sigma_r MLP(q / sigma_q)
+    double *red;               // [Pc][16]
+    double *q, *gext, *ghat;   // [Pc][32]
+    unsigned long long *fallbacks;
+};
+
+// one forward pass of the MLP over `rows` rows of modal amplitudes
+struct MlpArgs {
+    int rows;
+    int row_blocks;            // 16-row blocks
+    const int *rb_shape;       // [row_blocks] or null (all rows shape `shape`)
+    const int *rb_first;       // [row_blocks] first row or null (16 b)
+    const int *rb_count;       // [row_blocks] rows in the block or null
+    int shape;
+    const int *idx;            // [rows] input row of each batch row, or null
+    const double *q;           // inputs [*][32]
+    const double *lam;         // [S][32]
+    const uint16_t *wb;        // [S][kClParams] bfloat16 weights
+    const float *wf;           // [S][kClParams] float32 weights (biases read here)
+    const float *sig_q, *sig_r;  // [S][32]
+    double *g;                 // out: -lambda q + sigma_r y, [rows][32] (or null)
+    // training caches (or null): inputs and activations of each layer
+    float *y;                  // [rows][32]
+    uint16_t *xb, *h1, *h2;    // [rows][32], [rows][256], [rows][256]
+    float *z1, *z2;            // [rows][256]
+    const int *on;             // [P] particle flags or null: rows of inactive particles are skipped
+    const int *cpart;          // [rows] particle of each row (with on)
+};
+
+struct ClState {
+    bool ready = false;
+    int mode = 0;              // 0 off, 1 linear, 2 learned
+    int S = 0, Pc = 0;
+    int check_every = 100;
+    double err_tol = 0.05;
+    std::vector<int> h_cpart, h_cshape, h_shape_n, h_toff, h_shape_first;
+    std::vector<int> h_rb_shape, h_rb_first, h_rb_count;
+    std::vector<int> h_nmodes;
+    std::vector<int> h_trained;
+    ClArgs ca{};
+    MlpArgs ma{};
+    // device buffers
+    int *on = nullptr;
+    double *lam = nullptr, *sig = nullptr, *s0 = nullptr, *tau_c = nullptr;
+    float *phi = nullptr;
+    double *tX = nullptr, *tY = nullptr;
+    uint16_t *wb = nullptr;
+    float *wf = nullptr, *sig_q = nullptr, *sig_r = nullptr;
+    double *stats = nullptr;   // [4] device: sums of a check
+    double *per = nullptr;     // [Pc][4] device: per-particle check results
+    unsigned long long *fallbacks = nullptr;
+    int max_n = 0;             // nodes of the largest closure shape
+    std::vector<std::vector<double>> h_phi;  // per shape [n_s][2][K] (float64)
+    double last_err = -1.0, last_err_linear = -1.0;
+    int64_t checks = 0;
+    long long last_check_step = -1;
+    // training workspace
+    int tcap = 0;
+    float *t_y = nullptr, *t_z1 = nullptr, *t_z2 = nullptr, *t_dy = nullptr, *t_dz2 = nullptr,
+          *t_dz1 = nullptr, *t_grad = nullptr, *t_m = nullptr, *t_v = nullptr, *t_loss = nullptr;
+    uint16_t *t_xb = nullptr, *t_h1 = nullptr, *t_h2 = nullptr, *t_dyb = nullptr,
+             *t_dz2b = nullptr, *t_dz1b = nullptr;
+    int *t_idx = nullptr;
+    double *t_gbuf = nullptr;  // [rows][32] forward outputs
+    std::vector<int64_t> adam_t;
+    std::vector<double> h_lam, h_sig, h_tau_c;      // [S][32], [S][32], [S]
+    std::vector<std::vector<std::pair<int, int>>> h_tbonds;  // template bonds, local indices
+    double *fx = nullptr, *fy = nullptr, *smax = nullptr;
+    int64_t last_checked = 0;
 };
 
 struct Ctx {
     DevArgs a{};
+    ClState cl;
     pd_tuning tune{64, 1.0, 1, 1, 1.0};
     bool list_valid = false;     // candidate lists match the current state
     int64_t rebuilds = 0;
     hipGraphExec_t lgraph[2] = {nullptr, nullptr};  // kChunk list-mode steps per parity
+    std::map<long, hipGraphExec_t> lgraph_n;          // shorter replays, by (parity, length)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int precision = 0;
@@ -129,6 +240,10 @@ struct Ctx {
     int counting = 0;
     // host-side copies needed by setup/validation
     int N = 0, P = 0, A = 0, M = 0;
+    std::vector<double> h_x, h_y, h_vol, h_mass;
+    std::vector<int> h_poff, h_pmat;
+    std::vector<MatConst> h_mc;
+    const int *d_poff = nullptr;
     std::vector<int> h_rowlen;
     std::vector<uint32_t> h_slice_ptr;
     // per-aggregate grid (host)
@@ -146,6 +261,11 @@ struct BondArgs {
     const double *thr2;  // [M] (eps - 1e-9 eps)^2
     int N;
 };
+
+// ---- host linear algebra (pd_eig.cpp) ----
+// Eigenvalues (ascending, in w) and orthonormal eigenvectors (columns of A,
+// row-major n x n, overwritten) of the symmetric matrix A.
+void sym_eig(std::vector<double> &A, int n, std::vector<double> &w);
 
 // ---- launch wrappers (pd_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -167,6 +287,25 @@ hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream
 hipError_t launch_sum_terms(const DevArgs &a, uint32_t mask, double *fx, double *fy, hipStream_t s);
 hipError_t launch_damage(const DevArgs &a, double *phi, unsigned long long *nb, hipStream_t s);
 hipError_t launch_contacts_count(const DevArgs &a, int *cnt, hipStream_t s);
+hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int mode, int max_n,
+                             hipStream_t s);
+hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
+hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,
+                           double *stats, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s);
+hipError_t launch_gemm_bf16(int M, int N, int K, const uint16_t *A, long sam, long sak,
+                            const uint16_t *B, long sbk, long sbn, float *C, long ldc, int epi,
+                            const float *Z, uint16_t *Cb, hipStream_t s);
+hipError_t launch_mlp_loss(const MlpArgs &m, const double *g, float *dy, uint16_t *dyb,
+                           float *loss, hipStream_t s);
+hipError_t launch_colsum(const float *X, int rows, int cols, float *out, hipStream_t s);
+hipError_t launch_adam(float *w, uint16_t *wb, const float *g, float *m, float *v, int n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_mlp_init(float *w, uint16_t *wb, uint64_t seed, hipStream_t s);
+hipError_t launch_batch_idx(int *idx, int rows, int64_t n, uint64_t seed, int64_t it, hipStream_t s);
+hipError_t launch_norm_stats(const double *q, const double *g, const double *lam, int64_t n,
+                             float *sig_q, float *sig_r, hipStream_t s);
+hipError_t launch_f32_to_bf16(const float *x, uint16_t *y, int n, hipStream_t s);
 hipError_t launch_contacts_fill(const DevArgs &a, const long long *off, int *pi, int *pj,
                                 hipStream_t s);
 

@@ -562,7 +562,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                                             const double *Sy, const double *Sux,
                                             const double *Suy, const double *Sv, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
-                                            R &fpy, int &nbrk) {
+                                            R &fpy, int &nbrk, double &smx) {
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t sl = (uint32_t)i / kSlice;
@@ -618,6 +618,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                     const double num = EX * (DX + X) + EY * (DY + Y);
                     const double s = num * rcp_nr(l0 * (l + l0));
                     cand = valid && fabs(s) > s0 * (1.0 - 1e-10);
+                    if (MODE == M_FORCES && valid) smx = fmax(smx, fabs(s));
                     const double w = conic ? 1.0 - l0 * inv_eps : 1.0;
                     const double f = valid ? cw * w * s * Vi * Vj : 0.0;
                     g = f * rl;
@@ -633,6 +634,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                     const float num = EXf * (DXf + Xf) + EYf * (DYf + Yf);
                     const float s = num * __builtin_amdgcn_rcpf(l0 * (l + l0));
                     cand = valid && fabsf(s) > (float)(s0 - 2e-6);
+                    if (MODE == M_FORCES && valid) smx = fmax(smx, (double)fabsf(s));
                     const float w = conic ? 1.0f - l0 * (float)inv_eps : 1.0f;
                     const float f = valid ? (float)cw * w * s * (float)Vi * (float)Vj : 0.0f;
                     g = f * rl;
@@ -774,14 +776,19 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     R fsx = 0, fsy = 0, fnx = 0, fny = 0, fpx = 0, fpy = 0;
     double fwx = 0.0, fwy = 0.0;
     int nbrk = 0;
+    double smx = 0.0;
+    // a particle under the modal closure: no bond forces here; its external
+    // nodal force goes to the closure kernels, which integrate its nodes
+    const bool closure = MODE == M_STEP && a.cl_on && a.cl_on[pi];
     // List mode runs the bond loop first (its contact candidates never
     // involve intact bonds, so the order does not matter there), which keeps
     // fewer partial sums live through the loop.  Otherwise contact comes
     // first, because self-contact needs the bonds intact at the start of the
     // step and the bond loop commits breaks.
     if constexpr (LIST) {
-        bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi, Vi,
-                             fpx, fpy, nbrk);
+        if (!closure)
+            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
+                                 Vi, fpx, fpy, nbrk, smx);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
@@ -789,8 +796,9 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
-        bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi, Vi,
-                             fpx, fpy, nbrk);
+        if (!closure)
+            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
+                                 Vi, fpx, fpy, nbrk, smx);
     }
 
     // ---- combine the quad ------------------------------------------------------
@@ -805,6 +813,10 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     nbrk = quad_sum(nbrk);
     st |= __shfl_xor(st, 1, 64);
     st |= __shfl_xor(st, 2, 64);
+    if (MODE == M_FORCES) {
+        smx = fmax(smx, __shfl_xor(smx, 1, 64));
+        smx = fmax(smx, __shfl_xor(smx, 2, 64));
+    }
     if (sub != 0) return;
     if (MODE != M_FORCES) count(a, C_BROKEN, (unsigned long long)nbrk);
     if (LIST && nbrk) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
@@ -825,6 +837,13 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         T[7 * N + i] = fwy / Vi;
         T[8 * N + i] = mi * a.gx / Vi;
         T[9 * N + i] = mi * a.gy / Vi;
+        if (a.smax) a.smax[i] = smx;
+    } else if (closure) {
+        a.cl_fx[i] = ((double)fsx + (double)fnx) + fwx;
+        a.cl_fy[i] = ((double)fsy + (double)fny) + fwy;
+        a.ux_o[i] = uxi;
+        a.uy_o[i] = uyi;
+        if (!(isfinite(uxi) && isfinite(uyi))) st |= kStNonfinite;
     } else {
         const double axn = Fx / mi + a.gx, ayn = Fy / mi + a.gy;
         a.ax_o[i] = axn;

@@ -103,8 +103,27 @@ def load_library(path: str = LIB_PATH):
     L.pd_autotune.argtypes = [vp, C.c_int32, C.POINTER(Tuning)]
     L.pd_time_kernels.argtypes = [vp, C.c_int64, _dp, _ip, C.c_int32]
     L.pd_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    _fp = C.POINTER(C.c_float)
+    L.pd_closure_setup.argtypes = [vp, _ip, C.c_double, _dp, C.c_int32, C.c_double]
+    L.pd_closure_modes.argtypes = [vp, C.c_int32, _ip, _ip, _dp, _dp, _dp]
+    L.pd_closure_set_modes.argtypes = [vp, C.c_int32, _dp, _dp]
+    L.pd_closure_load.argtypes = [vp, C.c_int32, _fp, _fp, _fp]
+    L.pd_closure_get.argtypes = [vp, C.c_int32, _fp, _fp, _fp]
+    L.pd_closure_enable.argtypes = [vp, C.c_int32]
+    L.pd_closure_snapshot.argtypes = [vp, vp, vp, C.c_int32]
+    L.pd_closure_forward.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, C.c_int32]
+    L.pd_closure_grads.argtypes = [vp, C.c_int32, _dp, _dp, C.c_int64, _fp, _dp]
+    L.pd_closure_train.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, C.c_int32, C.c_int32,
+                                   C.c_double, C.c_uint64, _fp]
+    L.pd_closure_check.argtypes = [vp]
+    L.pd_closure_stats.argtypes = [vp, _dp]
+    L.pd_closure_particles.argtypes = [vp, _ip, _ip, _ip]
     _lib = L
     return L
+
+
+CLOSURE_MODES = 32
+CLOSURE_PARAMS = 82464
 
 
 def _p(a, t):
@@ -273,3 +292,116 @@ class PD:
         keys = ("nodes", "bonds", "slots", "cells", "radix_passes", "particles", "aggregates",
                 "max_window", "list_rebuilds", "list_slots")
         return {k: int(v) for k, v in zip(keys, out)}
+
+    # -- learned modal closure ---------------------------------------------
+    def closure_setup(self, shape_of_particle, gate_frac: float = 0.5, tau_c=None,
+                      check_every: int = 100, err_tol: float = 0.05):
+        sp = np.ascontiguousarray(shape_of_particle, dtype=np.int32)
+        tc = None if tau_c is None else np.ascontiguousarray(tau_c, dtype=np.float64)
+        self._chk(self.lib.pd_closure_setup(self.h, _p(sp, C.c_int32), float(gate_frac),
+                                            _p(tc, C.c_double), int(check_every), float(err_tol)))
+        st = self.closure_stats()
+        self.n_closure, self.n_shapes = int(st["particles"]), int(st["shapes"])
+
+    def closure_modes(self, shape: int):
+        """(phi [n_nodes, 32, 2], lambda [32], sigma [32], mode count)"""
+        nn, nm = C.c_int32(), C.c_int32()
+        self._chk(self.lib.pd_closure_modes(self.h, shape, C.byref(nn), C.byref(nm), None, None, None))
+        phi = np.zeros((nn.value, CLOSURE_MODES, 2))
+        lam, sig = np.zeros(CLOSURE_MODES), np.zeros(CLOSURE_MODES)
+        self._chk(self.lib.pd_closure_modes(self.h, shape, None, None, _p(phi, C.c_double),
+                                            _p(lam, C.c_double), _p(sig, C.c_double)))
+        return phi, lam, sig, nm.value
+
+    def closure_set_modes(self, shape: int, phi, lam):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        self._chk(self.lib.pd_closure_set_modes(self.h, shape, _p(phi, C.c_double),
+                                                _p(lam, C.c_double)))
+
+    def closure_load(self, shape: int, params, sig_q=None, sig_r=None):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        params, sig_q, sig_r = f(params), f(sig_q), f(sig_r)
+        assert params.size == CLOSURE_PARAMS
+        self._chk(self.lib.pd_closure_load(self.h, shape, _p(params, C.c_float),
+                                           _p(sig_q, C.c_float), _p(sig_r, C.c_float)))
+
+    def closure_get(self, shape: int):
+        p = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        sq = np.zeros(CLOSURE_MODES, dtype=np.float32)
+        sr = np.zeros(CLOSURE_MODES, dtype=np.float32)
+        self._chk(self.lib.pd_closure_get(self.h, shape, _p(p, C.c_float), _p(sq, C.c_float),
+                                          _p(sr, C.c_float)))
+        return p, sq, sr
+
+    def closure_enable(self, mode: int):
+        self._chk(self.lib.pd_closure_enable(self.h, int(mode)))
+
+    def closure_snapshot(self, device: bool = False):
+        """(q, g) [closure particles, 32]: modal amplitudes and modal plain bond force"""
+        n = self.n_closure
+        if device:
+            import torch
+            q = torch.empty((n, CLOSURE_MODES), dtype=torch.float64, device="cuda")
+            g = torch.empty((n, CLOSURE_MODES), dtype=torch.float64, device="cuda")
+            self._chk(self.lib.pd_closure_snapshot(self.h, C.c_void_p(q.data_ptr()),
+                                                   C.c_void_p(g.data_ptr()), 1))
+            return q, g
+        q = np.zeros((n, CLOSURE_MODES))
+        g = np.zeros((n, CLOSURE_MODES))
+        self._chk(self.lib.pd_closure_snapshot(self.h, C.c_void_p(q.ctypes.data),
+                                               C.c_void_p(g.ctypes.data), 0))
+        return q, g
+
+    def closure_forward(self, shape: int, q):
+        """g = -lambda q + sigma_r MLP(q / sigma_q) (numpy in, numpy out, or
+        cuda float64 tensors in and out)"""
+        if hasattr(q, "data_ptr"):
+            import torch
+            q = q.contiguous()
+            g = torch.empty_like(q)
+            self._chk(self.lib.pd_closure_forward(self.h, shape, C.c_void_p(q.data_ptr()),
+                                                  C.c_void_p(g.data_ptr()), q.shape[0], 1))
+            return g
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, CLOSURE_MODES)
+        g = np.zeros_like(q)
+        self._chk(self.lib.pd_closure_forward(self.h, shape, C.c_void_p(q.ctypes.data),
+                                              C.c_void_p(g.ctypes.data), q.shape[0], 0))
+        return g
+
+    def closure_grads(self, shape: int, q, g):
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, CLOSURE_MODES)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, CLOSURE_MODES)
+        out = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._chk(self.lib.pd_closure_grads(self.h, shape, _p(q, C.c_double), _p(g, C.c_double),
+                                            q.shape[0], _p(out, C.c_float), C.byref(loss)))
+        return loss.value, out
+
+    def closure_train(self, shape: int, q, g, iters: int = 2000, batch: int = 512,
+                      lr: float = 1e-3, seed: int = 0):
+        """Train on cuda float64 tensors q, g [n, 32]; returns the loss per iteration."""
+        q, g = q.contiguous(), g.contiguous()
+        loss = np.zeros(iters, dtype=np.float32)
+        self._chk(self.lib.pd_closure_train(self.h, shape, C.c_void_p(q.data_ptr()),
+                                            C.c_void_p(g.data_ptr()), q.shape[0], int(iters),
+                                            int(batch), float(lr), int(seed),
+                                            _p(loss, C.c_float)))
+        return loss
+
+    def closure_check(self):
+        self._chk(self.lib.pd_closure_check(self.h))
+
+    def closure_stats(self) -> dict:
+        out = np.zeros(8)
+        self._chk(self.lib.pd_closure_stats(self.h, _p(out, C.c_double)))
+        keys = ("particles", "active", "fallbacks", "checks", "err", "err_linear", "checked",
+                "shapes")
+        return dict(zip(keys, out.tolist()))
+
+    def closure_particles(self):
+        n = self.n_closure
+        p, s, a = (np.zeros(n, dtype=np.int32) for _ in range(3))
+        self._chk(self.lib.pd_closure_particles(self.h, _p(p, C.c_int32), _p(s, C.c_int32),
+                                                _p(a, C.c_int32)))
+        return p, s, a

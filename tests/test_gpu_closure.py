@@ -1,0 +1,419 @@
+"""GPU parity of the learned modal closure against the oracle (oracle/closure.py
+and the C oracle's force terms), through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, T_PD
+from oracle import closure as CL
+from paper_2108_07212_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+H = 0.08e-3
+BIG = 1e30
+
+
+def _pd():
+    from paper_2108_07212_amd import pd
+    return pd
+
+
+def bed(seed=21, n_per_shape=3, nodes=60, vmax=0.3):
+    return W.closure_bed(n_per_shape=n_per_shape, h=H, nodes=nodes, seed=seed, wall_speed=0.0,
+                         vmax=vmax)
+
+
+def first_of_shape(prob):
+    sp = prob.meta["shape_of_particle"]
+    return {int(s): int(np.nonzero(sp == s)[0][0]) for s in sorted(set(sp.tolist()))}
+
+
+def oracle_modes(prob, o, f32=True):
+    """shape -> (Phi [2n, 32] (float32 values), lambda, sigma), from the oracle"""
+    row, col = o.bonds()
+    k = o.constants()
+    out = {}
+    for s, pt in first_of_shape(prob).items():
+        mi = int(prob.particle_material[pt])
+        mat = prob.materials[mi]
+        K = CL.stiffness(prob, pt, row, col, k["cw"][mi], mat.horizon, mat.micro)
+        lam, Phi, _ = CL.modes(K, CL.node_masses(prob, pt))
+        if f32:
+            Phi = Phi.astype(np.float32).astype(np.float64)
+        out[s] = (Phi, lam, CL.stretch_bound(prob, pt, row, col, Phi))
+    return out
+
+
+def gpu_phi(Phi):
+    n, K = Phi.shape[0] // 2, Phi.shape[1]
+    out = np.zeros((n, 32, 2))
+    out[:, :K, 0] = Phi[0::2]
+    out[:, :K, 1] = Phi[1::2]
+    return out
+
+
+def modal_deformation(prob, modes, seed, frac_range, s0):
+    """u0 in each particle's rigid + modal space, R(theta_p) Phi q0, with seeded
+    q0 scaled so that sum |q0| sigma is a seeded fraction of s0"""
+    rng = np.random.default_rng(seed)
+    sp = prob.meta["shape_of_particle"]
+    first = first_of_shape(prob)
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        s = int(sp[p])
+        Phi, lam, sig = modes[s]
+        _, Xt = CL.reference_frame(prob, first[s])
+        _, Xp = CL.reference_frame(prob, p)
+        th = CL.best_fit_angle(Xt, Xp, CL.node_masses(prob, p))
+        q = rng.normal(0, 1, Phi.shape[1]) / (1.0 + np.arange(Phi.shape[1]))
+        q *= rng.uniform(*frac_range) * s0 / (np.abs(q) * sig).sum()
+        u = CL.rot(th, (Phi @ q).reshape(-1, 2))
+        n0, n1 = CL.particle_range(prob, p)
+        ux[n0:n1], uy[n0:n1] = u[:, 0], u[:, 1]
+    prob.u0x, prob.u0y = ux, uy
+    return prob
+
+
+def initial_q(prob, modes):
+    """shape -> modal amplitudes [particles, 32] of the initial state"""
+    first = first_of_shape(prob)
+    sp = prob.meta["shape_of_particle"]
+    out = {s: [] for s in modes}
+    for p in range(prob.n_particles):
+        s = int(sp[p])
+        n0, n1 = CL.particle_range(prob, p)
+        y = np.stack([prob.x[n0:n1] + prob.u0x[n0:n1], prob.y[n0:n1] + prob.u0y[n0:n1]], axis=1)
+        _, Xt = CL.reference_frame(prob, first[s])
+        z = np.zeros_like(y)
+        out[s].append(CL.project(Xt, CL.node_masses(prob, p), modes[s][0], y, z, z)["q"])
+    return {s: np.array(v) for s, v in out.items()}
+
+
+def load_modes(g, modes):
+    for s, (Phi, lam, _) in modes.items():
+        l32 = np.zeros(32)
+        l32[:len(lam)] = lam
+        g.closure_set_modes(s, gpu_phi(Phi), l32)
+
+
+def rand_params(seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for o, i in CL.LAYERS:
+        out.append((rng.normal(0, 1 / math.sqrt(i), (o, i)), 0.1 * rng.normal(0, 1, o)))
+    return CL.pack(out).astype(np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def setup_bed():
+    prob = bed()
+    o = Oracle(prob, contact_mode=1)
+    modes = oracle_modes(prob, o)
+    s0 = float(o.constants()["s0"][0])
+    return prob, modes, s0
+
+
+# ----------------------------------------------------------------------------
+# modes
+# ----------------------------------------------------------------------------
+def test_modes_match_oracle():
+    pd = _pd()
+    prob = bed(seed=22, nodes=80)
+    o = Oracle(prob, contact_mode=1)
+    ref = oracle_modes(prob, o, f32=False)
+    row, col = o.bonds()
+    kc = o.constants()
+    g = pd.PD(prob)
+    g.closure_setup(prob.meta["shape_of_particle"], check_every=0)
+    first = first_of_shape(prob)
+    for s, (Phi_o, lam_o, _) in ref.items():
+        mat = prob.materials[0]
+        K = CL.stiffness(prob, first[s], row, col, kc["cw"][0], mat.horizon, mat.micro)
+        alllam = CL.modes(K, CL.node_masses(prob, first[s]))[2][CL.N_RIGID:]
+        phi, lam, sig, nm = g.closure_modes(s)
+        assert nm == 32
+        np.testing.assert_allclose(lam, lam_o, rtol=1e-9)
+        Phi_g = np.zeros_like(Phi_o)
+        Phi_g[0::2], Phi_g[1::2] = phi[:, :, 0], phi[:, :, 1]
+        m = CL.node_masses(prob, first[s])
+        M = np.repeat(m, 2)
+        np.testing.assert_allclose(Phi_g.T @ (M[:, None] * Phi_g), np.eye(32), atol=1e-10)
+        # eigenvectors are unique up to sign and within clusters of equal
+        # eigenvalues: compare the M-orthogonal projector of every cluster
+        # that lies wholly among the first 32
+        k = 0
+        while k < 32:
+            e = k + 1
+            while e < len(alllam) and abs(alllam[e] - alllam[k]) <= 1e-7 * alllam[k]:
+                e += 1
+            if e <= 32:
+                Pg = Phi_g[:, k:e] @ Phi_g[:, k:e].T
+                Po = Phi_o[:, k:e] @ Phi_o[:, k:e].T
+                assert np.abs((Pg - Po) * M[None, :]).max() < 1e-7, (s, k, e)
+                if e == k + 1:  # a simple eigenvalue: its stretch bound is unique
+                    so = CL.stretch_bound(prob, first[s], row, col, Phi_o[:, k:e])[0]
+                    assert abs(sig[k] - so) <= 1e-9 * so
+            k = e
+
+
+def test_instances_must_copy_their_shape():
+    pd = _pd()
+    prob = bed(seed=23)
+    sp = prob.meta["shape_of_particle"].copy()
+    # a disk labelled as the shape of a plus
+    sp[np.nonzero(sp == 0)[0][1]] = 1
+    g = pd.PD(prob)
+    with pytest.raises(pd.PDError) as ei:
+        g.closure_setup(sp)
+    assert ei.value.status == pd.PD_E_INVALID
+
+
+# ----------------------------------------------------------------------------
+# the MLP: forward and gradients
+# ----------------------------------------------------------------------------
+def _mlp_ctx(setup_bed):
+    pd = _pd()
+    prob, modes, s0 = setup_bed
+    g = pd.PD(prob)
+    g.closure_setup(prob.meta["shape_of_particle"], check_every=0)
+    load_modes(g, modes)
+    return g, modes
+
+
+@pytest.mark.parametrize("n", [1, 16, 37, 300])
+def test_mlp_forward_matches_oracle(setup_bed, n):
+    g, modes = _mlp_ctx(setup_bed)
+    s = 2
+    lam = modes[s][1]
+    rng = np.random.default_rng(40 + n)
+    params = rand_params(41)
+    sq = rng.uniform(0.5, 2.0, 32).astype(np.float32)
+    sr = (rng.uniform(0.5, 2.0, 32) * 0.05 * lam * sq).astype(np.float32)
+    g.closure_load(s, params, sq, sr)
+    q = rng.normal(0, 1.5, (n, 32)) * sq
+    out = g.closure_forward(s, q)
+    ref = CL.closure_modal_force(q, lam, params, sq.astype(np.float64), sr.astype(np.float64))
+    # the MLP part to bfloat16 operand precision, the linear part exactly
+    mlp_g, mlp_o = out + lam * q, ref + lam * q
+    assert rel(mlp_g, mlp_o) < 1e-3
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-3 * np.abs(mlp_o).max() + 1e-12 * np.abs(lam * q).max())
+
+
+@pytest.mark.parametrize("n", [16, 45, 256])
+def test_mlp_gradients_match_oracle(setup_bed, n):
+    g, modes = _mlp_ctx(setup_bed)
+    s = 1
+    lam = modes[s][1]
+    rng = np.random.default_rng(50 + n)
+    params = rand_params(51)
+    sq = rng.uniform(0.5, 2.0, 32).astype(np.float32)
+    sr = rng.uniform(0.5, 2.0, 32).astype(np.float32)
+    g.closure_load(s, params, sq, sr)
+    q = rng.normal(0, 1.0, (n, 32)) * sq
+    gt = rng.normal(0, 1.0, (n, 32)) * sr - lam * q
+    loss_g, grads_g = g.closure_grads(s, q, gt)
+    loss_o, grads_o = CL.loss_and_grads(params, q, gt + lam * q, sq.astype(np.float64),
+                                        sr.astype(np.float64), bf16=True)
+    assert abs(loss_g - loss_o) <= 1e-5 * loss_o
+    k = 0
+    for (o, i), name in zip(CL.LAYERS, ("1", "2", "3")):
+        for part, size in (("W" + name, o * i), ("b" + name, o)):
+            a, b = grads_g[k:k + size], grads_o[k:k + size]
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), part
+            k += size
+
+
+# ----------------------------------------------------------------------------
+# the closure step
+# ----------------------------------------------------------------------------
+def _run_pair(setup_bed, steps, mode, frac_range=(0.05, 0.3), gate=0.5, tau_c=BIG, params=None,
+              seed=60):
+    pd = _pd()
+    prob, modes, s0 = setup_bed
+    prob = modal_deformation(bed(), modes, seed, frac_range, s0)
+    sp = prob.meta["shape_of_particle"]
+    S = len(modes)
+    g = pd.PD(prob)
+    g.closure_setup(sp, gate_frac=gate, tau_c=[tau_c] * S, check_every=0)
+    load_modes(g, modes)
+    sq = sr = None
+    if params is not None:
+        # inputs scaled to unit size, the network's output to a few per cent
+        # of the linear modal force
+        qs = initial_q(prob, modes)
+        sq = {s: np.sqrt((qs[s] ** 2).mean(0)).astype(np.float32).astype(np.float64) for s in modes}
+        sr = {s: (3e-2 * modes[s][1] * sq[s]).astype(np.float32).astype(np.float64) for s in modes}
+        for s in modes:
+            g.closure_load(s, params[s], sq[s], sr[s])
+    g.closure_enable(mode)
+    o = Oracle(prob, contact_mode=1)
+    st = CL.ClosureStepper(o, prob, sp, modes, [s0] * S, [tau_c] * S, gate, params=params,
+                           sig_q=sq, sig_r=sr)
+    off = []
+    for _ in range(steps):
+        off += st.step()
+    g.step(steps)
+    return g, o, st, off
+
+
+def _compare_states(g, o, tol):
+    a, b = g.get_state(), o.get_state()
+    for k in ("ux", "uy"):
+        assert rel(a[k], b[k]) < tol, k
+    for k in ("vx", "vy"):
+        assert rel(a[k], b[k]) < tol, k
+
+
+def test_linear_closure_steps_match_oracle(setup_bed):
+    g, o, st, off = _run_pair(setup_bed, 40, 1)
+    assert off == []
+    _compare_states(g, o, 1e-9)
+    p, s, act = g.closure_particles()
+    assert np.all(act == 1)
+    assert g.damage()[1] == 0
+
+
+def test_learned_closure_steps_match_oracle(setup_bed):
+    prob, modes, s0 = setup_bed
+    params = {s: rand_params(70 + s) for s in modes}
+    g, o, st, off = _run_pair(setup_bed, 30, 2, params=params)
+    _compare_states(g, o, 1e-6)
+
+
+def test_gate_fallbacks_match_oracle(setup_bed):
+    """Particles whose stretch bound passes the gate go back to the plain
+    bond force after the step, on both sides."""
+    g, o, st, off = _run_pair(setup_bed, 40, 1, frac_range=(0.02, 0.4), gate=0.2, seed=61)
+    assert len(off) > 0
+    p, s, act = g.closure_particles()
+    np.testing.assert_array_equal(act.astype(bool), st.active[p])
+    assert g.closure_stats()["fallbacks"] == len(off)
+    _compare_states(g, o, 1e-9)
+
+
+def test_periodic_check_matches_oracle(setup_bed):
+    g, o, st, off = _run_pair(setup_bed, 25, 1, seed=62)
+    g.closure_check()
+    e2, n2, l2, out = st.check(0.05)
+    stt = g.closure_stats()
+    assert abs(stt["err"] - math.sqrt(e2 / n2)) <= 1e-8 * math.sqrt(e2 / n2)
+    assert abs(stt["err_linear"] - math.sqrt(l2 / n2)) <= 1e-8 * math.sqrt(l2 / n2)
+    p, s, act = g.closure_particles()
+    np.testing.assert_array_equal(act.astype(bool), st.active[p])
+
+
+def test_snapshot_matches_oracle(setup_bed):
+    pd = _pd()
+    prob, modes, s0 = setup_bed
+    prob = modal_deformation(bed(), modes, 63, (0.05, 0.3), s0)
+    g = pd.PD(prob)
+    g.closure_setup(prob.meta["shape_of_particle"], check_every=0)
+    load_modes(g, modes)
+    q, gp = g.closure_snapshot()
+    o = Oracle(prob, contact_mode=1)
+    fx, fy = o.forces(T_PD)
+    st = o.get_state()
+    first = first_of_shape(prob)
+    p_of, s_of, _ = g.closure_particles()
+    for k, (p, s) in enumerate(zip(p_of, s_of)):
+        n0, n1 = CL.particle_range(prob, p)
+        V = prob.vol[n0:n1]
+        y = np.stack([prob.x[n0:n1] + st["ux"][n0:n1], prob.y[n0:n1] + st["uy"][n0:n1]], axis=1)
+        F = np.stack([fx[n0:n1] * V, fy[n0:n1] * V], axis=1)
+        _, Xt = CL.reference_frame(prob, first[s])
+        pr = CL.project(Xt, CL.node_masses(prob, p), modes[s][0], y, np.zeros_like(y), F)
+        assert rel(q[k], pr["q"]) < 1e-9
+        assert rel(gp[k], pr["gext"]) < 1e-9
+
+
+def test_closure_off_is_the_plain_path(setup_bed):
+    pd = _pd()
+    prob, modes, s0 = setup_bed
+    prob = modal_deformation(bed(), modes, 64, (0.05, 0.3), s0)
+    a = pd.PD(prob)
+    b = pd.PD(prob)
+    b.closure_setup(prob.meta["shape_of_particle"], check_every=0)
+    b.closure_enable(1)
+    b.closure_enable(0)
+    a.step(50)
+    b.step(50)
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("ux", "uy", "vx", "vy", "ax", "ay"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+
+
+# ----------------------------------------------------------------------------
+# training and what it gains over the linear closure
+# ----------------------------------------------------------------------------
+def test_training_gains_over_linear_closure():
+    """Train each shape's network on snapshots of a plain-PD run on the GPU,
+    then compare, on states of a different run made by the oracle, the modal
+    force of the learned and of the linear closure with the oracle's modal PD
+    force."""
+    pd = _pd()
+    import torch
+    base = bed(seed=80, n_per_shape=6, vmax=0.0)
+    o0 = Oracle(base, contact_mode=1)
+    modes = oracle_modes(base, o0)
+    s0 = float(o0.constants()["s0"][0])
+    S = len(modes)
+    sp = base.meta["shape_of_particle"]
+    # training data: a GPU run from seeded modal deformations
+    train = modal_deformation(bed(seed=80, n_per_shape=6, vmax=0.0), modes, 81, (0.3, 0.6), s0)
+    g = pd.PD(train)
+    g.closure_setup(sp, check_every=0)
+    load_modes(g, modes)
+    Q, G = [], []
+    for _ in range(400):
+        g.step(5)
+        q, gg = g.closure_snapshot(device=True)
+        Q.append(q)
+        G.append(gg)
+    Q, G = torch.cat(Q), torch.cat(G)
+    p_of, s_of, _ = g.closure_particles()
+    rows = np.tile(s_of, len(Q) // len(s_of))
+    losses = {}
+    for s in range(S):
+        sel = torch.from_numpy(np.nonzero(rows == s)[0]).cuda()
+        losses[s] = g.closure_train(s, Q[sel], G[sel], iters=1500, batch=256, lr=2e-3, seed=s)
+        assert losses[s][-100:].mean() < 0.5 * losses[s][:20].mean()
+    # held-out states: the oracle's own plain run from other deformations
+    test = modal_deformation(bed(seed=80, n_per_shape=6, vmax=0.0), modes, 82, (0.3, 0.6), s0)
+    o = Oracle(test, contact_mode=1)
+    first = first_of_shape(test)
+    err_l = {s: [0.0, 0.0] for s in range(S)}
+    err_n = {s: [0.0, 0.0] for s in range(S)}
+    for _ in range(20):
+        o.step(10)
+        st = o.get_state()
+        fx, fy = o.forces(T_PD)
+        qs = {s: [] for s in range(S)}
+        gs = {s: [] for s in range(S)}
+        for p in range(test.n_particles):
+            s = int(sp[p])
+            n0, n1 = CL.particle_range(test, p)
+            V = test.vol[n0:n1]
+            y = np.stack([test.x[n0:n1] + st["ux"][n0:n1], test.y[n0:n1] + st["uy"][n0:n1]], axis=1)
+            F = np.stack([fx[n0:n1] * V, fy[n0:n1] * V], axis=1)
+            _, Xt = CL.reference_frame(test, first[s])
+            pr = CL.project(Xt, CL.node_masses(test, p), modes[s][0], y, np.zeros_like(y), F)
+            qs[s].append(pr["q"])
+            gs[s].append(pr["gext"])
+        for s in range(S):
+            q, gp = np.array(qs[s]), np.array(gs[s])
+            gn = g.closure_forward(s, q)
+            gl = -modes[s][1] * q
+            err_n[s][0] += ((gn - gp) ** 2).sum()
+            err_l[s][0] += ((gl - gp) ** 2).sum()
+            err_n[s][1] += (gp ** 2).sum()
+    for s in range(S):
+        en = math.sqrt(err_n[s][0] / err_n[s][1])
+        el = math.sqrt(err_l[s][0] / err_n[s][1])
+        print(f"shape {s}: linear closure error {el:.3e}, learned {en:.3e}")
+        assert en < 0.7 * el, (s, en, el)
