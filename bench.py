@@ -122,6 +122,7 @@ def precision_split(pd, W, torch, steps):
         sps = steps / (time.perf_counter() - t0)
         n_pairs = g.sizes()["bonds"] // 2
         res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+                     "list_rebuilds": gr.sizes()["list_rebuilds"],
                      "force_kernel_ms": g.time_kernels(128)["force"][0]}
     return res
 
@@ -241,11 +242,13 @@ def closure(pd, W, torch, steps, train_iters):
     for s in range(4):
         sel = torch.nonzero(rows == s).flatten()
         L = g.closure_train(s, Q[sel], G[sel], iters=train_iters, batch=1024, lr=2e-3, seed=s)
-        losses[s] = [float(L[:50].mean()), float(L[-50:].mean())]
+        losses[s] = [float(L[0]), float(L[:50].mean()), float(L[-50:].mean())]
         params[s] = g.closure_get(s)
+        res.setdefault("sigma_r_mean", {})[s] = float(params[s][2].mean())
+        res.setdefault("samples", {})[s] = int(sel.numel())
     torch.cuda.synchronize()
     res["train_s"] = time.perf_counter() - t0
-    res["train_loss_first_last"] = losses
+    res["train_loss_first_head_last"] = losses
     # held-out snapshots: learned vs linear closure against the plain force
     test = modal_excitation(mk(), modes, 52, strain)
     gt = pd.PD(test)
@@ -282,6 +285,7 @@ def closure(pd, W, torch, steps, train_iters):
         st = gr.closure_stats()
         n_pairs = gr.sizes()["bonds"] // 2
         res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+                     "list_rebuilds": gr.sizes()["list_rebuilds"],
                      "active": st["active"], "fallbacks": st["fallbacks"], "checks": st["checks"],
                      "check_err": st["err"] if mode else None,
                      "check_err_linear": st["err_linear"] if mode else None}

@@ -251,7 +251,7 @@ pd_status pd_sizes(const pd_ctx *c, int64_t out[10]);
  * diameter).  Network parameters start at zero, i.e. the linear closure.
  * The closure starts switched off (pd_closure_enable).  PD_E_INVALID on a
  * particle that is not a copy of its shape, a shape with more than three
- * zero-stiffness modes, or more than 1536 nodes. */
+ * zero-stiffness modes, or more than 1024 nodes. */
 pd_status pd_closure_setup(pd_ctx *c, const int32_t *shape_of_particle, double gate_frac,
                            const double *tau_c, int32_t check_every, double err_tol);
 /* the shape's modes (host buffers, any may be NULL): n_nodes, mode count,

@@ -100,7 +100,7 @@ __device__ __forceinline__ bool replay_stale(const DevArgs &a, bool list) {
 //                 active particles; gext then holds the modal PD force
 // mode 2 (snapshot): as 1, for every closure particle
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int list, int mode) {
+__global__ __launch_bounds__(256, 4) void k_cl_project(DevArgs a, ClArgs c, int list, int mode) {
     extern __shared__ double shm[];
     if (replay_stale(a, list && mode == 0)) return;
     const int ci = blockIdx.x;
@@ -109,18 +109,27 @@ __global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int lis
     const int s = c.cshape[ci];
     const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
     const int t0 = c.toff[s];
-    double *red = shm;               // [4 * 8] reduction scratch
-    double *sub = shm + 32;          // [8][32][2] partial modal sums
-    double *UB = shm + 32 + 512;     // [n] body-frame displacement x, y, force x, y
+    double *red = shm;               // [4 * 16] reduction scratch
+    double *sub = shm + 64;          // [8][32][2] partial modal sums
+    // the particle's nodes, read once: positions relative to its first node,
+    // forces, masses
+    double *Px = shm + 576, *Py = Px + n, *Fx = Py + n, *Fy = Fx + n, *Ms = Fy + n;
     const double *ux = mode == 0 ? a.ux_o : a.ux;
     const double *uy = mode == 0 ? a.uy_o : a.uy;
     const int tid = threadIdx.x;
+    const double rx = a.x[n0] + ux[n0], ry = a.y[n0] + uy[n0];
 
-    double v7[7] = {0, 0, 0, 0, 0, 0, 0};
+    // every sum in one pass: moments about the first node, shifted to the
+    // centroid below (the template coordinates X are centred, so the
+    // Procrustes sums need no shift beyond sum m X, which is ~0)
+    double v[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) v[k] = 0.0;
     for (int k = tid; k < n; k += 256) {
         const int i = n0 + k;
         const double m = a.mass[i];
-        const double yx = a.x[i] + ux[i], yy = a.y[i] + uy[i];
+        const double yx = (a.x[i] + ux[i]) - rx, yy = (a.y[i] + uy[i]) - ry;
+        const double vx = a.vx[i], vy = a.vy[i];
         double fx, fy;
         if (mode == 0) {
             fx = a.cl_fx[i];
@@ -129,62 +138,50 @@ __global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int lis
             fx = a.terms[i] * a.vol[i];
             fy = a.terms[a.N + i] * a.vol[i];
         }
-        v7[0] += m;
-        v7[1] += m * yx;
-        v7[2] += m * yy;
-        v7[3] += m * a.vx[i];
-        v7[4] += m * a.vy[i];
-        v7[5] += fx;
-        v7[6] += fy;
-    }
-    block_sum<7>(v7, red);
-    const double M = v7[0];
-    const double cx = v7[1] / M, cy = v7[2] / M;
-    const double vcx = v7[3] / M, vcy = v7[4] / M;
-
-    double v6[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = tid; k < n; k += 256) {
-        const int i = n0 + k;
-        const double m = a.mass[i];
-        const double Yx = (a.x[i] + ux[i]) - cx, Yy = (a.y[i] + uy[i]) - cy;
         const double Xx = c.tX[t0 + k], Xy = c.tY[t0 + k];
-        double fx, fy;
-        if (mode == 0) {
-            fx = a.cl_fx[i];
-            fy = a.cl_fy[i];
-        } else {
-            fx = a.terms[i] * a.vol[i];
-            fy = a.terms[a.N + i] * a.vol[i];
-        }
-        const double dvx = a.vx[i] - vcx, dvy = a.vy[i] - vcy;
-        v6[0] += m * (Xx * Yy - Xy * Yx);
-        v6[1] += m * (Xx * Yx + Xy * Yy);
-        v6[2] += m * (Yx * Yx + Yy * Yy);
-        v6[3] += m * (Yx * dvy - Yy * dvx);
-        v6[4] += Yx * fy - Yy * fx;
-        v6[5] += sqrt(fx * fx + fy * fy);
+        Px[k] = yx;
+        Py[k] = yy;
+        Fx[k] = fx;
+        Fy[k] = fy;
+        Ms[k] = m;
+        v[0] += m;
+        v[1] += m * yx;
+        v[2] += m * yy;
+        v[3] += m * vx;
+        v[4] += m * vy;
+        v[5] += fx;
+        v[6] += fy;
+        v[7] += m * (Xx * yy - Xy * yx);
+        v[8] += m * (Xx * yx + Xy * yy);
+        v[9] += m * (yx * yx + yy * yy);
+        v[10] += m * (yx * vy - yy * vx);
+        v[11] += yx * fy - yy * fx;
+        v[12] += sqrt(fx * fx + fy * fy);
+        v[13] += m * Xx;
+        v[14] += m * Xy;
     }
-    block_sum<6>(v6, red);
-    const double phi = atan2(v6[0], v6[1]);
-    const double cp = cos(phi), sp = sin(phi);
-    const double I = v6[2];
-    // body-frame displacement and force, staged for the modal sums
+    block_sum<15>(v, red);
+    const double M = v[0];
+    const double cx = v[1] / M, cy = v[2] / M;        // centroid, relative
+    const double vcx = v[3] / M, vcy = v[4] / M;
+    const double Ftx = v[5], Fty = v[6];
+    const double cross = v[7] - (v[13] * cy - v[14] * cx);
+    const double dot = v[8] - (v[13] * cx + v[14] * cy);
+    const double I = v[9] - M * (cx * cx + cy * cy);
+    const double Lz = v[10] - M * (cx * vcy - cy * vcx);
+    const double tau = v[11] - (cx * Fty - cy * Ftx);
+    // the best-fit rotation: (cos, sin) = (dot, cross) / |(dot, cross)|
+    const double nr = sqrt(dot * dot + cross * cross);
+    const double cp = dot / nr, sp = cross / nr;
+    // body-frame displacement (times the mass) and force, in place
     for (int k = tid; k < n; k += 256) {
-        const int i = n0 + k;
-        const double Yx = (a.x[i] + ux[i]) - cx, Yy = (a.y[i] + uy[i]) - cy;
-        double fx, fy;
-        if (mode == 0) {
-            fx = a.cl_fx[i];
-            fy = a.cl_fy[i];
-        } else {
-            fx = a.terms[i] * a.vol[i];
-            fy = a.terms[a.N + i] * a.vol[i];
-        }
-        const double m = a.mass[i];
-        UB[4 * k + 0] = m * ((cp * Yx + sp * Yy) - c.tX[t0 + k]);
-        UB[4 * k + 1] = m * ((-sp * Yx + cp * Yy) - c.tY[t0 + k]);
-        UB[4 * k + 2] = cp * fx + sp * fy;
-        UB[4 * k + 3] = -sp * fx + cp * fy;
+        const double m = Ms[k];
+        const double Yx = Px[k] - cx, Yy = Py[k] - cy;
+        const double fx = Fx[k], fy = Fy[k];
+        Px[k] = m * ((cp * Yx + sp * Yy) - c.tX[t0 + k]);
+        Py[k] = m * ((-sp * Yx + cp * Yy) - c.tY[t0 + k]);
+        Fx[k] = cp * fx + sp * fy;
+        Fy[k] = -sp * fx + cp * fy;
     }
     __syncthreads();
     // modal sums: thread (g, k) takes nodes g, g + 8, ... of mode k
@@ -192,10 +189,20 @@ __global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int lis
         const int k = tid & 31, g = tid >> 5;
         double sq = 0.0, sf = 0.0;
         const float2 *ph = reinterpret_cast<const float2 *>(c.phi) + (size_t)t0 * kClModes + k;
-        for (int j = g; j < n; j += 8) {
-            const float2 f = ph[(size_t)j * kClModes];
-            sq += (double)f.x * UB[4 * j] + (double)f.y * UB[4 * j + 1];
-            sf += (double)f.x * UB[4 * j + 2] + (double)f.y * UB[4 * j + 3];
+        // four mode-row loads in flight per pass
+        for (int j0 = g; j0 < n; j0 += 32) {
+            float2 f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + 8 * u;
+                f[u] = j < n ? ph[(size_t)j * kClModes] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = min(j0 + 8 * u, n - 1);
+                sq += (double)f[u].x * Px[j] + (double)f[u].y * Py[j];
+                sf += (double)f[u].x * Fx[j] + (double)f[u].y * Fy[j];
+            }
         }
         sub[(g * 32 + k) * 2] = sq;
         sub[(g * 32 + k) * 2 + 1] = sf;
@@ -215,18 +222,20 @@ __global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int lis
         if (tid == 0) {
             double *R = c.red + (size_t)ci * 16;
             R[R_M] = M;
-            R[R_CX] = cx;
-            R[R_CY] = cy;
+            R[R_CX] = rx + cx;
+            R[R_CY] = ry + cy;
             R[R_VCX] = vcx;
             R[R_VCY] = vcy;
-            R[R_PHI] = phi;
+            R[R_PHI] = 0.0;
+            R[R_COS] = cp;
+            R[R_SIN] = sp;
             R[R_I] = I;
-            R[R_OM] = v6[3] / I;
-            R[R_FX] = v7[5];
-            R[R_FY] = v7[6];
-            R[R_TAU] = v6[4];
+            R[R_OM] = Lz / I;
+            R[R_FX] = Ftx;
+            R[R_FY] = Fty;
+            R[R_TAU] = tau;
             R[R_STRAIN] = b;
-            R[R_CONTACT] = v6[5];
+            R[R_CONTACT] = v[12];
         }
     }
 }
@@ -237,6 +246,7 @@ __global__ __launch_bounds__(256) void k_cl_project(DevArgs a, ClArgs c, int lis
 __global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list) {
     __shared__ double qdd[kClModes];
     __shared__ double R[16];
+    __shared__ int stale_any;
     if (replay_stale(a, list)) return;
     const int ci = blockIdx.x;
     const int p = c.cpart[ci];
@@ -251,26 +261,30 @@ __global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list)
         qdd[tid] = g + c.gext[ci * kClModes + tid];
     }
     if (tid < 16) R[tid] = c.red[(size_t)ci * 16 + tid];
+    if (tid == 0) stale_any = 0;
     __syncthreads();
     const double M = R[R_M], cx = R[R_CX], cy = R[R_CY];
-    const double cp = cos(R[R_PHI]), sp = sin(R[R_PHI]);
+    const double cp = R[R_COS], sp = R[R_SIN];
     const double alpha = R[R_TAU] / R[R_I], om2 = R[R_OM] * R[R_OM];
     const double atx = R[R_FX] / M + a.gx, aty = R[R_FY] / M + a.gy;
+    // a thread per node; the mode-major copy of the modes makes each load
+    // contiguous across the wavefront
     int st = 0;
     bool stale = false;
     for (int k = tid; k < n; k += 256) {
         const int i = n0 + k;
+        const float2 *ph = c.phiT + t0 + k;
+        float2 f[kClModes];
+#pragma unroll
+        for (int m = 0; m < kClModes; ++m) f[m] = ph[(size_t)m * c.NT];
+        double bx = 0.0, by = 0.0;
+#pragma unroll
+        for (int m = 0; m < kClModes; ++m) {
+            bx += (double)f[m].x * qdd[m];
+            by += (double)f[m].y * qdd[m];
+        }
         const double ux = a.ux_o[i], uy = a.uy_o[i];
         const double Yx = (a.x[i] + ux) - cx, Yy = (a.y[i] + uy) - cy;
-        // modal acceleration in the body frame, sum_k Phi_ik qdd_k
-        const float4 *ph = reinterpret_cast<const float4 *>(c.phi + (size_t)(t0 + k) * 2 * kClModes);
-        double bx = 0.0, by = 0.0;
-#pragma unroll 4
-        for (int m2 = 0; m2 < kClModes / 2; ++m2) {
-            const float4 f = ph[m2];
-            bx += (double)f.x * qdd[2 * m2] + (double)f.z * qdd[2 * m2 + 1];
-            by += (double)f.y * qdd[2 * m2] + (double)f.w * qdd[2 * m2 + 1];
-        }
         const double axn = ((atx - alpha * Yy) - om2 * Yx) + (cp * bx - sp * by);
         const double ayn = ((aty + alpha * Yx) - om2 * Yy) + (sp * bx + cp * by);
         const double vxn = a.vx[i] + a.hdt * (a.ax[i] + axn);
@@ -288,18 +302,20 @@ __global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list)
         }
     }
     if (st) atomicOr(a.status, st);
-    if (stale) {
-        const long long sprev = *a.step_base + a.chunk_k;
-        atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
-    }
+    if (stale) stale_any = 1;
     __syncthreads();
-    // gate for the next step: a particle whose bound on the bond stretch passes
-    // gate_frac * s0, or whose contact load passes tau_c, goes back to the
-    // plain bond force
-    if (tid == 0 &&
-        (R[R_STRAIN] > c.gate_frac * c.s0[s] || R[R_CONTACT] > c.tau_c[s])) {
-        a.cl_on[p] = 0;
-        atomicAdd(c.fallbacks, 1ull);
+    if (tid == 0) {
+        if (stale_any) {
+            const long long sprev = *a.step_base + a.chunk_k;
+            atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+        }
+        // gate for the next step: a particle whose bound on the bond stretch
+        // passes gate_frac * s0, or whose contact load passes tau_c, goes back
+        // to the plain bond force
+        if (R[R_STRAIN] > c.gate_frac * c.s0[s] || R[R_CONTACT] > c.tau_c[s]) {
+            a.cl_on[p] = 0;
+            atomicAdd(c.fallbacks, 1ull);
+        }
     }
 }
 
@@ -368,82 +384,103 @@ __global__ __launch_bounds__(256) void k_cl_check_sum(const double *per, int Pc,
 }
 
 // ---------------------------------------------------------------------------
-// the MLP forward: one wavefront per 16-row block.  MFMA operand layout
-// (v_mfma_f32_16x16x16 bf16): lane l holds A[l % 16][4 (l / 16) + t] and
-// B[4 (l / 16) + t][l % 16], t = 0..3, and receives D[4 (l / 16) + t][l % 16].
+// the MLP forward: one workgroup per 16-row block; its eight wavefronts split
+// the output columns of each layer (32 of the 256 hidden units each, all
+// weight fragments of a wave loaded before its MFMAs; the two 16-column tiles
+// of the last layer go to waves 0 and 1), and the layers meet in LDS.  MFMA operand layout (v_mfma_f32_16x16x16 bf16): lane l holds
+// A[l % 16][4 (l / 16) + t] and B[4 (l / 16) + t][l % 16], t = 0..3, and
+// receives D[4 (l / 16) + t][l % 16].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs m, DevArgs a, int list) {
-    __shared__ uint16_t H1s[4][16 * kClHidden];
-    __shared__ uint16_t H2s[4][16 * kClHidden];
+constexpr int kMlpWaves = 8;
+
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a, int list) {
+    __shared__ uint16_t Xs[16 * kClModes];
+    __shared__ uint16_t H1[16 * kClHidden];
+    __shared__ uint16_t H2[16 * kClHidden];
+    __shared__ int rows_ok[16];
     if (list && replay_stale(a, true)) return;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int rb = blockIdx.x * 4 + wv;
-    int s = m.shape, first = 16 * rb, cnt = 0;
-    if (rb < m.row_blocks) {
-        if (m.rb_shape) {
-            s = m.rb_shape[rb];
-            first = m.rb_first[rb];
-            cnt = m.rb_count[rb];
-        } else {
-            cnt = min(16, m.rows - first);
-        }
+    const int rb = blockIdx.x;
+    int s = m.shape, first = 16 * rb, cnt;
+    if (m.rb_shape) {
+        s = m.rb_shape[rb];
+        first = m.rb_first[rb];
+        cnt = m.rb_count[rb];
+    } else {
+        cnt = min(16, m.rows - first);
     }
     const uint16_t *W = m.wb + (size_t)s * kClParams;
     const float *Wf = m.wf + (size_t)s * kClParams;
-    uint16_t *H1 = H1s[wv], *H2 = H2s[wv];
     const int r = l & 15, kq = 4 * (l >> 4);
-    // row r of this lane's A operand
-    const bool rvalid = r < cnt && (!m.on || m.on[m.cpart[first + r]]);
-    const int src = rvalid ? (m.idx ? m.idx[first + r] : first + r) : 0;
-
-    // ---- layer 1: x (16 x 32) W1^T -----------------------------------------
-    bf16x4 ax[2];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int col = 16 * ks + kq + t;
-            float xv = 0.0f;
-            if (rvalid) xv = (float)(m.q[(size_t)src * kClModes + col] / (double)m.sig_q[s * kClModes + col]);
-            const uint16_t b = f2bf(xv);
-            ax[ks][t] = (short)b;
-            if (m.xb && rvalid) m.xb[(size_t)(first + r) * kClModes + col] = b;
-        }
+    if (threadIdx.x < 16) {
+        const int rr = threadIdx.x;
+        rows_ok[rr] = rr < cnt && (!m.on || m.on[m.cpart[first + rr]]);
     }
-    for (int j = 0; j < kClHidden / 16; ++j) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const int n = 16 * j + r;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const bf16x4 b = load4(W + kOffW1 + n * kClModes + 16 * ks + kq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax[ks], b, acc, 0, 0, 0);
+    __syncthreads();
+    // normalised inputs, bfloat16
+    for (int e = threadIdx.x; e < 16 * kClModes; e += 64 * kMlpWaves) {
+        const int row = e / kClModes, col = e % kClModes;
+        float xv = 0.0f;
+        if (rows_ok[row]) {
+            const int src = m.idx ? m.idx[first + row] : first + row;
+            xv = (float)(m.q[(size_t)src * kClModes + col] / (double)m.sig_q[s * kClModes + col]);
         }
-        const float bias = Wf[kOffB1 + n];
+        const uint16_t b = f2bf(xv);
+        Xs[e] = b;
+        if (m.xb && row < cnt) m.xb[(size_t)(first + row) * kClModes + col] = b;
+    }
+    __syncthreads();
+    // ---- layer 1: x (16 x 32) W1^T, columns 32 wv .. 32 wv + 31 -----------------
+    constexpr int TPW = kClHidden / 16 / kMlpWaves;  // column tiles per wave
+    {
+        const bf16x4 a0 = load4(Xs + r * kClModes + kq), a1 = load4(Xs + r * kClModes + 16 + kq);
+        bf16x4 bw[TPW][2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int row = kq + t;
-            const float z = acc[t] + bias;
-            const uint16_t h = f2bf(silu_f(z));
-            H1[row * kClHidden + n] = h;
-            if (m.z1 && row < cnt) {
-                m.z1[(size_t)(first + row) * kClHidden + n] = z;
-                m.h1[(size_t)(first + row) * kClHidden + n] = h;
+        for (int jj = 0; jj < TPW; ++jj) {
+            const int n = 16 * (TPW * wv + jj) + r;
+            bw[jj][0] = load4(W + kOffW1 + n * kClModes + kq);
+            bw[jj][1] = load4(W + kOffW1 + n * kClModes + 16 + kq);
+        }
+#pragma unroll
+        for (int jj = 0; jj < TPW; ++jj) {
+            const int n = 16 * (TPW * wv + jj) + r;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, bw[jj][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, bw[jj][1], acc, 0, 0, 0);
+            const float bias = Wf[kOffB1 + n];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = kq + t;
+                const float z = acc[t] + bias;
+                const uint16_t h = f2bf(silu_f(z));
+                H1[row * kClHidden + n] = h;
+                if (m.z1 && row < cnt) {
+                    m.z1[(size_t)(first + row) * kClHidden + n] = z;
+                    m.h1[(size_t)(first + row) * kClHidden + n] = h;
+                }
             }
         }
     }
     __syncthreads();
-    // ---- layer 2: h1 (16 x 256) W2^T ------------------------------------------
+    // ---- layer 2: h1 (16 x 256) W2^T, columns 32 wv .. 32 wv + 31 ---------------
     {
+        bf16x4 bw[TPW][16];
+#pragma unroll
+        for (int jj = 0; jj < TPW; ++jj) {
+            const uint16_t *wr = W + kOffW2 + (size_t)(16 * (TPW * wv + jj) + r) * kClHidden + kq;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) bw[jj][ks] = load4(wr + 16 * ks);
+        }
         bf16x4 ah[16];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H1 + r * kClHidden + 16 * ks + kq);
-        for (int j = 0; j < kClHidden / 16; ++j) {
+#pragma unroll
+        for (int jj = 0; jj < TPW; ++jj) {
+            const int n = 16 * (TPW * wv + jj) + r;
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            const int n = 16 * j + r;
-            const uint16_t *wr = W + kOffW2 + (size_t)n * kClHidden + kq;
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], load4(wr + 16 * ks), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], bw[jj][ks], acc, 0, 0, 0);
             const float bias = Wf[kOffB2 + n];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -459,32 +496,32 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs m, DevArgs a, int list)
         }
     }
     __syncthreads();
-    // ---- layer 3: h2 (16 x 256) W3^T ------------------------------------------
-    {
-        bf16x4 ah[16];
+    // ---- layer 3: h2 (16 x 256) W3^T, column tile wv (waves 0 and 1) -----------
+    if (wv < kClModes / 16) {
+        const int n = 16 * wv + r;
+        const uint16_t *wr = W + kOffW3 + (size_t)n * kClHidden + kq;
+        bf16x4 ah[16], bw[16];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
-        for (int j = 0; j < kClModes / 16; ++j) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            const int n = 16 * j + r;
-            const uint16_t *wr = W + kOffW3 + (size_t)n * kClHidden + kq;
+        for (int ks = 0; ks < 16; ++ks) {
+            ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
+            bw[ks] = load4(wr + 16 * ks);
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], load4(wr + 16 * ks), acc, 0, 0, 0);
-            const float bias = Wf[kOffB3 + n];
+        for (int ks = 0; ks < 16; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], bw[ks], acc, 0, 0, 0);
+        const float bias = Wf[kOffB3 + n];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = kq + t;
-                if (row >= cnt) continue;
-                if (m.on && !m.on[m.cpart[first + row]]) continue;
-                const float y = acc[t] + bias;
-                if (m.y) m.y[(size_t)(first + row) * kClModes + n] = y;
-                if (m.g) {
-                    const int sr = m.idx ? m.idx[first + row] : first + row;
-                    const double q = m.q[(size_t)sr * kClModes + n];
-                    m.g[(size_t)(first + row) * kClModes + n] =
-                        -m.lam[s * kClModes + n] * q + (double)m.sig_r[s * kClModes + n] * (double)y;
-                }
+        for (int t = 0; t < 4; ++t) {
+            const int row = kq + t;
+            if (!rows_ok[row]) continue;
+            const float y = acc[t] + bias;
+            if (m.y) m.y[(size_t)(first + row) * kClModes + n] = y;
+            if (m.g) {
+                const int sr = m.idx ? m.idx[first + row] : first + row;
+                const double q = m.q[(size_t)sr * kClModes + n];
+                m.g[(size_t)(first + row) * kClModes + n] =
+                    -m.lam[s * kClModes + n] * q + (double)m.sig_r[s * kClModes + n] * (double)y;
             }
         }
     }
@@ -534,15 +571,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
 }
 
 // dy = 2 (y - r / sigma_r) / (rows * 32), r = g + lambda q of the batch's
-// samples, and the mean squared error (one workgroup, fixed order)
+// samples; each workgroup leaves its part of the squared error in part[]
 __global__ __launch_bounds__(256) void k_mlp_loss(MlpArgs m, const double *g, float *dy,
-                                                  uint16_t *dyb, float *loss) {
+                                                  uint16_t *dyb, double *part) {
     __shared__ double sh[4];
     const int s = m.shape;
     const int total = m.rows * kClModes;
     const float scale = 2.0f / (float)total;
     double acc[1] = {0.0};
-    for (int e = threadIdx.x; e < total; e += 256) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < total) {
         const int b = e / kClModes, k = e % kClModes;
         const int src = m.idx ? m.idx[b] : b;
         const double q = m.q[(size_t)src * kClModes + k];
@@ -552,19 +590,31 @@ __global__ __launch_bounds__(256) void k_mlp_loss(MlpArgs m, const double *g, fl
         const float v = scale * d;
         dy[e] = v;
         dyb[e] = f2bf(v);
-        acc[0] += (double)d * (double)d;
+        acc[0] = (double)d * (double)d;
     }
     block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) *loss = (float)(acc[0] / total);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-// column sums of X [rows][cols] (bias gradients), one thread per column
-__global__ void k_colsum(const float *X, int rows, int cols, float *out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    float s = 0.0f;
-    for (int b = 0; b < rows; ++b) s += X[(size_t)b * cols + j];
-    out[j] = s;
+// the mean squared error from the per-workgroup parts, in order
+__global__ __launch_bounds__(256) void k_loss_sum(const double *part, int nparts, int total,
+                                                  float *loss) {
+    __shared__ double sh[4];
+    double v[1] = {0.0};
+    for (int k = threadIdx.x; k < nparts; k += 256) v[0] += part[k];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) *loss = (float)(v[0] / total);
+}
+
+// column sums of X [rows][cols] (bias gradients): one workgroup per column,
+// a fixed-order reduction
+__global__ __launch_bounds__(256) void k_colsum(const float *X, int rows, int cols, float *out) {
+    __shared__ double sh[4];
+    const int j = blockIdx.x;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < rows; b += 256) v[0] += (double)X[(size_t)b * cols + j];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) out[j] = (float)v[0];
 }
 
 __global__ void k_adam(float *w, uint16_t *wb, const float *g, float *mo, float *ve, int n, float lr,
@@ -646,7 +696,7 @@ __global__ void k_f32_to_bf16(const float *x, uint16_t *y, int n) {
 // ---------------------------------------------------------------------------
 static size_t project_lds(const ClArgs &c, int max_n) {
     (void)c;
-    return (size_t)(32 + 512 + 4 * max_n) * sizeof(double);
+    return (size_t)(64 + 512 + 5 * max_n) * sizeof(double);
 }
 
 hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int mode, int max_n,
@@ -679,8 +729,7 @@ hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, do
 hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s) {
     if (m.row_blocks <= 0) return hipSuccess;
     if (m.on && !m.cpart) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((m.row_blocks + 3) / 4), dim3(256), 0, s, m, a,
-                       list ? 1 : 0);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(m.row_blocks), dim3(64 * kMlpWaves), 0, s, m, a, list ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -693,14 +742,17 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const uint16_t *A, long sam, lo
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_loss(const MlpArgs &m, const double *g, float *dy, uint16_t *dyb, float *loss,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, m, g, dy, dyb, loss);
+hipError_t launch_mlp_loss(const MlpArgs &m, const double *g, float *dy, uint16_t *dyb, double *part,
+                           float *loss, hipStream_t s) {
+    const int total = m.rows * kClModes;
+    const int nb = (total + 255) / 256;
+    hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(256), 0, s, m, g, dy, dyb, part);
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, s, part, nb, total, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_colsum(const float *X, int rows, int cols, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256), dim3(256), 0, s, X, rows, cols, out);
+    hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, s, X, rows, cols, out);
     return hipGetLastError();
 }
 

@@ -215,6 +215,7 @@ hipError_t enqueue_step(Ctx &c, int cur) {
     hipError_t e = enqueue_search(c, cur, 1, 1);
     if (e != hipSuccess) return e;
     set_state_ptrs(c, cur);
+    // (the modal closure runs only with candidate lists: enqueue_list_steps)
     return launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream);
 }
 
@@ -331,7 +332,14 @@ hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
     for (int k = 0; k < n; ++k) {
         set_state_ptrs(c, (start + k) & 1);
         c.a.chunk_k = k;
-        hipError_t e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
+        hipError_t e;
+        if (c.cl.mode) {
+            // plain-force particles, then the closure particles' contact and walls
+            e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1);
+            if (e == hipSuccess) e = launch_cl_contact(c.a, c.precision, c.stream);
+        } else {
+            e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
+        }
         if (e != hipSuccess) return e;
         e = enqueue_closure(c, true);
         if (e != hipSuccess) return e;
@@ -580,6 +588,17 @@ pd_status upload_shape_modes(Ctx &c, int s) {
     for (size_t k = 0; k < f.size(); ++k) f[k] = (float)L.h_phi[s][k];
     HIPCHK(hipMemcpyAsync(L.phi + (size_t)L.h_toff[s] * 2 * kClModes, f.data(), f.size() * sizeof(float),
                           hipMemcpyHostToDevice, c.stream));
+    // mode-major copy: mode k of template node i at (k * NT + toff + i)
+    const size_t NT = (size_t)L.ca.NT;
+    for (int k = 0; k < kClModes; ++k) {
+        std::vector<float> col((size_t)2 * n);
+        for (int i = 0; i < n; ++i) {
+            col[2 * i] = f[((size_t)i * kClModes + k) * 2];
+            col[2 * i + 1] = f[((size_t)i * kClModes + k) * 2 + 1];
+        }
+        HIPCHK(hipMemcpyAsync(L.phiT + 2 * ((size_t)k * NT + L.h_toff[s]), col.data(),
+                              col.size() * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    }
     HIPCHK(hipMemcpyAsync(L.lam + s * kClModes, &L.h_lam[s * kClModes], kClModes * sizeof(double),
                           hipMemcpyHostToDevice, c.stream));
     HIPCHK(hipMemcpyAsync(L.sig + s * kClModes, &L.h_sig[s * kClModes], kClModes * sizeof(double),
@@ -701,7 +720,7 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
         const int pt = L.h_shape_first[s];
         const int n0 = c.h_poff[pt], n = c.h_poff[pt + 1] - n0;
         if (n > kClMaxNodes || n < 3)
-            return fail(c, PD_E_INVALID, "a closure particle has 3 .. 1536 nodes");
+            return fail(c, PD_E_INVALID, "a closure particle has 3 .. 1024 nodes");
         L.h_shape_n[s] = n;
         L.h_toff[s] = (int)tX.size();
         L.max_n = std::max(L.max_n, n);
@@ -751,6 +770,8 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     TRY(upload(c, &L.tX, tX.data(), tX.size()));
     TRY(upload(c, &L.tY, tY.data(), tY.size()));
     TRY(dalloc(c, &L.phi, tX.size() * 2 * kClModes));
+    TRY(dalloc(c, &L.phiT, tX.size() * 2 * kClModes));
+    L.ca.NT = (int)tX.size();
     TRY(dalloc(c, &L.lam, (size_t)S * kClModes));
     TRY(dalloc(c, &L.sig, (size_t)S * kClModes));
     for (int s = 0; s < S; ++s) TRY(shape_modes(c, s));
@@ -817,7 +838,10 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     HIPCHK(hipStreamSynchronize(c.stream));
 
     ClArgs &ca = L.ca;
+    const int NT = ca.NT;
     ca = ClArgs{};
+    ca.NT = NT;
+    ca.phiT = reinterpret_cast<const float2 *>(L.phiT);
     ca.Pc = L.Pc;
     ca.cpart = dcpart;
     ca.cshape = dcshape;
@@ -896,7 +920,7 @@ pd_status cl_training_buffers(Ctx &c, int rows) {
     }
     if (L.tcap >= rows) return PD_OK;
     void *bufs[] = {L.t_y, L.t_z1, L.t_z2, L.t_dy, L.t_dz2, L.t_dz1, L.t_xb, L.t_h1, L.t_h2,
-                    L.t_dyb, L.t_dz2b, L.t_dz1b, L.t_idx};
+                    L.t_dyb, L.t_dz2b, L.t_dz1b, L.t_idx, L.t_part};
     for (void *b : bufs) dfree(c, b);
     const size_t R = rows;
     TRY(dalloc(c, &L.t_y, R * kClModes));
@@ -912,6 +936,7 @@ pd_status cl_training_buffers(Ctx &c, int rows) {
     TRY(dalloc(c, &L.t_dz2b, R * kClHidden));
     TRY(dalloc(c, &L.t_dz1b, R * kClHidden));
     TRY(dalloc(c, &L.t_idx, R));
+    TRY(dalloc(c, &L.t_part, R * kClModes / 256 + 1));
     L.tcap = rows;
     return PD_OK;
 }
@@ -938,7 +963,7 @@ hipError_t cl_grad_batch(Ctx &c, int s, const double *q, const double *g, int ro
     m.z1 = L.t_z1;
     m.z2 = L.t_z2;
     hipError_t e = launch_mlp_forward(m, c.a, false, c.stream);
-    if (e == hipSuccess) e = launch_mlp_loss(m, g, L.t_dy, L.t_dyb, loss, c.stream);
+    if (e == hipSuccess) e = launch_mlp_loss(m, g, L.t_dy, L.t_dyb, L.t_part, loss, c.stream);
     const uint16_t *W = L.wb + (size_t)s * kClParams;
     float *G = L.t_grad;
     const hipStream_t st = c.stream;

@@ -105,7 +105,7 @@ struct DevArgs {
 // ---- modal closure -----------------------------------------------------------
 constexpr int kClModes = 32;        // modal amplitudes per particle (MLP width in and out)
 constexpr int kClHidden = 256;      // hidden width
-constexpr int kClMaxNodes = 1536;   // nodes per closure particle (projection LDS <= 64 KB)
+constexpr int kClMaxNodes = 1024;   // nodes per closure particle (projection LDS <= 64 KB)
 constexpr int kClParams = kClHidden * kClModes + kClHidden + kClHidden * kClHidden + kClHidden +
                           kClModes * kClHidden + kClModes;
 // packed parameter offsets: W1 [256][32], b1, W2 [256][256], b2, W3 [32][256], b3
@@ -117,7 +117,7 @@ constexpr int kOffW3 = kOffB2 + kClHidden;
 constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
 // per closure particle reduced quantities (red[16 * c + k])
 enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
-       R_N };
+       R_COS, R_SIN, R_N };
 
 struct ClArgs {
     int Pc;                    // closure particles (sorted by shape)
@@ -127,6 +127,8 @@ struct ClArgs {
     const int *toff;           // [S] first template node of a shape
     const double *tX, *tY;     // template coordinates about the mass centroid
     const float *phi;          // modes: phi[(toff + i) * 64 + 2 k + c]
+    const float2 *phiT;        // the same, mode-major: phiT[k * NT + toff + i] = (x, y)
+    int NT;                    // template nodes of all shapes
     const double *lam;         // [S][32] eigenvalues (0 past the shape's mode count)
     const double *sig;         // [S][32] linear stretch of each mode, max over bonds
     const double *s0;          // [S] critical stretch of the shape's material
@@ -177,6 +179,7 @@ struct ClState {
     int *on = nullptr;
     double *lam = nullptr, *sig = nullptr, *s0 = nullptr, *tau_c = nullptr;
     float *phi = nullptr;
+    float *phiT = nullptr;     // [32][NT] float2
     double *tX = nullptr, *tY = nullptr;
     uint16_t *wb = nullptr;
     float *wf = nullptr, *sig_q = nullptr, *sig_r = nullptr;
@@ -195,6 +198,7 @@ struct ClState {
     uint16_t *t_xb = nullptr, *t_h1 = nullptr, *t_h2 = nullptr, *t_dyb = nullptr,
              *t_dz2b = nullptr, *t_dz1b = nullptr;
     int *t_idx = nullptr;
+    double *t_part = nullptr;  // [rows * 32 / 256 + 1] loss parts
     double *t_gbuf = nullptr;  // [rows][32] forward outputs
     std::vector<int64_t> adam_t;
     std::vector<double> h_lam, h_sig, h_tau_c;      // [S][32], [S][32], [S]
@@ -280,7 +284,8 @@ hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout,
 hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t s);
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
-                        bool list = false);
+                        bool list = false, int sel = 0);
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s);
 hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
@@ -297,7 +302,7 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const uint16_t *A, long sam, lo
                             const uint16_t *B, long sbk, long sbn, float *C, long ldc, int epi,
                             const float *Z, uint16_t *Cb, hipStream_t s);
 hipError_t launch_mlp_loss(const MlpArgs &m, const double *g, float *dy, uint16_t *dyb,
-                           float *loss, hipStream_t s);
+                           double *part, float *loss, hipStream_t s);
 hipError_t launch_colsum(const float *X, int rows, int cols, float *out, hipStream_t s);
 hipError_t launch_adam(float *w, uint16_t *wb, const float *g, float *m, float *v, int n, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s);

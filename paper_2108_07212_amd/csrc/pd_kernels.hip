@@ -722,7 +722,10 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
 // wall and one corner; the quad then combines its partial sums in a fixed
 // order and lane 0 integrates.  LDS holds the block's window of bond partners
 // (reference and current positions, volumes).
-template <typename R, int MODE, bool LIST>
+// SEL (step mode with the modal closure on): 0 every node; 1 the nodes of
+// particles under the plain bond force; 2 the nodes of closure particles,
+// contact and walls only, in an instantiation without the bond code
+template <typename R, int MODE, bool LIST, int SEL = 0>
 __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     extern __shared__ double lds[];
     // list mode: this launch computes step sprev + 1 of a replay that started
@@ -738,9 +741,15 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     constexpr bool adv = (MODE == M_STEP);
     const int sub = threadIdx.x & 3;
     const int i = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    // with the closure split (SEL 1 / 2), a workgroup none of whose nodes is
+    // this launch's leaves before loading anything
+    if (SEL != 0) {
+        const int mine = (i < a.N && (a.cl_on[a.part[i]] != 0) == (SEL == 2)) ? 1 : 0;
+        if (!__syncthreads_or(mine)) return;
+    }
     int lo = 0;
     bool staged = false;
-    if (a.use_lds) {
+    if (SEL != 2 && a.use_lds) {
         lo = a.win_lo[blockIdx.x];
         const int cnt = a.win_hi[blockIdx.x] - lo + 1;
         staged = cnt > 0 && cnt <= lds_cap;
@@ -780,15 +789,18 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     // a particle under the modal closure: no bond forces here; its external
     // nodal force goes to the closure kernels, which integrate its nodes
     const bool closure = MODE == M_STEP && a.cl_on && a.cl_on[pi];
+    if (SEL == 1 && closure) return;   // whole quads leave together
+    if (SEL == 2 && !closure) return;
     // List mode runs the bond loop first (its contact candidates never
     // involve intact bonds, so the order does not matter there), which keeps
     // fewer partial sums live through the loop.  Otherwise contact comes
     // first, because self-contact needs the bonds intact at the start of the
     // step and the bond loop commits breaks.
     if constexpr (LIST) {
-        if (!closure)
-            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx);
+        if constexpr (SEL != 2)
+            if (!closure)
+                bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                     uyi, Vi, fpx, fpy, nbrk, smx);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
@@ -796,9 +808,10 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
-        if (!closure)
-            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx);
+        if constexpr (SEL != 2)
+            if (!closure)
+                bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                     uyi, Vi, fpx, fpy, nbrk, smx);
     }
 
     // ---- combine the quad ------------------------------------------------------
@@ -868,6 +881,53 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         }
     }
     if (st) atomicOr(a.status, st);
+}
+
+// Contact and wall forces of the nodes of particles under the modal closure
+// (list mode), one thread per node: every candidate and every wall and corner
+// region in turn.  The closure kernels integrate these nodes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
+    const long long sprev = *a.step_base + a.chunk_k;
+    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int pi = a.part[i];
+    if (!a.cl_on[pi]) return;
+    const double xi = a.x[i], yi = a.y[i];
+    double pxi, pyi, uxi, uyi;
+    advanced_pos(a, i, true, pxi, pyi, uxi, uyi);
+    const double vxi = a.vx[i], vyi = a.vy[i];
+    const double Vi = a.vol[i], mi = a.mass[i];
+    const int ag = a.pagg[pi];
+    const MatConst mc = a.mat[a.pmat[pi]];
+    const double t = (double)(sprev + 1) * a.dt;
+    int st = 0;
+    R fsx = 0, fsy = 0, fnx = 0, fny = 0;
+    double fwx = 0.0, fwy = 0.0;
+#pragma unroll 1
+    for (int sub = 0; sub < 4; ++sub)
+        contact_forces<R, true, true>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
+                                      fsx, fsy, fnx, fny);
+#pragma unroll 1
+    for (int part = 0; part < 4; ++part)
+        wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+    a.cl_fx[i] = ((double)fsx + (double)fnx) + fwx;
+    a.cl_fy[i] = ((double)fsy + (double)fny) + fwy;
+    a.ux_o[i] = uxi;
+    a.uy_o[i] = uyi;
+    if (!(isfinite(uxi) && isfinite(uyi))) st |= kStNonfinite;
+    if (st) atomicOr(a.status, st);
+}
+
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    if (!(a.cl_on && a.cl_fx && a.cl_fy)) return hipErrorInvalidValue;
+    if (precision == PD_PREC_FP64)
+        hipLaunchKernelGGL(k_cl_contact<double>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_cl_contact<float>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,12 +1066,23 @@ int force_lds_cap(int max_win) { return max_win > kMaxLdsNodes ? 0 : max_win; }
 
 template <typename R>
 static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b, size_t shm,
-                           hipStream_t s, int lds_cap) {
+                           hipStream_t s, int lds_cap, int sel) {
     if (mode == M_STEP) {
-        if (list)
-            hipLaunchKernelGGL((k_force<R, M_STEP, true>), g, b, shm, s, a, lds_cap);
-        else
-            hipLaunchKernelGGL((k_force<R, M_STEP, false>), g, b, shm, s, a, lds_cap);
+        if (list) {
+            if (sel == 1)
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 1>), g, b, shm, s, a, lds_cap);
+            else if (sel == 2)
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 2>), g, b, 0, s, a, lds_cap);
+            else
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 0>), g, b, shm, s, a, lds_cap);
+        } else {
+            if (sel == 1)
+                hipLaunchKernelGGL((k_force<R, M_STEP, false, 1>), g, b, shm, s, a, lds_cap);
+            else if (sel == 2)
+                hipLaunchKernelGGL((k_force<R, M_STEP, false, 2>), g, b, 0, s, a, lds_cap);
+            else
+                hipLaunchKernelGGL((k_force<R, M_STEP, false, 0>), g, b, shm, s, a, lds_cap);
+        }
     } else if (mode == M_FORCES) {
         hipLaunchKernelGGL((k_force<R, M_FORCES, false>), g, b, shm, s, a, lds_cap);
     } else {
@@ -1020,21 +1091,22 @@ static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b
 }
 
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
-                        bool list) {
+                        bool list, int sel) {
     if (a.N == 0) return hipSuccess;
+    if (sel && !(mode == M_STEP && a.cl_on)) return hipErrorInvalidValue;
     const int B = a.block_nodes;  // nodes per workgroup, four lanes each
     const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
     const dim3 g(grid_for(a.N, B)), b(4 * B);
     if (precision == PD_PREC_FP64)
-        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap);
+        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel);
     else
-        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap);
+        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap, sel);
     return hipGetLastError();
 }
 
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_list, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_build_list, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
