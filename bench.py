@@ -135,6 +135,10 @@ def batched(pd, W, torch, steps):
     prob = W.batched()
     g = pd.PD(prob)
     g.step(20)
+    t0 = time.perf_counter()
+    tuning = g.autotune(10)
+    t_tune = time.perf_counter() - t0
+    g.step(20)
     sizes = g.sizes()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,6 +149,7 @@ def batched(pd, W, torch, steps):
     fb = BYTES_PER_NODE_FORCE * sizes["nodes"] + BYTES_PER_BOND * sizes["bonds"]
     ach = fb / (kt["force"][0] * 1e-3) / 1e9
     res = {"workload": "batched_64", "aggregates": prob.n_aggregates, "nodes": sizes["nodes"],
+           "tuning": tuning, "autotune_s": t_tune,
            "directed_bonds": sizes["bonds"], "steps_per_s": sps,
            "bond_interactions_per_s": sizes["bonds"] // 2 * sps,
            "force_kernel": {"mean_launch_ms": kt["force"][0], "bytes_per_launch": fb,
@@ -154,6 +159,7 @@ def batched(pd, W, torch, steps):
     sub_steps = max(20, steps // 2)
     for a in range(prob.n_aggregates):
         ga = pd.PD(W.subproblem_aggregate(prob, a))
+        ga.set_tuning(**tuning)
         ga.step(5)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -369,8 +375,11 @@ def main():
         torch.cuda.synchronize()
         return steps / (time.perf_counter() - t0), g.sizes()["list_rebuilds"] - r0
 
-    # the contact set evaluated from exact distances every step, over the
-    # candidate lists (rebuilt by the cell-key radix sort when stale)
+    # the library's own autotuner (nodes per workgroup, skin, LDS staging),
+    # then the contact set evaluated from exact distances every step, over
+    # the candidate lists (rebuilt by the cell-key radix sort when stale)
+    g.step(min(args.warmup, 100))
+    g.autotune(50)
     g.step(args.warmup)
     sps, rebuilds = timed(args.steps)
     # per-kernel mean launch time (HIP events on the library's stream)

@@ -36,7 +36,11 @@
  *     all device memory it allocates.  Output buffers are caller-allocated:
  *     host pointers, or device pointers when on_device = 1.
  *   - Concurrency: one context is used by one host thread at a time.  Work is
- *     issued on the stream given at setup (NULL: the legacy default stream).
+ *     issued on the stream given at setup.  With NULL the library runs on a
+ *     stream of its own (graphs cannot be captured on the legacy default
+ *     stream); a call that reads or writes caller device buffers first waits
+ *     for the work already issued on the legacy default stream.  Calls return
+ *     when their work is complete.
  *   - Determinism: sums run in a fixed order (gather only, no floating-point
  *     atomics), so the same inputs on the same device give bitwise equal
  *     results for a fixed tuning.

@@ -83,6 +83,14 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
+// a particle that leaves the closure: list the force workgroups holding its
+// nodes (each at most once) for the plain-force launch of the next step
+__device__ void list_particle_blocks(const ClArgs &c, int p) {
+    const int n0 = c.poff[p], n1 = c.poff[p + 1];
+    for (int b = n0 / c.block_nodes; b <= (n1 - 1) / c.block_nodes; ++b)
+        if (atomicExch(&c.blk_listed[b], 1) == 0) c.pd_blocks[atomicAdd(c.n_pd_blocks, 1)] = b;
+}
+
 // list mode: a launch past the first stale step of a replay does nothing (the
 // same rule as the force kernel)
 __device__ __forceinline__ bool replay_stale(const DevArgs &a, bool list) {
@@ -92,7 +100,7 @@ __device__ __forceinline__ bool replay_stale(const DevArgs &a, bool list) {
 }
 
 // ---------------------------------------------------------------------------
-// projection on the rigid + modal coordinates
+// projection on the rigid + modal coordinates, in two kernels
 //
 // mode 0 (step):  positions x + u_o (the advanced displacement the force
 //                 kernel wrote), velocities v (previous step), forces cl_fx/fy
@@ -100,50 +108,47 @@ __device__ __forceinline__ bool replay_stale(const DevArgs &a, bool list) {
 //                 active particles; gext then holds the modal PD force
 // mode 2 (snapshot): as 1, for every closure particle
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 4) void k_cl_project(DevArgs a, ClArgs c, int list, int mode) {
-    extern __shared__ double shm[];
+__device__ __forceinline__ void node_force(const DevArgs &a, int mode, int i, double &fx,
+                                           double &fy) {
+    if (mode == 0) {
+        fx = a.cl_fx[i];
+        fy = a.cl_fy[i];
+    } else {
+        fx = a.terms[i] * a.vol[i];
+        fy = a.terms[a.N + i] * a.vol[i];
+    }
+}
+
+// k_cl_moments: one workgroup per closure particle, one pass over its nodes:
+// moments about the particle's first node give the centroid, the Procrustes
+// sums (the template coordinates are centred), the polar moment, the angular
+// momentum, the total force, the torque and the contact load
+__global__ __launch_bounds__(256) void k_cl_moments(DevArgs a, ClArgs c, int list, int mode) {
+    __shared__ double red[4 * 16];
     if (replay_stale(a, list && mode == 0)) return;
     const int ci = blockIdx.x;
     const int p = c.cpart[ci];
-    if (mode < 2 && !a.cl_on[p]) return;
+    if (mode < 2 && !a.cl_on[p]) {
+        if (threadIdx.x == 0) c.red[(size_t)ci * 16 + R_ACTIVE] = 0.0;
+        return;
+    }
     const int s = c.cshape[ci];
     const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
     const int t0 = c.toff[s];
-    double *red = shm;               // [4 * 16] reduction scratch
-    double *sub = shm + 64;          // [8][32][2] partial modal sums
-    // the particle's nodes, read once: positions relative to its first node,
-    // forces, masses
-    double *Px = shm + 576, *Py = Px + n, *Fx = Py + n, *Fy = Fx + n, *Ms = Fy + n;
     const double *ux = mode == 0 ? a.ux_o : a.ux;
     const double *uy = mode == 0 ? a.uy_o : a.uy;
-    const int tid = threadIdx.x;
     const double rx = a.x[n0] + ux[n0], ry = a.y[n0] + uy[n0];
-
-    // every sum in one pass: moments about the first node, shifted to the
-    // centroid below (the template coordinates X are centred, so the
-    // Procrustes sums need no shift beyond sum m X, which is ~0)
     double v[15];
 #pragma unroll
     for (int k = 0; k < 15; ++k) v[k] = 0.0;
-    for (int k = tid; k < n; k += 256) {
+    for (int k = threadIdx.x; k < n; k += 256) {
         const int i = n0 + k;
         const double m = a.mass[i];
         const double yx = (a.x[i] + ux[i]) - rx, yy = (a.y[i] + uy[i]) - ry;
         const double vx = a.vx[i], vy = a.vy[i];
         double fx, fy;
-        if (mode == 0) {
-            fx = a.cl_fx[i];
-            fy = a.cl_fy[i];
-        } else {
-            fx = a.terms[i] * a.vol[i];
-            fy = a.terms[a.N + i] * a.vol[i];
-        }
+        node_force(a, mode, i, fx, fy);
         const double Xx = c.tX[t0 + k], Xy = c.tY[t0 + k];
-        Px[k] = yx;
-        Py[k] = yy;
-        Fx[k] = fx;
-        Fy[k] = fy;
-        Ms[k] = m;
         v[0] += m;
         v[1] += m * yx;
         v[2] += m * yy;
@@ -161,8 +166,9 @@ __global__ __launch_bounds__(256, 4) void k_cl_project(DevArgs a, ClArgs c, int 
         v[14] += m * Xy;
     }
     block_sum<15>(v, red);
+    if (threadIdx.x != 0) return;
     const double M = v[0];
-    const double cx = v[1] / M, cy = v[2] / M;        // centroid, relative
+    const double cx = v[1] / M, cy = v[2] / M;  // centroid, relative to the first node
     const double vcx = v[3] / M, vcy = v[4] / M;
     const double Ftx = v[5], Fty = v[6];
     const double cross = v[7] - (v[13] * cy - v[14] * cx);
@@ -172,117 +178,184 @@ __global__ __launch_bounds__(256, 4) void k_cl_project(DevArgs a, ClArgs c, int 
     const double tau = v[11] - (cx * Fty - cy * Ftx);
     // the best-fit rotation: (cos, sin) = (dot, cross) / |(dot, cross)|
     const double nr = sqrt(dot * dot + cross * cross);
-    const double cp = dot / nr, sp = cross / nr;
-    // body-frame displacement (times the mass) and force, in place
-    for (int k = tid; k < n; k += 256) {
-        const double m = Ms[k];
-        const double Yx = Px[k] - cx, Yy = Py[k] - cy;
-        const double fx = Fx[k], fy = Fy[k];
-        Px[k] = m * ((cp * Yx + sp * Yy) - c.tX[t0 + k]);
-        Py[k] = m * ((-sp * Yx + cp * Yy) - c.tY[t0 + k]);
-        Fx[k] = cp * fx + sp * fy;
-        Fy[k] = -sp * fx + cp * fy;
+    double *R = c.red + (size_t)ci * 16;
+    R[R_M] = M;
+    R[R_CX] = rx + cx;
+    R[R_CY] = ry + cy;
+    R[R_VCX] = vcx;
+    R[R_VCY] = vcy;
+    R[R_PHI] = 0.0;
+    R[R_COS] = dot / nr;
+    R[R_SIN] = cross / nr;
+    R[R_I] = I;
+    R[R_OM] = Lz / I;
+    R[R_FX] = Ftx;
+    R[R_FY] = Fty;
+    R[R_TAU] = tau;
+    R[R_CONTACT] = v[12];
+    R[R_ACTIVE] = 1.0;
+}
+
+// k_cl_modal: one workgroup per (block of up to 16 closure particles of one
+// shape, 32-node slice of the shape).  The slice's modes and every
+// particle's m u_body and f_body on it are staged in LDS; thread (particle p,
+// mode k) adds the slice's terms of q_pk = (Phi^T M u_body)_k and
+// gext_pk = (Phi^T f_body)_k, and leaves them in part[]; k_cl_modal_sum adds
+// the slices in order.  Each staged mode entry serves 16 particles.
+constexpr int kModalSlice = 32;
+
+__global__ __launch_bounds__(512) void k_cl_modal(DevArgs a, ClArgs c, int list, int mode) {
+    __shared__ float2 Ph[kModalSlice][kClModes];
+    __shared__ double4 U[16][kModalSlice];
+    __shared__ double Rs[16][4];
+    __shared__ int pn0[16], pok[16];
+    if (replay_stale(a, list && mode == 0)) return;
+    const int rb = blockIdx.x, sl = blockIdx.y;
+    const int s = c.rb_shape[rb], first = c.rb_first[rb], cnt = c.rb_count[rb];
+    const int t0 = c.toff[s];
+    const int n = c.poff[c.cpart[first] + 1] - c.poff[c.cpart[first]];
+    const int j0 = sl * kModalSlice;
+    if (j0 >= n) return;  // a slice past this shape's nodes (uniform)
+    const int tid = threadIdx.x;
+    if (tid < 16) {
+        int ok = 0, n0 = 0;
+        if (tid < cnt) {
+            const int p = c.cpart[first + tid];
+            ok = mode == 2 || a.cl_on[p];
+            n0 = c.poff[p];
+            const double *R = c.red + (size_t)(first + tid) * 16;
+            Rs[tid][0] = R[R_CX];
+            Rs[tid][1] = R[R_CY];
+            Rs[tid][2] = R[R_COS];
+            Rs[tid][3] = R[R_SIN];
+        }
+        pok[tid] = ok;
+        pn0[tid] = n0;
     }
     __syncthreads();
-    // modal sums: thread (g, k) takes nodes g, g + 8, ... of mode k
+    const double *ux = mode == 0 ? a.ux_o : a.ux;
+    const double *uy = mode == 0 ? a.uy_o : a.uy;
+    const float2 *phi2 = reinterpret_cast<const float2 *>(c.phi);
+    for (int e = tid; e < kModalSlice * kClModes; e += 512) {
+        const int jj = e / kClModes, kk = e % kClModes;
+        Ph[jj][kk] = j0 + jj < n ? phi2[(size_t)(t0 + j0 + jj) * kClModes + kk]
+                                 : make_float2(0.f, 0.f);
+    }
     {
-        const int k = tid & 31, g = tid >> 5;
-        double sq = 0.0, sf = 0.0;
-        const float2 *ph = reinterpret_cast<const float2 *>(c.phi) + (size_t)t0 * kClModes + k;
-        // four mode-row loads in flight per pass
-        for (int j0 = g; j0 < n; j0 += 32) {
-            float2 f[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = j0 + 8 * u;
-                f[u] = j < n ? ph[(size_t)j * kClModes] : make_float2(0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = min(j0 + 8 * u, n - 1);
-                sq += (double)f[u].x * Px[j] + (double)f[u].y * Py[j];
-                sf += (double)f[u].x * Fx[j] + (double)f[u].y * Fy[j];
-            }
+        const int q = tid / kModalSlice, jj = tid % kModalSlice;  // 16 x 32 = 512
+        double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (pok[q] && j0 + jj < n) {
+            const int i = pn0[q] + j0 + jj;
+            const double m = a.mass[i];
+            const double Yx = (a.x[i] + ux[i]) - Rs[q][0], Yy = (a.y[i] + uy[i]) - Rs[q][1];
+            const double cp = Rs[q][2], sp = Rs[q][3];
+            double fx, fy;
+            node_force(a, mode, i, fx, fy);
+            w.x = m * ((cp * Yx + sp * Yy) - c.tX[t0 + j0 + jj]);
+            w.y = m * ((-sp * Yx + cp * Yy) - c.tY[t0 + j0 + jj]);
+            w.z = cp * fx + sp * fy;
+            w.w = -sp * fx + cp * fy;
         }
-        sub[(g * 32 + k) * 2] = sq;
-        sub[(g * 32 + k) * 2 + 1] = sf;
+        U[q][jj] = w;
     }
     __syncthreads();
-    if (tid < 32) {
-        double sq = 0.0, sf = 0.0;
-        for (int g = 0; g < 8; ++g) {
-            sq += sub[(g * 32 + tid) * 2];
-            sf += sub[(g * 32 + tid) * 2 + 1];
-        }
-        c.q[ci * kClModes + tid] = sq;
-        c.gext[ci * kClModes + tid] = sf;
-        // first-order bound of the largest bond stretch, sum_k |q_k| sigma_k
-        double b = fabs(sq) * c.sig[s * kClModes + tid];
-        for (int o = 16; o > 0; o >>= 1) b += __shfl_xor(b, o, 32);
-        if (tid == 0) {
-            double *R = c.red + (size_t)ci * 16;
-            R[R_M] = M;
-            R[R_CX] = rx + cx;
-            R[R_CY] = ry + cy;
-            R[R_VCX] = vcx;
-            R[R_VCY] = vcy;
-            R[R_PHI] = 0.0;
-            R[R_COS] = cp;
-            R[R_SIN] = sp;
-            R[R_I] = I;
-            R[R_OM] = Lz / I;
-            R[R_FX] = Ftx;
-            R[R_FY] = Fty;
-            R[R_TAU] = tau;
-            R[R_STRAIN] = b;
-            R[R_CONTACT] = v[12];
-        }
+    const int pp = tid >> 5, k = tid & 31;
+    if (pp >= cnt || !pok[pp]) return;
+    double sq = 0.0, sf = 0.0;
+    const int jn = min(kModalSlice, n - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+        const float2 f = Ph[jj][k];
+        const double4 w = U[pp][jj];
+        sq += (double)f.x * w.x + (double)f.y * w.y;
+        sf += (double)f.x * w.z + (double)f.y * w.w;
     }
+    double *out = c.part + (((size_t)(first + pp) * c.n_slices + sl) * kClModes + k) * 2;
+    out[0] = sq;
+    out[1] = sf;
+}
+
+// the slices' parts in order: q, gext and the stretch bound of each particle
+__global__ __launch_bounds__(256) void k_cl_modal_sum(DevArgs a, ClArgs c, int list, int mode) {
+    if (replay_stale(a, list && mode == 0)) return;
+    const int ci = blockIdx.x * 8 + (threadIdx.x >> 5), k = threadIdx.x & 31;
+    if (ci >= c.Pc) return;
+    const int p = c.cpart[ci];
+    if (mode < 2 && !a.cl_on[p]) return;
+    const int s = c.cshape[ci];
+    const int n = c.poff[p + 1] - c.poff[p];
+    const int ns = (n + kModalSlice - 1) / kModalSlice;
+    const double *in = c.part + ((size_t)ci * c.n_slices * kClModes + k) * 2;
+    double sq = 0.0, sf = 0.0;
+    for (int sl = 0; sl < ns; ++sl) {
+        sq += in[(size_t)sl * kClModes * 2];
+        sf += in[(size_t)sl * kClModes * 2 + 1];
+    }
+    c.q[ci * kClModes + k] = sq;
+    c.gext[ci * kClModes + k] = sf;
+    // first-order bound of the largest bond stretch, sum_k |q_k| sigma_k
+    double b = fabs(sq) * c.sig[s * kClModes + k];
+    for (int o = 16; o > 0; o >>= 1) b += __shfl_xor(b, o, 32);
+    if (k == 0) c.red[(size_t)ci * 16 + R_STRAIN] = b;
 }
 
 // ---------------------------------------------------------------------------
 // nodal accelerations of the rigid + modal motion, velocity update, gate
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list) {
-    __shared__ double qdd[kClModes];
-    __shared__ double R[16];
-    __shared__ int stale_any;
+__global__ __launch_bounds__(512) void k_cl_apply(DevArgs a, ClArgs c, int list) {
+    __shared__ float2 PhT[kClModes][kModalSlice];  // mode-major: lanes of one mode are conflict-free
+    __shared__ double Qd[16][kClModes];
+    __shared__ double Rs[16][16];
+    __shared__ int pn0[16], pok[16];
     if (replay_stale(a, list)) return;
-    const int ci = blockIdx.x;
-    const int p = c.cpart[ci];
-    if (!a.cl_on[p]) return;
-    const int s = c.cshape[ci];
-    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int rb = blockIdx.x, sl = blockIdx.y;
+    const int s = c.rb_shape[rb], first = c.rb_first[rb], cnt = c.rb_count[rb];
     const int t0 = c.toff[s];
+    const int n = c.poff[c.cpart[first] + 1] - c.poff[c.cpart[first]];
+    const int j0 = sl * kModalSlice;
+    if (j0 >= n) return;  // uniform
     const int tid = threadIdx.x;
-    if (tid < kClModes) {
-        const double q = c.q[ci * kClModes + tid];
-        const double g = c.learned ? c.ghat[ci * kClModes + tid] : -c.lam[s * kClModes + tid] * q;
-        qdd[tid] = g + c.gext[ci * kClModes + tid];
+    // which particles step under the closure was fixed by k_cl_moments
+    // (the gate below may clear cl_on while other slices still run)
+    if (tid < 16) {
+        int ok = 0;
+        if (tid < cnt) ok = c.red[(size_t)(first + tid) * 16 + R_ACTIVE] != 0.0;
+        pok[tid] = ok;
+        pn0[tid] = tid < cnt ? c.poff[c.cpart[first + tid]] : 0;
     }
-    if (tid < 16) R[tid] = c.red[(size_t)ci * 16 + tid];
-    if (tid == 0) stale_any = 0;
-    __syncthreads();
-    const double M = R[R_M], cx = R[R_CX], cy = R[R_CY];
-    const double cp = R[R_COS], sp = R[R_SIN];
-    const double alpha = R[R_TAU] / R[R_I], om2 = R[R_OM] * R[R_OM];
-    const double atx = R[R_FX] / M + a.gx, aty = R[R_FY] / M + a.gy;
-    // a thread per node; the mode-major copy of the modes makes each load
-    // contiguous across the wavefront
-    int st = 0;
-    bool stale = false;
-    for (int k = tid; k < n; k += 256) {
-        const int i = n0 + k;
-        const float2 *ph = c.phiT + t0 + k;
-        float2 f[kClModes];
-#pragma unroll
-        for (int m = 0; m < kClModes; ++m) f[m] = ph[(size_t)m * c.NT];
-        double bx = 0.0, by = 0.0;
-#pragma unroll
-        for (int m = 0; m < kClModes; ++m) {
-            bx += (double)f[m].x * qdd[m];
-            by += (double)f[m].y * qdd[m];
+    {
+        const int q = tid >> 5, k = tid & 31;  // 16 x 32
+        if (q < cnt) {
+            const int ci = first + q;
+            const double qq = c.q[ci * kClModes + k];
+            const double g = c.learned ? c.ghat[ci * kClModes + k] : -c.lam[s * kClModes + k] * qq;
+            Qd[q][k] = g + c.gext[ci * kClModes + k];
+            if (k < 16) Rs[q][k] = c.red[(size_t)ci * 16 + k];
         }
+        const int jj = tid >> 4, kk2 = (tid & 15) * 2;  // 32 nodes x 16 mode pairs
+        const float4 f = j0 + jj < n
+                             ? reinterpret_cast<const float4 *>(c.phi + (size_t)(t0 + j0 + jj) * 2 * kClModes)[kk2 / 2]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+        PhT[kk2][jj] = make_float2(f.x, f.y);
+        PhT[kk2 + 1][jj] = make_float2(f.z, f.w);
+    }
+    __syncthreads();
+    const int q = tid >> 5, jj = tid & 31;
+    int st = 0;
+    int stale = 0;
+    if (q < cnt && pok[q] && j0 + jj < n) {
+        double bx = 0.0, by = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < kClModes; ++k) {
+            const float2 f = PhT[k][jj];
+            bx += (double)f.x * Qd[q][k];
+            by += (double)f.y * Qd[q][k];
+        }
+        const double *R = Rs[q];
+        const double M = R[R_M], cx = R[R_CX], cy = R[R_CY];
+        const double cp = R[R_COS], sp = R[R_SIN];
+        const double alpha = R[R_TAU] / R[R_I], om2 = R[R_OM] * R[R_OM];
+        const double atx = R[R_FX] / M + a.gx, aty = R[R_FY] / M + a.gy;
+        const int i = pn0[q] + j0 + jj;
         const double ux = a.ux_o[i], uy = a.uy_o[i];
         const double Yx = (a.x[i] + ux) - cx, Yy = (a.y[i] + uy) - cy;
         const double axn = ((atx - alpha * Yy) - om2 * Yx) + (cp * bx - sp * by);
@@ -298,22 +371,23 @@ __global__ __launch_bounds__(256) void k_cl_apply(DevArgs a, ClArgs c, int list)
             const double unx = (ux + a.dt * vxn) + a.hdt2 * axn;
             const double uny = (uy + a.dt * vyn) + a.hdt2 * ayn;
             const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
-            if (!(ex * ex + ey * ey <= a.move2)) stale = true;
+            if (!(ex * ex + ey * ey <= a.move2)) stale = 1;
         }
     }
     if (st) atomicOr(a.status, st);
-    if (stale) stale_any = 1;
-    __syncthreads();
-    if (tid == 0) {
-        if (stale_any) {
-            const long long sprev = *a.step_base + a.chunk_k;
-            atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
-        }
-        // gate for the next step: a particle whose bound on the bond stretch
-        // passes gate_frac * s0, or whose contact load passes tau_c, goes back
-        // to the plain bond force
+    if (__syncthreads_or(stale) && tid == 0) {
+        const long long sprev = *a.step_base + a.chunk_k;
+        atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+    }
+    // gate for the next step (once per particle, by the first slice): a
+    // particle whose bound on the bond stretch passes gate_frac * s0, or
+    // whose contact load passes tau_c, goes back to the plain bond force
+    if (sl == 0 && jj == 0 && q < cnt && pok[q]) {
+        const double *R = Rs[q];
         if (R[R_STRAIN] > c.gate_frac * c.s0[s] || R[R_CONTACT] > c.tau_c[s]) {
+            const int p = c.cpart[first + q];
             a.cl_on[p] = 0;
+            list_particle_blocks(c, p);
             atomicAdd(c.fallbacks, 1ull);
         }
     }
@@ -366,6 +440,7 @@ __global__ __launch_bounds__(256) void k_cl_check_part(DevArgs a, ClArgs c, doub
         const double scale = fmax(sqrt(n2), sqrt(q2));
         if (mx > c.gate_frac * c.s0[s] || sqrt(e2) > err_tol * scale) {
             a.cl_on[p] = 0;
+            list_particle_blocks(c, p);
             atomicAdd(c.fallbacks, 1ull);
         }
     }
@@ -694,26 +769,26 @@ __global__ void k_f32_to_bf16(const float *x, uint16_t *y, int n) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static size_t project_lds(const ClArgs &c, int max_n) {
-    (void)c;
-    return (size_t)(64 + 512 + 5 * max_n) * sizeof(double);
-}
-
 hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int mode, int max_n,
                              hipStream_t s) {
     if (c.Pc <= 0) return hipSuccess;
     // the buffers each mode reads
     if (mode == 0 ? !(a.cl_on && a.cl_fx && a.cl_fy) : !a.terms) return hipErrorInvalidValue;
     if (mode == 1 && !a.cl_on) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cl_project, dim3(c.Pc), dim3(256), project_lds(c, max_n), s, a, c,
-                       list ? 1 : 0, mode);
+    if (!c.rb_shape || c.n_rb <= 0) return hipErrorInvalidValue;
+    if (!c.part || c.n_slices * kModalSlice < max_n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cl_moments, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0, mode);
+    hipLaunchKernelGGL(k_cl_modal, dim3(c.n_rb, c.n_slices), dim3(512), 0, s, a, c, list ? 1 : 0,
+                       mode);
+    hipLaunchKernelGGL(k_cl_modal_sum, dim3((c.Pc + 7) / 8), dim3(256), 0, s, a, c, list ? 1 : 0,
+                       mode);
     return hipGetLastError();
 }
 
 hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s) {
     if (c.Pc <= 0) return hipSuccess;
-    if (!a.cl_on) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cl_apply, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0);
+    if (!a.cl_on || !c.rb_shape) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cl_apply, dim3(c.n_rb, c.n_slices), dim3(512), 0, s, a, c, list ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -419,6 +419,17 @@ pd_status set_device_step(Ctx &c) {
     return PD_OK;
 }
 
+// Work on device buffers the caller produced must follow the caller's work.
+// Without a stream from the caller, the library runs on a stream of its own
+// (the legacy default stream cannot be captured into graphs) that waits here
+// for everything issued so far on the legacy default stream.
+pd_status after_caller(Ctx &c) {
+    if (!c.own_stream) return PD_OK;
+    HIPCHK(hipEventRecord(c.caller_ev, nullptr));
+    HIPCHK(hipStreamWaitEvent(c.stream, c.caller_ev, 0));
+    return PD_OK;
+}
+
 // forces at the current state into the term buffer (M_FORCES)
 pd_status eval_terms(Ctx &c) {
     if (!c.a.terms) TRY(dalloc(c, &c.a.terms, (size_t)10 * c.N));
@@ -861,6 +872,12 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     ca.gext = gext;
     ca.ghat = ghat;
     ca.fallbacks = L.fallbacks;
+    ca.rb_shape = rbs;
+    ca.rb_first = rbf;
+    ca.rb_count = rbc;
+    ca.n_rb = (int)L.h_rb_shape.size();
+    ca.n_slices = (L.max_n + 31) / 32;
+    TRY(dalloc(c, &ca.part, Pc * ca.n_slices * kClModes * 2));
     MlpArgs &m = L.ma;
     m = MlpArgs{};
     m.rows = L.Pc;
@@ -988,6 +1005,44 @@ hipError_t cl_grad_batch(Ctx &c, int s, const double *q, const double *g, int ro
     return e;
 }
 
+// the force workgroups holding nodes of particles under the plain force
+pd_status cl_block_list(Ctx &c) {
+    ClState &L = c.cl;
+    const int B = c.tune.block_nodes;
+    const int nb = (c.N + B - 1) / B;
+    if (L.blk_cap < nb) {
+        dfree(c, L.pd_blocks);
+        dfree(c, L.blk_listed);
+        TRY(dalloc(c, &L.pd_blocks, (size_t)nb));
+        TRY(dalloc(c, &L.blk_listed, (size_t)nb));
+        L.blk_cap = nb;
+    }
+    if (!L.n_pd_blocks) TRY(dalloc(c, &L.n_pd_blocks, 1));
+    std::vector<int> on(c.P);
+    HIPCHK(hipMemcpyAsync(on.data(), L.on, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    std::vector<int> listed(nb, 0), list;
+    for (int p = 0; p < c.P; ++p) {
+        if (on[p]) continue;
+        const int n0 = c.h_poff[p], n1 = c.h_poff[p + 1];
+        for (int b = n0 / B; b <= (n1 - 1) / B; ++b) listed[b] = 1;
+    }
+    for (int b = 0; b < nb; ++b)
+        if (listed[b]) list.push_back(b);
+    const int n = (int)list.size();
+    if (n) HIPCHK(hipMemcpyAsync(L.pd_blocks, list.data(), n * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(L.blk_listed, listed.data(), nb * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(L.n_pd_blocks, &n, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    c.a.pd_blocks = L.pd_blocks;
+    c.a.n_pd_blocks = L.n_pd_blocks;
+    L.ca.pd_blocks = L.pd_blocks;
+    L.ca.n_pd_blocks = L.n_pd_blocks;
+    L.ca.blk_listed = L.blk_listed;
+    L.ca.block_nodes = B;
+    return PD_OK;
+}
+
 pd_status check_shape(Ctx &c, int s) {
     if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
     if (s < 0 || s >= c.cl.S) return fail(c, PD_E_INVALID, "bad shape id");
@@ -1013,6 +1068,7 @@ void pd_destroy(pd_ctx *ctx) {
     invalidate_graph(c);
     for (void *p : c.owned) hipFree(p);
     if (c.own_stream && c.stream) hipStreamDestroy(c.stream);
+    if (c.caller_ev) hipEventDestroy(c.caller_ev);
     delete ctx;
 }
 
@@ -1069,6 +1125,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     } else {
         HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
         c.own_stream = true;
+        HIPCHK(hipEventCreateWithFlags(&c.caller_ev, hipEventDisableTiming));
     }
     // ---- host-side per node / particle data ----
     std::vector<int> part(N), pagg(P, 0);
@@ -1311,6 +1368,7 @@ pd_status pd_step(pd_ctx *ctx, int64_t n) {
 pd_status pd_forces(pd_ctx *ctx, uint32_t mask, double *fx, double *fy, int32_t on_device) {
     if (!ctx || !fx || !fy) return PD_E_INVALID;
     Ctx &c = ctx->c;
+    if (on_device) TRY(after_caller(c));
     TRY(eval_terms(c));
     double *ox = fx, *oy = fy;
     if (!on_device) {
@@ -1330,6 +1388,7 @@ pd_status pd_forces(pd_ctx *ctx, uint32_t mask, double *fx, double *fy, int32_t 
 pd_status pd_damage(pd_ctx *ctx, double *phi, int64_t *nb, int32_t on_device) {
     if (!ctx) return PD_E_INVALID;
     Ctx &c = ctx->c;
+    if (on_device) TRY(after_caller(c));
     unsigned long long *dnb;
     if (!c.dev_i) TRY(dalloc(c, &c.dev_i, 4));
     dnb = (unsigned long long *)c.dev_i;
@@ -1540,6 +1599,7 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         TRY(build_grid(c, box.data()));
     }
     if (rewin) TRY(build_windows(c));
+    if (rewin && c.cl.mode) TRY(cl_block_list(c));
     invalidate_graph(c);
     return PD_OK;
 }
@@ -1840,6 +1900,7 @@ pd_status pd_closure_enable(pd_ctx *ctx, int32_t mode) {
     c.a.cl_on = mode ? L.on : nullptr;
     c.a.cl_fx = L.fx;
     c.a.cl_fy = L.fy;
+    if (mode) TRY(cl_block_list(c));
     L.last_check_step = c.step;
     invalidate_graph(c);
     return PD_OK;
@@ -1850,6 +1911,7 @@ pd_status pd_closure_snapshot(pd_ctx *ctx, double *q, double *g, int32_t on_devi
     Ctx &c = ctx->c;
     if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
     ClState &L = c.cl;
+    if (on_device) TRY(after_caller(c));
     TRY(eval_terms(c));
     set_state_ptrs(c, c.cur);
     HIPCHK(launch_cl_project(c.a, L.ca, false, 2, L.max_n, c.stream));
@@ -1868,6 +1930,7 @@ pd_status pd_closure_forward(pd_ctx *ctx, int32_t shape, const double *q, double
     TRY(check_shape(c, shape));
     if (n == 0) return PD_OK;
     ClState &L = c.cl;
+    if (on_device) TRY(after_caller(c));
     const double *dq = q;
     double *dg = g, *tq = nullptr, *tg = nullptr;
     const size_t nb = (size_t)n * kClModes * sizeof(double);
@@ -1931,6 +1994,7 @@ pd_status pd_closure_train(pd_ctx *ctx, int32_t shape, const double *q, const do
     Ctx &c = ctx->c;
     TRY(check_shape(c, shape));
     ClState &L = c.cl;
+    TRY(after_caller(c));
     TRY(cl_training_buffers(c, batch));
     float *dl;
     TRY(dalloc(c, &dl, (size_t)iters));

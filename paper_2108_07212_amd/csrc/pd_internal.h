@@ -100,6 +100,10 @@ struct DevArgs {
     double *cl_fx, *cl_fy;     // [N]
     // M_FORCES: largest |stretch| over each node's intact bonds, or null
     double *smax;
+    // with the closure on: the force workgroups holding nodes under the plain
+    // force (a list that only grows), and its length
+    const int *pd_blocks;
+    const int *n_pd_blocks;
 };
 
 // ---- modal closure -----------------------------------------------------------
@@ -117,7 +121,7 @@ constexpr int kOffW3 = kOffB2 + kClHidden;
 constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
 // per closure particle reduced quantities (red[16 * c + k])
 enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
-       R_COS, R_SIN, R_N };
+       R_COS, R_SIN, R_ACTIVE, R_N };
 
 struct ClArgs {
     int Pc;                    // closure particles (sorted by shape)
@@ -128,6 +132,10 @@ struct ClArgs {
     const double *tX, *tY;     // template coordinates about the mass centroid
     const float *phi;          // modes: phi[(toff + i) * 64 + 2 k + c]
     const float2 *phiT;        // the same, mode-major: phiT[k * NT + toff + i] = (x, y)
+    const int *rb_shape, *rb_first, *rb_count;  // blocks of <= 16 particles of one shape
+    int n_rb;
+    double *part;              // [Pc][n_slices][32][2] partial modal sums
+    int n_slices;              // 32-node slices of the largest shape
     int NT;                    // template nodes of all shapes
     const double *lam;         // [S][32] eigenvalues (0 past the shape's mode count)
     const double *sig;         // [S][32] linear stretch of each mode, max over bonds
@@ -138,6 +146,9 @@ struct ClArgs {
     double *red;               // [Pc][16]
     double *q, *gext, *ghat;   // [Pc][32]
     unsigned long long *fallbacks;
+    // list of force workgroups with plain-force nodes, appended on fallback
+    int *pd_blocks, *n_pd_blocks, *blk_listed;
+    int block_nodes;
 };
 
 // one forward pass of the MLP over `rows` rows of modal amplitudes
@@ -204,6 +215,8 @@ struct ClState {
     std::vector<double> h_lam, h_sig, h_tau_c;      // [S][32], [S][32], [S]
     std::vector<std::vector<std::pair<int, int>>> h_tbonds;  // template bonds, local indices
     double *fx = nullptr, *fy = nullptr, *smax = nullptr;
+    int *pd_blocks = nullptr, *n_pd_blocks = nullptr, *blk_listed = nullptr;
+    int blk_cap = 0;
     int64_t last_checked = 0;
 };
 
@@ -217,6 +230,7 @@ struct Ctx {
     std::map<long, hipGraphExec_t> lgraph_n;          // shorter replays, by (parity, length)
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipEvent_t caller_ev = nullptr;  // with an own stream: orders it after the legacy default stream
     int precision = 0;
     int cur = 0;                 // index of the buffer with the current state
     long long step = 0;          // host copy of the step counter

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "pd_internal.h"
 
 namespace pd {
@@ -549,6 +551,28 @@ __device__ __forceinline__ T quad_sum(T v) {
     return v;
 }
 
+// The start of node i's SELL-16 row for lane `sub`: slice base, row width and
+// the lane's first batch of slot words, loaded early (before the workgroup's
+// LDS staging) so that these dependent loads overlap the staging loads.
+constexpr int kBatch = 8;
+struct SlotHead {
+    uint32_t base;
+    int W;
+    uint32_t ev[kBatch];
+};
+
+__device__ __forceinline__ void slot_head(const DevArgs &a, int i, int sub, SlotHead &h) {
+    const uint32_t sl = (uint32_t)i / kSlice;
+    const uint32_t p0 = a.slice_ptr[sl], p1 = a.slice_ptr[sl + 1];
+    h.base = p0 + (uint32_t)i % kSlice;
+    h.W = (int)((p1 - p0) / kSlice);
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const int k = sub + 4 * t;
+        h.ev[t] = k < h.W ? a.col[h.base + (uint32_t)k * kSlice] : kBroken;
+    }
+}
+
 // Bond forces of node i from the slots k = sub, sub + 4, ... of its SELL-16
 // row (lane `sub` of the node's quad).  Every slot runs the same branch-free
 // arithmetic (padding and broken slots are masked), so consecutive slots form
@@ -562,23 +586,23 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                                             const double *Sy, const double *Sux,
                                             const double *Suy, const double *Sv, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
-                                            R &fpy, int &nbrk, double &smx) {
+                                            R &fpy, int &nbrk, double &smx,
+                                            const SlotHead &h) {
     constexpr bool adv = (MODE == M_STEP);
     {
-        const uint32_t sl = (uint32_t)i / kSlice;
-        const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
-        const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+        const uint32_t base = h.base;
+        const int W = h.W;
         const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
         const bool conic = mc.conic != 0;
         // this lane's slots k = sub + 4 t; their words are fetched in batches of
-        // kBatch before any of them is used, so the loads overlap
-        constexpr int kBatch = 8;
+        // kBatch before any of them is used, so the loads overlap (the first
+        // batch comes with the row head)
         for (int k0 = sub; k0 < W; k0 += 4 * kBatch) {
             uint32_t ev[kBatch];
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int k = k0 + 4 * t;
-                ev[t] = k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken;
+                ev[t] = k0 == sub ? h.ev[t] : (k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken);
             }
 #pragma unroll 2
             for (int t = 0; t < kBatch; ++t) {
@@ -666,10 +690,10 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                                                int sub, int pi, int ag, double xi, double yi,
                                                double pxi, double pyi, double vxi, double vyi,
                                                double Vi, double mi, R &fsx, R &fsy, R &fnx,
-                                               R &fny) {
+                                               R &fny, int nc_pre = -1) {
     if (LIST) {
         // candidates listed at the last rebuild (intact bonds excluded)
-        const int nc = a.clist_n[i];
+        const int nc = nc_pre >= 0 ? nc_pre : a.clist_n[i];
         for (int q = sub; q < nc; q += 4) {
             const int j = (int)a.clist[(size_t)q * a.N + i];
             double pxj, pyj, ux, uy;
@@ -722,36 +746,39 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
 // wall and one corner; the quad then combines its partial sums in a fixed
 // order and lane 0 integrates.  LDS holds the block's window of bond partners
 // (reference and current positions, volumes).
-// SEL (step mode with the modal closure on): 0 every node; 1 the nodes of
-// particles under the plain bond force; 2 the nodes of closure particles,
-// contact and walls only, in an instantiation without the bond code
-template <typename R, int MODE, bool LIST, int SEL = 0>
-__global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
-    extern __shared__ double lds[];
-    // list mode: this launch computes step sprev + 1 of a replay that started
-    // after step *step_base; once a list has gone stale, that step and every
-    // later one of the replay are no-ops (the check is uniform over the grid)
-    long long sprev = 0;
-    if (LIST) {
-        sprev = *a.step_base + a.chunk_k;
-        if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
-    }
+// The step (or force evaluation) of the nodes of force workgroup `blk`.
+// SEL (step mode with the modal closure on): 0 every node; 1 only the nodes
+// of particles under the plain bond force (closure nodes are left to
+// k_cl_contact and the closure kernels).
+template <typename R, int MODE, bool LIST, int SEL>
+__device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int blk,
+                                            long long sprev, double *lds) {
     double *Sx = lds, *Sy = lds + lds_cap, *Sux = lds + 2 * lds_cap, *Suy = lds + 3 * lds_cap,
            *Sv = lds + 4 * lds_cap;
     constexpr bool adv = (MODE == M_STEP);
     const int sub = threadIdx.x & 3;
-    const int i = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
-    // with the closure split (SEL 1 / 2), a workgroup none of whose nodes is
-    // this launch's leaves before loading anything
-    if (SEL != 0) {
-        const int mine = (i < a.N && (a.cl_on[a.part[i]] != 0) == (SEL == 2)) ? 1 : 0;
+    const int i = blk * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    if (SEL == 1) {
+        const int mine = (i < a.N && !a.cl_on[a.part[i]]) ? 1 : 0;
         if (!__syncthreads_or(mine)) return;
     }
+    // this node's own data and the head of its bond row, issued before the
+    // staging loads (indices clamped: the loads of i >= N are discarded)
+    const int ic = i < a.N ? i : a.N - 1;
+    const double xi = a.x[ic], yi = a.y[ic];
+    double pxi, pyi, uxi, uyi;
+    advanced_pos(a, ic, adv, pxi, pyi, uxi, uyi);
+    const double vxi = a.vx[ic], vyi = a.vy[ic];  // velocities of the previous step
+    const double Vi = a.vol[ic], mi = a.mass[ic];
+    const int pi = a.part[ic];
+    SlotHead head;
+    slot_head(a, ic, sub, head);
+    const int nc_pre = LIST ? a.clist_n[ic] : -1;
     int lo = 0;
     bool staged = false;
-    if (SEL != 2 && a.use_lds) {
-        lo = a.win_lo[blockIdx.x];
-        const int cnt = a.win_hi[blockIdx.x] - lo + 1;
+    if (SEL == 0 && a.use_lds) {
+        lo = a.win_lo[blk];
+        const int cnt = a.win_hi[blk] - lo + 1;
         staged = cnt > 0 && cnt <= lds_cap;
         if (staged) {
             for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
@@ -769,12 +796,6 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     }
     if (i >= a.N) return;  // whole quads leave together
 
-    const double xi = a.x[i], yi = a.y[i];
-    double pxi, pyi, uxi, uyi;
-    advanced_pos(a, i, adv, pxi, pyi, uxi, uyi);
-    const double vxi = a.vx[i], vyi = a.vy[i];  // velocities of the previous step
-    const double Vi = a.vol[i], mi = a.mass[i];
-    const int pi = a.part[i];
     const int mt = a.pmat[pi];
     const int ag = a.pagg[pi];
     const MatConst mc = a.mat[mt];
@@ -790,28 +811,25 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     // nodal force goes to the closure kernels, which integrate its nodes
     const bool closure = MODE == M_STEP && a.cl_on && a.cl_on[pi];
     if (SEL == 1 && closure) return;   // whole quads leave together
-    if (SEL == 2 && !closure) return;
     // List mode runs the bond loop first (its contact candidates never
     // involve intact bonds, so the order does not matter there), which keeps
     // fewer partial sums live through the loop.  Otherwise contact comes
     // first, because self-contact needs the bonds intact at the start of the
     // step and the bond loop commits breaks.
     if constexpr (LIST) {
-        if constexpr (SEL != 2)
-            if (!closure)
-                bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                     uyi, Vi, fpx, fpy, nbrk, smx);
+        if (!closure)
+            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
+                                 Vi, fpx, fpy, nbrk, smx, head);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
-                                     fsx, fsy, fnx, fny);
+                                     fsx, fsy, fnx, fny, nc_pre);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
     } else {
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
-        if constexpr (SEL != 2)
-            if (!closure)
-                bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                     uyi, Vi, fpx, fpy, nbrk, smx);
+        if (!closure)
+            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
+                                 Vi, fpx, fpy, nbrk, smx, head);
     }
 
     // ---- combine the quad ------------------------------------------------------
@@ -881,6 +899,29 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         }
     }
     if (st) atomicOr(a.status, st);
+}
+
+template <typename R, int MODE, bool LIST, int SEL = 0>
+__global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
+    extern __shared__ double lds[];
+    // list mode: this launch computes step sprev + 1 of a replay that started
+    // after step *step_base; once a list has gone stale, that step and every
+    // later one of the replay are no-ops (the check is uniform over the grid)
+    long long sprev = 0;
+    if (LIST) {
+        sprev = *a.step_base + a.chunk_k;
+        if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    }
+    if (SEL == 1) {
+        // slot blockIdx.x of the list of force workgroups that hold nodes
+        // under the plain force (listed at switch-on, appended by the kernels
+        // that make a particle fall back from the closure); no LDS staging,
+        // so that the workgroups past the list's end cost next to nothing
+        if ((int)blockIdx.x >= *a.n_pd_blocks) return;
+        force_block<R, MODE, LIST, SEL>(a, 0, a.pd_blocks[blockIdx.x], sprev, lds);
+    } else {
+        force_block<R, MODE, LIST, SEL>(a, lds_cap, blockIdx.x, sprev, lds);
+    }
 }
 
 // Contact and wall forces of the nodes of particles under the modal closure
@@ -1070,18 +1111,11 @@ static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b
     if (mode == M_STEP) {
         if (list) {
             if (sel == 1)
-                hipLaunchKernelGGL((k_force<R, M_STEP, true, 1>), g, b, shm, s, a, lds_cap);
-            else if (sel == 2)
-                hipLaunchKernelGGL((k_force<R, M_STEP, true, 2>), g, b, 0, s, a, lds_cap);
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 1>), g, b, 0, s, a, lds_cap);
             else
                 hipLaunchKernelGGL((k_force<R, M_STEP, true, 0>), g, b, shm, s, a, lds_cap);
         } else {
-            if (sel == 1)
-                hipLaunchKernelGGL((k_force<R, M_STEP, false, 1>), g, b, shm, s, a, lds_cap);
-            else if (sel == 2)
-                hipLaunchKernelGGL((k_force<R, M_STEP, false, 2>), g, b, 0, s, a, lds_cap);
-            else
-                hipLaunchKernelGGL((k_force<R, M_STEP, false, 0>), g, b, shm, s, a, lds_cap);
+            hipLaunchKernelGGL((k_force<R, M_STEP, false, 0>), g, b, shm, s, a, lds_cap);
         }
     } else if (mode == M_FORCES) {
         hipLaunchKernelGGL((k_force<R, M_FORCES, false>), g, b, shm, s, a, lds_cap);
@@ -1093,7 +1127,8 @@ static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list, int sel) {
     if (a.N == 0) return hipSuccess;
-    if (sel && !(mode == M_STEP && a.cl_on)) return hipErrorInvalidValue;
+    if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
+        return hipErrorInvalidValue;
     const int B = a.block_nodes;  // nodes per workgroup, four lanes each
     const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
     const dim3 g(grid_for(a.N, B)), b(4 * B);
