@@ -122,7 +122,6 @@ def precision_split(pd, W, torch, steps):
         sps = steps / (time.perf_counter() - t0)
         n_pairs = g.sizes()["bonds"] // 2
         res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
-                     "list_rebuilds": gr.sizes()["list_rebuilds"],
                      "force_kernel_ms": g.time_kernels(128)["force"][0]}
     return res
 

@@ -533,6 +533,17 @@ __global__ void k_build_list(DevArgs a) {
         atomicMax(a.overflow, n);
         n = a.maxc;
     }
+    // ascending partner index: the order contact sums run in does not depend
+    // on how the list came about (a rebuild or appends after breaks)
+    for (int k = 1; k < n; ++k) {
+        const uint32_t v = a.clist[(size_t)k * a.N + i];
+        int m = k - 1;
+        while (m >= 0 && a.clist[(size_t)m * a.N + i] > v) {
+            a.clist[(size_t)(m + 1) * a.N + i] = a.clist[(size_t)m * a.N + i];
+            --m;
+        }
+        a.clist[(size_t)(m + 1) * a.N + i] = v;
+    }
     a.clist_n[i] = n;
     a.ubx[i] = (float)uxi;
     a.uby[i] = (float)uyi;
@@ -587,7 +598,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                                             const double *Suy, const double *Sv, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
                                             R &fpy, int &nbrk, double &smx,
-                                            const SlotHead &h) {
+                                            const SlotHead &h, int (&bj)[4]) {
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t base = h.base;
@@ -670,6 +681,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                     const double sx = (EX * (DX + X) + EY * (DY + Y)) / (l0x * (lx + l0x));
                     if (fabs(sx) > s0) {
                         if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
+                        if (nbrk < 4) bj[nbrk] = j;  // partners for the candidate list
                         ++nbrk;
                         g = 0;
                     }
@@ -682,7 +694,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
 }
 
 // Contact forces of node i (lane `sub` of its quad): with candidate lists
-// (LIST), every fourth listed candidate; otherwise the nodes of the cells
+// (LIST), the listed candidates j with j mod 4 = sub; otherwise the nodes of the cells
 // sub, sub + 4, sub + 8 of the 3 x 3 neighbourhood.  Pairs closer than R_c
 // act; an intact bond replaces contact between nodes of one particle.
 template <typename R, bool LIST, bool adv>
@@ -693,21 +705,33 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                                                R &fny, int nc_pre = -1) {
     if (LIST) {
         // candidates listed at the last rebuild (intact bonds excluded)
+        // candidate j goes to lane j mod 4, in ascending j (the list is
+        // sorted): a lane's sum then depends only on the pairs within R_c,
+        // not on which extra candidates the list holds (it is a superset that
+        // depends on when it was built)
         const int nc = nc_pre >= 0 ? nc_pre : a.clist_n[i];
-        for (int q = sub; q < nc; q += 4) {
-            const int j = (int)a.clist[(size_t)q * a.N + i];
-            double pxj, pyj, ux, uy;
-            advanced_pos(a, j, adv, pxj, pyj, ux, uy);
-            const double ddx = pxj - pxi, ddy = pyj - pyi;
-            const double r2 = ddx * ddx + ddy * ddy;
-            if (!(r2 < a.Rc2)) continue;
-            if (r2 == 0.0) {
-                count(a, C_COINC);
-                continue;
+        constexpr int kCB = 8;  // list entries fetched together
+        for (int q0 = 0; q0 < nc; q0 += kCB) {
+            int js[kCB];
+#pragma unroll
+            for (int t = 0; t < kCB; ++t)
+                js[t] = q0 + t < nc ? (int)a.clist[(size_t)(q0 + t) * a.N + i] : -1;
+            for (int t = 0; t < kCB; ++t) {
+                const int j = js[t];
+                if (j < 0 || (j & 3) != sub) continue;
+                double pxj, pyj, ux, uy;
+                advanced_pos(a, j, adv, pxj, pyj, ux, uy);
+                const double ddx = pxj - pxi, ddy = pyj - pyi;
+                const double r2 = ddx * ddx + ddy * ddy;
+                if (!(r2 < a.Rc2)) continue;
+                if (r2 == 0.0) {
+                    count(a, C_COINC);
+                    continue;
+                }
+                const int pj = a.part[j];
+                contact_pair<R>(a, mc, i, j, pj == pi, pj, xi, yi, ddx, ddy, r2, vxi, vyi,
+                                a.vx[j], a.vy[j], Vi, mi, fsx, fsy, fnx, fny);
             }
-            const int pj = a.part[j];
-            contact_pair<R>(a, mc, i, j, pj == pi, pj, xi, yi, ddx, ddy, r2, vxi, vyi, a.vx[j],
-                            a.vy[j], Vi, mi, fsx, fsy, fnx, fny);
         }
     } else {
         // nodes of the 3 x 3 neighbouring cells, cells sub, sub + 4, sub + 8
@@ -806,6 +830,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     R fsx = 0, fsy = 0, fnx = 0, fny = 0, fpx = 0, fpy = 0;
     double fwx = 0.0, fwy = 0.0;
     int nbrk = 0;
+    int bj[4] = {0, 0, 0, 0};
     double smx = 0.0;
     // a particle under the modal closure: no bond forces here; its external
     // nodal force goes to the closure kernels, which integrate its nodes
@@ -819,7 +844,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     if constexpr (LIST) {
         if (!closure)
             bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx, head);
+                                 Vi, fpx, fpy, nbrk, smx, head, bj);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny, nc_pre);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
@@ -829,7 +854,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
             bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx, head);
+                                 Vi, fpx, fpy, nbrk, smx, head, bj);
     }
 
     // ---- combine the quad ------------------------------------------------------
@@ -841,6 +866,58 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     fny = quad_sum(fny);
     fwx = quad_sum(fwx);
     fwy = quad_sum(fwy);
+    // list mode: a bond that broke makes its pair a self-contact candidate
+    // from the next step on; if the pair was within the list radius at the
+    // last rebuild (build-time positions, with a margin), this lane appends it
+    // to the node's own candidate list, in lane order; a full list means a
+    // rebuild instead
+    bool relist = false;
+    if (LIST && MODE == M_STEP) {
+        int keep = 0;
+        uint32_t kj[4];
+        const int nb = nbrk < 4 ? nbrk : 4;
+        if (nb) {
+            const double bxi = xi + (double)a.ubx[i], byi = yi + (double)a.uby[i];
+            for (int t = 0; t < nb; ++t) {
+                const int j = bj[t];
+                const double dx = (a.x[j] + (double)a.ubx[j]) - bxi;
+                const double dy = (a.y[j] + (double)a.uby[j]) - byi;
+                if (dx * dx + dy * dy < a.Rl2 * (1.0 + 1e-6)) kj[keep++] = (uint32_t)j;
+            }
+        }
+        for (int t = keep; t < 4; ++t) kj[t] = 0xffffffffu;
+        int over = nbrk > 4 ? 1 : 0;
+        over |= __shfl_xor(over, 1, 64);
+        over |= __shfl_xor(over, 2, 64);
+        int tot = keep;
+        tot += __shfl_xor(tot, 1, 64);
+        tot += __shfl_xor(tot, 2, 64);
+        // lane 0 gathers the quad's partners and merges them into the node's
+        // sorted list
+        uint32_t nj[16];
+        const int q0 = (int)(threadIdx.x & ~3u);
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) nj[4 * l + t] = __shfl(kj[t], q0 + l, 64);
+        if (over || nc_pre + tot > a.maxc) {
+            relist = true;
+        } else if (sub == 0 && tot) {
+            int n = nc_pre;
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t v = nj[e];
+                if (v == 0xffffffffu) continue;
+                int m = n - 1;
+                while (m >= 0 && a.clist[(size_t)m * a.N + i] > v) {
+                    a.clist[(size_t)(m + 1) * a.N + i] = a.clist[(size_t)m * a.N + i];
+                    --m;
+                }
+                a.clist[(size_t)(m + 1) * a.N + i] = v;
+                ++n;
+            }
+            a.clist_n[i] = n;
+        }
+    }
     nbrk = quad_sum(nbrk);
     st |= __shfl_xor(st, 1, 64);
     st |= __shfl_xor(st, 2, 64);
@@ -850,7 +927,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     }
     if (sub != 0) return;
     if (MODE != M_FORCES) count(a, C_BROKEN, (unsigned long long)nbrk);
-    if (LIST && nbrk) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+    if (LIST && relist) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
 
     // ---- outputs ---------------------------------------------------------------
     const double Fx = (((double)fpx + (double)fsx) + (double)fnx) + fwx;

@@ -207,6 +207,50 @@ def test_trajectory_two_disks_contact_1000(pdmod):
     assert np.array_equal(sg["broken"], so["broken"])
 
 
+def test_breaks_during_list_steps(pdmod):
+    """A 40 m/s head-on impact breaks bonds while the candidate lists are in
+    use: each broken pair joins its nodes' lists in the step it breaks (no
+    rebuild).  The first 75 steps (bonds break, fragments touch) follow the
+    oracle; after that, contact onsets near ties make any rounding difference
+    grow about a thousandfold per 25 steps, in the oracle as well, so the
+    remaining check is the list path against the every-step cell search on
+    the GPU, which must give the same states and broken bonds."""
+    _say("case: breaks during list steps")
+
+    def impact():
+        prob = W.two_disks(contact_active=True)
+        vy = np.zeros(prob.n_nodes)
+        vy[prob.particle_offset[1]:] = -40.0
+        prob.v0y = vy
+        return prob
+
+    prob = impact()
+    g, o = pdmod.PD(prob), Oracle(prob)
+    assert g.tuning()["skin_factor"] > 0
+    for k in range(3):
+        eu, ev, sg, so = _traj(g, o, 25)
+        assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (k, eu, ev)
+        assert np.array_equal(sg["broken"], so["broken"]), k
+    assert int(so["broken"].sum()) > 50
+    assert o.counters()["self_"] > 0
+    lst, srch = pdmod.PD(impact()), pdmod.PD(impact())
+    srch.set_tuning(skin_factor=0.0)
+    r0 = lst.sizes()["list_rebuilds"]
+    for k in range(3):
+        lst.step(50)
+        srch.step(50)
+        a, b = lst.get_state(), srch.get_state()
+        assert np.array_equal(a["broken"], b["broken"]), k
+        eu = max(_relerr(a["ux"], b["ux"]), _relerr(a["uy"], b["uy"]))
+        ev = max(_relerr(a["vx"], b["vx"]), _relerr(a["vy"], b["vy"]))
+        assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (k, eu, ev)
+    assert int(a["broken"].sum()) > 200
+    lst.step(150)
+    # rebuilds come from motion (a node moving half the skin), not from the
+    # hundreds of steps with a break
+    assert lst.sizes()["list_rebuilds"] - r0 < 40
+
+
 @pytest.mark.parametrize("seed", [11, 12])
 def test_trajectory_bed_100(pdmod, seed):
     """A herded bed with gravity 5000 m/s^2: contact, friction, damping,
