@@ -110,7 +110,15 @@ def precision_split(pd, W, torch, steps):
         errs.append(float(max(np.abs(f32[0] - f64[0]).max(), np.abs(f32[1] - f64[1]).max()) / scale))
         g64.step(steps // 4)
     g32b = pd.PD(prob, precision=1)
-    g32b.step(steps)
+    series = []
+    for k in range(8):
+        g32b.step(steps // 8)
+        ob = g32b.observables()
+        series.append({"step": (k + 1) * (steps // 8),
+                       "top_wall_force_y": float(ob["wall_force"][0, 3, 1]),
+                       "volume_fraction": float(ob["volume_fraction"][0]),
+                       "damage": float(ob["broken"][0] / ob["reference"][0])})
+    res["fp32_observables"] = series
     res["force_rel_err_fp32_vs_fp64_max_norm"] = errs
     res["broken_directed_fp64"] = int(g64.damage()[1])
     res["broken_directed_fp32"] = int(g32b.damage()[1])

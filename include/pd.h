@@ -214,6 +214,22 @@ pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launc
  * [8] candidate-list rebuilds so far, [9] candidate slots per node. */
 pd_status pd_sizes(const pd_ctx *c, int64_t out[10]);
 
+/* Compaction observables at the current state (Sec. 7.4), per aggregate a,
+ * out[12 a + k] (host buffer of 12 n_aggregates doubles):
+ *   k = 0..7  force the particles exert on the left, right, floor and top wall
+ *             (x, y each): minus the sum over the aggregate's nodes of each
+ *             wall's share of the wall force of Sec. 4.5 (eq. wall-total),
+ *             positions x + u, velocities v, top wall at t = step dt; a
+ *             corner correction counts half for each of its two walls
+ *   k = 8     volume fraction: sum of nodal areas / box area at time t
+ *   k = 9, 10 broken and reference directed bonds (bulk damage = k9 / k10)
+ *   k = 11    top-wall height at time t */
+pd_status pd_observables(pd_ctx *c, double *out);
+/* damage of each particle, broken / reference directed bonds of its nodes
+ * (Sec. 3.1; 0 for a particle without bonds); host or device buffer of
+ * n_particles doubles */
+pd_status pd_particle_damage(pd_ctx *c, double *out, int32_t on_device);
+
 /* ---------------------------------------------------------------------------
  * Learned modal closure (an extension: the paper has no reduced-order model).
  *

@@ -88,6 +88,7 @@ def _lib(openmp: bool):
         L.or_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp,
                                    C.POINTER(C.c_uint8), C.c_int64]
         L.or_counters.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.or_wall_reactions.argtypes = [vp, _dp]
         L.or_segment_in_particle.argtypes = [vp, C.c_int32, C.c_double, C.c_double,
                                              C.c_double, C.c_double]
         L.or_wall_segment.argtypes = [C.c_double, C.c_double, _dp, _dp]
@@ -212,6 +213,14 @@ class Oracle:
         self.lib.or_counters(self.h, _ptr(out, C.c_int64))
         return dict(inter=out[0], self_=out[1], stick=out[2], slip=out[3], wall=out[4],
                     coincident=out[5], broken=out[6])
+
+    def wall_reactions(self):
+        """[n_aggregates, 4 walls (left, right, floor, top), 2]: force the
+        particles exert on each wall at the current state"""
+        A = self.prob.n_aggregates
+        out = np.zeros(8 * A)
+        self.lib.or_wall_reactions(self.h, _ptr(out, C.c_double))
+        return out.reshape(A, 4, 2)
 
     def segment_in_particle(self, p, a, b) -> bool:
         return bool(self.lib.or_segment_in_particle(self.h, p, a[0], a[1], b[0], b[1]))

@@ -562,9 +562,12 @@ static void wall_region(const or_ctx *c, int i, double Kn, double A, double Frma
     ++cnt[4];
 }
 
-/* walls of node i: left, right, floor, top (top at height yhi0 - v t) */
-static int wall_node(or_ctx *c, int i, double t, const double *vx, const double *vy,
-                     int64_t *cnt) {
+/* walls of node i: left, right, floor, top (top at height yhi0 - v t).
+ * With split != NULL, also each wall's share of the force on the node:
+ * split[2 w], split[2 w + 1] for wall w; a wall segment counts for its wall,
+ * a corner correction half for each of its two walls. */
+static int wall_node_split(or_ctx *c, int i, double t, const double *vx, const double *vy,
+                           int64_t *cnt, double *split) {
     const int a = c->pagg[c->part[i]];
     const double Rc = c->Rc;
     const double xlo = c->box[4 * a], xhi = c->box[4 * a + 1], ylo = c->box[4 * a + 2];
@@ -585,9 +588,17 @@ static int wall_node(or_ctx *c, int i, double t, const double *vx, const double 
             double A, g;
             or_wall_segment(Rc, d[w], &A, &g);
             const double Frmag = Kn * c->vol[i] * or_wall_segment_gap(Rc, d[w]);
-            if (A > 0.0)
-                wall_region(c, i, Kn, A, Frmag, nx[w], ny[w], 0.0, wv[w], vx, vy, +1.0, &fx, &fy,
+            if (A > 0.0) {
+                double rx = 0.0, ry = 0.0;
+                wall_region(c, i, Kn, A, Frmag, nx[w], ny[w], 0.0, wv[w], vx, vy, +1.0, &rx, &ry,
                             cnt);
+                fx += rx;
+                fy += ry;
+                if (split) {
+                    split[2 * w] += rx;
+                    split[2 * w + 1] += ry;
+                }
+            }
         }
     }
     /* adjacent pairs: (left, floor), (floor, right), (right, top), (top, left) */
@@ -605,12 +616,26 @@ static int wall_node(or_ctx *c, int i, double t, const double *vx, const double 
             /* corner region moves with the top wall when it borders it */
             double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
             const double Frmag = Kn * (Rc - dist) * c->vol[i] * A;
-            wall_region(c, i, Kn, A, Frmag, ex, ey, 0.0, wvy, vx, vy, -1.0, &fx, &fy, cnt);
+            double rx = 0.0, ry = 0.0;
+            wall_region(c, i, Kn, A, Frmag, ex, ey, 0.0, wvy, vx, vy, -1.0, &rx, &ry, cnt);
+            fx += rx;
+            fy += ry;
+            if (split) {
+                split[2 * wa] += 0.5 * rx;
+                split[2 * wa + 1] += 0.5 * ry;
+                split[2 * wb] += 0.5 * rx;
+                split[2 * wb + 1] += 0.5 * ry;
+            }
         }
     }
     c->F[T_WALL][0][i] = fx;
     c->F[T_WALL][1][i] = fy;
     return st;
+}
+
+static int wall_node(or_ctx *c, int i, double t, const double *vx, const double *vy,
+                     int64_t *cnt) {
+    return wall_node_split(c, i, t, vx, vy, cnt, NULL);
 }
 
 /* PD force on node i (eq. peri, eq. pmb); bonds with |s| > s0 carry no force
@@ -887,6 +912,31 @@ int or_forces(or_ctx *c, uint32_t mask, double *fx, double *fy) {
 }
 
 /* Sec. 3.1: damage = broken bonds / reference bonds at the node */
+/* Force the particles exert on each wall at the current state (positions
+ * x + u, velocities v, top wall at time step * dt): minus the sum over the
+ * aggregate's nodes of each wall's share of the wall force (Sec. 4.5, with a
+ * corner correction split evenly between its two walls).
+ * out[8 a + 2 w + k], walls w = left, right, floor, top; k = x, y. */
+int or_wall_reactions(or_ctx *c, double *out) {
+    const int N = c->N;
+    for (int i = 0; i < N; ++i) {
+        c->px[i] = c->x[i] + c->ux[i];
+        c->py[i] = c->y[i] + c->uy[i];
+    }
+    for (int k = 0; k < 8 * c->A; ++k) out[k] = 0.0;
+    const double t = (double)c->step * c->dt;
+    int64_t cnt[8] = {0};
+    int st = OR_OK;
+    for (int i = 0; i < N; ++i) {
+        double split[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int s = wall_node_split(c, i, t, c->vx, c->vy, cnt, split);
+        if (s != OR_OK) st = s;
+        const int a = c->pagg[c->part[i]];
+        for (int k = 0; k < 8; ++k) out[8 * a + k] -= split[k];
+    }
+    return st;
+}
+
 int or_damage(const or_ctx *c, double *phi, int64_t *nb) {
     int64_t tot = 0;
     for (int i = 0; i < c->N; ++i) {

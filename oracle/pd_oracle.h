@@ -75,6 +75,11 @@ int or_step(or_ctx *c, int64_t n_steps);
 /* force density by term at the current state (breaks not committed) */
 int or_forces(or_ctx *c, uint32_t mask, double *fx, double *fy);
 
+/* force the particles exert on each wall at the current state, per aggregate:
+ * out[8 a + 2 w + k], w = left, right, floor, top, k = x, y (a corner
+ * correction split evenly between its two walls); modifies the force buffers */
+int or_wall_reactions(or_ctx *c, double *out);
+
 /* damage ratio per node and number of broken directed bonds */
 int or_damage(const or_ctx *c, double *phi, int64_t *n_broken_directed);
 

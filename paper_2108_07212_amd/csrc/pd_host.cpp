@@ -1180,6 +1180,20 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     if (p->top_wall_speed)
         for (int q = 0; q < A; ++q) vtop[q] = p->top_wall_speed[q];
     TRY(upload(c, &dvtop, vtop.data(), A));
+    // per aggregate: its particles in order, box, top-wall speed, particle area
+    {
+        std::vector<int> cnt(A + 1, 0), parts(P);
+        for (int q = 0; q < P; ++q) ++cnt[pagg[q] + 1];
+        for (int a2 = 0; a2 < A; ++a2) cnt[a2 + 1] += cnt[a2];
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (int q = 0; q < P; ++q) parts[fill[pagg[q]]++] = q;
+        TRY(upload(c, &c.d_agg_pstart, cnt.data(), A + 1));
+        TRY(upload(c, &c.d_agg_parts, parts.data(), P));
+        c.h_box.assign(p->box, p->box + 4 * (size_t)A);
+        c.h_vtop = vtop;
+        c.h_agg_vol.assign(A, 0.0);
+        for (int i = 0; i < N; ++i) c.h_agg_vol[pagg[part[i]]] += p->vol[i];
+    }
     // kept for the modal-closure setup
     c.h_x.assign(p->x, p->x + N);
     c.h_y.assign(p->y, p->y + N);
@@ -1409,6 +1423,49 @@ pd_status pd_damage(pd_ctx *ctx, double *phi, int64_t *nb, int32_t on_device) {
         HIPCHK(hipMemcpyAsync(phi, dphi, c.N * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     if (nb) *nb = (int64_t)h;
+    return PD_OK;
+}
+
+pd_status pd_observables(pd_ctx *ctx, double *out) {
+    if (!ctx || !out) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    const int A = c.A;
+    if (!c.d_split) TRY(dalloc(c, &c.d_split, 8 * (size_t)c.N));
+    if (!c.d_obs) TRY(dalloc(c, &c.d_obs, 10 * (size_t)A));
+    set_state_ptrs(c, c.cur);
+    HIPCHK(launch_observables(c.a, c.d_split, c.d_agg_pstart, c.d_agg_parts, c.d_poff, c.d_obs,
+                              c.stream));
+    std::vector<double> r(10 * (size_t)A);
+    HIPCHK(hipMemcpyAsync(r.data(), c.d_obs, r.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    const double t = (double)c.step * c.a.dt;
+    for (int a = 0; a < A; ++a) {
+        double *o = out + 12 * (size_t)a;
+        for (int k = 0; k < 8; ++k) o[k] = r[10 * a + k];
+        const double *b = &c.h_box[4 * (size_t)a];
+        const double ytop = b[3] - c.h_vtop[a] * t;
+        o[8] = c.h_agg_vol[a] / ((b[1] - b[0]) * (ytop - b[2]));
+        o[9] = r[10 * a + 8];
+        o[10] = r[10 * a + 9];
+        o[11] = ytop;
+    }
+    return PD_OK;
+}
+
+pd_status pd_particle_damage(pd_ctx *ctx, double *out, int32_t on_device) {
+    if (!ctx || !out) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (on_device) {
+        TRY(after_caller(c));
+        HIPCHK(launch_particle_damage(c.a, c.d_poff, out, c.stream));
+    } else {
+        if (!c.d_pdamage) TRY(dalloc(c, &c.d_pdamage, (size_t)c.P));
+        HIPCHK(launch_particle_damage(c.a, c.d_poff, c.d_pdamage, c.stream));
+        HIPCHK(hipMemcpyAsync(out, c.d_pdamage, c.P * sizeof(double), hipMemcpyDeviceToHost,
+                              c.stream));
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
     return PD_OK;
 }
 

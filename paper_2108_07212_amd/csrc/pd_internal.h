@@ -259,6 +259,9 @@ struct Ctx {
     // host-side copies needed by setup/validation
     int N = 0, P = 0, A = 0, M = 0;
     std::vector<double> h_x, h_y, h_vol, h_mass;
+    std::vector<double> h_box, h_vtop, h_agg_vol;  // per aggregate: box, top-wall speed, sum of V
+    int *d_agg_pstart = nullptr, *d_agg_parts = nullptr;
+    double *d_split = nullptr, *d_obs = nullptr, *d_pdamage = nullptr;
     std::vector<int> h_poff, h_pmat;
     std::vector<MatConst> h_mc;
     const int *d_poff = nullptr;
@@ -300,6 +303,9 @@ int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
+hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
+                              const int *agg_parts, const int *poff, double *out, hipStream_t s);
+hipError_t launch_particle_damage(const DevArgs &a, const int *poff, double *out, hipStream_t s);
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s);
 hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);

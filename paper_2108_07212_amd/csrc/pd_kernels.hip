@@ -384,9 +384,26 @@ __device__ __forceinline__ void wall_region(const DevArgs &a, double Kn, double 
 // `part` (left, right, floor, top) and the corner `part` of (left, floor),
 // (floor, right), (right, top), (top, left), whose region is subtracted
 // (inclusion-exclusion, eq. wall-total).
+// The same for one lane's wall and corner, returned apart: seg (the wall
+// `part`'s segment region) and cor (the corner `part`, already subtracted).
+__device__ void wall_parts(const DevArgs &a, int ag, int part, double px, double py, double vxi,
+                           double vyi, double mi, double Vi, double Kn, double t, double &sgx,
+                           double &sgy, double &crx, double &cry, int &st);
+
 __device__ void wall_forces(const DevArgs &a, int ag, int part, double px, double py, double vxi,
                             double vyi, double mi, double Vi, double Kn, double t, double &fx,
                             double &fy, int &st) {
+    double sgx = 0.0, sgy = 0.0, crx = 0.0, cry = 0.0;
+    wall_parts(a, ag, part, px, py, vxi, vyi, mi, Vi, Kn, t, sgx, sgy, crx, cry, st);
+    fx += sgx;
+    fy += sgy;
+    fx += crx;
+    fy += cry;
+}
+
+__device__ void wall_parts(const DevArgs &a, int ag, int part, double px, double py, double vxi,
+                           double vyi, double mi, double Vi, double Kn, double t, double &fx,
+                           double &fy, double &crx, double &cry, int &st) {
     const double Rc = a.Rc;
     const double vtop = a.vtop[ag];
     const double d[4] = {px - a.box[4 * ag], a.box[4 * ag + 1] - px, py - a.box[4 * ag + 2],
@@ -433,7 +450,7 @@ __device__ void wall_forces(const DevArgs &a, int ag, int part, double px, doubl
     const double dist = sqrt(cx * cx + cy * cy);
     const double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;
     const double Fr = Kn * (Rc - dist) * Vi * A;
-    wall_region(a, Kn, A, Fr, cx / dist, cy / dist, wvy, vxi, vyi, mi, Vi, -1.0, fx, fy);
+    wall_region(a, Kn, A, Fr, cx / dist, cy / dist, wvy, vxi, vyi, mi, Vi, -1.0, crx, cry);
 }
 
 // bond (i, j) is in the reference set and intact (scan of i's own row)
@@ -1045,6 +1062,121 @@ hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
         hipLaunchKernelGGL(k_cl_contact<double>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_cl_contact<float>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction observables (Sec. 7.4): wall reactions, bond counts, damage
+// ---------------------------------------------------------------------------
+// each wall's share of the wall force on node i at the current state
+// (positions x + u, velocities v, top wall at t = step dt): a wall segment
+// counts for its wall, a corner correction half for each of its two walls
+__global__ void k_wall_split(DevArgs a, double *split) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int pi = a.part[i];
+    const int ag = a.pagg[pi];
+    const MatConst mc = a.mat[a.pmat[pi]];
+    const double px = a.x[i] + a.ux[i], py = a.y[i] + a.uy[i];
+    const double t = (double)(*a.step) * a.dt;
+    double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int pa[4] = {0, 2, 1, 3}, pb[4] = {2, 1, 3, 0};
+    int st = 0;
+    for (int part = 0; part < 4; ++part) {
+        double sgx = 0.0, sgy = 0.0, crx = 0.0, cry = 0.0;
+        wall_parts(a, ag, part, px, py, a.vx[i], a.vy[i], a.mass[i], a.vol[i], mc.Kn, t, sgx, sgy,
+                   crx, cry, st);
+        w[2 * part] += sgx;
+        w[2 * part + 1] += sgy;
+        w[2 * pa[part]] += 0.5 * crx;
+        w[2 * pa[part] + 1] += 0.5 * cry;
+        w[2 * pb[part]] += 0.5 * crx;
+        w[2 * pb[part] + 1] += 0.5 * cry;
+    }
+    for (int k = 0; k < 8; ++k) split[(size_t)k * a.N + i] = w[k];
+}
+
+// per aggregate (one workgroup each, over its particles in order): minus the
+// sum of the walls' shares (the force on each wall), broken and reference
+// directed bonds; out[10 a + k]
+__global__ __launch_bounds__(256) void k_obs_reduce(DevArgs a, const double *split,
+                                                    const int *agg_pstart, const int *agg_parts,
+                                                    const int *poff, double *out) {
+    __shared__ double sh[4 * 10];
+    const int ag = blockIdx.x;
+    double v[10];
+    for (int k = 0; k < 10; ++k) v[k] = 0.0;
+    for (int q = agg_pstart[ag]; q < agg_pstart[ag + 1]; ++q) {
+        const int p = agg_parts[q];
+        for (int i = poff[p] + threadIdx.x; i < poff[p + 1]; i += 256) {
+            for (int k = 0; k < 8; ++k) v[k] -= split[(size_t)k * a.N + i];
+            const uint32_t sl = (uint32_t)i / kSlice;
+            const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
+            const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+            for (int k = 0; k < W; ++k) {
+                const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+                if ((int)(e & kIndexMask) == i) continue;  // padding
+                v[9] += 1.0;
+                if (e & kBroken) v[8] += 1.0;
+            }
+        }
+    }
+    for (int k = 0; k < 10; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 10; ++k) sh[w * 10 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int k = threadIdx.x;
+        out[10 * ag + k] = ((sh[k] + sh[10 + k]) + sh[20 + k]) + sh[30 + k];
+    }
+}
+
+// broken / reference directed bonds of each particle (one workgroup each)
+__global__ __launch_bounds__(256) void k_particle_damage(DevArgs a, const int *poff, double *out) {
+    __shared__ unsigned sh[8];
+    const int p = blockIdx.x;
+    unsigned nb = 0, nr = 0;
+    for (int i = poff[p] + threadIdx.x; i < poff[p + 1]; i += 256) {
+        const uint32_t sl = (uint32_t)i / kSlice;
+        const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
+        const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+        for (int k = 0; k < W; ++k) {
+            const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+            if ((int)(e & kIndexMask) == i) continue;
+            ++nr;
+            if (e & kBroken) ++nb;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        nb += __shfl_xor(nb, o, 64);
+        nr += __shfl_xor(nr, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[2 * w] = nb;
+        sh[2 * w + 1] = nr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned b = sh[0] + sh[2] + sh[4] + sh[6], r = sh[1] + sh[3] + sh[5] + sh[7];
+        out[p] = r ? (double)b / (double)r : 0.0;
+    }
+}
+
+hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
+                              const int *agg_parts, const int *poff, double *out, hipStream_t s) {
+    DevArgs b = a;
+    b.counting = 0;  // an observation, not a step: no event counts
+    hipLaunchKernelGGL(k_wall_split, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, b, split);
+    hipLaunchKernelGGL(k_obs_reduce, dim3(a.A), dim3(256), 0, s, b, split, agg_pstart, agg_parts, poff,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_damage(const DevArgs &a, const int *poff, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_particle_damage, dim3(a.P), dim3(256), 0, s, a, poff, out);
     return hipGetLastError();
 }
 

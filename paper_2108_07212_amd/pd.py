@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     L.pd_autotune.argtypes = [vp, C.c_int32, C.POINTER(Tuning)]
     L.pd_time_kernels.argtypes = [vp, C.c_int64, _dp, _ip, C.c_int32]
     L.pd_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.pd_observables.argtypes = [vp, _dp]
+    L.pd_particle_damage.argtypes = [vp, vp, C.c_int32]
     _fp = C.POINTER(C.c_float)
     L.pd_closure_setup.argtypes = [vp, _ip, C.c_double, _dp, C.c_int32, C.c_double]
     L.pd_closure_modes.argtypes = [vp, C.c_int32, _ip, _ip, _dp, _dp, _dp]
@@ -292,6 +294,23 @@ class PD:
         keys = ("nodes", "bonds", "slots", "cells", "radix_passes", "particles", "aggregates",
                 "max_window", "list_rebuilds", "list_slots")
         return {k: int(v) for k, v in zip(keys, out)}
+
+    # -- compaction observables -------------------------------------------
+    def observables(self):
+        """dict of per-aggregate arrays: wall_force [A, 4, 2] (left, right,
+        floor, top; force on the wall), volume_fraction, broken, reference
+        (directed bonds), top_wall_y"""
+        A = self.prob.n_aggregates
+        out = np.zeros(12 * A)
+        self._chk(self.lib.pd_observables(self.h, _p(out, C.c_double)))
+        o = out.reshape(A, 12)
+        return dict(wall_force=o[:, :8].reshape(A, 4, 2), volume_fraction=o[:, 8],
+                    broken=o[:, 9], reference=o[:, 10], top_wall_y=o[:, 11])
+
+    def particle_damage(self):
+        out = np.zeros(self.prob.n_particles)
+        self._chk(self.lib.pd_particle_damage(self.h, C.c_void_p(out.ctypes.data), 0))
+        return out
 
     # -- learned modal closure ---------------------------------------------
     def closure_setup(self, shape_of_particle, gate_frac: float = 0.5, tau_c=None,

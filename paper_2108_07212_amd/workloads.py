@@ -530,3 +530,26 @@ def closure_bed(n_per_shape: int = 500, h: float = 0.08e-3, nodes: int = 400, se
         prob.v0x = np.repeat(vel[:, 0], counts)
         prob.v0y = np.repeat(vel[:, 1], counts)
     return prob
+
+
+def jitter_nodes(prob: Problem, seed: int, vol_frac: float = 0.4, pos_frac: float = 0.25) -> Problem:
+    """Unstructured-like nodes: every nodal volume scaled by a seeded factor
+    uniform in [1 - vol_frac, 1 + vol_frac], and the nodes of particles
+    without boundary loops (disks) moved by a seeded offset uniform in
+    [-pos_frac h, pos_frac h]^2 (such a particle has no boundary a node could
+    cross).  Draw order: volumes, then offsets."""
+    rng = np.random.default_rng(seed)
+    h = prob.meta["h"]
+    prob.vol = prob.vol * rng.uniform(1.0 - vol_frac, 1.0 + vol_frac, prob.n_nodes)
+    dx = rng.uniform(-pos_frac * h, pos_frac * h, (prob.n_nodes, 2))
+    lo = prob.loop_offset
+    po = prob.particle_offset
+    x, y = prob.x.copy(), prob.y.copy()
+    for p in range(prob.n_particles):
+        if lo[p + 1] == lo[p]:
+            s = slice(po[p], po[p + 1])
+            x[s] += dx[s, 0]
+            y[s] += dx[s, 1]
+    prob.x, prob.y = x, y
+    prob.meta = dict(prob.meta, jitter=(seed, vol_frac, pos_frac))
+    return prob

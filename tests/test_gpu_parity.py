@@ -267,6 +267,66 @@ def test_trajectory_bed_100(pdmod, seed):
     assert np.array_equal(pg, po)
 
 
+@pytest.mark.parametrize("seed", [41, 42])
+def test_unequal_volumes_and_offlattice_nodes(pdmod, seed):
+    """Nodal volumes jittered by up to 40 % and disk nodes moved off the
+    lattice: bond sets bit-exact, per-term forces and a 100-step trajectory
+    with friction, damping and gravity (whose coefficients use the volume of
+    the node they act on, so V_i != V_j shows) against the oracle."""
+    _say(f"case: unequal volumes seed={seed}")
+    prob = W.jitter_nodes(_herd(_bed(10, seed, g=(0.0, -5000.0)), 0.45, seed=seed, dv=0.5), seed)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro) and np.array_equal(cg, co)
+    _check_forces(g, o, "t0")
+    eu, ev, sg, so = _traj(g, o, 100)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
+    assert o.counters()["inter"] > 0 and o.counters()["slip"] + o.counters()["stick"] > 0
+    # per-step forces at the oracle's state after the run
+    g.set_state(so)
+    _check_forces(g, o, "t100")
+
+
+@pytest.mark.parametrize("vtop", [0.0, 2.0])
+def test_compaction_observables(pdmod, vtop):
+    """Wall reactions, bond counts, volume fraction and per-particle damage of
+    a bed pressed into the floor and the left wall (top wall moving down at
+    vtop) against the oracle's wall split and the plain definitions."""
+    _say(f"case: observables vtop={vtop}")
+    h = 0.12e-3
+    prob = _bed(8, 51, h=h, g=(0.0, -5000.0), vtop=vtop)
+    xlo, ylo = prob.box[0, 0], prob.box[0, 2]
+    prob.u0x = np.full(prob.n_nodes, -(prob.x.min() - xlo) + 0.3 * h)
+    prob.u0y = np.full(prob.n_nodes, -(prob.y.min() - ylo) + 0.3 * h)
+    W.perturb(prob, 52, dv=0.5)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    for k in range(3):
+        eu, ev, sg, so = _traj(g, o, 40)
+        assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (k, eu, ev)
+        obs = g.observables()
+        R = o.wall_reactions()
+        scale = np.abs(R).max()
+        assert scale > 0
+        assert np.abs(obs["wall_force"] - R).max() <= 1e-12 * scale, k
+        row, col = o.bonds()
+        assert obs["reference"][0] == len(col)
+        assert obs["broken"][0] == int(so["broken"].sum())
+        t = so["step"] * prob.dt
+        ytop = prob.box[0, 3] - vtop * t
+        area = (prob.box[0, 1] - prob.box[0, 0]) * (ytop - prob.box[0, 2])
+        assert abs(obs["top_wall_y"][0] - ytop) <= 1e-15 * abs(ytop)
+        assert abs(obs["volume_fraction"][0] - prob.vol.sum() / area) <= 1e-13
+        # per-particle damage: broken / reference directed bonds of its nodes
+        rows = np.repeat(np.arange(prob.n_nodes), np.diff(row))
+        part = np.repeat(np.arange(prob.n_particles), np.diff(prob.particle_offset))
+        nb = np.bincount(part[rows], weights=so["broken"].astype(float), minlength=prob.n_particles)
+        nr = np.bincount(part[rows], minlength=prob.n_particles)
+        ref = np.where(nr > 0, nb / np.maximum(nr, 1), 0.0)
+        np.testing.assert_array_equal(g.particle_damage(), ref)
+
+
 def test_damage_after_breaking(pdmod):
     _say("case: damage")
     h = 0.125e-3

@@ -697,3 +697,95 @@ def test_bond_stretch_against_exact_arithmetic(strain):
     assert float(fxe) != 0.0
     assert fx[0] == pytest.approx(float(fxe), rel=1e-14)
     assert fy[0] == pytest.approx(float(fye), rel=1e-14)
+
+
+def test_momentum_with_unequal_volumes():
+    """With unequal nodal volumes the PD bond force (c_w s V_i V_j e) and the
+    repulsion (K_n (R_c - d) V_i V_j e) stay pairwise antisymmetric, so with
+    damping, friction, walls and gravity off the total momentum is conserved;
+    damping and friction are not antisymmetric for V_i != V_j (their
+    coefficients use V_i of the node they act on)."""
+    h = 0.12e-3
+    parts, bx = W.mixed_bed(6, h, 14e-3, 14e-3, 31)
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], [-1.0, 1.0, -1.0, 1.0],
+                      contact_radius=0.95 * h, friction_mu=0.0, damping_ratio=0.0, dt=1e-7)
+    prob = W.jitter_nodes(prob, 32)
+    cx, cy = prob.x.mean(), prob.y.mean()
+    po = prob.particle_offset
+    vx, vy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        sl = slice(po[p], po[p + 1])
+        dx, dy = prob.x[sl].mean() - cx, prob.y[sl].mean() - cy
+        ux[sl], uy[sl] = -0.45 * dx, -0.45 * dy  # rigidly herded close together
+        vx[sl] = -3.0 * np.sign(dx)
+        vy[sl] = -3.0 * np.sign(dy)
+    prob.u0x, prob.u0y = ux, uy
+    prob.v0x, prob.v0y = vx, vy
+    o = Oracle(prob, contact_mode=1)
+    m = prob.materials[0].rho * prob.vol
+    p0 = np.array([(m * vx).sum(), (m * vy).sum()])
+    o.step(400)
+    st = o.get_state()
+    p1 = np.array([(m * st["vx"]).sum(), (m * st["vy"]).sum()])
+    assert o.counters()["inter"] > 0
+    scale = (m * np.hypot(vx, vy)).sum()
+    assert np.abs(p1 - p0).max() < 1e-12 * scale
+
+
+# ----------------------------------------------------------------------------
+# compaction observables: wall reactions
+# ----------------------------------------------------------------------------
+def _one_node(px, py, box, h=0.1e-3, v=(0.0, 0.0)):
+    return W.single_node_particles([(px, py)], [v], h * h, box, contact_radius=0.95 * h, h=h,
+                                   friction_mu=0.5, damping_ratio=0.8, dt=1e-8)
+
+
+def test_wall_reaction_single_wall():
+    """A node near the floor only: the floor carries minus the node's wall
+    force, the other walls nothing."""
+    h = 0.1e-3
+    prob = _one_node(2e-3, 0.3 * h, [0.0, 4e-3, 0.0, 4e-3], h, v=(0.2, -0.1))
+    o = Oracle(prob)
+    fx, fy = o.forces(8)
+    R = o.wall_reactions()[0]
+    F = np.array([fx[0], fy[0]]) * prob.vol[0]
+    assert np.abs(F).max() > 0
+    np.testing.assert_allclose(R[2], -F, rtol=1e-14)
+    assert np.abs(R[[0, 1, 3]]).max() == 0.0
+
+
+def test_wall_reactions_sum_to_the_wall_force():
+    """Over a bed pressed into the floor and a corner, the reactions of the
+    four walls add up to minus the total wall force on the nodes."""
+    h = 0.12e-3
+    parts, bx = W.mixed_bed(6, h, 9e-3, 9e-3, 33)
+    prob = W.assemble(parts, h, [W.Material(horizon=3 * h)], bx, contact_radius=0.95 * h,
+                      friction_mu=0.5, damping_ratio=0.8, dt=1e-7, top_wall_speed=[0.5])
+    # the whole bed shifted rigidly so its lowest and leftmost nodes sit
+    # inside the floor's and the left wall's contact zones
+    xlo, ylo = bx[0], bx[2]
+    prob.u0x = np.full(prob.n_nodes, -(prob.x.min() - xlo) + 0.3 * h)
+    prob.u0y = np.full(prob.n_nodes, -(prob.y.min() - ylo) + 0.3 * h)
+    W.perturb(prob, 34, dv=0.3)
+    o = Oracle(prob)
+    o.step(20)
+    fx, fy = o.forces(8)
+    total = -np.array([(fx * prob.vol).sum(), (fy * prob.vol).sum()])
+    R = o.wall_reactions()[0]
+    assert np.abs(total).max() > 0
+    np.testing.assert_allclose(R.sum(0), total, rtol=1e-12, atol=1e-15 * np.abs(R).max())
+
+
+def test_wall_reaction_corner_symmetry():
+    """A node on the diagonal of the lower-left corner moving along it: by
+    the mirror symmetry about the diagonal, the left wall's reaction (x) and
+    the floor's (y) are equal, and their transverse parts too."""
+    h = 0.1e-3
+    d = 0.4 * h
+    prob = _one_node(d, d, [0.0, 4e-3, 0.0, 4e-3], h, v=(-0.1, -0.1))
+    o = Oracle(prob)
+    R = o.wall_reactions()[0]
+    assert R[0, 0] != 0.0
+    assert abs(R[0, 0] - R[2, 1]) <= 1e-14 * abs(R[0, 0])
+    assert abs(R[0, 1] - R[2, 0]) <= 1e-14 * abs(R[0, 0])
