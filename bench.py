@@ -308,6 +308,37 @@ def closure(pd, W, torch, steps, train_iters):
     return res
 
 
+def fragmentation(pd, W, torch, micro_s):
+    """The notched square of side 1 mm struck from above and below by two
+    1 x 0.5 mm rectangles at 20 m/s (4000 nodes, M1 material, h = 25 um,
+    horizon 3h, dt = 2 ns), for the two toughness values of the paper: the
+    child particles of the square (components of its intact-bond graph
+    holding at least 1% of its nodes), all components, broken bonds and the
+    step rate, after micro_s microseconds."""
+    import numpy as np
+    res = {"workload": "notched_impact (side 1 mm, 20 m/s, h = 25 um)", "t_us": micro_s}
+    for Gc in (135.0, 13.5):
+        prob = W.notched_impact(Gc=Gc, n_side=40, dt=2e-9)
+        g = pd.PD(prob)
+        steps = int(round(micro_s * 1e-6 / prob.dt))
+        n_a = int(prob.particle_offset[1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        sps = steps / (time.perf_counter() - t0)
+        lab, cnt, nc = g.fragments(min_nodes=max(1, n_a // 100))
+        sizes = np.bincount(lab[:n_a], minlength=n_a)
+        big = sorted((int(v) for v in sizes[sizes > 0]), reverse=True)
+        res[f"Gc_{Gc:g}"] = {"children_of_square": int(cnt[0]),
+                             "children_of_rectangles": [int(cnt[1]), int(cnt[2])],
+                             "components_all": int(nc), "largest_pieces_of_square": big[:4],
+                             "broken_directed": int(g.damage()[1]), "steps": steps,
+                             "steps_per_s": sps}
+        del g
+    return res
+
+
 def copy_calibration(torch, mib=256, reps=10):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters of a profiler run: the counters of this run divided by
@@ -335,7 +366,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)
-    ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure"),
+    ap.add_argument("--impact-us", type=float, default=40.0)
+    ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure",
+                                           "fragmentation"),
                     default="settling",
                     help="settling: the headline line (plus the variants unless "
                          "--no-variants); compaction / batched: only that variant")
@@ -368,6 +401,9 @@ def main():
     if args.workload == "closure":
         print(json.dumps({"closure": closure(pd, W, torch, args.closure_steps, args.train_iters)}),
               flush=True)
+        return
+    if args.workload == "fragmentation":
+        print(json.dumps({"fragmentation": fragmentation(pd, W, torch, args.impact_us)}), flush=True)
         return
     prob = W.settling()
     g = pd.PD(prob)
@@ -434,6 +470,7 @@ def main():
         out["precision_split"] = precision_split(pd, W, torch, args.split_steps)
         out["batched"] = batched(pd, W, torch, args.batched_steps)
         out["closure"] = closure(pd, W, torch, args.closure_steps, args.train_iters)
+        out["fragmentation"] = fragmentation(pd, W, torch, args.impact_us)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.settling(), args.cpu_seconds, n_pairs)
     print(json.dumps(out), flush=True)

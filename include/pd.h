@@ -229,6 +229,23 @@ pd_status pd_observables(pd_ctx *c, double *out);
  * (Sec. 3.1; 0 for a particle without bonds); host or device buffer of
  * n_particles doubles */
 pd_status pd_particle_damage(pd_ctx *c, double *out, int32_t on_device);
+/* Fragments (the child particles of Sec. 7.3): the connected components of
+ * the graph of nodes joined by their intact bonds.  Bonds never join two
+ * particles, so each component lies in one particle; a node that lost
+ * every bond is a component of its own.  A bond joins its two nodes while
+ * either of its directed copies is intact (the step breaks both together;
+ * only pd_set_state can load copies that differ).  Reads the current bond
+ * state only.
+ *   label         N int32 (nullable): label[i] = smallest node index of
+ *                 node i's component
+ *   count         n_particles int32 (nullable): count[p] = components of
+ *                 particle p with at least min_nodes nodes (min_nodes >= 1)
+ *   n_components  (nullable) the number of all components
+ * on_device = 1: label and count are device buffers on the library's
+ * device, 0: host buffers.  Synchronous; the work is a few label rounds
+ * (each a pass over the bond slots), bounded by N + 1. */
+pd_status pd_fragments(pd_ctx *c, int32_t min_nodes, int32_t *label, int32_t *count,
+                       int64_t *n_components, int32_t on_device);
 
 /* ---------------------------------------------------------------------------
  * Learned modal closure (an extension: the paper has no reduced-order model).

@@ -6,3 +6,4 @@ seeded inputs from paper_2108_07212_amd.workloads.
 """
 from .oracle import Oracle, build_oracle, oracle_library_path  # noqa: F401
 from .oracle import T_PD, T_SELF, T_NBR, T_WALL, T_BODY, T_ALL  # noqa: F401
+from .fragments import components, child_counts  # noqa: F401

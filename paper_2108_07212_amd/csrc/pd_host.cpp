@@ -1469,6 +1469,38 @@ pd_status pd_particle_damage(pd_ctx *ctx, double *out, int32_t on_device) {
     return PD_OK;
 }
 
+pd_status pd_fragments(pd_ctx *ctx, int32_t min_nodes, int32_t *label, int32_t *count,
+                       int64_t *n_components, int32_t on_device) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (min_nodes < 1) return fail(c, PD_E_INVALID, "pd_fragments: min_nodes must be >= 1");
+    const size_t N = (size_t)c.N, P = (size_t)c.P;
+    if (!c.d_cc) TRY(dalloc(c, &c.d_cc, 2 * N + P + 4));
+    int *L = c.d_cc, *size = c.d_cc + N, *cnt = c.d_cc + 2 * N, *flags = c.d_cc + 2 * N + P;
+    if (on_device) TRY(after_caller(c));
+    HIPCHK(launch_cc_init(L, c.N, c.stream));
+    // each round takes every label to the smallest one within one more hop,
+    // so at most N + 1 rounds reach the fixed point
+    int changed = 1;
+    for (int64_t round = 0; changed; ++round) {
+        if (round > (int64_t)N + 1) return fail(c, PD_E_DEVICE, "pd_fragments: labels did not settle");
+        HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), c.stream));
+        HIPCHK(launch_cc_round(c.a, L, flags, c.stream));
+        HIPCHK(hipMemcpyAsync(&changed, flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+    }
+    HIPCHK(hipMemsetAsync(size, 0, (N + P + 4) * sizeof(int), c.stream));
+    HIPCHK(launch_cc_count(c.a, L, size, min_nodes, cnt, flags + 1, c.stream));
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (label && N) HIPCHK(hipMemcpyAsync(label, L, N * sizeof(int), k, c.stream));
+    if (count && P) HIPCHK(hipMemcpyAsync(count, cnt, P * sizeof(int), k, c.stream));
+    int ncomp = 0;
+    HIPCHK(hipMemcpyAsync(&ncomp, flags + 1, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (n_components) *n_components = ncomp;
+    return PD_OK;
+}
+
 int64_t pd_n_bonds(const pd_ctx *ctx) { return ctx ? ctx->c.nnz : -1; }
 
 static pd_status download_col(Ctx &c, std::vector<uint32_t> &col) {

@@ -262,6 +262,7 @@ struct Ctx {
     std::vector<double> h_box, h_vtop, h_agg_vol;  // per aggregate: box, top-wall speed, sum of V
     int *d_agg_pstart = nullptr, *d_agg_parts = nullptr;
     double *d_split = nullptr, *d_obs = nullptr, *d_pdamage = nullptr;
+    int *d_cc = nullptr;  // fragments: labels [N], sizes [N], counts [P], flags [4]
     std::vector<int> h_poff, h_pmat;
     std::vector<MatConst> h_mc;
     const int *d_poff = nullptr;
@@ -306,6 +307,10 @@ hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s);
 hipError_t launch_particle_damage(const DevArgs &a, const int *poff, double *out, hipStream_t s);
+hipError_t launch_cc_init(int *L, int n, hipStream_t s);
+hipError_t launch_cc_round(const DevArgs &a, int *L, int *changed, hipStream_t s);
+hipError_t launch_cc_count(const DevArgs &a, const int *L, int *size, int min_nodes, int *count,
+                           int *stats, hipStream_t s);
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s);
 hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);

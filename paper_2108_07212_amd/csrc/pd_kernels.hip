@@ -1165,6 +1165,111 @@ __global__ __launch_bounds__(256) void k_particle_damage(DevArgs a, const int *p
     }
 }
 
+// ---------------------------------------------------------------------------
+// fragments: connected components of the intact-bond graph (the child
+// particles of Sec. 7.3).  Labels only ever decrease and always name a node
+// of the same component, so the fixed point is the smallest node index of
+// each component whatever the order of the updates.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_relaxed(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_cc_init(int *L, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) L[i] = i;
+}
+
+// every node takes the smallest label among itself and its intact partners,
+// hooks its current label onto it, and pushes it to partners that hold a
+// larger one (so a bond joins its nodes if either directed copy is intact)
+__global__ __launch_bounds__(256) void k_cc_hook(DevArgs a, int *L, int *changed) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.N) return;
+    const int li = ld_relaxed(L + i);
+    int m = li, top = li;
+    const uint32_t sl = (uint32_t)i / kSlice;
+    const uint32_t base = a.slice_ptr[sl] + (uint32_t)i % kSlice;
+    const int W = (int)((a.slice_ptr[sl + 1] - a.slice_ptr[sl]) / kSlice);
+    for (int k = 0; k < W; ++k) {
+        const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+        const int j = (int)(e & kIndexMask);
+        if (j == i || (e & kBroken)) continue;
+        const int lj = ld_relaxed(L + j);
+        m = min(m, lj);
+        top = max(top, lj);
+    }
+    if (m < li) {
+        atomicMin(L + i, m);
+        atomicMin(L + li, m);
+    }
+    const bool push = top > m;
+    if (push) {
+        for (int k = 0; k < W; ++k) {
+            const uint32_t e = a.col[base + (uint32_t)k * kSlice];
+            const int j = (int)(e & kIndexMask);
+            if (j == i || (e & kBroken)) continue;
+            const int lj = ld_relaxed(L + j);
+            if (lj > m) {
+                atomicMin(L + j, m);
+                atomicMin(L + lj, m);
+            }
+        }
+    }
+    if (m < li || push) atomicOr(changed, 1);
+}
+
+// pointer jumping: follow labels down to a node that names itself
+__global__ __launch_bounds__(256) void k_cc_jump(int *L, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int v = ld_relaxed(L + i);
+    for (;;) {  // strictly decreasing, so at most i rounds
+        const int w = ld_relaxed(L + v);
+        if (w >= v) break;
+        v = w;
+    }
+    atomicMin(L + i, v);
+}
+
+// size[label] += 1 for every node
+__global__ __launch_bounds__(256) void k_cc_size(const int *L, int *size, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) atomicAdd(size + L[i], 1);
+}
+
+// per particle, the components with at least min_nodes nodes; stats[0] counts all
+__global__ __launch_bounds__(256) void k_cc_count(DevArgs a, const int *L, const int *size,
+                                                  int min_nodes, int *count, int *stats) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.N || L[i] != i) return;
+    atomicAdd(stats, 1);
+    if (size[i] >= min_nodes) atomicAdd(count + a.part[i], 1);
+}
+
+hipError_t launch_cc_init(int *L, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cc_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc_round(const DevArgs &a, int *L, int *changed, hipStream_t s) {
+    if (a.N <= 0) return hipSuccess;
+    const dim3 g((unsigned)((a.N + 255) / 256));
+    hipLaunchKernelGGL(k_cc_hook, g, dim3(256), 0, s, a, L, changed);
+    hipLaunchKernelGGL(k_cc_jump, g, dim3(256), 0, s, L, a.N);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc_count(const DevArgs &a, const int *L, int *size, int min_nodes, int *count,
+                           int *stats, hipStream_t s) {
+    if (a.N <= 0) return hipSuccess;
+    const dim3 g((unsigned)((a.N + 255) / 256));
+    hipLaunchKernelGGL(k_cc_size, g, dim3(256), 0, s, L, size, a.N);
+    hipLaunchKernelGGL(k_cc_count, g, dim3(256), 0, s, a, L, size, min_nodes, count, stats);
+    return hipGetLastError();
+}
+
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s) {
     DevArgs b = a;

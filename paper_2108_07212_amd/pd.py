@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     L.pd_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
     L.pd_observables.argtypes = [vp, _dp]
     L.pd_particle_damage.argtypes = [vp, vp, C.c_int32]
+    L.pd_fragments.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int64), C.c_int32]
     _fp = C.POINTER(C.c_float)
     L.pd_closure_setup.argtypes = [vp, _ip, C.c_double, _dp, C.c_int32, C.c_double]
     L.pd_closure_modes.argtypes = [vp, C.c_int32, _ip, _ip, _dp, _dp, _dp]
@@ -311,6 +313,17 @@ class PD:
         out = np.zeros(self.prob.n_particles)
         self._chk(self.lib.pd_particle_damage(self.h, C.c_void_p(out.ctypes.data), 0))
         return out
+
+    def fragments(self, min_nodes: int = 1):
+        """(label [N] int32: smallest node index of each node's component of
+        the intact-bond graph, count [P] int32: components per particle with
+        at least min_nodes nodes, number of all components)"""
+        lab = np.zeros(self.N, dtype=np.int32)
+        cnt = np.zeros(self.prob.n_particles, dtype=np.int32)
+        nc = C.c_int64()
+        self._chk(self.lib.pd_fragments(self.h, int(min_nodes), _p(lab, C.c_int32),
+                                        _p(cnt, C.c_int32), C.byref(nc), 0))
+        return lab, cnt, nc.value
 
     # -- learned modal closure ---------------------------------------------
     def closure_setup(self, shape_of_particle, gate_frac: float = 0.5, tau_c=None,

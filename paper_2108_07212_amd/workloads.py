@@ -553,3 +553,71 @@ def jitter_nodes(prob: Problem, seed: int, vol_frac: float = 0.4, pos_frac: floa
     prob.x, prob.y = x, y
     prob.meta = dict(prob.meta, jitter=(seed, vol_frac, pos_frac))
     return prob
+
+
+# ----------------------------------------------------------------------------
+# notched square hit by two rectangles (Sec. 7.3)
+# ----------------------------------------------------------------------------
+def cell_nodes(half_w: float, half_h: float, h: float) -> np.ndarray:
+    """Cell centres ((i + 1/2) h, (j + 1/2) h) of the uniform grid that tiles
+    the rectangle [-half_w, half_w] x [-half_h, half_h], body frame, row-major
+    (j outer).  No node lies on the rectangle's edges or on its mid-lines."""
+    nx, ny = int(round(half_w / h)), int(round(half_h / h))
+    if nx < 1 or ny < 1 or abs(nx * h - half_w) > 1e-9 * h or abs(ny * h - half_h) > 1e-9 * h:
+        raise ValueError("half sizes must be whole multiples of h")
+    xs = (np.arange(-nx, nx) + 0.5) * h
+    ys = (np.arange(-ny, ny) + 0.5) * h
+    gy, gx = np.meshgrid(ys, xs, indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel()], axis=1)
+
+
+def notched_square_loop(R: float, notch_half_width: float) -> np.ndarray:
+    """Counter-clockwise boundary of the square [-R, R]^2 with a slot of
+    half-width notch_half_width along y = 0 from the left edge to the
+    centre."""
+    w = notch_half_width
+    return np.array([(-R, -R), (R, -R), (R, R), (-R, R), (-R, w), (0.0, w), (0.0, -w), (-R, -w)],
+                    dtype=np.float64)
+
+
+def notched_impact(Gc: float = 135.0, side: float = 1e-3, n_side: int = 50, speed: float = 20.0,
+                   horizon_factor: float = 3.0, dt: float = 2e-9, gap: float | None = None,
+                   material: str = "M1", precision: int = PREC_FP64) -> Problem:
+    """Sec. 7.3: a square particle A of side `side` with a notch from the
+    middle of its left edge to its centre, struck at the same time from above
+    and below by rectangles B and C of side x side/2 moving at +-`speed`
+    toward it; friction and damping off, no gravity.
+
+    The paper gives neither the mesh size nor the horizon.  Here the nodes
+    are the cell centres of a grid of spacing h = side / n_side (so no node
+    lies on the notch line), the horizon is horizon_factor * h, and the notch
+    is a slot of width h/5 (narrower than the node spacing: it removes
+    exactly the bonds that cross the notch line left of the centre).  The
+    material is M1 of Tab. tab:material (E = 191 GPa, k = 159.2 GPa,
+    rho = 8000 kg/m^3), the one the paper assigns to its two- and
+    three-particle tests, or M2 (E = 1.23 GPa, k = 2 GPa, rho = 1200 kg/m^3),
+    with the given toughness Gc.  B and C start with a
+    surface gap of `gap` (default h) to A.  Particle order: A, B, C.
+    """
+    h = side / n_side
+    R = 0.5 * side
+    if n_side % 2:
+        raise ValueError("n_side must be even (the notch runs between node rows)")
+    g = h if gap is None else gap
+    rho, k, E = {"M1": (8000.0, 159.2e9, 191e9), "M2": (1200.0, 2e9, 1.23e9)}[material]
+    mat = Material(rho=rho, bulk_k=k, young_E=E, Gc=Gc, horizon=horizon_factor * h)
+    nodes_a = cell_nodes(R, R, h)
+    nodes_r = cell_nodes(R, 0.5 * R, h)
+    rect = [np.array([(-R, -0.5 * R), (R, -0.5 * R), (R, 0.5 * R), (-R, 0.5 * R)])]
+    L = 6.0 * R
+    yb = R + g + 0.5 * R
+    parts = [Particle("notched", R, (0.0, 0.0), nodes_body=nodes_a,
+                      loops_body=[notched_square_loop(R, 0.1 * h)]),
+             Particle("rect", R, (0.0, yb), velocity=(0.0, -speed), nodes_body=nodes_r,
+                      loops_body=rect),
+             Particle("rect", R, (0.0, -yb), velocity=(0.0, speed), nodes_body=nodes_r,
+                      loops_body=rect)]
+    return assemble(parts, h, [mat], [-L, L, -L, L], contact_radius=0.95 * h, friction_mu=0.0,
+                    damping_ratio=0.0, dt=dt, gravity=(0.0, 0.0), precision=precision,
+                    meta=dict(name=f"notched_impact_{material}_Gc{Gc:g}", Gc=Gc, side=side,
+                              n_side=n_side, speed=speed, material=material))
