@@ -339,6 +339,52 @@ def fragmentation(pd, W, torch, micro_s):
     return res
 
 
+def settle_shapes(pd, W, torch, micro_s, every_us):
+    """Settling of beds of one shape each from jammed security disks (perturbed
+    disks, squares, plus shapes, rings; 25 x 50 mm container, the parameters
+    of Sec. 7.3: eps = 0.5 mm, h = eps/8, R_c = eps/5, mu = r_d = 0.8,
+    5000 m/s^2, dt = 70 ns, FP64): packing of the security disks, the bed's
+    volume fraction at the start and after micro_s microseconds (particle area
+    over width x bed height, and the same with rings counted as full disks),
+    its kinetic energy series, broken bonds and the step rate."""
+    import numpy as np
+    res = {"workload": "jammed_settling (25 x 50 mm, eps = 0.5 mm, h = eps/8)", "t_us": micro_s}
+    for shape in W.SETTLE_SHAPES:
+        prob = W.jammed_settling(shape)
+        g = pd.PD(prob)
+        width = prob.box[0, 1] - prob.box[0, 0]
+        sizes = g.sizes()
+
+        def frac(uy):
+            H = float(np.max(prob.y + uy))
+            return (float(prob.vol.sum()) / (width * H), prob.meta["filled_area"] / (width * H), H)
+
+        phi0 = frac(np.zeros(prob.n_nodes))
+        g.step(20)
+        tun = g.autotune(10)
+        every = int(round(every_us * 1e-6 / prob.dt))
+        n_chunks = max(1, int(round(micro_s / every_us)))
+        ke = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_chunks):
+            g.step(every)
+            s = g.get_state()
+            ke.append(float(0.5 * 1200.0 * np.sum(prob.vol * (s["vx"] ** 2 + s["vy"] ** 2))))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phi1 = frac(s["uy"])
+        res[shape] = {"particles": prob.n_particles, "nodes": sizes["nodes"],
+                      "directed_bonds": sizes["bonds"], "packing": prob.meta["packing"],
+                      "phi_start": phi0[0], "phi_end": phi1[0],
+                      "phi_filled_start": phi0[1], "phi_filled_end": phi1[1],
+                      "bed_height_mm_end": 1e3 * phi1[2], "kinetic_energy_series": ke,
+                      "broken_directed": int(g.damage()[1]), "tuning": tun,
+                      "steps": every * n_chunks, "steps_per_s": every * n_chunks / wall}
+        del g
+    return res
+
+
 def copy_calibration(torch, mib=256, reps=10):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters of a profiler run: the counters of this run divided by
@@ -367,8 +413,10 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--impact-us", type=float, default=40.0)
+    ap.add_argument("--settle-us", type=float, default=14000.0)
+    ap.add_argument("--settle-every-us", type=float, default=1400.0)
     ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure",
-                                           "fragmentation"),
+                                           "fragmentation", "settle_shapes"),
                     default="settling",
                     help="settling: the headline line (plus the variants unless "
                          "--no-variants); compaction / batched: only that variant")
@@ -401,6 +449,10 @@ def main():
     if args.workload == "closure":
         print(json.dumps({"closure": closure(pd, W, torch, args.closure_steps, args.train_iters)}),
               flush=True)
+        return
+    if args.workload == "settle_shapes":
+        print(json.dumps({"settle_shapes": settle_shapes(pd, W, torch, args.settle_us,
+                                                         args.settle_every_us)}), flush=True)
         return
     if args.workload == "fragmentation":
         print(json.dumps({"fragmentation": fragmentation(pd, W, torch, args.impact_us)}), flush=True)

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SHAPES = ("disk", "plus", "ring", "lshape")
+SHAPES = ("disk", "plus", "ring", "lshape", "square")
 
 # enum values shared with the C records (see include/pd.h)
 MICRO_CONST, MICRO_CONIC = 0, 1
@@ -55,6 +55,9 @@ def shape_loops(shape: str, R: float, n_circle: int = 64) -> list:
         return [np.array(v, dtype=np.float64)]
     if shape == "ring":
         return [_circle(R, n_circle, True), _circle(0.5 * R, n_circle, False)]
+    if shape == "square":
+        a = R / math.sqrt(2.0)  # inscribed in the circle of radius R (Sec. 7.2)
+        return [np.array([(-a, -a), (a, -a), (a, a), (-a, a)], dtype=np.float64)]
     if shape == "lshape":
         h2 = 0.5 * R
         v = np.array([(0, 0), (R, 0), (R, h2), (h2, h2), (h2, R), (0, R)], dtype=np.float64)
@@ -78,7 +81,28 @@ def shape_area(shape: str, R: float) -> float:
         return math.pi * R * R * 0.75
     if shape == "lshape":
         return 0.75 * R * R
+    if shape == "square":
+        return 2.0 * R * R
     raise ValueError(shape)
+
+
+def perturbed_disk_loop(R: float, rng: np.random.Generator, n: int = 20,
+                        phi: float = 0.6) -> np.ndarray:
+    """Sec. 7.2: the polygon with vertices r_k (cos t_k, sin t_k), t_k = 2 pi k / n,
+    r_k = R (1 - X_k), X_k ~ U[0, 1 - phi] independent (counter-clockwise,
+    about the centre of the disk of radius R that bounds it)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    r = R * (1.0 - rng.uniform(0.0, 1.0 - phi, size=n))
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+def polygon_area(loops: list) -> float:
+    """Signed-area sum of the loops (outer counter-clockwise, holes clockwise)."""
+    a = 0.0
+    for lp in loops:
+        x, y = lp[:, 0], lp[:, 1]
+        a += 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+    return a
 
 
 def _inside_even_odd(px: np.ndarray, py: np.ndarray, loops: list) -> np.ndarray:
@@ -122,10 +146,21 @@ def body_nodes(shape: str, R: float, h: float, margin: float = 1e-3) -> np.ndarr
     py = (jj * h).ravel().astype(np.float64)
     if shape == "disk":
         keep = (iig.ravel() ** 2 + jj.ravel() ** 2) * (h * h) <= R * R * (1.0 + 1e-9)
-    else:
-        loops = shape_loops(shape, R)
-        keep = _inside_even_odd(px, py, loops)
-        keep &= _dist_to_loops(px, py, loops) > margin * h
+        return np.stack([px[keep], py[keep]], axis=1)
+    return loop_nodes(shape_loops(shape, R), R, h, margin)
+
+
+def loop_nodes(loops: list, R: float, h: float, margin: float = 1e-3) -> np.ndarray:
+    """Lattice points (i h, j h) strictly inside the loops (even-odd rule) and
+    farther than margin*h from them, row-major; the loops lie within the
+    circle of radius R about the origin."""
+    n = int(math.ceil(R / h)) + 1
+    ii = np.arange(-n, n + 1)
+    jj, iig = np.meshgrid(ii, ii, indexing="ij")
+    px = (iig * h).ravel().astype(np.float64)
+    py = (jj * h).ravel().astype(np.float64)
+    keep = _inside_even_odd(px, py, loops)
+    keep &= _dist_to_loops(px, py, loops) > margin * h
     return np.stack([px[keep], py[keep]], axis=1)
 
 
@@ -621,3 +656,202 @@ def notched_impact(Gc: float = 135.0, side: float = 1e-3, n_side: int = 50, spee
                     damping_ratio=0.0, dt=dt, gravity=(0.0, 0.0), precision=precision,
                     meta=dict(name=f"notched_impact_{material}_Gc{Gc:g}", Gc=Gc, side=side,
                               n_side=n_side, speed=speed, material=material))
+
+
+# ----------------------------------------------------------------------------
+# jammed security disks (Sec. 7.1)
+# ----------------------------------------------------------------------------
+def triangle_incircles(pts: np.ndarray, tri: np.ndarray):
+    """Incircle of every triangle (Sec. 7.1, step 2): centre
+    (v1 l1 + v2 l2 + v3 l3) / (l1 + l2 + l3) with l_k the length of the side
+    opposite v_k, radius 2 |T| / (l1 + l2 + l3)."""
+    v1, v2, v3 = pts[tri[:, 0]], pts[tri[:, 1]], pts[tri[:, 2]]
+    l1 = np.linalg.norm(v2 - v3, axis=1)
+    l2 = np.linalg.norm(v1 - v3, axis=1)
+    l3 = np.linalg.norm(v1 - v2, axis=1)
+    per = l1 + l2 + l3
+    c = (v1 * l1[:, None] + v2 * l2[:, None] + v3 * l3[:, None]) / per[:, None]
+    area = 0.5 * np.abs((v2[:, 0] - v1[:, 0]) * (v3[:, 1] - v1[:, 1])
+                        - (v3[:, 0] - v1[:, 0]) * (v2[:, 1] - v1[:, 1]))
+    return c, 2.0 * area / per
+
+
+def _box_mesh(width: float, height: float, size: float, rng: np.random.Generator,
+              jitter: float = 0.15):
+    """Triangular mesh of the box [0, width] x [0, height]: nodes every ~size
+    along the edges (corners included) and a jittered triangular lattice of
+    spacing size inside, kept half a spacing from the edges; Delaunay
+    triangles (the box is convex, so they tile it)."""
+    from scipy.spatial import Delaunay
+    nx = max(1, int(round(width / size)))
+    ny = max(1, int(round(height / size)))
+    bx = np.linspace(0.0, width, nx + 1)
+    by = np.linspace(0.0, height, ny + 1)[1:-1]
+    bnd = np.concatenate([np.stack([bx, np.zeros_like(bx)], 1), np.stack([bx, np.full_like(bx, height)], 1),
+                          np.stack([np.zeros_like(by), by], 1), np.stack([np.full_like(by, width), by], 1)])
+    dy = size * math.sqrt(3.0) / 2.0
+    rows = []
+    for r in range(int(height / dy) + 2):
+        y = r * dy
+        xs = np.arange(0.0, width + size, size) + (0.5 * size if r % 2 else 0.0)
+        rows.append(np.stack([xs, np.full_like(xs, y)], 1))
+    inner = np.concatenate(rows)
+    inner = inner + rng.uniform(-jitter * size, jitter * size, inner.shape)
+    m = 0.5 * size
+    keep = ((inner[:, 0] > m) & (inner[:, 0] < width - m) & (inner[:, 1] > m)
+            & (inner[:, 1] < height - m))
+    pts = np.concatenate([bnd, inner[keep]])
+    tri = Delaunay(pts).simplices
+    v1, v2, v3 = pts[tri[:, 0]], pts[tri[:, 1]], pts[tri[:, 2]]
+    area = 0.5 * np.abs((v2[:, 0] - v1[:, 0]) * (v3[:, 1] - v1[:, 1])
+                        - (v3[:, 0] - v1[:, 0]) * (v2[:, 1] - v1[:, 1]))
+    return pts, tri[area > 1e-9 * size * size]
+
+
+def jammed_disks(width: float, height: float, mesh_size: float, seed: int, shrink: float = 0.0,
+                 x0: float = 0.0, y0: float = 0.0):
+    """Security disks by the construction of Sec. 7.1: a triangular mesh of the
+    box, the incircle of every triangle, and for every mesh node v the largest
+    circle centred in the star of v (the triangles at v) that meets no
+    incircle of the triangles at v or next to them and stays in the box: its
+    centre c maximises min(min_T |c - c_T| - r_T, distance to the box edges),
+    found by Nelder-Mead from v; nodal circles that still overlap one another
+    give up the overlap in equal parts.  Then every radius shrinks by
+    `shrink` (R_c / 2 in the paper); disks left with no positive radius are
+    dropped.  Returns (centres [n, 2], radii [n], stats, origin [n]) with
+    origin -1 for an incircle and the mesh node for a nodal circle."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(seed)
+    pts, tri = _box_mesh(width, height, mesh_size, rng)
+    cT, rT = triangle_incircles(pts, tri)
+    star = [[] for _ in range(len(pts))]
+    for t, (a, b, c) in enumerate(tri):
+        star[a].append(t)
+        star[b].append(t)
+        star[c].append(t)
+    box_area = width * height
+    phi_incircles = float(np.sum(np.pi * rT ** 2) / box_area)
+    cn = np.zeros_like(pts)
+    rn = np.zeros(len(pts))
+    for v in range(len(pts)):
+        ts = np.array(star[v], dtype=np.int64)
+        ring = np.unique(np.concatenate([star[w] for w in np.unique(tri[ts])]))
+        cc, rr = cT[ring], rT[ring]
+        A, B, Cc = pts[tri[ts, 0]], pts[tri[ts, 1]], pts[tri[ts, 2]]
+
+        def in_star(c):
+            d1 = (B[:, 0] - A[:, 0]) * (c[1] - A[:, 1]) - (B[:, 1] - A[:, 1]) * (c[0] - A[:, 0])
+            d2 = (Cc[:, 0] - B[:, 0]) * (c[1] - B[:, 1]) - (Cc[:, 1] - B[:, 1]) * (c[0] - B[:, 0])
+            d3 = (A[:, 0] - Cc[:, 0]) * (c[1] - Cc[:, 1]) - (A[:, 1] - Cc[:, 1]) * (c[0] - Cc[:, 0])
+            neg = (d1 < 0) | (d2 < 0) | (d3 < 0)
+            pos = (d1 > 0) | (d2 > 0) | (d3 > 0)
+            return bool(np.any(~(neg & pos)))
+
+        def gap(c):
+            if not in_star(c):
+                return -1.0
+            d = np.sqrt((cc[:, 0] - c[0]) ** 2 + (cc[:, 1] - c[1]) ** 2) - rr
+            return min(d.min(), c[0], width - c[0], c[1], height - c[1])
+
+        # start a hair inside the star (boundary nodes sit on the box edge)
+        start = pts[v] + 1e-3 * (cT[ts].mean(axis=0) - pts[v])
+        r0 = gap(start)
+        res = minimize(lambda c: -gap(c), start, method="Nelder-Mead",
+                       options=dict(xatol=1e-9 * mesh_size, fatol=1e-12 * mesh_size, maxiter=4000))
+        cn[v], rn[v] = (res.x, -res.fun) if -res.fun > r0 else (start, r0)
+    # nodal circles of neighbouring nodes may still meet: split each overlap
+    from scipy.spatial import cKDTree
+    tree = cKDTree(cn)
+    overlaps = 0
+    for a, b in sorted(tree.query_pairs(2.0 * max(rn.max(), 1e-300))):
+        d = float(np.hypot(*(cn[a] - cn[b])))
+        o = rn[a] + rn[b] - d
+        if o > 0:
+            overlaps += 1
+            rn[a] -= 0.5 * o
+            rn[b] -= 0.5 * o
+    centres = np.concatenate([cT, cn])
+    radii = np.concatenate([rT, rn])
+    # what the optimiser's tolerance leaves of overlaps with incircles farther
+    # away: the nodal circle gives it up
+    nT = len(rT)
+    tree = cKDTree(centres)
+    for a, b in sorted(tree.query_pairs(2.0 * float(radii.max()))):
+        o = radii[a] + radii[b] - float(np.hypot(*(centres[a] - centres[b])))
+        if o > 0:
+            k = b if b >= nT else a
+            if k < nT:
+                raise RuntimeError("incircles of a triangulation overlap")
+            radii[k] -= o
+    phi_jammed = float(np.sum(np.pi * radii[radii > 0] ** 2) / box_area)
+    radii = radii - shrink
+    keep = radii > 0
+    stats = dict(mesh_nodes=int(len(pts)), triangles=int(len(tri)),
+                 packing_incircles=phi_incircles, packing_jammed=phi_jammed,
+                 packing_final=float(np.sum(np.pi * radii[keep] ** 2) / box_area),
+                 nodal_overlaps_split=overlaps, dropped=int((~keep).sum()))
+    centres = centres[keep] + np.array([x0, y0])
+    origin = np.concatenate([np.full(len(rT), -1), np.arange(len(rn))])[keep]
+    return centres, radii[keep], stats, origin
+
+
+SETTLE_SHAPES = ("pdisk", "square", "plus", "ring")
+
+
+def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
+                    mesh_size: float = 3.2e-3, seed: int = 6, eps: float = 0.5e-3,
+                    r_min: float = 0.4e-3, gravity: float = -5000.0, dt: float = 70e-9,
+                    Gc: float = 135.0, precision: int = PREC_FP64) -> Problem:
+    """Settling of one particle shape from jammed security disks (Sec. 7.3):
+    the disks of jammed_disks over the container inset by R_c / 2 (mesh size
+    mesh_size), shrunk by R_c / 2 and keeping those of radius >= r_min; in each a
+    particle whose farthest point lies on the disk's circle, randomly
+    oriented.  Shapes: "pdisk" (perturbed disk, 20 vertices, phi = 0.6, a
+    polygon of its own per particle), "square" (side sqrt(2) R), "plus" (the
+    plus shape of the other workloads, scaled into the disk), "ring" (inner
+    radius R/2), "disk".  Parameters of Sec. 7.3: eps = 0.5 mm, h = eps/8,
+    R_c = eps/5, mu = 0.8, r_d = 0.8, g = 5000 m/s^2, dt = 70 ns, material M2
+    of Tab. tab:material (E = 1.23 GPa, k = 2 GPa, rho = 1200 kg/m^3); the
+    paper gives no G_c for this test (the default 135 J/m^2 leaves the
+    particles intact under their weight).
+
+    Draw order: the mesh jitter (default_rng(seed)), then default_rng(seed + 1)
+    for the orientations and, for perturbed disks, the vertex radii
+    particle by particle."""
+    h = eps / 8.0
+    Rc = eps / 5.0
+    # jammed in the container inset by R_c / 2, then shrunk by R_c / 2: every
+    # gap between particles and to the walls is at least R_c, so no contact or
+    # wall force acts at t = 0
+    centres, radii, st, _ = jammed_disks(width - Rc, height - Rc, mesh_size, seed,
+                                         shrink=0.5 * Rc, x0=0.5 * Rc, y0=0.5 * Rc)
+    keep = radii >= r_min
+    centres, radii = centres[keep], radii[keep]
+    rng = np.random.default_rng(seed + 1)
+    th = rng.uniform(0.0, 2.0 * np.pi, size=len(radii))
+    plus_reach = math.hypot(1.0, 0.25)  # farthest vertex of the plus shape, in units of R
+    parts = []
+    for k, (c, rs) in enumerate(zip(centres, radii)):
+        cen = (float(c[0]), float(c[1]))
+        if shape == "pdisk":
+            lp = perturbed_disk_loop(float(rs), rng)
+            parts.append(Particle("pdisk", float(rs), cen, float(th[k]), loops_body=[lp],
+                                  nodes_body=loop_nodes([lp], float(rs), h)))
+        elif shape == "plus":
+            parts.append(Particle("plus", float(rs) / plus_reach, cen, float(th[k])))
+        elif shape in ("square", "ring", "disk"):
+            parts.append(Particle(shape, float(rs), cen, float(th[k])))
+        else:
+            raise ValueError(f"unknown shape {shape!r}")
+    mat = Material(rho=1200.0, bulk_k=2e9, young_E=1.23e9, Gc=Gc, horizon=eps)
+    prob = assemble(parts, h, [mat], [0.0, width, 0.0, height], contact_radius=Rc,
+                    friction_mu=0.8, damping_ratio=0.8, dt=dt, gravity=(0.0, gravity),
+                    precision=precision,
+                    meta=dict(name=f"jammed_settling_{shape}", shape=shape, seed=seed,
+                              security_radii=radii, packing=st, dropped_small=int((~keep).sum())))
+    # area the particle occupies inside its outer boundary (holes filled):
+    # the paper's annulus fractions count the hole as particle volume
+    prob.meta["filled_area"] = float(sum(
+        abs(polygon_area([p.loops_body[0] if p.loops_body else shape_loops(p.shape, p.R)[0]]))
+        for p in parts))
+    return prob
