@@ -96,6 +96,23 @@ def perturbed_disk_loop(R: float, rng: np.random.Generator, n: int = 20,
     return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
 
 
+def plus_loop(R: float, c: float = 0.2) -> np.ndarray:
+    """Sec. 7.2 plus shape inscribed in the circle of radius R with inner
+    radius cR: the re-entrant corners lie at distance cR from the centre (arm
+    half-width w = cR / sqrt 2) and the arm tips' corners on the circle
+    (arm half-length sqrt(R^2 - w^2)); counter-clockwise."""
+    w = c * R / math.sqrt(2.0)
+    L = math.sqrt(R * R - w * w)
+    v = [(L, -w), (L, w), (w, w), (w, L), (-w, L), (-w, w), (-L, w), (-L, -w), (-w, -w),
+         (-w, -L), (w, -L), (w, -w)]
+    return np.array(v, dtype=np.float64)
+
+
+def ring_loops(R: float, tau: float = 0.6, n_circle: int = 64) -> list:
+    """Sec. 7.2 annulus: outer radius R, inner radius tau R (hole clockwise)."""
+    return [_circle(R, n_circle, True), _circle(tau * R, n_circle, False)]
+
+
 def polygon_area(loops: list) -> float:
     """Signed-area sum of the loops (outer counter-clockwise, holes clockwise)."""
     a = 0.0
@@ -806,10 +823,10 @@ def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
     the disks of jammed_disks over the container inset by R_c / 2 (mesh size
     mesh_size), shrunk by R_c / 2 and keeping those of radius >= r_min; in each a
     particle whose farthest point lies on the disk's circle, randomly
-    oriented.  Shapes: "pdisk" (perturbed disk, 20 vertices, phi = 0.6, a
-    polygon of its own per particle), "square" (side sqrt(2) R), "plus" (the
-    plus shape of the other workloads, scaled into the disk), "ring" (inner
-    radius R/2), "disk".  Parameters of Sec. 7.3: eps = 0.5 mm, h = eps/8,
+    oriented about the disk's centre.  Shapes with the parameters of Sec. 7.2:
+    "pdisk" (perturbed disk, 20 vertices, phi = 0.6, a polygon of its own per
+    particle), "square" (side sqrt(2) R), "plus" (inner radius 0.2 R),
+    "ring" (inner radius 0.6 R), and "disk".  Parameters of Sec. 7.3: eps = 0.5 mm, h = eps/8,
     R_c = eps/5, mu = 0.8, r_d = 0.8, g = 5000 m/s^2, dt = 70 ns, material M2
     of Tab. tab:material (E = 1.23 GPa, k = 2 GPa, rho = 1200 kg/m^3); the
     paper gives no G_c for this test (the default 135 J/m^2 leaves the
@@ -829,7 +846,6 @@ def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
     centres, radii = centres[keep], radii[keep]
     rng = np.random.default_rng(seed + 1)
     th = rng.uniform(0.0, 2.0 * np.pi, size=len(radii))
-    plus_reach = math.hypot(1.0, 0.25)  # farthest vertex of the plus shape, in units of R
     parts = []
     for k, (c, rs) in enumerate(zip(centres, radii)):
         cen = (float(c[0]), float(c[1]))
@@ -837,9 +853,11 @@ def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
             lp = perturbed_disk_loop(float(rs), rng)
             parts.append(Particle("pdisk", float(rs), cen, float(th[k]), loops_body=[lp],
                                   nodes_body=loop_nodes([lp], float(rs), h)))
-        elif shape == "plus":
-            parts.append(Particle("plus", float(rs) / plus_reach, cen, float(th[k])))
-        elif shape in ("square", "ring", "disk"):
+        elif shape in ("plus", "ring"):
+            lps = [plus_loop(float(rs))] if shape == "plus" else ring_loops(float(rs))
+            parts.append(Particle(shape, float(rs), cen, float(th[k]), loops_body=lps,
+                                  nodes_body=loop_nodes(lps, float(rs), h)))
+        elif shape in ("square", "disk"):
             parts.append(Particle(shape, float(rs), cen, float(th[k])))
         else:
             raise ValueError(f"unknown shape {shape!r}")

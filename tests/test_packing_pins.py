@@ -98,6 +98,23 @@ def test_square_shape():
     assert len(W.body_nodes("square", R, h)) == (2 * k + 1) ** 2
 
 
+def test_plus_and_ring_of_the_settling_study():
+    """Plus with inner radius cR: re-entrant corners at distance cR, tips on
+    the circle, area 8 L w - 4 w^2 (two crossed 2L x 2w bars); annulus area
+    of the polygons against pi R^2 (1 - tau^2) up to the 64-gon's deficit."""
+    R, c = 1.0, 0.2
+    lp = W.plus_loop(R, c)
+    rr = np.hypot(lp[:, 0], lp[:, 1])
+    np.testing.assert_allclose(np.sort(rr)[:4], c * R, rtol=1e-14)
+    np.testing.assert_allclose(np.sort(rr)[4:], R, rtol=1e-14)
+    w = c * R / math.sqrt(2)
+    L = math.sqrt(R * R - w * w)
+    np.testing.assert_allclose(W.polygon_area([lp]), 8 * L * w - 4 * w * w, rtol=1e-14)
+    n = 64
+    poly = 0.5 * n * math.sin(2 * math.pi / n)  # area of the unit n-gon
+    np.testing.assert_allclose(W.polygon_area(W.ring_loops(R, 0.6, n)), poly * (1 - 0.36), rtol=1e-13)
+
+
 def test_perturbed_disk_shape():
     """Vertex radii in [phi R, R]; mean area of the random 20-gon equals
     (n/2) sin(2 pi/n) R^2 E[1 - X]^2 with X ~ U[0, 1 - phi] (independent
