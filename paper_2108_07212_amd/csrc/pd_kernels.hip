@@ -571,11 +571,35 @@ __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v;
 // ---------------------------------------------------------------------------
 // the force kernel
 // ---------------------------------------------------------------------------
+// The value of lane l ^ X (X = 1 or 2) of the same quad: a DPP quad
+// permutation (register to register, no LDS round trip).  Every lane of a
+// quad is active wherever these are used (quads leave together).
+template <int X>
+__device__ __forceinline__ int quad_xor(int v) {
+    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
+}
+template <int X>
+__device__ __forceinline__ unsigned quad_xor(unsigned v) {
+    return (unsigned)quad_xor<X>((int)v);
+}
+template <int X>
+__device__ __forceinline__ float quad_xor(float v) {
+    return __int_as_float(quad_xor<X>(__float_as_int(v)));
+}
+template <int X>
+__device__ __forceinline__ double quad_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = quad_xor<X>((int)(b & 0xffffffffll));
+    const int hi = quad_xor<X>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // sum over the four lanes of a node's quad in a fixed order, (l0 + l1) + (l2 + l3)
 template <typename T>
 __device__ __forceinline__ T quad_sum(T v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+    v += quad_xor<1>(v);
+    v += quad_xor<2>(v);
     return v;
 }
 
@@ -815,6 +839,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     SlotHead head;
     slot_head(a, ic, sub, head);
     const int nc_pre = LIST ? a.clist_n[ic] : -1;
+    // the epilogue's own-node loads, issued now rather than at the end
+    const double axi = a.ax[ic], ayi = a.ay[ic];
+    const double ubxi = LIST ? (double)a.ubx[ic] : 0.0, ubyi = LIST ? (double)a.uby[ic] : 0.0;
     int lo = 0;
     bool staged = false;
     if (SEL == 0 && a.use_lds) {
@@ -889,12 +916,13 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     // to the node's own candidate list, in lane order; a full list means a
     // rebuild instead
     bool relist = false;
-    if (LIST && MODE == M_STEP) {
+    // (skipped by a wavefront without a break: all its quads have nothing to append)
+    if (LIST && MODE == M_STEP && __any(nbrk > 0)) {
         int keep = 0;
         uint32_t kj[4];
         const int nb = nbrk < 4 ? nbrk : 4;
         if (nb) {
-            const double bxi = xi + (double)a.ubx[i], byi = yi + (double)a.uby[i];
+            const double bxi = xi + ubxi, byi = yi + ubyi;
             for (int t = 0; t < nb; ++t) {
                 const int j = bj[t];
                 const double dx = (a.x[j] + (double)a.ubx[j]) - bxi;
@@ -904,11 +932,11 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         }
         for (int t = keep; t < 4; ++t) kj[t] = 0xffffffffu;
         int over = nbrk > 4 ? 1 : 0;
-        over |= __shfl_xor(over, 1, 64);
-        over |= __shfl_xor(over, 2, 64);
+        over |= quad_xor<1>(over);
+        over |= quad_xor<2>(over);
         int tot = keep;
-        tot += __shfl_xor(tot, 1, 64);
-        tot += __shfl_xor(tot, 2, 64);
+        tot += quad_xor<1>(tot);
+        tot += quad_xor<2>(tot);
         // lane 0 gathers the quad's partners and merges them into the node's
         // sorted list
         uint32_t nj[16];
@@ -936,11 +964,11 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         }
     }
     nbrk = quad_sum(nbrk);
-    st |= __shfl_xor(st, 1, 64);
-    st |= __shfl_xor(st, 2, 64);
+    st |= quad_xor<1>(st);
+    st |= quad_xor<2>(st);
     if (MODE == M_FORCES) {
-        smx = fmax(smx, __shfl_xor(smx, 1, 64));
-        smx = fmax(smx, __shfl_xor(smx, 2, 64));
+        smx = fmax(smx, quad_xor<1>(smx));
+        smx = fmax(smx, quad_xor<2>(smx));
     }
     if (sub != 0) return;
     if (MODE != M_FORCES) count(a, C_BROKEN, (unsigned long long)nbrk);
@@ -974,8 +1002,8 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         a.ax_o[i] = axn;
         a.ay_o[i] = ayn;
         if (MODE == M_STEP) {
-            const double vxn = vxi + a.hdt * (a.ax[i] + axn);
-            const double vyn = vyi + a.hdt * (a.ay[i] + ayn);
+            const double vxn = vxi + a.hdt * (axi + axn);
+            const double vyn = vyi + a.hdt * (ayi + ayn);
             a.vx_o[i] = vxn;
             a.vy_o[i] = vyn;
             a.ux_o[i] = uxi;
@@ -986,7 +1014,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                 // the next step's displacement against the one the list was built at
                 const double unx = (uxi + a.dt * vxn) + a.hdt2 * axn;
                 const double uny = (uyi + a.dt * vyn) + a.hdt2 * ayn;
-                const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
+                const double ex = unx - ubxi, ey = uny - ubyi;
                 if (!(ex * ex + ey * ey <= a.move2))
                     atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
             }
