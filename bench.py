@@ -413,8 +413,8 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--impact-us", type=float, default=40.0)
-    ap.add_argument("--settle-us", type=float, default=14000.0)
-    ap.add_argument("--settle-every-us", type=float, default=1400.0)
+    ap.add_argument("--settle-us", type=float, default=10000.0)
+    ap.add_argument("--settle-every-us", type=float, default=1000.0)
     ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure",
                                            "fragmentation", "settle_shapes"),
                     default="settling",
@@ -523,6 +523,7 @@ def main():
         out["batched"] = batched(pd, W, torch, args.batched_steps)
         out["closure"] = closure(pd, W, torch, args.closure_steps, args.train_iters)
         out["fragmentation"] = fragmentation(pd, W, torch, args.impact_us)
+        out["settle_shapes"] = settle_shapes(pd, W, torch, args.settle_us, args.settle_every_us)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.settling(), args.cpu_seconds, n_pairs)
     print(json.dumps(out), flush=True)

@@ -632,9 +632,12 @@ __device__ __forceinline__ void slot_head(const DevArgs &a, int i, int sub, Slot
 // stretch comes within 1e-10 (FP64) or 2e-6 (FP32) of s0 is re-decided with
 // the stretch evaluated in IEEE FP64 (correctly rounded square roots and
 // division), the exact decision of Sec. 3.1.
-template <typename R, int MODE>
+// STAGED: partner data from the workgroup's LDS window (a separate
+// instantiation, so that no load merges LDS and global addresses into one
+// generic access).
+template <typename R, int MODE, bool STAGED>
 __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc, int i, int sub,
-                                            bool staged, int lo, const double *Sx,
+                                            int lo, const double *Sx,
                                             const double *Sy, const double *Sux,
                                             const double *Suy, const double *Sv, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
@@ -656,14 +659,17 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                 const int k = k0 + 4 * t;
                 ev[t] = k0 == sub ? h.ev[t] : (k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken);
             }
-#pragma unroll 2
+            // fully unrolled, so that ev[t] is a register and not a select
+            // chain; a lane past its row's end (padding only) leaves the loop
+#pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int k = k0 + 4 * t;
+                if (k >= W) break;
                 const uint32_t e = ev[t];
                 const bool valid = (e & kBroken) == 0;
                 const int j = valid ? (int)e : i;
                 double xj, yj, uxj, uyj, Vj;
-                if (staged) {
+                if constexpr (STAGED) {
                     const int q = j - lo;
                     xj = Sx[q];
                     yj = Sy[q];
@@ -887,8 +893,10 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     // step and the bond loop commits breaks.
     if constexpr (LIST) {
         if (!closure)
-            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx, head, bj);
+            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj)
+                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny, nc_pre);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
@@ -897,8 +905,10 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
-            bond_forces<R, MODE>(a, mc, i, sub, staged, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi, uyi,
-                                 Vi, fpx, fpy, nbrk, smx, head, bj);
+            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj)
+                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj);
     }
 
     // ---- combine the quad ------------------------------------------------------

@@ -818,7 +818,7 @@ SETTLE_SHAPES = ("pdisk", "square", "plus", "ring")
 def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
                     mesh_size: float = 3.2e-3, seed: int = 6, eps: float = 0.5e-3,
                     r_min: float = 0.4e-3, gravity: float = -5000.0, dt: float = 70e-9,
-                    Gc: float = 135.0, precision: int = PREC_FP64) -> Problem:
+                    Gc: float | None = None, precision: int = PREC_FP64) -> Problem:
     """Settling of one particle shape from jammed security disks (Sec. 7.3):
     the disks of jammed_disks over the container inset by R_c / 2 (mesh size
     mesh_size), shrunk by R_c / 2 and keeping those of radius >= r_min; in each a
@@ -828,9 +828,10 @@ def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
     particle), "square" (side sqrt(2) R), "plus" (inner radius 0.2 R),
     "ring" (inner radius 0.6 R), and "disk".  Parameters of Sec. 7.3: eps = 0.5 mm, h = eps/8,
     R_c = eps/5, mu = 0.8, r_d = 0.8, g = 5000 m/s^2, dt = 70 ns, material M2
-    of Tab. tab:material (E = 1.23 GPa, k = 2 GPa, rho = 1200 kg/m^3); the
-    paper gives no G_c for this test (the default 135 J/m^2 leaves the
-    particles intact under their weight).
+    of Tab. tab:material (E = 1.23 GPa, k = 2 GPa, rho = 1200 kg/m^3).  The
+    paper turns damage on only for its compaction study (Sec. 7.4), so by
+    default bonds do not break here (Gc = None: a toughness so large that
+    the critical stretch is never reached); a value turns damage on.
 
     Draw order: the mesh jitter (default_rng(seed)), then default_rng(seed + 1)
     for the orientations and, for perturbed disks, the vertex radii
@@ -861,7 +862,8 @@ def jammed_settling(shape: str, width: float = 25e-3, height: float = 50e-3,
             parts.append(Particle(shape, float(rs), cen, float(th[k])))
         else:
             raise ValueError(f"unknown shape {shape!r}")
-    mat = Material(rho=1200.0, bulk_k=2e9, young_E=1.23e9, Gc=Gc, horizon=eps)
+    mat = Material(rho=1200.0, bulk_k=2e9, young_E=1.23e9, Gc=1e30 if Gc is None else Gc,
+                   horizon=eps)
     prob = assemble(parts, h, [mat], [0.0, width, 0.0, height], contact_radius=Rc,
                     friction_mu=0.8, damping_ratio=0.8, dt=dt, gravity=(0.0, gravity),
                     precision=precision,
