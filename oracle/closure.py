@@ -410,3 +410,191 @@ def max_stretch(prob, p, st, row=None, col=None, _cache={}):
             l = np.hypot(X + st["ux"][j] - st["ux"][i], Y + st["uy"][j] - st["uy"][i])
             best = max(best, abs(l - L) / L)
     return best
+
+
+# ----------------------------------------------------------------------------
+# reduced form: rigid + modal state integrated directly
+# ----------------------------------------------------------------------------
+def boundary_nodes(prob, p, Rc):
+    """Template-local boundary nodes of particle p: those with fewer other
+    nodes of p within 4 R_c (differences of reference positions) than the
+    largest such count over p's nodes."""
+    n0, n1 = particle_range(prob, p)
+    x, y = prob.x[n0:n1], prob.y[n0:n1]
+    D = 4.0 * Rc
+    D2 = D * D
+    dx = x[None, :] - x[:, None]   # [j, i] = x_i - x_j
+    dy = y[None, :] - y[:, None]
+    cnt = (dx * dx + dy * dy < D2).sum(1) - 1   # the node itself counts at distance 0
+    return np.nonzero(cnt < cnt.max())[0]
+
+
+class ReducedStepper:
+    """The closure's reduced form (a step in the same order as the library's):
+    each closure particle's state is its centroid c, rotation angle phi about
+    its shape's template, modal amplitudes q, and their rates and
+    accelerations.  At start, from the nodal state: mass centroid, velocity
+    and acceleration of the centroid, best-fit angle, angular velocity and
+    acceleration from the angular momentum and its rate about the centroid,
+    q, q' and q'' as projections of the body-frame deformation, velocity and
+    acceleration left after the rigid motion.  A step: nodal positions
+    advanced (u + dt v + dt^2/2 a); c, phi, q advanced the same way; contact
+    and wall forces from the C oracle at those positions (previous
+    velocities); the boundary nodes' forces reduced to F, the torque about c
+    (arms from the reconstructed positions) and Phi^T R(-phi) f; accelerations
+    F/M + g, tau / I(q) with I(q) = I0 + 2 b.q + q.q (b_k = sum m X.phi_k),
+    g(q) + Phi^T R(-phi) f; rates by the trapezoidal rule; the gate; every
+    node of the particle reconstructed (x + u = c + R(phi)(X + Phi q),
+    velocity and acceleration by differentiation, without the Coriolis term
+    of the modal rate)."""
+
+    def __init__(self, o, prob, shape_of_particle, modes, s0, tau_c, gate_frac,
+                 params=None, sig_q=None, sig_r=None):
+        self.o, self.prob = o, prob
+        self.sp = np.asarray(shape_of_particle)
+        self.modes = modes
+        self.s0, self.tau_c, self.gate = s0, tau_c, gate_frac
+        self.params, self.sig_q, self.sig_r = params, sig_q, sig_r
+        self.templates, self.bnd, self.I0, self.b, self.M = {}, {}, {}, {}, {}
+        for s in sorted(set(self.sp[self.sp >= 0].tolist())):
+            pt = int(np.nonzero(self.sp == s)[0][0])
+            X = reference_frame(prob, pt)[1]
+            m = node_masses(prob, pt)
+            Phi = modes[s][0]
+            self.templates[s] = X
+            self.bnd[s] = boundary_nodes(prob, pt, prob.contact_radius)
+            self.M[s] = m.sum()
+            self.I0[s] = (m * (X ** 2).sum(1)).sum()
+            self.b[s] = Phi.T @ (np.repeat(m, 2) * X.ravel())
+        self.active = self.sp >= 0
+        rho = np.array([prob.materials[int(mm)].rho for mm in prob.particle_material])
+        self.rho_node = np.repeat(rho, np.diff(prob.particle_offset))
+        self.state = {}
+        st = o.get_state()
+        for p in np.nonzero(self.active)[0]:
+            self.state[p] = self._init(p, st)
+        self._write_all(st)
+
+    def _g(self, s, q):
+        Phi, lam, _ = self.modes[s]
+        if self.params is None:
+            return closure_modal_force(q, lam)[0]
+        return closure_modal_force(q, lam, self.params[s], self.sig_q[s], self.sig_r[s])[0]
+
+    def _init(self, p, st):
+        prob = self.prob
+        s = int(self.sp[p])
+        n0, n1 = particle_range(prob, p)
+        m = node_masses(prob, p)
+        M = m.sum()
+        X = self.templates[s]
+        Phi = self.modes[s][0]
+        y = np.stack([prob.x[n0:n1] + st["ux"][n0:n1], prob.y[n0:n1] + st["uy"][n0:n1]], 1)
+        v = np.stack([st["vx"][n0:n1], st["vy"][n0:n1]], 1)
+        a = np.stack([st["ax"][n0:n1], st["ay"][n0:n1]], 1)
+        c = (m[:, None] * y).sum(0) / M
+        vc = (m[:, None] * v).sum(0) / M
+        ac = (m[:, None] * a).sum(0) / M
+        Y = y - c
+        phi = best_fit_angle(X, Y, m)
+        I = (m * (Y ** 2).sum(1)).sum()
+        dv, da = v - vc, a - ac
+        om = (m * (Y[:, 0] * dv[:, 1] - Y[:, 1] * dv[:, 0])).sum() / I
+        al = (m * (Y[:, 0] * da[:, 1] - Y[:, 1] * da[:, 0])).sum() / I
+        zY = np.stack([-Y[:, 1], Y[:, 0]], 1)  # z x Y
+        body = lambda w: rot(-phi, w).ravel()
+        mm = np.repeat(m, 2)
+        q = Phi.T @ (mm * (rot(-phi, Y) - X).ravel())
+        qv = Phi.T @ (mm * body(dv - om * zY))
+        qa = Phi.T @ (mm * body(da - al * zY + om * om * Y))
+        return dict(c=c, vc=vc, ac=ac, phi=phi, om=om, al=al, q=q, qv=qv, qa=qa)
+
+    def _nodes(self, p):
+        """positions, velocities, accelerations of every node of p"""
+        s = int(self.sp[p])
+        r = self.state[p]
+        X = self.templates[s]
+        Phi = self.modes[s][0]
+        Z = X + (Phi @ r["q"]).reshape(-1, 2)
+        Y = rot(r["phi"], Z)
+        zY = np.stack([-Y[:, 1], Y[:, 0]], 1)
+        pos = r["c"] + Y
+        vel = r["vc"] + r["om"] * zY + rot(r["phi"], (Phi @ r["qv"]).reshape(-1, 2))
+        acc = r["ac"] + r["al"] * zY - r["om"] ** 2 * Y + rot(r["phi"], (Phi @ r["qa"]).reshape(-1, 2))
+        return pos, vel, acc
+
+    def _write(self, p, arrs):
+        prob = self.prob
+        n0, n1 = particle_range(prob, p)
+        pos, vel, acc = self._nodes(p)
+        arrs["ux"][n0:n1] = pos[:, 0] - prob.x[n0:n1]
+        arrs["uy"][n0:n1] = pos[:, 1] - prob.y[n0:n1]
+        arrs["vx"][n0:n1], arrs["vy"][n0:n1] = vel[:, 0], vel[:, 1]
+        arrs["ax"][n0:n1], arrs["ay"][n0:n1] = acc[:, 0], acc[:, 1]
+
+    def _write_all(self, st):
+        arrs = {k: st[k].copy() for k in ("ux", "uy", "vx", "vy", "ax", "ay")}
+        for p in np.nonzero(self.active)[0]:
+            self._write(p, arrs)
+        self.o.set_state(dict(st, **arrs))
+
+    def step(self):
+        from .oracle import T_PD, T_SELF, T_NBR, T_WALL
+        o, prob = self.o, self.prob
+        st = o.get_state()
+        dt = prob.dt
+        h2 = 0.5 * dt * dt
+        ux = (st["ux"] + dt * st["vx"]) + h2 * st["ax"]
+        uy = (st["uy"] + dt * st["vy"]) + h2 * st["ay"]
+        o.set_state(dict(st, ux=ux, uy=uy, step=st["step"] + 1))
+        fpx, fpy = o.forces(T_PD)
+        fcx, fcy = o.forces(T_SELF | T_NBR | T_WALL)
+        gx, gy = prob.gravity
+        ax = (fpx + fcx) / self.rho_node + gx
+        ay = (fpy + fcy) / self.rho_node + gy
+        vx = st["vx"] + (0.5 * dt) * (st["ax"] + ax)
+        vy = st["vy"] + (0.5 * dt) * (st["ay"] + ay)
+        arrs = dict(ux=ux, uy=uy, vx=vx, vy=vy, ax=ax, ay=ay)
+        gate_off = []
+        for p in np.nonzero(self.active)[0]:
+            s = int(self.sp[p])
+            r = self.state[p]
+            Phi, lam, sig = self.modes[s]
+            X = self.templates[s]
+            n0, n1 = particle_range(prob, p)
+            V = prob.vol[n0:n1]
+            r["c"] = (r["c"] + dt * r["vc"]) + h2 * r["ac"]
+            r["phi"] = (r["phi"] + dt * r["om"]) + h2 * r["al"]
+            r["q"] = (r["q"] + dt * r["qv"]) + h2 * r["qa"]
+            B = self.bnd[s]
+            f = np.stack([fcx[n0:n1][B] * V[B], fcy[n0:n1][B] * V[B]], 1)
+            Z = X[B] + (Phi @ r["q"]).reshape(-1, 2)[B]
+            Y = rot(r["phi"], Z)
+            F = f.sum(0)
+            tau = (Y[:, 0] * f[:, 1] - Y[:, 1] * f[:, 0]).sum()
+            load = np.sqrt((f ** 2).sum(1)).sum()
+            fb = np.zeros((n1 - n0, 2))
+            fb[B] = rot(-r["phi"], f)
+            gext = Phi.T @ fb.ravel()
+            q = r["q"]
+            I = self.I0[s] + 2.0 * (self.b[s] @ q) + q @ q
+            ac = F / self.M[s] + np.array([gx, gy])
+            al = tau / I
+            qa = self._g(s, q) + gext
+            r["vc"] = r["vc"] + (0.5 * dt) * (r["ac"] + ac)
+            r["om"] = r["om"] + (0.5 * dt) * (r["al"] + al)
+            r["qv"] = r["qv"] + (0.5 * dt) * (r["qa"] + qa)
+            r["ac"], r["al"], r["qa"] = ac, al, qa
+            self._write(p, arrs)
+            strain = float((np.abs(q) * sig).sum())
+            if strain > self.gate * self.s0[s] or load > self.tau_c[s]:
+                gate_off.append(p)
+        o.set_state(dict(st, step=st["step"] + 1, **arrs))
+        for p in gate_off:
+            self.active[p] = False
+        return gate_off
+
+    def check(self, err_tol):
+        """The periodic check at the current (reconstructed) nodal state, as
+        ClosureStepper.check."""
+        return ClosureStepper.check(self, err_tol)

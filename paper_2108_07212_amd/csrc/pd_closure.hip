@@ -394,6 +394,390 @@ __global__ __launch_bounds__(512) void k_cl_apply(DevArgs a, ClArgs c, int list)
 }
 
 // ---------------------------------------------------------------------------
+// reduced mode: a closure particle's state is its centroid c, rotation angle
+// phi about the template orientation and modal amplitudes q, with their rates
+// and accelerations, integrated by velocity Verlet.  A node's position is
+// c + R(phi) (X + Phi q), its velocity and acceleration follow by
+// differentiation (without the Coriolis term of the modal rate, as in the
+// nodal form).  A step reconstructs only the particle's boundary nodes (the
+// ones that can meet other particles or walls); every node is reconstructed
+// before anything reads the nodal state.
+// ---------------------------------------------------------------------------
+struct RcRigid {
+    double cx, cy, vx, vy, ax, ay, cp, sp, om, al;
+};
+
+__device__ __forceinline__ RcRigid rc_rigid(const double *R) {
+    RcRigid r;
+    r.cx = R[RS_CX];
+    r.cy = R[RS_CY];
+    r.vx = R[RS_VX];
+    r.vy = R[RS_VY];
+    r.ax = R[RS_AX];
+    r.ay = R[RS_AY];
+    r.cp = cos(R[RS_PHI]);
+    r.sp = sin(R[RS_PHI]);
+    r.om = R[RS_OM];
+    r.al = R[RS_AL];
+    return r;
+}
+
+// body-frame position X + Phi q, modal velocity Phi qv and acceleration
+// Phi qa of template node t (Q, Qv, Qa in LDS; pass null to skip)
+__device__ __forceinline__ void rc_body(const ClArgs &c, int t, const double *Q, const double *Qv,
+                                        const double *Qa, double &zx, double &zy, double &wx,
+                                        double &wy, double &bx, double &by) {
+    const float4 *row = reinterpret_cast<const float4 *>(c.phi + (size_t)t * 2 * kClModes);
+    zx = c.tX[t];
+    zy = c.tY[t];
+    wx = wy = bx = by = 0.0;
+#pragma unroll 4
+    for (int k2 = 0; k2 < kClModes / 2; ++k2) {
+        const float4 f = row[k2];  // (x, y) of modes 2 k2 and 2 k2 + 1
+        const int k = 2 * k2;
+        zx += (double)f.x * Q[k] + (double)f.z * Q[k + 1];
+        zy += (double)f.y * Q[k] + (double)f.w * Q[k + 1];
+        if (Qv) {
+            wx += (double)f.x * Qv[k] + (double)f.z * Qv[k + 1];
+            wy += (double)f.y * Qv[k] + (double)f.w * Qv[k + 1];
+        }
+        if (Qa) {
+            bx += (double)f.x * Qa[k] + (double)f.z * Qa[k + 1];
+            by += (double)f.y * Qa[k] + (double)f.w * Qa[k + 1];
+        }
+    }
+}
+
+// node i (template node t) of a reduced particle into the given buffers
+__device__ __forceinline__ int rc_write(const DevArgs &a, const ClArgs &c, int i, int t,
+                                        const RcRigid &r, const double *Q, const double *Qv,
+                                        const double *Qa, double *ux, double *uy, double *vx,
+                                        double *vy, double *ax, double *ay) {
+    double zx, zy, wx, wy, bx, by;
+    rc_body(c, t, Q, Qv, Qa, zx, zy, wx, wy, bx, by);
+    const double Yx = r.cp * zx - r.sp * zy, Yy = r.sp * zx + r.cp * zy;
+    const double px = r.cx + Yx, py = r.cy + Yy;
+    const double om2 = r.om * r.om;
+    const double nvx = (r.vx - r.om * Yy) + (r.cp * wx - r.sp * wy);
+    const double nvy = (r.vy + r.om * Yx) + (r.sp * wx + r.cp * wy);
+    const double nax = ((r.ax - r.al * Yy) - om2 * Yx) + (r.cp * bx - r.sp * by);
+    const double nay = ((r.ay + r.al * Yx) - om2 * Yy) + (r.sp * bx + r.cp * by);
+    ux[i] = px - a.x[i];
+    uy[i] = py - a.y[i];
+    vx[i] = nvx;
+    vy[i] = nvy;
+    ax[i] = nax;
+    ay[i] = nay;
+    return (isfinite(px) && isfinite(py) && isfinite(nvx) && isfinite(nvy)) ? 0 : kStNonfinite;
+}
+
+// k_rc_init: the reduced state of every active closure particle from the
+// current nodal state: centroid, velocity and acceleration of the mass
+// centroid; the best-fit angle; angular velocity and acceleration from the
+// angular momentum and its rate about the centroid; q, its rate and its
+// acceleration as projections of the body-frame deformation, velocity and
+// acceleration left after the rigid motion
+__global__ __launch_bounds__(256) void k_rc_init(DevArgs a, ClArgs c) {
+    __shared__ double red[4 * 14];
+    __shared__ double part[8][kClModes][3];
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    if (!a.cl_on[p]) return;
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int t0 = c.toff[s];
+    const double rx = a.x[n0] + a.ux[n0], ry = a.y[n0] + a.uy[n0];
+    double v[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) v[k] = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const int i = n0 + j;
+        const double m = a.mass[i];
+        const double yx = (a.x[i] + a.ux[i]) - rx, yy = (a.y[i] + a.uy[i]) - ry;
+        const double Xx = c.tX[t0 + j], Xy = c.tY[t0 + j];
+        v[0] += m;
+        v[1] += m * yx;
+        v[2] += m * yy;
+        v[3] += m * a.vx[i];
+        v[4] += m * a.vy[i];
+        v[5] += m * a.ax[i];
+        v[6] += m * a.ay[i];
+        v[7] += m * (Xx * yy - Xy * yx);
+        v[8] += m * (Xx * yx + Xy * yy);
+        v[9] += m * (yx * yx + yy * yy);
+        v[10] += m * (yx * a.vy[i] - yy * a.vx[i]);
+        v[11] += m * (yx * a.ay[i] - yy * a.ax[i]);
+        v[12] += m * Xx;
+        v[13] += m * Xy;
+    }
+    block_sum<14>(v, red);
+    const double M = v[0];
+    const double cx = v[1] / M, cy = v[2] / M;  // about the first node
+    const double vcx = v[3] / M, vcy = v[4] / M, acx = v[5] / M, acy = v[6] / M;
+    const double cross = v[7] - (v[12] * cy - v[13] * cx);
+    const double dot = v[8] - (v[12] * cx + v[13] * cy);
+    const double I = v[9] - M * (cx * cx + cy * cy);
+    const double om = (v[10] - M * (cx * vcy - cy * vcx)) / I;
+    const double al = (v[11] - (cx * v[6] - cy * v[5])) / I;
+    const double phi = atan2(cross, dot);
+    const double cp = cos(phi), sp = sin(phi), om2 = om * om;
+    const double Cx = rx + cx, Cy = ry + cy;
+    if (threadIdx.x == 0) {
+        double *R = c.rs + (size_t)ci * 16;
+        R[RS_CX] = Cx;
+        R[RS_CY] = Cy;
+        R[RS_VX] = vcx;
+        R[RS_VY] = vcy;
+        R[RS_AX] = acx;
+        R[RS_AY] = acy;
+        R[RS_PHI] = phi;
+        R[RS_OM] = om;
+        R[RS_AL] = al;
+    }
+    // projections, thread (mode k, part of the nodes)
+    const int k = threadIdx.x & 31, pt = threadIdx.x >> 5;
+    double sq = 0.0, sv = 0.0, sa = 0.0;
+    for (int j = pt; j < n; j += 8) {
+        const int i = n0 + j;
+        const double m = a.mass[i];
+        const double Yx = (a.x[i] + a.ux[i]) - Cx, Yy = (a.y[i] + a.uy[i]) - Cy;
+        const double dvx = (a.vx[i] - vcx) + om * Yy, dvy = (a.vy[i] - vcy) - om * Yx;
+        const double dax = ((a.ax[i] - acx) + al * Yy) + om2 * Yx;
+        const double day = ((a.ay[i] - acy) - al * Yx) + om2 * Yy;
+        const double zx = (cp * Yx + sp * Yy) - c.tX[t0 + j], zy = (-sp * Yx + cp * Yy) - c.tY[t0 + j];
+        const double bvx = cp * dvx + sp * dvy, bvy = -sp * dvx + cp * dvy;
+        const double bax = cp * dax + sp * day, bay = -sp * dax + cp * day;
+        const float fx = c.phi[((size_t)(t0 + j) * kClModes + k) * 2];
+        const float fy = c.phi[((size_t)(t0 + j) * kClModes + k) * 2 + 1];
+        sq += m * ((double)fx * zx + (double)fy * zy);
+        sv += m * ((double)fx * bvx + (double)fy * bvy);
+        sa += m * ((double)fx * bax + (double)fy * bay);
+    }
+    part[pt][k][0] = sq;
+    part[pt][k][1] = sv;
+    part[pt][k][2] = sa;
+    __syncthreads();
+    if (threadIdx.x < kClModes) {
+        double q = 0.0, qv = 0.0, qa = 0.0;
+        for (int u = 0; u < 8; ++u) {
+            q += part[u][k][0];
+            qv += part[u][k][1];
+            qa += part[u][k][2];
+        }
+        c.qr[ci * kClModes + k] = q;
+        c.qv[ci * kClModes + k] = qv;
+        c.qa[ci * kClModes + k] = qa;
+    }
+}
+
+// k_rc_sync: every node of every active reduced particle into the current
+// nodal state
+__global__ __launch_bounds__(256) void k_rc_sync(DevArgs a, ClArgs c) {
+    __shared__ double Q[3][kClModes];
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    if (!a.cl_on[p]) return;
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int t0 = c.toff[s];
+    if (threadIdx.x < kClModes) {
+        Q[0][threadIdx.x] = c.qr[ci * kClModes + threadIdx.x];
+        Q[1][threadIdx.x] = c.qv[ci * kClModes + threadIdx.x];
+        Q[2][threadIdx.x] = c.qa[ci * kClModes + threadIdx.x];
+    }
+    __syncthreads();
+    const RcRigid r = rc_rigid(c.rs + (size_t)ci * 16);
+    int st = 0;
+    for (int j = threadIdx.x; j < n; j += 256)
+        st |= rc_write(a, c, n0 + j, t0 + j, r, Q[0], Q[1], Q[2], const_cast<double *>(a.ux),
+                       const_cast<double *>(a.uy), const_cast<double *>(a.vx),
+                       const_cast<double *>(a.vy), const_cast<double *>(a.ax),
+                       const_cast<double *>(a.ay));
+    if (st) atomicOr(a.status, st);
+}
+
+// k_rc_reduce (a step, after the contact forces of the boundary nodes):
+// positions of the reduced state advanced, then the external nodal forces
+// (contact and walls act only on boundary nodes) reduced to the total force,
+// the torque about the centroid, the contact load and the modal force
+// Phi^T R(-phi) f; q goes to the MLP's input
+__global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list) {
+    __shared__ double red[4 * 4];
+    __shared__ double FB[2][kClMaxNodes];
+    __shared__ double Q[kClModes];
+    __shared__ double part[8][kClModes];
+    __shared__ double Rg[3];
+    if (replay_stale(a, list)) return;
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    double *RR = c.red + (size_t)ci * 16;
+    if (!a.cl_on[p]) {
+        if (threadIdx.x == 0) RR[R_ACTIVE] = 0.0;
+        return;
+    }
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p];
+    const int t0 = c.toff[s];
+    const int b0 = c.boff[s], nb = c.boff[s + 1] - b0;
+    double *R = c.rs + (size_t)ci * 16;
+    const int tid = threadIdx.x;
+    if (tid < kClModes) {
+        const int k = tid;
+        const double q = (c.qr[ci * kClModes + k] + a.dt * c.qv[ci * kClModes + k]) +
+                         a.hdt2 * c.qa[ci * kClModes + k];
+        Q[k] = q;
+        c.qr[ci * kClModes + k] = q;
+        c.q[ci * kClModes + k] = q;
+    } else if (tid == kClModes) {
+        const double cx = (R[RS_CX] + a.dt * R[RS_VX]) + a.hdt2 * R[RS_AX];
+        const double cy = (R[RS_CY] + a.dt * R[RS_VY]) + a.hdt2 * R[RS_AY];
+        const double phi = (R[RS_PHI] + a.dt * R[RS_OM]) + a.hdt2 * R[RS_AL];
+        R[RS_CX] = cx;
+        R[RS_CY] = cy;
+        R[RS_PHI] = phi;
+        Rg[0] = cx;
+        Rg[1] = cy;
+        Rg[2] = phi;
+    }
+    __syncthreads();
+    const double cp = cos(Rg[2]), sp = sin(Rg[2]);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = tid; b < nb; b += 256) {
+        const int j = c.bnd[b0 + b];
+        const int i = n0 + j;
+        const double fx = a.cl_fx[i], fy = a.cl_fy[i];
+        double zx, zy, wx, wy, bx, by;
+        rc_body(c, t0 + j, Q, nullptr, nullptr, zx, zy, wx, wy, bx, by);
+        const double Yx = cp * zx - sp * zy, Yy = sp * zx + cp * zy;
+        v[0] += fx;
+        v[1] += fy;
+        v[2] += Yx * fy - Yy * fx;
+        v[3] += sqrt(fx * fx + fy * fy);
+        FB[0][b] = cp * fx + sp * fy;
+        FB[1][b] = -sp * fx + cp * fy;
+    }
+    block_sum<4>(v, red);  // (syncs, so FB is complete afterwards)
+    const int k = tid & 31, pt = tid >> 5;
+    double g = 0.0;
+    for (int b = pt; b < nb; b += 8) {
+        const int t = t0 + c.bnd[b0 + b];
+        const float fx = c.phi[((size_t)t * kClModes + k) * 2];
+        const float fy = c.phi[((size_t)t * kClModes + k) * 2 + 1];
+        g += (double)fx * FB[0][b] + (double)fy * FB[1][b];
+    }
+    part[pt][k] = g;
+    __syncthreads();
+    if (tid < 64) {  // wavefront 0: lanes 0..31 hold the modes
+        double ge = 0.0, sb = 0.0, bq = 0.0;
+        if (tid < kClModes) {
+            for (int u = 0; u < 8; ++u) ge += part[u][k];
+            c.gext[ci * kClModes + k] = ge;
+            const double q = Q[k];
+            sb = fabs(q) * c.sig[s * kClModes + k];
+            bq = 2.0 * c.bvec[s * kClModes + k] * q + q * q;
+        }
+        for (int o = 16; o > 0; o >>= 1) {
+            sb += __shfl_xor(sb, o, 64);
+            bq += __shfl_xor(bq, o, 64);
+        }
+        if (tid == 0) {
+            RR[R_M] = c.Mt[s];
+            RR[R_CX] = Rg[0];
+            RR[R_CY] = Rg[1];
+            RR[R_PHI] = Rg[2];
+            RR[R_COS] = cp;
+            RR[R_SIN] = sp;
+            RR[R_I] = c.I0[s] + bq;
+            RR[R_FX] = v[0];
+            RR[R_FY] = v[1];
+            RR[R_TAU] = v[2];
+            RR[R_CONTACT] = v[3];
+            RR[R_STRAIN] = sb;
+            RR[R_ACTIVE] = 1.0;
+        }
+    }
+}
+
+// k_rc_update (the end of a step): accelerations and rates of the reduced
+// state (F/M + g, tau/I, the closure's modal force plus the external one),
+// the gate, and the reconstruction of the boundary nodes (every node of a
+// particle that leaves the closure) into the step's output state
+__global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list) {
+    __shared__ double Q[3][kClModes];
+    __shared__ double Rn[16];
+    __shared__ int fb;
+    if (replay_stale(a, list)) return;
+    const int ci = blockIdx.x;
+    const double *RR = c.red + (size_t)ci * 16;
+    if (RR[R_ACTIVE] == 0.0) return;
+    const int p = c.cpart[ci];
+    const int s = c.cshape[ci];
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int t0 = c.toff[s];
+    const int b0 = c.boff[s], nb = c.boff[s + 1] - b0;
+    double *R = c.rs + (size_t)ci * 16;
+    const int tid = threadIdx.x;
+    if (tid < kClModes) {
+        const int k = tid;
+        const double q = c.qr[ci * kClModes + k];
+        const double g = c.learned ? c.ghat[ci * kClModes + k] : -c.lam[s * kClModes + k] * q;
+        const double qa = g + c.gext[ci * kClModes + k];
+        const double qv = c.qv[ci * kClModes + k] + a.hdt * (c.qa[ci * kClModes + k] + qa);
+        c.qv[ci * kClModes + k] = qv;
+        c.qa[ci * kClModes + k] = qa;
+        Q[0][k] = q;
+        Q[1][k] = qv;
+        Q[2][k] = qa;
+    } else if (tid == kClModes) {
+        const double M = RR[R_M];
+        const double ax = RR[R_FX] / M + a.gx, ay = RR[R_FY] / M + a.gy;
+        const double al = RR[R_TAU] / RR[R_I];
+        const double vx = R[RS_VX] + a.hdt * (R[RS_AX] + ax);
+        const double vy = R[RS_VY] + a.hdt * (R[RS_AY] + ay);
+        const double om = R[RS_OM] + a.hdt * (R[RS_AL] + al);
+        R[RS_VX] = vx;
+        R[RS_VY] = vy;
+        R[RS_AX] = ax;
+        R[RS_AY] = ay;
+        R[RS_OM] = om;
+        R[RS_AL] = al;
+        for (int u = 0; u < RS_N; ++u) Rn[u] = R[u];
+        // gate for the next step: past gate_frac s0 on the stretch bound, or
+        // past tau_c on the contact load, the particle leaves the closure
+        // with every node reconstructed now
+        int off = 0;
+        if (RR[R_STRAIN] > c.gate_frac * c.s0[s] || RR[R_CONTACT] > c.tau_c[s]) {
+            off = 1;
+            a.cl_on[p] = 0;
+            list_particle_blocks(c, p);
+            atomicAdd(c.fallbacks, 1ull);
+        }
+        fb = off;
+    }
+    __syncthreads();
+    const RcRigid r = rc_rigid(Rn);
+    const int cnt = fb ? n : nb;
+    int st = 0, stale = 0;
+    for (int b = tid; b < cnt; b += 256) {
+        const int j = fb ? b : c.bnd[b0 + b];
+        const int i = n0 + j;
+        st |= rc_write(a, c, i, t0 + j, r, Q[0], Q[1], Q[2], a.ux_o, a.uy_o, a.vx_o, a.vy_o,
+                       a.ax_o, a.ay_o);
+        if (list) {
+            const double unx = (a.ux_o[i] + a.dt * a.vx_o[i]) + a.hdt2 * a.ax_o[i];
+            const double uny = (a.uy_o[i] + a.dt * a.vy_o[i]) + a.hdt2 * a.ay_o[i];
+            const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
+            if (!(ex * ex + ey * ey <= a.move2)) stale = 1;
+        }
+    }
+    if (st) atomicOr(a.status, st);
+    if (__syncthreads_or(stale) && tid == 0) {
+        const long long sprev = *a.step_base + a.chunk_k;
+        atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // periodic check against the plain bond force: per particle, the modal force
 // of the closure vs the modal PD force (in c.gext after a mode-1 projection),
 // and the largest true bond stretch (smax per node, from the force kernel)
@@ -789,6 +1173,38 @@ hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStre
     if (c.Pc <= 0) return hipSuccess;
     if (!a.cl_on || !c.rb_shape) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cl_apply, dim3(c.n_rb, c.n_slices), dim3(512), 0, s, a, c, list ? 1 : 0);
+    return hipGetLastError();
+}
+
+static bool rc_ready(const DevArgs &a, const ClArgs &c) {
+    return a.cl_on && c.rs && c.qr && c.qv && c.qa && c.bnd && c.boff && c.Mt && c.I0 && c.bvec;
+}
+
+hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!rc_ready(a, c)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_init, dim3(c.Pc), dim3(256), 0, s, a, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!rc_ready(a, c)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_sync, dim3(c.Pc), dim3(256), 0, s, a, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_rc_reduce(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!rc_ready(a, c) || !a.cl_fx || !a.cl_fy) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_reduce, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!rc_ready(a, c)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_update, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0);
     return hipGetLastError();
 }
 

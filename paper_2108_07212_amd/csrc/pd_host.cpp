@@ -318,6 +318,14 @@ void invalidate_graph(Ctx &c) {
 // the closure particles, the MLP (learned closure), nodal accelerations
 hipError_t enqueue_closure(Ctx &c, bool list) {
     if (c.cl.mode == 0) return hipSuccess;
+    if (c.cl.reduced) {
+        // reduced state: advance, reduce the boundary forces, (MLP), update
+        // and reconstruct the boundary nodes
+        hipError_t e = launch_rc_reduce(c.a, c.cl.ca, list, c.stream);
+        if (e == hipSuccess && c.cl.mode == 2) e = launch_mlp_forward(c.cl.ma, c.a, list, c.stream);
+        if (e == hipSuccess) e = launch_rc_update(c.a, c.cl.ca, list, c.stream);
+        return e;
+    }
     hipError_t e = launch_cl_project(c.a, c.cl.ca, list, 0, c.cl.max_n, c.stream);
     if (e != hipSuccess) return e;
     if (c.cl.mode == 2) {
@@ -336,7 +344,9 @@ hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
         if (c.cl.mode) {
             // plain-force particles, then the closure particles' contact and walls
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1);
-            if (e == hipSuccess) e = launch_cl_contact(c.a, c.precision, c.stream);
+            if (e == hipSuccess)
+                e = c.cl.reduced ? launch_cl_contact(c.a, c.precision, c.stream, c.cl.bnode, c.cl.n_bnode)
+                                 : launch_cl_contact(c.a, c.precision, c.stream);
         } else {
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
         }
@@ -430,8 +440,11 @@ pd_status after_caller(Ctx &c) {
     return PD_OK;
 }
 
+pd_status rc_sync(Ctx &c);
+
 // forces at the current state into the term buffer (M_FORCES)
 pd_status eval_terms(Ctx &c) {
+    TRY(rc_sync(c));
     if (!c.a.terms) TRY(dalloc(c, &c.a.terms, (size_t)10 * c.N));
     HIPCHK(enqueue_search(c, c.cur, 0, 0));
     set_state_ptrs(c, c.cur);
@@ -451,9 +464,49 @@ pd_status alloc_lists(Ctx &c, int maxc) {
     return PD_OK;
 }
 
+// reduced closure: every node of every active reduced particle written into
+// the current nodal state (a step writes only the boundary nodes)
+pd_status rc_sync(Ctx &c) {
+    if (!(c.cl.ready && c.cl.mode && c.cl.reduced)) return PD_OK;
+    set_state_ptrs(c, c.cur);
+    HIPCHK(launch_rc_sync(c.a, c.cl.ca, c.stream));
+    return PD_OK;
+}
+
+pd_status cl_block_list(Ctx &c);
+
+// after a rebuild: a reduced particle whose interior node has contact
+// candidates (or is one) leaves the closure, with its nodes just synced
+pd_status rc_guard(Ctx &c) {
+    ClState &L = c.cl;
+    if (!(L.ready && L.mode && L.reduced)) return PD_OK;
+    HIPCHK(hipMemsetAsync(L.guard, 0, (size_t)c.P * sizeof(int), c.stream));
+    HIPCHK(launch_rc_guard(c.a, L.inner, L.guard, c.stream));
+    std::vector<int> g(c.P), on(c.P);
+    HIPCHK(hipMemcpyAsync(g.data(), L.guard, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(on.data(), L.on, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    unsigned long long n = 0;
+    for (int p = 0; p < c.P; ++p)
+        if (g[p] && on[p]) {
+            on[p] = 0;
+            ++n;
+        }
+    if (n == 0) return PD_OK;
+    unsigned long long fb = 0;
+    HIPCHK(hipMemcpyAsync(&fb, L.fallbacks, sizeof fb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    fb += n;
+    HIPCHK(hipMemcpyAsync(L.fallbacks, &fb, sizeof fb, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(L.on, on.data(), c.P * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    TRY(cl_block_list(c));
+    return PD_OK;
+}
+
 // candidate lists at the advanced positions of the current state: keys, radix
 // sort and cell starts there, then the per-node lists
 pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
+    TRY(rc_sync(c));
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIPCHK(hipMemsetAsync(c.a.overflow, 0, sizeof(int), c.stream));
         set_state_ptrs(c, c.cur);
@@ -474,7 +527,7 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
         if (over == 0) {
             c.list_valid = true;
             ++c.rebuilds;
-            return PD_OK;
+            return rc_guard(c);
         }
         int m = c.a.maxc;
         while (m < over) m *= 2;
@@ -614,6 +667,18 @@ pd_status upload_shape_modes(Ctx &c, int s) {
                           hipMemcpyHostToDevice, c.stream));
     HIPCHK(hipMemcpyAsync(L.sig + s * kClModes, &L.h_sig[s * kClModes], kClModes * sizeof(double),
                           hipMemcpyHostToDevice, c.stream));
+    // reduced mode: b_k = sum m X . phi_k with the modes as the kernels hold
+    // them, so that the polar moment is I0 + 2 b.q + q.q
+    if (L.bvec) {
+        const int t0 = L.h_toff[s], m0 = c.h_poff[L.h_shape_first[s]];
+        std::vector<double> b(kClModes, 0.0);
+        for (int k = 0; k < kClModes; ++k)
+            for (int i = 0; i < n; ++i)
+                b[k] += c.h_mass[m0 + i] * (L.h_tX[t0 + i] * (double)f[((size_t)i * kClModes + k) * 2] +
+                                             L.h_tY[t0 + i] * (double)f[((size_t)i * kClModes + k) * 2 + 1]);
+        HIPCHK(hipMemcpyAsync(L.bvec + s * kClModes, b.data(), kClModes * sizeof(double),
+                              hipMemcpyHostToDevice, c.stream));
+    }
     HIPCHK(hipStreamSynchronize(c.stream));
     return PD_OK;
 }
@@ -778,8 +843,68 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     }
     // device buffers
     const size_t Pc = L.Pc;
+    L.h_tX = tX;
+    L.h_tY = tY;
     TRY(upload(c, &L.tX, tX.data(), tX.size()));
     TRY(upload(c, &L.tY, tY.data(), tY.size()));
+    // reduced mode: a template node is interior when every other template node
+    // that a lattice could put within 4 R_c of it is there (its count of nodes
+    // within 4 R_c is the template's largest); the rest are boundary nodes,
+    // the only ones a step reconstructs.  Differences of reference positions,
+    // no contraction: the same set as the oracle's.
+    {
+        const double Db = 4.0 * c.a.Rc, D2 = Db * Db;
+        std::vector<int> boff(1, 0), bnd, bnode;
+        std::vector<uint8_t> inner(c.N, 0);
+        L.h_bnd.assign(S, {});
+        std::vector<double> Mt(S), I0(S);
+        for (int s = 0; s < S; ++s) {
+            const int pt = L.h_shape_first[s];
+            const int n0 = c.h_poff[pt], n = L.h_shape_n[s];
+            std::vector<int> cnt(n, 0);
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    if (i == j) continue;
+                    const double dx = c.h_x[n0 + i] - c.h_x[n0 + j], dy = c.h_y[n0 + i] - c.h_y[n0 + j];
+                    if (dx * dx + dy * dy < D2) ++cnt[j];
+                }
+            const int full = *std::max_element(cnt.begin(), cnt.end());
+            for (int j = 0; j < n; ++j)
+                if (cnt[j] < full) L.h_bnd[s].push_back(j);
+            bnd.insert(bnd.end(), L.h_bnd[s].begin(), L.h_bnd[s].end());
+            boff.push_back((int)bnd.size());
+            double M = 0.0, I = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double m = c.h_mass[n0 + i];
+                M += m;
+                I += m * (tX[L.h_toff[s] + i] * tX[L.h_toff[s] + i] + tY[L.h_toff[s] + i] * tY[L.h_toff[s] + i]);
+            }
+            Mt[s] = M;
+            I0[s] = I;
+        }
+        for (int k = 0; k < L.Pc; ++k) {
+            const int p = L.h_cpart[k], s = L.h_cshape[k];
+            const int n0 = c.h_poff[p], n = L.h_shape_n[s];
+            for (int j = 0; j < n; ++j) inner[n0 + j] = 1;
+            for (int j : L.h_bnd[s]) {
+                inner[n0 + j] = 0;
+                bnode.push_back(n0 + j);
+            }
+        }
+        TRY(upload(c, &L.bnd, bnd.data(), std::max<size_t>(bnd.size(), 1)));
+        TRY(upload(c, &L.boff, boff.data(), boff.size()));
+        TRY(upload(c, &L.bnode, bnode.data(), std::max<size_t>(bnode.size(), 1)));
+        L.n_bnode = (int)bnode.size();
+        TRY(upload(c, &L.inner, inner.data(), (size_t)c.N));
+        TRY(upload(c, &L.Mt, Mt.data(), S));
+        TRY(upload(c, &L.I0, I0.data(), S));
+        TRY(dalloc(c, &L.bvec, (size_t)S * kClModes));
+        TRY(dalloc(c, &L.guard, (size_t)c.P));
+        TRY(dalloc(c, &L.rs, Pc * 16));
+        TRY(dalloc(c, &L.qr, Pc * kClModes));
+        TRY(dalloc(c, &L.qv, Pc * kClModes));
+        TRY(dalloc(c, &L.qa, Pc * kClModes));
+    }
     TRY(dalloc(c, &L.phi, tX.size() * 2 * kClModes));
     TRY(dalloc(c, &L.phiT, tX.size() * 2 * kClModes));
     L.ca.NT = (int)tX.size();
@@ -878,6 +1003,15 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     ca.n_rb = (int)L.h_rb_shape.size();
     ca.n_slices = (L.max_n + 31) / 32;
     TRY(dalloc(c, &ca.part, Pc * ca.n_slices * kClModes * 2));
+    ca.rs = L.rs;
+    ca.qr = L.qr;
+    ca.qv = L.qv;
+    ca.qa = L.qa;
+    ca.bnd = L.bnd;
+    ca.boff = L.boff;
+    ca.Mt = L.Mt;
+    ca.I0 = L.I0;
+    ca.bvec = L.bvec;
     MlpArgs &m = L.ma;
     m = MlpArgs{};
     m.rows = L.Pc;
@@ -1429,6 +1563,7 @@ pd_status pd_damage(pd_ctx *ctx, double *phi, int64_t *nb, int32_t on_device) {
 pd_status pd_observables(pd_ctx *ctx, double *out) {
     if (!ctx || !out) return PD_E_INVALID;
     Ctx &c = ctx->c;
+    TRY(rc_sync(c));
     const int A = c.A;
     if (!c.d_split) TRY(dalloc(c, &c.d_split, 8 * (size_t)c.N));
     if (!c.d_obs) TRY(dalloc(c, &c.d_obs, 10 * (size_t)A));
@@ -1529,6 +1664,7 @@ pd_status pd_bonds(pd_ctx *ctx, int32_t *row, int32_t *col) {
 pd_status pd_contacts(pd_ctx *ctx, int32_t *pi, int32_t *pj, int64_t cap, int64_t *count) {
     if (!ctx) return PD_E_INVALID;
     Ctx &c = ctx->c;
+    TRY(rc_sync(c));
     HIPCHK(enqueue_search(c, c.cur, 0, 0));
     set_state_ptrs(c, c.cur);
     int *dcnt;
@@ -1576,6 +1712,7 @@ pd_status pd_get_state(pd_ctx *ctx, double *ux, double *uy, double *vx, double *
                        double *ay, uint8_t *broken, int64_t *step) {
     if (!ctx) return PD_E_INVALID;
     Ctx &c = ctx->c;
+    TRY(rc_sync(c));
     double *dst[6] = {ux, uy, vx, vy, ax, ay};
     const double *src[6] = {c.U[c.cur][0], c.U[c.cur][1], c.V[c.cur][0], c.V[c.cur][1],
                             c.Acc[c.cur][0], c.Acc[c.cur][1]};
@@ -1628,6 +1765,13 @@ pd_status pd_set_state(pd_ctx *ctx, const double *ux, const double *uy, const do
     c.status = 0;
     c.list_valid = false;
     set_state_ptrs(c, 0);
+    if (c.cl.ready && c.cl.mode && c.cl.reduced) {
+        // the reduced state of the closure particles from the loaded nodes,
+        // which are then put on the rigid + modal motion
+        HIPCHK(launch_rc_init(c.a, c.cl.ca, c.stream));
+        TRY(rc_sync(c));
+        HIPCHK(hipStreamSynchronize(c.stream));
+    }
     return PD_OK;
 }
 
@@ -1974,10 +2118,16 @@ pd_status pd_closure_enable(pd_ctx *ctx, int32_t mode) {
     if (!ctx) return PD_E_INVALID;
     Ctx &c = ctx->c;
     if (!c.cl.ready) return fail(c, PD_E_STATE, "the closure is not set up");
-    if (mode < 0 || mode > 2) return fail(c, PD_E_INVALID, "mode is 0 (off), 1 (linear) or 2 (learned)");
+    const bool reduced = (mode & PD_CLOSURE_REDUCED) != 0;
+    mode &= ~PD_CLOSURE_REDUCED;
+    if (mode < 0 || mode > 2)
+        return fail(c, PD_E_INVALID, "mode is 0 (off), 1 (linear) or 2 (learned), optionally | PD_CLOSURE_REDUCED");
     if (mode && !(c.tune.skin_factor > 0.0))
         return fail(c, PD_E_INVALID, "the modal closure runs with candidate lists (skin_factor > 0)");
+    if (mode && reduced && c.tune.skin_factor > 1.0)
+        return fail(c, PD_E_INVALID, "the reduced closure needs skin_factor <= 1 (boundary layer of 4 R_c)");
     ClState &L = c.cl;
+    TRY(rc_sync(c));  // leaving a reduced mode: the nodes first
     HIPCHK(hipStreamSynchronize(c.stream));
     std::vector<int> on(c.P, 0);
     if (mode)
@@ -1985,13 +2135,23 @@ pd_status pd_closure_enable(pd_ctx *ctx, int32_t mode) {
     HIPCHK(hipMemcpyAsync(L.on, on.data(), c.P * sizeof(int), hipMemcpyHostToDevice, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     L.mode = mode;
+    L.reduced = mode && reduced;
     L.ca.learned = mode == 2 ? 1 : 0;
     c.a.cl_on = mode ? L.on : nullptr;
     c.a.cl_fx = L.fx;
     c.a.cl_fy = L.fy;
     if (mode) TRY(cl_block_list(c));
+    if (L.reduced) {
+        // the reduced state from the current nodes, which are then put on the
+        // rigid + modal motion; lists are rebuilt (the guard needs them)
+        set_state_ptrs(c, c.cur);
+        HIPCHK(launch_rc_init(c.a, L.ca, c.stream));
+        TRY(rc_sync(c));
+        c.list_valid = false;
+    }
     L.last_check_step = c.step;
     invalidate_graph(c);
+    HIPCHK(hipStreamSynchronize(c.stream));
     return PD_OK;
 }
 

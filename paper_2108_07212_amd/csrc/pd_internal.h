@@ -123,6 +123,11 @@ constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
 enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
        R_COS, R_SIN, R_ACTIVE, R_N };
 
+// reduced state of a closure particle (reduced mode): centroid position,
+// velocity and acceleration, rotation angle about the template orientation,
+// angular velocity and acceleration; [Pc][16]
+enum { RS_CX = 0, RS_CY, RS_VX, RS_VY, RS_AX, RS_AY, RS_PHI, RS_OM, RS_AL, RS_N };
+
 struct ClArgs {
     int Pc;                    // closure particles (sorted by shape)
     const int *cpart;          // [Pc] particle index
@@ -149,6 +154,13 @@ struct ClArgs {
     // list of force workgroups with plain-force nodes, appended on fallback
     int *pd_blocks, *n_pd_blocks, *blk_listed;
     int block_nodes;
+    // reduced mode: the particle's state is (centroid, angle, modal
+    // amplitudes) and their rates; only boundary nodes are reconstructed in a
+    // step, every node before anything reads the nodal state
+    double *rs;                // [Pc][16] RS_* entries
+    double *qr, *qv, *qa;      // [Pc][32] modal amplitudes, rates, accelerations
+    const int *bnd, *boff;     // template-local boundary nodes of shape s: bnd[boff[s] .. boff[s+1])
+    const double *Mt, *I0, *bvec;  // [S] mass, polar moment of the template; [S][32] sum m X . phi_k
 };
 
 // one forward pass of the MLP over `rows` rows of modal amplitudes
@@ -198,6 +210,17 @@ struct ClState {
     double *per = nullptr;     // [Pc][4] device: per-particle check results
     unsigned long long *fallbacks = nullptr;
     int max_n = 0;             // nodes of the largest closure shape
+    // reduced mode
+    bool reduced = false;
+    double *rs = nullptr, *qr = nullptr, *qv = nullptr, *qa = nullptr;
+    int *bnd = nullptr, *boff = nullptr;     // boundary nodes per shape (template-local)
+    int *bnode = nullptr;                    // global boundary nodes of all closure particles
+    int n_bnode = 0;
+    uint8_t *inner = nullptr;                // [N] 1: interior node of a closure particle
+    int *guard = nullptr;                    // [P] particles whose interior met a contact
+    double *Mt = nullptr, *I0 = nullptr, *bvec = nullptr;
+    std::vector<std::vector<int>> h_bnd;     // per shape, template-local boundary nodes
+    std::vector<double> h_tX, h_tY;          // template coordinates (host copy)
     std::vector<std::vector<double>> h_phi;  // per shape [n_s][2][K] (float64)
     double last_err = -1.0, last_err_linear = -1.0;
     int64_t checks = 0;
@@ -303,7 +326,9 @@ hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0);
-hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s,
+                             const int *nodes = nullptr, int n_nodes = 0);
+hipError_t launch_rc_guard(const DevArgs &a, const uint8_t *inner, int *flag, hipStream_t s);
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s);
 hipError_t launch_particle_damage(const DevArgs &a, const int *poff, double *out, hipStream_t s);
@@ -320,6 +345,10 @@ hipError_t launch_contacts_count(const DevArgs &a, int *cnt, hipStream_t s);
 hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int mode, int max_n,
                              hipStream_t s);
 hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
+hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s);
+hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s);
+hipError_t launch_rc_reduce(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
+hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,
                            double *stats, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s);

@@ -1060,11 +1060,13 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
 // (list mode), one thread per node: every candidate and every wall and corner
 // region in turn.  The closure kernels integrate these nodes.
 template <typename R>
-__global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
+__global__ __launch_bounds__(256) void k_cl_contact(DevArgs a, const int *nodes, int n_nodes) {
     const long long sprev = *a.step_base + a.chunk_k;
     if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    // every node, or only the listed ones (the boundary nodes of reduced particles)
+    if (tid >= (nodes ? n_nodes : a.N)) return;
+    const int i = nodes ? nodes[tid] : tid;
     const int pi = a.part[i];
     if (!a.cl_on[pi]) return;
     const double xi = a.x[i], yi = a.y[i];
@@ -1093,13 +1095,40 @@ __global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
     if (st) atomicOr(a.status, st);
 }
 
-hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
-    if (a.N == 0) return hipSuccess;
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s, const int *nodes,
+                             int n_nodes) {
+    const int n = nodes ? n_nodes : a.N;
+    if (n <= 0) return hipSuccess;
     if (!(a.cl_on && a.cl_fx && a.cl_fy)) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((n + 255) / 256));
     if (precision == PD_PREC_FP64)
-        hipLaunchKernelGGL(k_cl_contact<double>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_cl_contact<double>, g, dim3(256), 0, s, a, nodes, n_nodes);
     else
-        hipLaunchKernelGGL(k_cl_contact<float>, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_cl_contact<float>, g, dim3(256), 0, s, a, nodes, n_nodes);
+    return hipGetLastError();
+}
+
+// After a list rebuild with reduced particles: a particle whose interior
+// node (one the steps do not reconstruct) has contact candidates, or is one,
+// is flagged; the host returns it to the plain force.
+__global__ void k_rc_guard(DevArgs a, const uint8_t *inner, int *flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int n = a.clist_n[i];
+    if (n == 0) return;
+    const int pi = a.part[i];
+    if (inner[i] && a.cl_on[pi]) flag[pi] = 1;
+    for (int k = 0; k < n; ++k) {
+        const int j = (int)a.clist[(size_t)k * a.N + i];
+        const int pj = a.part[j];
+        if (inner[j] && a.cl_on[pj]) flag[pj] = 1;
+    }
+}
+
+hipError_t launch_rc_guard(const DevArgs &a, const uint8_t *inner, int *flag, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    if (!(a.cl_on && a.clist && a.clist_n && inner && flag)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_guard, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, inner, flag);
     return hipGetLastError();
 }
 

@@ -128,6 +128,7 @@ def load_library(path: str = LIB_PATH):
 
 CLOSURE_MODES = 32
 CLOSURE_PARAMS = 82464
+CLOSURE_REDUCED = 4  # pd_closure_enable flag: reduced rigid + modal state
 
 
 def _p(a, t):

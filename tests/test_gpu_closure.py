@@ -233,10 +233,10 @@ def test_mlp_gradients_match_oracle(setup_bed, n):
 # the closure step
 # ----------------------------------------------------------------------------
 def _run_pair(setup_bed, steps, mode, frac_range=(0.05, 0.3), gate=0.5, tau_c=BIG, params=None,
-              seed=60):
+              seed=60, reduced=False, prob=None):
     pd = _pd()
-    prob, modes, s0 = setup_bed
-    prob = modal_deformation(bed(), modes, seed, frac_range, s0)
+    prob0, modes, s0 = setup_bed
+    prob = modal_deformation(bed() if prob is None else prob, modes, seed, frac_range, s0)
     sp = prob.meta["shape_of_particle"]
     S = len(modes)
     g = pd.PD(prob)
@@ -251,10 +251,11 @@ def _run_pair(setup_bed, steps, mode, frac_range=(0.05, 0.3), gate=0.5, tau_c=BI
         sr = {s: (3e-2 * modes[s][1] * sq[s]).astype(np.float32).astype(np.float64) for s in modes}
         for s in modes:
             g.closure_load(s, params[s], sq[s], sr[s])
-    g.closure_enable(mode)
+    g.closure_enable(mode | (pd.CLOSURE_REDUCED if reduced else 0))
     o = Oracle(prob, contact_mode=1)
-    st = CL.ClosureStepper(o, prob, sp, modes, [s0] * S, [tau_c] * S, gate, params=params,
-                           sig_q=sq, sig_r=sr)
+    Stepper = CL.ReducedStepper if reduced else CL.ClosureStepper
+    st = Stepper(o, prob, sp, modes, [s0] * S, [tau_c] * S, gate, params=params, sig_q=sq,
+                 sig_r=sr)
     off = []
     for _ in range(steps):
         off += st.step()
@@ -306,6 +307,75 @@ def test_periodic_check_matches_oracle(setup_bed):
     assert abs(stt["err_linear"] - math.sqrt(l2 / n2)) <= 1e-8 * math.sqrt(l2 / n2)
     p, s, act = g.closure_particles()
     np.testing.assert_array_equal(act.astype(bool), st.active[p])
+
+
+# ----------------------------------------------------------------------------
+# the reduced form (rigid + modal state, boundary nodes only)
+# ----------------------------------------------------------------------------
+def test_reduced_switch_on_keeps_a_modal_state(setup_bed):
+    """Switching the reduced form on projects the nodes on the rigid + modal
+    motion; a state already there comes back unchanged."""
+    pd = _pd()
+    prob, modes, s0 = setup_bed
+    prob = modal_deformation(bed(), modes, 65, (0.05, 0.3), s0)
+    g = pd.PD(prob)
+    g.closure_setup(prob.meta["shape_of_particle"], check_every=0)
+    load_modes(g, modes)
+    a = g.get_state()
+    g.closure_enable(1 | pd.CLOSURE_REDUCED)
+    b = g.get_state()
+    scale = max(np.abs(a["ux"]).max(), np.abs(a["uy"]).max())
+    for k in ("ux", "uy"):
+        assert np.abs(a[k] - b[k]).max() <= 1e-6 * scale, k
+
+
+def test_reduced_linear_steps_match_oracle(setup_bed):
+    g, o, st, off = _run_pair(setup_bed, 40, 1, reduced=True)
+    assert off == []
+    _compare_states(g, o, 1e-9)
+    p, s, act = g.closure_particles()
+    assert np.all(act == 1)
+
+
+def test_reduced_learned_steps_match_oracle(setup_bed):
+    prob, modes, s0 = setup_bed
+    params = {s: rand_params(70 + s) for s in modes}
+    g, o, st, off = _run_pair(setup_bed, 30, 2, params=params, reduced=True)
+    _compare_states(g, o, 1e-6)
+
+
+def test_reduced_gate_fallbacks_match_oracle(setup_bed):
+    g, o, st, off = _run_pair(setup_bed, 40, 1, frac_range=(0.02, 0.4), gate=0.2, seed=61,
+                              reduced=True)
+    assert len(off) > 0
+    p, s, act = g.closure_particles()
+    np.testing.assert_array_equal(act.astype(bool), st.active[p])
+    assert g.closure_stats()["fallbacks"] == len(off)
+    _compare_states(g, o, 1e-9)
+
+
+def test_reduced_with_interior_nodes_matches_oracle():
+    """Particles of 300 nodes: part of each is interior and only its boundary
+    nodes are reconstructed in a step; trajectories (all nodes, read back
+    reconstructed) and the periodic check follow the oracle."""
+    pd = _pd()
+    prob = W.closure_bed(n_per_shape=2, h=H, nodes=300, seed=23, wall_speed=0.0, vmax=0.3)
+    o = Oracle(prob, contact_mode=1)
+    modes = oracle_modes(prob, o)
+    s0 = float(o.constants()["s0"][0])
+    first = first_of_shape(prob)
+    n_b = sum(len(CL.boundary_nodes(prob, pt, prob.contact_radius)) for pt in first.values())
+    n_all = sum(int(np.diff(prob.particle_offset)[pt]) for pt in first.values())
+    assert n_b < 0.9 * n_all
+    g, o, st, off = _run_pair((prob, modes, s0), 60, 1, reduced=True, seed=66,
+                              prob=W.closure_bed(n_per_shape=2, h=H, nodes=300, seed=23,
+                                                 wall_speed=0.0, vmax=0.3))
+    assert off == []
+    _compare_states(g, o, 1e-9)
+    g.closure_check()
+    e2, n2, l2, out = st.check(0.05)
+    stt = g.closure_stats()
+    assert abs(stt["err"] - math.sqrt(e2 / n2)) <= 1e-7 * math.sqrt(e2 / n2)
 
 
 def test_snapshot_matches_oracle(setup_bed):
