@@ -220,8 +220,9 @@ def closure(pd, W, torch, steps, train_iters):
     (disk, plus, ring, L; about 390 nodes each, 781 500 nodes) under
     compaction: snapshots of a plain run train each shape's network on the
     GPU; then plain, linear-closure and learned-closure runs from another
-    excitation are timed, with the closure checked against the plain bond
-    force every 100 steps."""
+    excitation are timed, in the nodal form and in the reduced form (rigid +
+    modal state, boundary nodes only), with the closure checked against the
+    plain bond force every 100 steps."""
     import numpy as np
     mk = lambda: W.closure_bed(vmax=0.5)
     prob = mk()
@@ -283,7 +284,9 @@ def closure(pd, W, torch, steps, train_iters):
     res["heldout_modal_force_err"] = {"learned": (e_n / n2) ** 0.5, "linear": (e_l / n2) ** 0.5}
     del gt
     # timed runs from the held-out excitation
-    for name, mode in (("plain", 0), ("linear", 1), ("learned", 2)):
+    R = pd.CLOSURE_REDUCED
+    for name, mode in (("plain", 0), ("linear", 1), ("learned", 2), ("reduced_linear", 1 | R),
+                       ("reduced_learned", 2 | R)):
         gr = pd.PD(modal_excitation(mk(), modes, 52, strain))
         gr.closure_setup(sp)
         for s in range(4):
@@ -303,8 +306,8 @@ def closure(pd, W, torch, steps, train_iters):
                      "check_err": st["err"] if mode else None,
                      "check_err_linear": st["err_linear"] if mode else None}
         del gr
-    res["speedup_learned_vs_plain"] = res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"]
-    res["speedup_linear_vs_plain"] = res["linear"]["steps_per_s"] / res["plain"]["steps_per_s"]
+    for name in ("linear", "learned", "reduced_linear", "reduced_learned"):
+        res[f"speedup_{name}_vs_plain"] = res[name]["steps_per_s"] / res["plain"]["steps_per_s"]
     return res
 
 

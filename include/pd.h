@@ -308,23 +308,28 @@ pd_status pd_closure_get(pd_ctx *c, int32_t shape, float *params, float *sig_q, 
  * closure.  Switching on admits every closure particle; its state should lie
  * in its rigid + modal space (an undeformed particle does).
  *
- * mode | PD_CLOSURE_REDUCED (1 or 2 only; needs skin_factor <= 1): the
- * reduced form.  A closure particle's state is then its centroid, its
- * rotation angle and its modal amplitudes with their rates and accelerations
- * (velocity Verlet on those: centroid acceleration F/M + g, angular
- * acceleration tau/I(q) with I(q) = I0 + 2 b.q + q.q, modal acceleration
+ * mode | PD_CLOSURE_REDUCED (1 or 2 only): the reduced form.  A closure
+ * particle's state is then its centroid, its rotation angle and its modal
+ * amplitudes with their rates and accelerations (velocity Verlet on those:
+ * centroid acceleration F/M + g, angular acceleration tau/I(q) with
+ * I(q) = I0 + 2 b.q + q.q, b_k = sum m X.phi_k, modal acceleration
  * g(q) + Phi^T R(-phi) f), set at switch-on from the current nodes by the
  * same projections (mass centroid, best-fit angle, angular momentum and its
  * rate, modal projections of the body-frame deformation, velocity and
- * acceleration).  A step computes contact and wall forces and reconstructs
- * nodes only for the particle's boundary nodes (template nodes with fewer
- * template nodes within 4 R_c than the template's interior ones); every
- * node is reconstructed (x + u = c + R(phi)(X + Phi q), velocity and
- * acceleration by differentiation) before any call reads the nodal state,
- * and pd_set_state re-derives the reduced state from the loaded nodes.  A
- * particle whose interior node comes within a candidate list's reach of
- * another particle (checked at each list rebuild) returns to the plain
- * bond force, as the gate and the periodic check return others. */
+ * acceleration).  At each candidate-list rebuild the particle's active nodes
+ * are listed: nodes with contact candidates, candidates of any node, and
+ * nodes within the list radius of a wall.  A step computes contact and wall
+ * forces for the active nodes only (the others cannot meet anything before
+ * the next rebuild), reduces them with torque arms from the advanced nodal
+ * positions, and reconstructs only the active nodes
+ * (x + u = c + R(phi)(X + Phi q), velocity and acceleration by
+ * differentiation); a bound on every node's motion since the rebuild,
+ * |c - c_rb| + |phi - phi_rb| (r_max + sum |q_rb,k| phimax_k) +
+ * sum |q_k - q_rb,k| phimax_k, against half the skin triggers the next
+ * rebuild, and with a moving top wall the lists are rebuilt before it has
+ * moved half the skin.  Every node is reconstructed before any call reads
+ * the nodal state, and pd_set_state re-derives the reduced state from the
+ * loaded nodes. */
 #define PD_CLOSURE_REDUCED 4
 pd_status pd_closure_enable(pd_ctx *c, int32_t mode);
 /* Training snapshot at the current state, for every closure particle in the

@@ -415,20 +415,6 @@ def max_stretch(prob, p, st, row=None, col=None, _cache={}):
 # ----------------------------------------------------------------------------
 # reduced form: rigid + modal state integrated directly
 # ----------------------------------------------------------------------------
-def boundary_nodes(prob, p, Rc):
-    """Template-local boundary nodes of particle p: those with fewer other
-    nodes of p within 4 R_c (differences of reference positions) than the
-    largest such count over p's nodes."""
-    n0, n1 = particle_range(prob, p)
-    x, y = prob.x[n0:n1], prob.y[n0:n1]
-    D = 4.0 * Rc
-    D2 = D * D
-    dx = x[None, :] - x[:, None]   # [j, i] = x_i - x_j
-    dy = y[None, :] - y[:, None]
-    cnt = (dx * dx + dy * dy < D2).sum(1) - 1   # the node itself counts at distance 0
-    return np.nonzero(cnt < cnt.max())[0]
-
-
 class ReducedStepper:
     """The closure's reduced form (a step in the same order as the library's):
     each closure particle's state is its centroid c, rotation angle phi about
@@ -440,8 +426,8 @@ class ReducedStepper:
     acceleration left after the rigid motion.  A step: nodal positions
     advanced (u + dt v + dt^2/2 a); c, phi, q advanced the same way; contact
     and wall forces from the C oracle at those positions (previous
-    velocities); the boundary nodes' forces reduced to F, the torque about c
-    (arms from the reconstructed positions) and Phi^T R(-phi) f; accelerations
+    velocities); the nodal forces reduced to F, the torque about c (arms from
+    the advanced nodal positions) and Phi^T R(-phi) f; accelerations
     F/M + g, tau / I(q) with I(q) = I0 + 2 b.q + q.q (b_k = sum m X.phi_k),
     g(q) + Phi^T R(-phi) f; rates by the trapezoidal rule; the gate; every
     node of the particle reconstructed (x + u = c + R(phi)(X + Phi q),
@@ -449,24 +435,24 @@ class ReducedStepper:
     of the modal rate)."""
 
     def __init__(self, o, prob, shape_of_particle, modes, s0, tau_c, gate_frac,
-                 params=None, sig_q=None, sig_r=None):
+                 params=None, sig_q=None, sig_r=None, active=None):
+        """active: which closure particles start in the closure (default all)"""
         self.o, self.prob = o, prob
         self.sp = np.asarray(shape_of_particle)
         self.modes = modes
         self.s0, self.tau_c, self.gate = s0, tau_c, gate_frac
         self.params, self.sig_q, self.sig_r = params, sig_q, sig_r
-        self.templates, self.bnd, self.I0, self.b, self.M = {}, {}, {}, {}, {}
+        self.templates, self.I0, self.b, self.M = {}, {}, {}, {}
         for s in sorted(set(self.sp[self.sp >= 0].tolist())):
             pt = int(np.nonzero(self.sp == s)[0][0])
             X = reference_frame(prob, pt)[1]
             m = node_masses(prob, pt)
             Phi = modes[s][0]
             self.templates[s] = X
-            self.bnd[s] = boundary_nodes(prob, pt, prob.contact_radius)
             self.M[s] = m.sum()
             self.I0[s] = (m * (X ** 2).sum(1)).sum()
             self.b[s] = Phi.T @ (np.repeat(m, 2) * X.ravel())
-        self.active = self.sp >= 0
+        self.active = (self.sp >= 0) if active is None else np.asarray(active, dtype=bool).copy()
         rho = np.array([prob.materials[int(mm)].rho for mm in prob.particle_material])
         self.rho_node = np.repeat(rho, np.diff(prob.particle_offset))
         self.state = {}
@@ -566,16 +552,12 @@ class ReducedStepper:
             r["c"] = (r["c"] + dt * r["vc"]) + h2 * r["ac"]
             r["phi"] = (r["phi"] + dt * r["om"]) + h2 * r["al"]
             r["q"] = (r["q"] + dt * r["qv"]) + h2 * r["qa"]
-            B = self.bnd[s]
-            f = np.stack([fcx[n0:n1][B] * V[B], fcy[n0:n1][B] * V[B]], 1)
-            Z = X[B] + (Phi @ r["q"]).reshape(-1, 2)[B]
-            Y = rot(r["phi"], Z)
+            f = np.stack([fcx[n0:n1] * V, fcy[n0:n1] * V], 1)
+            Y = np.stack([prob.x[n0:n1] + ux[n0:n1], prob.y[n0:n1] + uy[n0:n1]], 1) - r["c"]
             F = f.sum(0)
             tau = (Y[:, 0] * f[:, 1] - Y[:, 1] * f[:, 0]).sum()
             load = np.sqrt((f ** 2).sum(1)).sum()
-            fb = np.zeros((n1 - n0, 2))
-            fb[B] = rot(-r["phi"], f)
-            gext = Phi.T @ fb.ravel()
+            gext = Phi.T @ rot(-r["phi"], f).ravel()
             q = r["q"]
             I = self.I0[s] + 2.0 * (self.b[s] @ q) + q @ q
             ac = F / self.M[s] + np.array([gx, gy])

@@ -399,9 +399,10 @@ __global__ __launch_bounds__(512) void k_cl_apply(DevArgs a, ClArgs c, int list)
 // and accelerations, integrated by velocity Verlet.  A node's position is
 // c + R(phi) (X + Phi q), its velocity and acceleration follow by
 // differentiation (without the Coriolis term of the modal rate, as in the
-// nodal form).  A step reconstructs only the particle's boundary nodes (the
-// ones that can meet other particles or walls); every node is reconstructed
-// before anything reads the nodal state.
+// nodal form).  A step handles only the particle's active nodes (listed at the
+// last list rebuild: the only ones that can meet other nodes or walls before
+// the next); every node is reconstructed before anything reads the nodal
+// state.
 // ---------------------------------------------------------------------------
 struct RcRigid {
     double cx, cy, vx, vy, ax, ay, cp, sp, om, al;
@@ -596,10 +597,47 @@ __global__ __launch_bounds__(256) void k_rc_sync(DevArgs a, ClArgs c) {
     if (st) atomicOr(a.status, st);
 }
 
-// k_rc_reduce (a step, after the contact forces of the boundary nodes):
+// k_rc_collect (at a list rebuild, after k_rc_mark): the active nodes of each
+// reduced particle in ascending order (wavefront ballots), and the reduced
+// positions the motion bound is measured from
+__global__ __launch_bounds__(256) void k_rc_collect(DevArgs a, ClArgs c, const uint8_t *act) {
+    __shared__ int wc[4];
+    const int ci = blockIdx.x;
+    const int p = c.cpart[ci];
+    if (!a.cl_on[p]) return;
+    const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int total = 0;
+    for (int base = 0; base < n; base += 256) {
+        const int j = base + (int)threadIdx.x;
+        const bool f = j < n && act[n0 + j];
+        const unsigned long long bal = __ballot(f);
+        if (l == 0) wc[w] = __popcll(bal);
+        __syncthreads();
+        int off = total;
+        for (int u = 0; u < w; ++u) off += wc[u];
+        if (f) {
+            const int rank = __popcll(bal & ((1ull << l) - 1ull));
+            c.alist[(size_t)ci * c.max_n + off + rank] = n0 + j;
+        }
+        total += wc[0] + wc[1] + wc[2] + wc[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        c.acnt[ci] = total;
+        double *R = c.rs + (size_t)ci * 16;
+        R[RS_RBX] = R[RS_CX];
+        R[RS_RBY] = R[RS_CY];
+        R[RS_RBPHI] = R[RS_PHI];
+    }
+    if (threadIdx.x < kClModes) c.qrb[ci * kClModes + threadIdx.x] = c.qr[ci * kClModes + threadIdx.x];
+}
+
+// k_rc_reduce (a step, after the contact forces of the active nodes):
 // positions of the reduced state advanced, then the external nodal forces
-// (contact and walls act only on boundary nodes) reduced to the total force,
-// the torque about the centroid, the contact load and the modal force
+// (contact and walls act only on active nodes) reduced to the total force,
+// the torque about the centroid (arms from the advanced nodal positions the
+// contact forces were evaluated at), the contact load and the modal force
 // Phi^T R(-phi) f; q goes to the MLP's input
 __global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list) {
     __shared__ double red[4 * 4];
@@ -618,7 +656,8 @@ __global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list
     const int s = c.cshape[ci];
     const int n0 = c.poff[p];
     const int t0 = c.toff[s];
-    const int b0 = c.boff[s], nb = c.boff[s + 1] - b0;
+    const int na = c.acnt[ci];
+    const int *al = c.alist + (size_t)ci * c.max_n;
     double *R = c.rs + (size_t)ci * 16;
     const int tid = threadIdx.x;
     if (tid < kClModes) {
@@ -642,13 +681,10 @@ __global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list
     __syncthreads();
     const double cp = cos(Rg[2]), sp = sin(Rg[2]);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = tid; b < nb; b += 256) {
-        const int j = c.bnd[b0 + b];
-        const int i = n0 + j;
+    for (int b = tid; b < na; b += 256) {
+        const int i = al[b];
         const double fx = a.cl_fx[i], fy = a.cl_fy[i];
-        double zx, zy, wx, wy, bx, by;
-        rc_body(c, t0 + j, Q, nullptr, nullptr, zx, zy, wx, wy, bx, by);
-        const double Yx = cp * zx - sp * zy, Yy = sp * zx + cp * zy;
+        const double Yx = (a.x[i] + a.ux_o[i]) - Rg[0], Yy = (a.y[i] + a.uy_o[i]) - Rg[1];
         v[0] += fx;
         v[1] += fy;
         v[2] += Yx * fy - Yy * fx;
@@ -659,8 +695,8 @@ __global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list
     block_sum<4>(v, red);  // (syncs, so FB is complete afterwards)
     const int k = tid & 31, pt = tid >> 5;
     double g = 0.0;
-    for (int b = pt; b < nb; b += 8) {
-        const int t = t0 + c.bnd[b0 + b];
+    for (int b = pt; b < na; b += 8) {
+        const int t = t0 + (al[b] - n0);
         const float fx = c.phi[((size_t)t * kClModes + k) * 2];
         const float fy = c.phi[((size_t)t * kClModes + k) * 2 + 1];
         g += (double)fx * FB[0][b] + (double)fy * FB[1][b];
@@ -700,8 +736,10 @@ __global__ __launch_bounds__(256) void k_rc_reduce(DevArgs a, ClArgs c, int list
 
 // k_rc_update (the end of a step): accelerations and rates of the reduced
 // state (F/M + g, tau/I, the closure's modal force plus the external one),
-// the gate, and the reconstruction of the boundary nodes (every node of a
-// particle that leaves the closure) into the step's output state
+// the gate, the reconstruction of the active nodes (every node of a particle
+// that leaves the closure) into the step's output state, and the bound on
+// every node's motion since the last list rebuild (the particle's next
+// position against its rebuild one, through centroid, angle and modes)
 __global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list) {
     __shared__ double Q[3][kClModes];
     __shared__ double Rn[16];
@@ -714,9 +752,11 @@ __global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list
     const int s = c.cshape[ci];
     const int n0 = c.poff[p], n = c.poff[p + 1] - n0;
     const int t0 = c.toff[s];
-    const int b0 = c.boff[s], nb = c.boff[s + 1] - b0;
+    const int na = c.acnt[ci];
+    const int *al = c.alist + (size_t)ci * c.max_n;
     double *R = c.rs + (size_t)ci * 16;
     const int tid = threadIdx.x;
+    __shared__ double mb[2];
     if (tid < kClModes) {
         const int k = tid;
         const double q = c.qr[ci * kClModes + k];
@@ -728,6 +768,19 @@ __global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list
         Q[0][k] = q;
         Q[1][k] = qv;
         Q[2][k] = qa;
+        // the modal part of the motion bound, at the next step's amplitudes
+        const double pm = c.phimax[s * kClModes + k];
+        const double qb = c.qrb[ci * kClModes + k];
+        double dq = fabs(((q + a.dt * qv) + a.hdt2 * qa) - qb) * pm;
+        double zq = fabs(qb) * pm;
+        for (int o = 16; o > 0; o >>= 1) {
+            dq += __shfl_xor(dq, o, 32);
+            zq += __shfl_xor(zq, o, 32);
+        }
+        if (k == 0) {
+            mb[0] = dq;
+            mb[1] = zq;
+        }
     } else if (tid == kClModes) {
         const double M = RR[R_M];
         const double ax = RR[R_FX] / M + a.gx, ay = RR[R_FY] / M + a.gy;
@@ -756,19 +809,28 @@ __global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list
     }
     __syncthreads();
     const RcRigid r = rc_rigid(Rn);
-    const int cnt = fb ? n : nb;
+    const int cnt = fb ? n : na;
     int st = 0, stale = 0;
     for (int b = tid; b < cnt; b += 256) {
-        const int j = fb ? b : c.bnd[b0 + b];
-        const int i = n0 + j;
-        st |= rc_write(a, c, i, t0 + j, r, Q[0], Q[1], Q[2], a.ux_o, a.uy_o, a.vx_o, a.vy_o,
-                       a.ax_o, a.ay_o);
-        if (list) {
+        const int i = fb ? n0 + b : al[b];
+        st |= rc_write(a, c, i, t0 + (i - n0), r, Q[0], Q[1], Q[2], a.ux_o, a.uy_o, a.vx_o,
+                       a.vy_o, a.ax_o, a.ay_o);
+        if (list && fb) {  // a particle leaving the closure: its nodes' own check
             const double unx = (a.ux_o[i] + a.dt * a.vx_o[i]) + a.hdt2 * a.ax_o[i];
             const double uny = (a.uy_o[i] + a.dt * a.vy_o[i]) + a.hdt2 * a.ay_o[i];
             const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
             if (!(ex * ex + ey * ey <= a.move2)) stale = 1;
         }
+    }
+    if (list && !fb && tid == 0) {
+        // |c' - c_rb| + |phi' - phi_rb| (r_max + sum |q_rb| phimax) + sum |q' - q_rb| phimax
+        // bounds every node's displacement since the rebuild, at the next step
+        const double cx = (Rn[RS_CX] + a.dt * Rn[RS_VX]) + a.hdt2 * Rn[RS_AX];
+        const double cy = (Rn[RS_CY] + a.dt * Rn[RS_VY]) + a.hdt2 * Rn[RS_AY];
+        const double ph = (Rn[RS_PHI] + a.dt * Rn[RS_OM]) + a.hdt2 * Rn[RS_AL];
+        const double B = hypot(cx - R[RS_RBX], cy - R[RS_RBY]) +
+                         fabs(ph - R[RS_RBPHI]) * (c.rmax[s] + mb[1]) + mb[0];
+        if (!(B * B <= a.move2)) stale = 1;
     }
     if (st) atomicOr(a.status, st);
     if (__syncthreads_or(stale) && tid == 0) {
@@ -1177,7 +1239,8 @@ hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStre
 }
 
 static bool rc_ready(const DevArgs &a, const ClArgs &c) {
-    return a.cl_on && c.rs && c.qr && c.qv && c.qa && c.bnd && c.boff && c.Mt && c.I0 && c.bvec;
+    return a.cl_on && c.rs && c.qr && c.qv && c.qa && c.qrb && c.alist && c.acnt && c.Mt && c.I0 &&
+           c.bvec && c.phimax && c.rmax;
 }
 
 hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s) {
@@ -1191,6 +1254,13 @@ hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s) {
     if (c.Pc <= 0) return hipSuccess;
     if (!rc_ready(a, c)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rc_sync, dim3(c.Pc), dim3(256), 0, s, a, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_rc_collect(const DevArgs &a, const ClArgs &c, const uint8_t *act, hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!rc_ready(a, c) || !act) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_collect, dim3(c.Pc), dim3(256), 0, s, a, c, act);
     return hipGetLastError();
 }
 

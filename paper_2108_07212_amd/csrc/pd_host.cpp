@@ -345,7 +345,8 @@ hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
             // plain-force particles, then the closure particles' contact and walls
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1);
             if (e == hipSuccess)
-                e = c.cl.reduced ? launch_cl_contact(c.a, c.precision, c.stream, c.cl.bnode, c.cl.n_bnode)
+                e = c.cl.reduced ? launch_rc_contact(c.a, c.precision, c.cl.ca.cpart, c.cl.Pc, c.cl.alist,
+                                                     c.cl.acnt, c.cl.max_n, c.stream)
                                  : launch_cl_contact(c.a, c.precision, c.stream);
         } else {
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
@@ -475,31 +476,16 @@ pd_status rc_sync(Ctx &c) {
 
 pd_status cl_block_list(Ctx &c);
 
-// after a rebuild: a reduced particle whose interior node has contact
-// candidates (or is one) leaves the closure, with its nodes just synced
-pd_status rc_guard(Ctx &c) {
+// after a rebuild: the active nodes of every reduced particle (nodes with
+// candidates, candidates, nodes near a wall), the motion bound's origin
+pd_status rc_activate(Ctx &c) {
     ClState &L = c.cl;
     if (!(L.ready && L.mode && L.reduced)) return PD_OK;
-    HIPCHK(hipMemsetAsync(L.guard, 0, (size_t)c.P * sizeof(int), c.stream));
-    HIPCHK(launch_rc_guard(c.a, L.inner, L.guard, c.stream));
-    std::vector<int> g(c.P), on(c.P);
-    HIPCHK(hipMemcpyAsync(g.data(), L.guard, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipMemcpyAsync(on.data(), L.on, c.P * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
-    unsigned long long n = 0;
-    for (int p = 0; p < c.P; ++p)
-        if (g[p] && on[p]) {
-            on[p] = 0;
-            ++n;
-        }
-    if (n == 0) return PD_OK;
-    unsigned long long fb = 0;
-    HIPCHK(hipMemcpyAsync(&fb, L.fallbacks, sizeof fb, hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
-    fb += n;
-    HIPCHK(hipMemcpyAsync(L.fallbacks, &fb, sizeof fb, hipMemcpyHostToDevice, c.stream));
-    HIPCHK(hipMemcpyAsync(L.on, on.data(), c.P * sizeof(int), hipMemcpyHostToDevice, c.stream));
-    TRY(cl_block_list(c));
+    set_state_ptrs(c, c.cur);
+    HIPCHK(hipMemsetAsync(L.act, 0, (size_t)c.N, c.stream));
+    HIPCHK(launch_rc_mark(c.a, L.act, (double)(c.step + 1) * c.a.dt, c.stream));
+    HIPCHK(launch_rc_collect(c.a, L.ca, L.act, c.stream));
+    L.rb_step = c.step;
     return PD_OK;
 }
 
@@ -527,7 +513,7 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
         if (over == 0) {
             c.list_valid = true;
             ++c.rebuilds;
-            return rc_guard(c);
+            return rc_activate(c);
         }
         int m = c.a.maxc;
         while (m < over) m *= 2;
@@ -550,6 +536,16 @@ pd_status step_lists(Ctx &c, int64_t n) {
             TRY(closure_check(c));
             c.cl.last_check_step = c.step;
         }
+        // reduced closure: the moving top wall may approach a node that is not
+        // active by at most half the skin between rebuilds
+        int64_t n_wall = 0;
+        if (c.cl.mode && c.cl.reduced) {
+            double vmax = 0.0;
+            for (double v : c.h_vtop) vmax = std::max(vmax, fabs(v));
+            const double skin = sqrt(c.a.Rl2) - c.a.Rc;
+            if (vmax > 0.0) n_wall = std::max<int64_t>(1, (int64_t)floor(0.5 * skin / (vmax * c.a.dt)));
+            if (n_wall > 0 && c.step - c.cl.rb_step >= n_wall) c.list_valid = false;
+        }
         if (!c.list_valid) TRY(rebuild_lists(c));
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
@@ -557,6 +553,7 @@ pd_status step_lists(Ctx &c, int64_t n) {
         int64_t lim = std::min<int64_t>(left, kChunk);
         if (c.cl.mode && c.cl.check_every > 0)
             lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
+        if (n_wall > 0) lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - c.cl.rb_step)));
         const int chunk = (int)lim;
         if (c.tune.use_graph && chunk == kChunk) {
             TRY(ensure_list_graph(c));
@@ -669,14 +666,19 @@ pd_status upload_shape_modes(Ctx &c, int s) {
                           hipMemcpyHostToDevice, c.stream));
     // reduced mode: b_k = sum m X . phi_k with the modes as the kernels hold
     // them, so that the polar moment is I0 + 2 b.q + q.q
-    if (L.bvec) {
+    // and phimax_k = max_i |phi_k(i)|, for the bound on the motion
+    if (L.bvec && L.phimax) {
         const int t0 = L.h_toff[s], m0 = c.h_poff[L.h_shape_first[s]];
-        std::vector<double> b(kClModes, 0.0);
+        std::vector<double> b(kClModes, 0.0), pm(kClModes, 0.0);
         for (int k = 0; k < kClModes; ++k)
-            for (int i = 0; i < n; ++i)
-                b[k] += c.h_mass[m0 + i] * (L.h_tX[t0 + i] * (double)f[((size_t)i * kClModes + k) * 2] +
-                                             L.h_tY[t0 + i] * (double)f[((size_t)i * kClModes + k) * 2 + 1]);
+            for (int i = 0; i < n; ++i) {
+                const double fx = f[((size_t)i * kClModes + k) * 2], fy = f[((size_t)i * kClModes + k) * 2 + 1];
+                b[k] += c.h_mass[m0 + i] * (L.h_tX[t0 + i] * fx + L.h_tY[t0 + i] * fy);
+                pm[k] = std::max(pm[k], sqrt(fx * fx + fy * fy));
+            }
         HIPCHK(hipMemcpyAsync(L.bvec + s * kClModes, b.data(), kClModes * sizeof(double),
+                              hipMemcpyHostToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(L.phimax + s * kClModes, pm.data(), kClModes * sizeof(double),
                               hipMemcpyHostToDevice, c.stream));
     }
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -847,63 +849,39 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     L.h_tY = tY;
     TRY(upload(c, &L.tX, tX.data(), tX.size()));
     TRY(upload(c, &L.tY, tY.data(), tY.size()));
-    // reduced mode: a template node is interior when every other template node
-    // that a lattice could put within 4 R_c of it is there (its count of nodes
-    // within 4 R_c is the template's largest); the rest are boundary nodes,
-    // the only ones a step reconstructs.  Differences of reference positions,
-    // no contraction: the same set as the oracle's.
+    // reduced mode: per-shape mass, polar moment and size; buffers of the
+    // reduced state and of the active node lists
     {
-        const double Db = 4.0 * c.a.Rc, D2 = Db * Db;
-        std::vector<int> boff(1, 0), bnd, bnode;
-        std::vector<uint8_t> inner(c.N, 0);
-        L.h_bnd.assign(S, {});
-        std::vector<double> Mt(S), I0(S);
+        std::vector<double> Mt(S), I0(S), rmax(S);
         for (int s = 0; s < S; ++s) {
             const int pt = L.h_shape_first[s];
             const int n0 = c.h_poff[pt], n = L.h_shape_n[s];
-            std::vector<int> cnt(n, 0);
-            for (int j = 0; j < n; ++j)
-                for (int i = 0; i < n; ++i) {
-                    if (i == j) continue;
-                    const double dx = c.h_x[n0 + i] - c.h_x[n0 + j], dy = c.h_y[n0 + i] - c.h_y[n0 + j];
-                    if (dx * dx + dy * dy < D2) ++cnt[j];
-                }
-            const int full = *std::max_element(cnt.begin(), cnt.end());
-            for (int j = 0; j < n; ++j)
-                if (cnt[j] < full) L.h_bnd[s].push_back(j);
-            bnd.insert(bnd.end(), L.h_bnd[s].begin(), L.h_bnd[s].end());
-            boff.push_back((int)bnd.size());
-            double M = 0.0, I = 0.0;
+            double M = 0.0, I = 0.0, r = 0.0;
             for (int i = 0; i < n; ++i) {
                 const double m = c.h_mass[n0 + i];
+                const double X = tX[L.h_toff[s] + i], Y = tY[L.h_toff[s] + i];
                 M += m;
-                I += m * (tX[L.h_toff[s] + i] * tX[L.h_toff[s] + i] + tY[L.h_toff[s] + i] * tY[L.h_toff[s] + i]);
+                I += m * (X * X + Y * Y);
+                r = std::max(r, sqrt(X * X + Y * Y));
             }
             Mt[s] = M;
             I0[s] = I;
+            rmax[s] = r;
         }
-        for (int k = 0; k < L.Pc; ++k) {
-            const int p = L.h_cpart[k], s = L.h_cshape[k];
-            const int n0 = c.h_poff[p], n = L.h_shape_n[s];
-            for (int j = 0; j < n; ++j) inner[n0 + j] = 1;
-            for (int j : L.h_bnd[s]) {
-                inner[n0 + j] = 0;
-                bnode.push_back(n0 + j);
-            }
-        }
-        TRY(upload(c, &L.bnd, bnd.data(), std::max<size_t>(bnd.size(), 1)));
-        TRY(upload(c, &L.boff, boff.data(), boff.size()));
-        TRY(upload(c, &L.bnode, bnode.data(), std::max<size_t>(bnode.size(), 1)));
-        L.n_bnode = (int)bnode.size();
-        TRY(upload(c, &L.inner, inner.data(), (size_t)c.N));
         TRY(upload(c, &L.Mt, Mt.data(), S));
         TRY(upload(c, &L.I0, I0.data(), S));
+        TRY(upload(c, &L.rmax, rmax.data(), S));
         TRY(dalloc(c, &L.bvec, (size_t)S * kClModes));
-        TRY(dalloc(c, &L.guard, (size_t)c.P));
+        TRY(dalloc(c, &L.phimax, (size_t)S * kClModes));
         TRY(dalloc(c, &L.rs, Pc * 16));
         TRY(dalloc(c, &L.qr, Pc * kClModes));
         TRY(dalloc(c, &L.qv, Pc * kClModes));
         TRY(dalloc(c, &L.qa, Pc * kClModes));
+        TRY(dalloc(c, &L.qrb, Pc * kClModes));
+        TRY(dalloc(c, &L.alist, Pc * (size_t)L.max_n));
+        TRY(dalloc(c, &L.acnt, Pc));
+        TRY(dalloc(c, &L.act, (size_t)c.N));
+        HIPCHK(hipMemsetAsync(L.acnt, 0, Pc * sizeof(int), c.stream));
     }
     TRY(dalloc(c, &L.phi, tX.size() * 2 * kClModes));
     TRY(dalloc(c, &L.phiT, tX.size() * 2 * kClModes));
@@ -1007,11 +985,15 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     ca.qr = L.qr;
     ca.qv = L.qv;
     ca.qa = L.qa;
-    ca.bnd = L.bnd;
-    ca.boff = L.boff;
+    ca.qrb = L.qrb;
+    ca.alist = L.alist;
+    ca.acnt = L.acnt;
+    ca.max_n = L.max_n;
     ca.Mt = L.Mt;
     ca.I0 = L.I0;
     ca.bvec = L.bvec;
+    ca.phimax = L.phimax;
+    ca.rmax = L.rmax;
     MlpArgs &m = L.ma;
     m = MlpArgs{};
     m.rows = L.Pc;
@@ -2124,8 +2106,6 @@ pd_status pd_closure_enable(pd_ctx *ctx, int32_t mode) {
         return fail(c, PD_E_INVALID, "mode is 0 (off), 1 (linear) or 2 (learned), optionally | PD_CLOSURE_REDUCED");
     if (mode && !(c.tune.skin_factor > 0.0))
         return fail(c, PD_E_INVALID, "the modal closure runs with candidate lists (skin_factor > 0)");
-    if (mode && reduced && c.tune.skin_factor > 1.0)
-        return fail(c, PD_E_INVALID, "the reduced closure needs skin_factor <= 1 (boundary layer of 4 R_c)");
     ClState &L = c.cl;
     TRY(rc_sync(c));  // leaving a reduced mode: the nodes first
     HIPCHK(hipStreamSynchronize(c.stream));

@@ -126,7 +126,8 @@ enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R
 // reduced state of a closure particle (reduced mode): centroid position,
 // velocity and acceleration, rotation angle about the template orientation,
 // angular velocity and acceleration; [Pc][16]
-enum { RS_CX = 0, RS_CY, RS_VX, RS_VY, RS_AX, RS_AY, RS_PHI, RS_OM, RS_AL, RS_N };
+enum { RS_CX = 0, RS_CY, RS_VX, RS_VY, RS_AX, RS_AY, RS_PHI, RS_OM, RS_AL, RS_N,
+       RS_RBX = 10, RS_RBY, RS_RBPHI };  // centroid and angle at the last list rebuild
 
 struct ClArgs {
     int Pc;                    // closure particles (sorted by shape)
@@ -155,12 +156,17 @@ struct ClArgs {
     int *pd_blocks, *n_pd_blocks, *blk_listed;
     int block_nodes;
     // reduced mode: the particle's state is (centroid, angle, modal
-    // amplitudes) and their rates; only boundary nodes are reconstructed in a
-    // step, every node before anything reads the nodal state
+    // amplitudes) and their rates; a step handles only the particle's active
+    // nodes (listed at the last list rebuild: nodes with contact candidates,
+    // candidates of others, or within the list radius of a wall), every node
+    // is reconstructed before anything reads the nodal state
     double *rs;                // [Pc][16] RS_* entries
     double *qr, *qv, *qa;      // [Pc][32] modal amplitudes, rates, accelerations
-    const int *bnd, *boff;     // template-local boundary nodes of shape s: bnd[boff[s] .. boff[s+1])
+    double *qrb;               // [Pc][32] modal amplitudes at the last list rebuild
+    int *alist, *acnt;         // [Pc][max_n] active nodes (global index, ascending), [Pc] counts
+    int max_n;                 // stride of alist
     const double *Mt, *I0, *bvec;  // [S] mass, polar moment of the template; [S][32] sum m X . phi_k
+    const double *phimax, *rmax;   // [S][32] max_i |phi_k(i)|, [S] max_i |X_i|: the motion bound
 };
 
 // one forward pass of the MLP over `rows` rows of modal amplitudes
@@ -212,15 +218,12 @@ struct ClState {
     int max_n = 0;             // nodes of the largest closure shape
     // reduced mode
     bool reduced = false;
-    double *rs = nullptr, *qr = nullptr, *qv = nullptr, *qa = nullptr;
-    int *bnd = nullptr, *boff = nullptr;     // boundary nodes per shape (template-local)
-    int *bnode = nullptr;                    // global boundary nodes of all closure particles
-    int n_bnode = 0;
-    uint8_t *inner = nullptr;                // [N] 1: interior node of a closure particle
-    int *guard = nullptr;                    // [P] particles whose interior met a contact
-    double *Mt = nullptr, *I0 = nullptr, *bvec = nullptr;
-    std::vector<std::vector<int>> h_bnd;     // per shape, template-local boundary nodes
+    double *rs = nullptr, *qr = nullptr, *qv = nullptr, *qa = nullptr, *qrb = nullptr;
+    int *alist = nullptr, *acnt = nullptr;   // active nodes per closure particle
+    uint8_t *act = nullptr;                  // [N] active flags (rebuild time)
+    double *Mt = nullptr, *I0 = nullptr, *bvec = nullptr, *phimax = nullptr, *rmax = nullptr;
     std::vector<double> h_tX, h_tY;          // template coordinates (host copy)
+    int64_t rb_step = 0;                     // step of the last list rebuild
     std::vector<std::vector<double>> h_phi;  // per shape [n_s][2][K] (float64)
     double last_err = -1.0, last_err_linear = -1.0;
     int64_t checks = 0;
@@ -326,9 +329,10 @@ hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0);
-hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s,
-                             const int *nodes = nullptr, int n_nodes = 0);
-hipError_t launch_rc_guard(const DevArgs &a, const uint8_t *inner, int *flag, hipStream_t s);
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
+hipError_t launch_rc_contact(const DevArgs &a, int precision, const int *cpart, int Pc,
+                             const int *alist, const int *acnt, int max_n, hipStream_t s);
+hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStream_t s);
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s);
 hipError_t launch_particle_damage(const DevArgs &a, const int *poff, double *out, hipStream_t s);
@@ -347,6 +351,7 @@ hipError_t launch_cl_project(const DevArgs &a, const ClArgs &c, bool list, int m
 hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s);
 hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s);
+hipError_t launch_rc_collect(const DevArgs &a, const ClArgs &c, const uint8_t *act, hipStream_t s);
 hipError_t launch_rc_reduce(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,

@@ -1056,19 +1056,12 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     }
 }
 
-// Contact and wall forces of the nodes of particles under the modal closure
-// (list mode), one thread per node: every candidate and every wall and corner
-// region in turn.  The closure kernels integrate these nodes.
+// Contact and wall forces of a node of a particle under the modal closure
+// (list mode): every candidate and every wall and corner region in turn.
+// The closure kernels integrate these nodes.
 template <typename R>
-__global__ __launch_bounds__(256) void k_cl_contact(DevArgs a, const int *nodes, int n_nodes) {
-    const long long sprev = *a.step_base + a.chunk_k;
-    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    // every node, or only the listed ones (the boundary nodes of reduced particles)
-    if (tid >= (nodes ? n_nodes : a.N)) return;
-    const int i = nodes ? nodes[tid] : tid;
+__device__ __forceinline__ void cl_contact_node(const DevArgs &a, int i, long long sprev) {
     const int pi = a.part[i];
-    if (!a.cl_on[pi]) return;
     const double xi = a.x[i], yi = a.y[i];
     double pxi, pyi, uxi, uyi;
     advanced_pos(a, i, true, pxi, pyi, uxi, uyi);
@@ -1095,40 +1088,84 @@ __global__ __launch_bounds__(256) void k_cl_contact(DevArgs a, const int *nodes,
     if (st) atomicOr(a.status, st);
 }
 
-hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s, const int *nodes,
-                             int n_nodes) {
-    const int n = nodes ? n_nodes : a.N;
-    if (n <= 0) return hipSuccess;
+// every node of the closure particles, a thread per node
+template <typename R>
+__global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
+    const long long sprev = *a.step_base + a.chunk_k;
+    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N || !a.cl_on[a.part[i]]) return;
+    cl_contact_node<R>(a, i, sprev);
+}
+
+// reduced closure: the active nodes of each closure particle (a workgroup per
+// particle)
+template <typename R>
+__global__ __launch_bounds__(256) void k_rc_contact(DevArgs a, const int *cpart, const int *alist,
+                                                    const int *acnt, int max_n) {
+    const long long sprev = *a.step_base + a.chunk_k;
+    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    const int ci = blockIdx.x;
+    if (!a.cl_on[cpart[ci]]) return;
+    const int n = acnt[ci];
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        cl_contact_node<R>(a, alist[(size_t)ci * max_n + k], sprev);
+}
+
+hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
     if (!(a.cl_on && a.cl_fx && a.cl_fy)) return hipErrorInvalidValue;
-    const dim3 g((unsigned)((n + 255) / 256));
+    const dim3 g((unsigned)((a.N + 255) / 256));
     if (precision == PD_PREC_FP64)
-        hipLaunchKernelGGL(k_cl_contact<double>, g, dim3(256), 0, s, a, nodes, n_nodes);
+        hipLaunchKernelGGL(k_cl_contact<double>, g, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_cl_contact<float>, g, dim3(256), 0, s, a, nodes, n_nodes);
+        hipLaunchKernelGGL(k_cl_contact<float>, g, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-// After a list rebuild with reduced particles: a particle whose interior
-// node (one the steps do not reconstruct) has contact candidates, or is one,
-// is flagged; the host returns it to the plain force.
-__global__ void k_rc_guard(DevArgs a, const uint8_t *inner, int *flag) {
+hipError_t launch_rc_contact(const DevArgs &a, int precision, const int *cpart, int Pc,
+                             const int *alist, const int *acnt, int max_n, hipStream_t s) {
+    if (Pc <= 0) return hipSuccess;
+    if (!(a.cl_on && a.cl_fx && a.cl_fy && cpart && alist && acnt)) return hipErrorInvalidValue;
+    if (precision == PD_PREC_FP64)
+        hipLaunchKernelGGL(k_rc_contact<double>, dim3(Pc), dim3(256), 0, s, a, cpart, alist, acnt, max_n);
+    else
+        hipLaunchKernelGGL(k_rc_contact<float>, dim3(Pc), dim3(256), 0, s, a, cpart, alist, acnt, max_n);
+    return hipGetLastError();
+}
+
+// At a list rebuild (positions advanced as the lists were built), the active
+// nodes of closure particles: those with contact candidates, the candidates
+// of any node, and those within the list radius of a wall of their
+// aggregate.  Until the next rebuild no other node can come within R_c of
+// anything: nodes move less than half the skin between rebuilds (the lists'
+// own rule, a bound on the rigid + modal motion for reduced particles) and
+// the top wall is held to half the skin as well.
+__global__ void k_rc_mark(DevArgs a, uint8_t *act, double t_next) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const int n = a.clist_n[i];
-    if (n == 0) return;
     const int pi = a.part[i];
-    if (inner[i] && a.cl_on[pi]) flag[pi] = 1;
+    const bool mine = a.cl_on[pi] != 0;
+    const int n = a.clist_n[i];
+    if (mine) {
+        double px, py, ux, uy;
+        advanced_pos(a, i, true, px, py, ux, uy);
+        const int ag = a.pagg[pi];
+        const double *b = a.box + 4 * ag;
+        const double top = b[3] - a.vtop[ag] * t_next;
+        const double rl = sqrt(a.Rl2);
+        if (n > 0 || px - b[0] < rl || b[1] - px < rl || py - b[2] < rl || top - py < rl) act[i] = 1;
+    }
     for (int k = 0; k < n; ++k) {
         const int j = (int)a.clist[(size_t)k * a.N + i];
-        const int pj = a.part[j];
-        if (inner[j] && a.cl_on[pj]) flag[pj] = 1;
+        if (a.cl_on[a.part[j]]) act[j] = 1;
     }
 }
 
-hipError_t launch_rc_guard(const DevArgs &a, const uint8_t *inner, int *flag, hipStream_t s) {
+hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    if (!(a.cl_on && a.clist && a.clist_n && inner && flag)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rc_guard, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, inner, flag);
+    if (!(a.cl_on && a.clist && a.clist_n && act)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rc_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, act, t_next);
     return hipGetLastError();
 }
 
