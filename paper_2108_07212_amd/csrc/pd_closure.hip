@@ -1,17 +1,23 @@
 // pd_closure.hip -- kernels of the learned modal closure.
 //
-//   k_cl_project  one workgroup per closure particle: mass centroid, best-fit
+// Nodal form (every node of a closure particle integrated each step):
+//   k_cl_moments  one workgroup per closure particle: mass centroid, best-fit
 //                 rotation (weighted 2-D Procrustes about the centroid),
-//                 polar moment, angular velocity, total external force and
-//                 torque, modal amplitudes q = Phi^T M u_body and the modal
-//                 external force Phi^T f_body, and the gate quantities
-//   k_mlp_fwd     the 32 -> 256 -> 256 -> 32 SiLU MLP on 16-row blocks, one
-//                 wavefront per block, bfloat16 operands and float32
-//                 accumulation on the matrix cores (v_mfma 16x16x16 bf16),
-//                 hidden activations in LDS
-//   k_cl_apply    one workgroup per closure particle: nodal acceleration of
-//                 the rigid + modal motion, velocity-Verlet velocity update,
-//                 and the per-step gate
+//                 polar moment, angular velocity, total external force,
+//                 torque and contact load
+//   k_cl_modal,   particle blocks x 32-node slices with the slice's modes in
+//   k_cl_modal_sum  LDS: q = Phi^T M u_body and the modal external force
+//                 Phi^T f_body, then the slices summed in order
+//   k_cl_apply    nodal accelerations of the rigid + modal motion,
+//                 velocity-Verlet velocity update, the per-step gate
+// Reduced form (centroid, angle and modal amplitudes integrated directly):
+//   k_rc_init, k_rc_sync, k_rc_collect, k_rc_reduce, k_rc_update
+// Both:
+//   k_mlp_fwd     the 32 -> 256 -> 256 -> 32 SiLU MLP on 16-row blocks, eight
+//                 wavefronts splitting the columns, bfloat16 operands and
+//                 float32 accumulation on the matrix cores (v_mfma 16x16x16
+//                 bf16), hidden activations in LDS
+//   k_cl_check_part, k_cl_check_sum: the periodic check against the plain force
 //   k_gemm        strided bf16 GEMM on the matrix cores (training backward)
 //   k_mlp_loss, k_colsum, k_adam, k_mlp_init, k_batch_idx, k_norm_stats:
 //                 the rest of a training iteration
