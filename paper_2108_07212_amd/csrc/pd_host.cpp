@@ -319,10 +319,12 @@ void invalidate_graph(Ctx &c) {
 hipError_t enqueue_closure(Ctx &c, bool list) {
     if (c.cl.mode == 0) return hipSuccess;
     if (c.cl.reduced) {
-        // reduced state: advance, reduce the boundary forces, (MLP), update
-        // and reconstruct the boundary nodes
-        hipError_t e = launch_rc_reduce(c.a, c.cl.ca, list, c.stream);
-        if (e == hipSuccess && c.cl.mode == 2) e = launch_mlp_forward(c.cl.ma, c.a, list, c.stream);
+        // reduced state: contact of the active nodes, advance and reduction,
+        // then (learned) the MLP and the update, or (linear) the update in
+        // the same kernel
+        if (c.cl.mode == 1) return launch_rc_step(c.a, c.cl.ca, c.precision, list, true, c.stream);
+        hipError_t e = launch_rc_step(c.a, c.cl.ca, c.precision, list, false, c.stream);
+        if (e == hipSuccess) e = launch_mlp_forward(c.cl.ma, c.a, list, c.stream);
         if (e == hipSuccess) e = launch_rc_update(c.a, c.cl.ca, list, c.stream);
         return e;
     }
@@ -344,10 +346,8 @@ hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
         if (c.cl.mode) {
             // plain-force particles, then the closure particles' contact and walls
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1);
-            if (e == hipSuccess)
-                e = c.cl.reduced ? launch_rc_contact(c.a, c.precision, c.cl.ca.cpart, c.cl.Pc, c.cl.alist,
-                                                     c.cl.acnt, c.cl.max_n, c.stream)
-                                 : launch_cl_contact(c.a, c.precision, c.stream);
+            // (the reduced form evaluates its contact inside its step kernel)
+            if (e == hipSuccess && !c.cl.reduced) e = launch_cl_contact(c.a, c.precision, c.stream);
         } else {
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
         }

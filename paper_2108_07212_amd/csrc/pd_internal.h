@@ -330,8 +330,8 @@ int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
-hipError_t launch_rc_contact(const DevArgs &a, int precision, const int *cpart, int Pc,
-                             const int *alist, const int *acnt, int max_n, hipStream_t s);
+hipError_t launch_rc_step(const DevArgs &a, const ClArgs &c, int precision, bool list, bool fuse_update,
+                          hipStream_t s);
 hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStream_t s);
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s);
@@ -352,7 +352,6 @@ hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStre
 hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s);
 hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s);
 hipError_t launch_rc_collect(const DevArgs &a, const ClArgs &c, const uint8_t *act, hipStream_t s);
-hipError_t launch_rc_reduce(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,
                            double *stats, hipStream_t s);

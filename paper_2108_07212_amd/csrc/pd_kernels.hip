@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "pd_internal.h"
+#include "pd_closure_dev.h"
 
 namespace pd {
 
@@ -1045,12 +1046,13 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
     }
     if (SEL == 1) {
-        // slot blockIdx.x of the list of force workgroups that hold nodes
-        // under the plain force (listed at switch-on, appended by the kernels
-        // that make a particle fall back from the closure); no LDS staging,
-        // so that the workgroups past the list's end cost next to nothing
-        if ((int)blockIdx.x >= *a.n_pd_blocks) return;
-        force_block<R, MODE, LIST, SEL>(a, 0, a.pd_blocks[blockIdx.x], sprev, lds);
+        // slots blockIdx.x, + gridDim.x, ... of the list of force workgroups
+        // that hold nodes under the plain force (listed at switch-on, appended
+        // by the kernels that make a particle fall back from the closure); no
+        // LDS staging.  The list cannot grow during this launch.
+        const int nl = *a.n_pd_blocks;
+        for (int slot = blockIdx.x; slot < nl; slot += gridDim.x)
+            force_block<R, MODE, LIST, SEL>(a, 0, a.pd_blocks[slot], sprev, lds);
     } else {
         force_block<R, MODE, LIST, SEL>(a, lds_cap, blockIdx.x, sprev, lds);
     }
@@ -1098,18 +1100,26 @@ __global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
     cl_contact_node<R>(a, i, sprev);
 }
 
-// reduced closure: the active nodes of each closure particle (a workgroup per
-// particle)
+// reduced closure, one workgroup per closure particle: the contact and wall
+// forces of its active nodes, then (same workgroup) the reduction of the
+// reduced step, and with fuse_update (linear closure: nothing between) the
+// update as well
 template <typename R>
-__global__ __launch_bounds__(256) void k_rc_contact(DevArgs a, const int *cpart, const int *alist,
-                                                    const int *acnt, int max_n) {
-    const long long sprev = *a.step_base + a.chunk_k;
-    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+__global__ __launch_bounds__(256) void k_rc_step(DevArgs a, ClArgs c, int list, int fuse_update) {
+    if (replay_stale(a, list != 0)) return;
     const int ci = blockIdx.x;
-    if (!a.cl_on[cpart[ci]]) return;
-    const int n = acnt[ci];
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        cl_contact_node<R>(a, alist[(size_t)ci * max_n + k], sprev);
+    if (a.cl_on[c.cpart[ci]]) {
+        const long long sprev = *a.step_base + a.chunk_k;
+        const int n = c.acnt[ci];
+        for (int k = threadIdx.x; k < n; k += blockDim.x)
+            cl_contact_node<R>(a, c.alist[(size_t)ci * c.max_n + k], sprev);
+    }
+    __syncthreads();  // this particle's cl_fx / cl_fy and advanced positions are written
+    rc_reduce_body(a, c, list);
+    if (fuse_update) {
+        __syncthreads();
+        rc_update_body(a, c, list);
+    }
 }
 
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
@@ -1123,14 +1133,18 @@ hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rc_contact(const DevArgs &a, int precision, const int *cpart, int Pc,
-                             const int *alist, const int *acnt, int max_n, hipStream_t s) {
-    if (Pc <= 0) return hipSuccess;
-    if (!(a.cl_on && a.cl_fx && a.cl_fy && cpart && alist && acnt)) return hipErrorInvalidValue;
+hipError_t launch_rc_step(const DevArgs &a, const ClArgs &c, int precision, bool list, bool fuse_update,
+                          hipStream_t s) {
+    if (c.Pc <= 0) return hipSuccess;
+    if (!(a.cl_on && a.cl_fx && a.cl_fy && c.rs && c.qr && c.qv && c.qa && c.qrb && c.alist && c.acnt &&
+          c.Mt && c.I0 && c.bvec && c.phimax && c.rmax))
+        return hipErrorInvalidValue;
     if (precision == PD_PREC_FP64)
-        hipLaunchKernelGGL(k_rc_contact<double>, dim3(Pc), dim3(256), 0, s, a, cpart, alist, acnt, max_n);
+        hipLaunchKernelGGL(k_rc_step<double>, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0,
+                           fuse_update ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_rc_contact<float>, dim3(Pc), dim3(256), 0, s, a, cpart, alist, acnt, max_n);
+        hipLaunchKernelGGL(k_rc_step<float>, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0,
+                           fuse_update ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1548,8 +1562,11 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
         return hipErrorInvalidValue;
     const int B = a.block_nodes;  // nodes per workgroup, four lanes each
-    const size_t shm = a.use_lds ? (size_t)lds_cap * 5 * sizeof(double) : 0;
-    const dim3 g(grid_for(a.N, B)), b(4 * B);
+    // the plain-force-only launch walks its list of workgroups with a stride
+    // of at most 1024 workgroups (four per compute unit) and stages nothing
+    const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * 5 * sizeof(double) : 0;
+    const unsigned nb = (unsigned)grid_for(a.N, B);
+    const dim3 g(sel ? std::min(nb, 1024u) : nb), b(4 * B);
     if (precision == PD_PREC_FP64)
         launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel);
     else
