@@ -38,16 +38,30 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def tuning_key(t: dict) -> str:
+    return f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}"
+
+
+def parse_tuning(text: str) -> dict:
+    """'block_nodes=128,use_lds=1,skin_factor=0.5' -> dict"""
+    out = {}
+    for part in filter(None, text.split(",")):
+        k, v = part.split("=")
+        out[k.strip()] = float(v) if k.strip() in ("skin_factor", "cell_factor") else int(v)
+    return out
+
+
+def measured_traffic(kernel: str, workload: str, tuning: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source with the same nodes per
+    workgroup and LDS staging."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    e = rec.get(kernel, {}).get(workload)
+    e = rec.get(kernel, {}).get(workload, {}).get(tuning_key(tuning))
     if not e or e.get("kernel_source") != kernel_source_hash():
         return None
     return e.get("hbm_bytes_per_launch")
@@ -134,7 +148,7 @@ def precision_split(pd, W, torch, steps):
     return res
 
 
-def batched(pd, W, torch, steps):
+def batched(pd, W, torch, steps, tuning_fixed=None):
     """64 independent settling aggregates of 50-400 particles (about 6.4M
     nodes) in one problem, FP64 state and FP32 forces: steps/s of the batch,
     the roofline of its force kernel, and the time of the same 64 aggregates
@@ -143,7 +157,11 @@ def batched(pd, W, torch, steps):
     g = pd.PD(prob)
     g.step(20)
     t0 = time.perf_counter()
-    tuning = g.autotune(10)
+    if tuning_fixed:
+        g.set_tuning(**tuning_fixed)
+        tuning = g.tuning()
+    else:
+        tuning = g.autotune(10)
     t_tune = time.perf_counter() - t0
     g.step(20)
     sizes = g.sizes()
@@ -160,7 +178,8 @@ def batched(pd, W, torch, steps):
            "directed_bonds": sizes["bonds"], "steps_per_s": sps,
            "bond_interactions_per_s": sizes["bonds"] // 2 * sps,
            "force_kernel": {"mean_launch_ms": kt["force"][0], "bytes_per_launch": fb,
-                            "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS}}
+                            "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS,
+                            "traffic": measured_traffic("force", "batched_64", tuning)}}
     del g
     seq = 0.0
     sub_steps = max(20, steps // 2)
@@ -416,6 +435,9 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--impact-us", type=float, default=40.0)
+    ap.add_argument("--tuning", default="",
+                    help="fixed tuning instead of the autotuner for the headline and batched "
+                         "runs, e.g. block_nodes=128,use_lds=1,skin_factor=0.5 (profiling runs)")
     ap.add_argument("--settle-us", type=float, default=10000.0)
     ap.add_argument("--settle-every-us", type=float, default=1000.0)
     ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure",
@@ -447,7 +469,9 @@ def main():
               flush=True)
         return
     if args.workload == "batched":
-        print(json.dumps({"batched": batched(pd, W, torch, args.batched_steps)}), flush=True)
+        print(json.dumps({"batched": batched(pd, W, torch, args.batched_steps,
+                                             parse_tuning(args.tuning) if args.tuning else None)}),
+              flush=True)
         return
     if args.workload == "closure":
         print(json.dumps({"closure": closure(pd, W, torch, args.closure_steps, args.train_iters)}),
@@ -477,7 +501,10 @@ def main():
     # then the contact set evaluated from exact distances every step, over
     # the candidate lists (rebuilt by the cell-key radix sort when stale)
     g.step(min(args.warmup, 100))
-    g.autotune(50)
+    if args.tuning:
+        g.set_tuning(**parse_tuning(args.tuning))
+    else:
+        g.autotune(50)
     g.step(args.warmup)
     sps, rebuilds = timed(args.steps)
     # per-kernel mean launch time (HIP events on the library's stream)
@@ -491,7 +518,7 @@ def main():
     g.set_tuning(**tun)
     force_bytes = BYTES_PER_NODE_FORCE * N + BYTES_PER_BOND * n_dir
     achieved = force_bytes / (force_ms * 1e-3) / 1e9
-    traffic = measured_traffic("force", "settling_100")
+    traffic = measured_traffic("force", "settling_100", g.tuning())
     out = {
         "metric": "PD bond interactions/s (plain FP64, settling bed)",
         "value": n_pairs * sps,
