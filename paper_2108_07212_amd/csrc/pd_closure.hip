@@ -16,7 +16,10 @@
 //   k_mlp_fwd     the 32 -> 256 -> 256 -> 32 SiLU MLP on 16-row blocks, eight
 //                 wavefronts splitting the columns, bfloat16 operands and
 //                 float32 accumulation on the matrix cores (v_mfma 16x16x16
-//                 bf16), hidden activations in LDS
+//                 bf16), weights read in fragment order, hidden activations
+//                 in LDS
+//   k_mlp_pack    a shape's weights into that fragment order (after every
+//                 change of the weights)
 //   k_cl_check_part, k_cl_check_sum: the periodic check against the plain force
 //   k_gemm        strided bf16 GEMM on the matrix cores (training backward)
 //   k_mlp_loss, k_colsum, k_adam, k_mlp_init, k_batch_idx, k_norm_stats:
@@ -610,20 +613,26 @@ __global__ __launch_bounds__(256) void k_cl_check_sum(const double *per, int Pc,
 
 // ---------------------------------------------------------------------------
 // the MLP forward: one workgroup per 16-row block; its eight wavefronts split
-// the output columns of each layer (32 of the 256 hidden units each, all
-// weight fragments of a wave loaded before its MFMAs; the two 16-column tiles
-// of the last layer go to waves 0 and 1), and the layers meet in LDS.  MFMA operand layout (v_mfma_f32_16x16x16 bf16): lane l holds
-// A[l % 16][4 (l / 16) + t] and B[4 (l / 16) + t][l % 16], t = 0..3, and
-// receives D[4 (l / 16) + t][l % 16].
+// the output columns of each layer (32 of the 256 hidden units each; the two
+// 16-column tiles of the last layer go to waves 0 and 1), and the layers meet
+// in LDS.  The launch is latency-bound (2 000 rows are 125 workgroups), so
+// the loads are issued at the start in the order they are needed, with no
+// branch between them: the block's inputs first, then every weight fragment
+// (fragment order: 512 contiguous bytes per wavefront load) and bias of the
+// wave's three layers.  Every row of the block is computed and written,
+// also those of particles that are off (their consumers skip them; rows are
+// independent); a replay that has gone stale computes but writes nothing.
+// MFMA operand layout
+// (v_mfma_f32_16x16x16 bf16): lane l holds A[l % 16][4 (l / 16) + t] and
+// B[4 (l / 16) + t][l % 16], t = 0..3, and receives D[4 (l / 16) + t][l % 16].
 // ---------------------------------------------------------------------------
 constexpr int kMlpWaves = 8;
 
 __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a, int list) {
+    static_assert(16 * kClModes == 64 * kMlpWaves, "one input element per thread");
     __shared__ uint16_t Xs[16 * kClModes];
     __shared__ uint16_t H1[16 * kClHidden];
     __shared__ uint16_t H2[16 * kClHidden];
-    __shared__ int rows_ok[16];
-    if (list && replay_stale(a, true)) return;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int rb = blockIdx.x;
     int s = m.shape, first = 16 * rb, cnt;
@@ -634,49 +643,76 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
     } else {
         cnt = min(16, m.rows - first);
     }
-    const uint16_t *W = m.wb + (size_t)s * kClParams;
+    const uint16_t *F = m.wfr + (size_t)s * kClFrag;
     const float *Wf = m.wf + (size_t)s * kClParams;
     const int r = l & 15, kq = 4 * (l >> 4);
-    if (threadIdx.x < 16) {
-        const int rr = threadIdx.x;
-        rows_ok[rr] = rr < cnt && (!m.on || m.on[m.cpart[first + rr]]);
+    constexpr int TPW = kClHidden / 16 / kMlpWaves;  // column tiles per wave
+    // lane l's part of fragment f of a matrix
+    auto frag = [&](int base, int f) { return load4(F + base + f * kFragElems + 4 * l); };
+    // ---- this thread's input element (row, col) = (tid / 32, tid % 32) ---------
+    // (indices clamped to the block's rows, so that no load waits on a branch)
+    const int xrow = threadIdx.x / kClModes, xcol = threadIdx.x % kClModes;
+    const int xr = min(xrow, cnt - 1);
+    const double qin = m.q[(size_t)(m.idx ? m.idx[first + xr] : first + xr) * kClModes + xcol];
+    const float sq = m.sig_q[s * kClModes + xcol];
+    // ---- the wave's weights and biases --------------------------------------
+    bf16x4 w1[TPW][2], w2[TPW][16], w3[16];
+    float b1[TPW], b2[TPW];
+#pragma unroll
+    for (int jj = 0; jj < TPW; ++jj) {
+        const int n = 16 * (TPW * wv + jj) + r;
+        const int tile = TPW * wv + jj;
+        w1[jj][0] = frag(kFragW1, tile * (kClModes / 16));
+        w1[jj][1] = frag(kFragW1, tile * (kClModes / 16) + 1);
+        b1[jj] = Wf[kOffB1 + n];
     }
-    __syncthreads();
-    // normalised inputs, bfloat16
-    for (int e = threadIdx.x; e < 16 * kClModes; e += 64 * kMlpWaves) {
-        const int row = e / kClModes, col = e % kClModes;
-        float xv = 0.0f;
-        if (rows_ok[row]) {
-            const int src = m.idx ? m.idx[first + row] : first + row;
-            xv = (float)(m.q[(size_t)src * kClModes + col] / (double)m.sig_q[s * kClModes + col]);
+#pragma unroll
+    for (int jj = 0; jj < TPW; ++jj) {
+        const int n = 16 * (TPW * wv + jj) + r;
+        const int tile = TPW * wv + jj;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) w2[jj][ks] = frag(kFragW2, tile * (kClHidden / 16) + ks);
+        b2[jj] = Wf[kOffB2 + n];
+    }
+    const bool last = wv < kClModes / 16;  // waves of the last layer
+    const int n3 = 16 * (last ? wv : 0) + r;
+    float b3 = 0.0f, sr3 = 0.0f;
+    double lam3 = 0.0, q3[4] = {0.0, 0.0, 0.0, 0.0};
+    if (last) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) w3[ks] = frag(kFragW3, wv * (kClHidden / 16) + ks);
+        b3 = Wf[kOffB3 + n3];
+        if (m.g) {
+            lam3 = m.lam[s * kClModes + n3];
+            sr3 = m.sig_r[s * kClModes + n3];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = min(kq + t, cnt - 1);
+                q3[t] = m.q[(size_t)(m.idx ? m.idx[first + row] : first + row) * kClModes + n3];
+            }
         }
+    }
+    // ---- inputs, bfloat16 -----------------------------------------------------
+    {
+        const float xv = xrow < cnt ? (float)(qin / (double)sq) : 0.0f;  // padding rows: 0
         const uint16_t b = f2bf(xv);
-        Xs[e] = b;
-        if (m.xb && row < cnt) m.xb[(size_t)(first + row) * kClModes + col] = b;
+        Xs[threadIdx.x] = b;
+        if (m.xb && xrow < cnt) m.xb[(size_t)(first + xrow) * kClModes + xcol] = b;
     }
     __syncthreads();
     // ---- layer 1: x (16 x 32) W1^T, columns 32 wv .. 32 wv + 31 -----------------
-    constexpr int TPW = kClHidden / 16 / kMlpWaves;  // column tiles per wave
     {
         const bf16x4 a0 = load4(Xs + r * kClModes + kq), a1 = load4(Xs + r * kClModes + 16 + kq);
-        bf16x4 bw[TPW][2];
-#pragma unroll
-        for (int jj = 0; jj < TPW; ++jj) {
-            const int n = 16 * (TPW * wv + jj) + r;
-            bw[jj][0] = load4(W + kOffW1 + n * kClModes + kq);
-            bw[jj][1] = load4(W + kOffW1 + n * kClModes + 16 + kq);
-        }
 #pragma unroll
         for (int jj = 0; jj < TPW; ++jj) {
             const int n = 16 * (TPW * wv + jj) + r;
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, bw[jj][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, bw[jj][1], acc, 0, 0, 0);
-            const float bias = Wf[kOffB1 + n];
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, w1[jj][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, w1[jj][1], acc, 0, 0, 0);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int row = kq + t;
-                const float z = acc[t] + bias;
+                const float z = acc[t] + b1[jj];
                 const uint16_t h = f2bf(silu_f(z));
                 H1[row * kClHidden + n] = h;
                 if (m.z1 && row < cnt) {
@@ -689,13 +725,6 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
     __syncthreads();
     // ---- layer 2: h1 (16 x 256) W2^T, columns 32 wv .. 32 wv + 31 ---------------
     {
-        bf16x4 bw[TPW][16];
-#pragma unroll
-        for (int jj = 0; jj < TPW; ++jj) {
-            const uint16_t *wr = W + kOffW2 + (size_t)(16 * (TPW * wv + jj) + r) * kClHidden + kq;
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) bw[jj][ks] = load4(wr + 16 * ks);
-        }
         bf16x4 ah[16];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H1 + r * kClHidden + 16 * ks + kq);
@@ -705,12 +734,11 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], bw[jj][ks], acc, 0, 0, 0);
-            const float bias = Wf[kOffB2 + n];
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], w2[jj][ks], acc, 0, 0, 0);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int row = kq + t;
-                const float z = acc[t] + bias;
+                const float z = acc[t] + b2[jj];
                 const uint16_t h = f2bf(silu_f(z));
                 H2[row * kClHidden + n] = h;
                 if (m.z2 && row < cnt) {
@@ -722,32 +750,23 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
     }
     __syncthreads();
     // ---- layer 3: h2 (16 x 256) W3^T, column tile wv (waves 0 and 1) -----------
-    if (wv < kClModes / 16) {
-        const int n = 16 * wv + r;
-        const uint16_t *wr = W + kOffW3 + (size_t)n * kClHidden + kq;
-        bf16x4 ah[16], bw[16];
+    if (last) {
+        const bool stale = list && replay_stale(a, true);
+        bf16x4 ah[16];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
-            bw[ks] = load4(wr + 16 * ks);
-        }
+        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], bw[ks], acc, 0, 0, 0);
-        const float bias = Wf[kOffB3 + n];
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], w3[ks], acc, 0, 0, 0);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int row = kq + t;
-            if (!rows_ok[row]) continue;
-            const float y = acc[t] + bias;
-            if (m.y) m.y[(size_t)(first + row) * kClModes + n] = y;
-            if (m.g) {
-                const int sr = m.idx ? m.idx[first + row] : first + row;
-                const double q = m.q[(size_t)sr * kClModes + n];
-                m.g[(size_t)(first + row) * kClModes + n] =
-                    -m.lam[s * kClModes + n] * q + (double)m.sig_r[s * kClModes + n] * (double)y;
-            }
+            if (stale || row >= cnt) continue;
+            const float y = acc[t] + b3;
+            if (m.y) m.y[(size_t)(first + row) * kClModes + n3] = y;
+            if (m.g)
+                m.g[(size_t)(first + row) * kClModes + n3] = -lam3 * q3[t] + (double)sr3 * (double)y;
         }
     }
 }
@@ -867,6 +886,24 @@ __device__ __forceinline__ double hash_u01(uint64_t seed, uint64_t i) {
 
 // W1, W2 uniform with variance 2 / (fan_in + fan_out); W3 and the biases
 // zero, so the untrained closure is the linear one
+// one shape's bfloat16 weights into fragment order (one element per thread)
+__global__ __launch_bounds__(256) void k_mlp_pack(const uint16_t *wb, uint16_t *wfr) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= kClFrag) return;
+    int off, K, f;
+    if (o < kFragW2) {
+        off = kOffW1, K = kClModes, f = (o - kFragW1) / kFragElems;
+    } else if (o < kFragW3) {
+        off = kOffW2, K = kClHidden, f = (o - kFragW2) / kFragElems;
+    } else {
+        off = kOffW3, K = kClHidden, f = (o - kFragW3) / kFragElems;
+    }
+    const int l = (o / 4) % 64, t = o % 4;
+    const int tile = f / (K / 16), ks = f % (K / 16);
+    const int n = 16 * tile + l % 16, k = 16 * ks + 4 * (l / 16) + t;
+    wfr[o] = wb[off + n * K + k];
+}
+
 __global__ void k_mlp_init(float *w, uint16_t *wb, uint64_t seed) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kClParams) return;
@@ -986,7 +1023,7 @@ hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, do
 
 hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s) {
     if (m.row_blocks <= 0) return hipSuccess;
-    if (m.on && !m.cpart) return hipErrorInvalidValue;
+    if (!m.wfr || !m.wf || !m.q) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mlp_fwd, dim3(m.row_blocks), dim3(64 * kMlpWaves), 0, s, m, a, list ? 1 : 0);
     return hipGetLastError();
 }
@@ -1018,6 +1055,11 @@ hipError_t launch_adam(float *w, uint16_t *wb, const float *g, float *m, float *
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
     hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, wb, g, m, v, n, lr, b1, b2,
                        eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack(const uint16_t *wb, uint16_t *wfr, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3(kClFrag / 256), dim3(256), 0, s, wb, wfr);
     return hipGetLastError();
 }
 

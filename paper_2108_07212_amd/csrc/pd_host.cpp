@@ -927,6 +927,8 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     TRY(dalloc(c, &L.wb, (size_t)S * kClParams));
     HIPCHK(hipMemsetAsync(L.wf, 0, (size_t)S * kClParams * sizeof(float), c.stream));
     HIPCHK(hipMemsetAsync(L.wb, 0, (size_t)S * kClParams * sizeof(uint16_t), c.stream));
+    TRY(dalloc(c, &L.wfr, (size_t)S * kClFrag));
+    HIPCHK(hipMemsetAsync(L.wfr, 0, (size_t)S * kClFrag * sizeof(uint16_t), c.stream));
     std::vector<float> ones((size_t)S * kClModes, 1.0f);
     TRY(upload(c, &L.sig_q, ones.data(), ones.size()));
     TRY(upload(c, &L.sig_r, ones.data(), ones.size()));
@@ -1004,12 +1006,11 @@ pd_status closure_setup(Ctx &c, const int32_t *sp, double gate_frac, const doubl
     m.q = q;
     m.lam = L.lam;
     m.wb = L.wb;
+    m.wfr = L.wfr;
     m.wf = L.wf;
     m.sig_q = L.sig_q;
     m.sig_r = L.sig_r;
     m.g = ghat;
-    m.on = L.on;
-    m.cpart = dcpart;
     L.check_every = check_every;
     L.err_tol = err_tol;
     L.ready = true;
@@ -1086,6 +1087,7 @@ hipError_t cl_grad_batch(Ctx &c, int s, const double *q, const double *g, int ro
     m.q = q;
     m.lam = L.lam;
     m.wb = L.wb;
+    m.wfr = L.wfr;
     m.wf = L.wf;
     m.sig_q = L.sig_q;
     m.sig_r = L.sig_r;
@@ -2067,6 +2069,8 @@ pd_status pd_closure_load(pd_ctx *ctx, int32_t shape, const float *params, const
     float *w = L.wf + (size_t)shape * kClParams;
     HIPCHK(hipMemcpyAsync(w, params, kClParams * sizeof(float), hipMemcpyHostToDevice, c.stream));
     HIPCHK(launch_f32_to_bf16(w, L.wb + (size_t)shape * kClParams, kClParams, c.stream));
+    HIPCHK(launch_mlp_pack(L.wb + (size_t)shape * kClParams, L.wfr + (size_t)shape * kClFrag,
+                           c.stream));
     if (sig_q)
         HIPCHK(hipMemcpyAsync(L.sig_q + shape * kClModes, sig_q, kClModes * sizeof(float),
                               hipMemcpyHostToDevice, c.stream));
@@ -2177,6 +2181,7 @@ pd_status pd_closure_forward(pd_ctx *ctx, int32_t shape, const double *q, double
     m.q = dq;
     m.lam = L.lam;
     m.wb = L.wb;
+    m.wfr = L.wfr;
     m.wf = L.wf;
     m.sig_q = L.sig_q;
     m.sig_r = L.sig_r;
@@ -2234,7 +2239,11 @@ pd_status pd_closure_train(pd_ctx *ctx, int32_t shape, const double *q, const do
     // normalisation from the data: rms of the inputs and of the targets
     HIPCHK(launch_norm_stats(q, g, L.lam + shape * kClModes, n, L.sig_q + shape * kClModes,
                              L.sig_r + shape * kClModes, c.stream));
-    if (!L.h_trained[shape]) HIPCHK(launch_mlp_init(w, wb, seed, c.stream));
+    uint16_t *wfr = L.wfr + shape * (size_t)kClFrag;
+    if (!L.h_trained[shape]) {
+        HIPCHK(launch_mlp_init(w, wb, seed, c.stream));
+        HIPCHK(launch_mlp_pack(wb, wfr, c.stream));
+    }
     if (L.adam_t[shape] == 0) {
         HIPCHK(hipMemsetAsync(mo, 0, P * sizeof(float), c.stream));
         HIPCHK(hipMemsetAsync(ve, 0, P * sizeof(float), c.stream));
@@ -2250,6 +2259,7 @@ pd_status pd_closure_train(pd_ctx *ctx, int32_t shape, const double *q, const do
         const float c2 = (float)(1.0 - pow((double)b2, (double)t));
         HIPCHK(launch_adam(w, wb, L.t_grad, mo, ve, kClParams, (float)lrt, b1, b2, 1e-8f, c1, c2,
                            c.stream));
+        HIPCHK(launch_mlp_pack(wb, wfr, c.stream));
     }
     if (loss_out)
         HIPCHK(hipMemcpyAsync(loss_out, dl, iters * sizeof(float), hipMemcpyDeviceToHost, c.stream));

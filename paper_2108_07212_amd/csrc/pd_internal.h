@@ -119,6 +119,16 @@ constexpr int kOffW2 = kOffB1 + kClHidden;
 constexpr int kOffB2 = kOffW2 + kClHidden * kClHidden;
 constexpr int kOffW3 = kOffB2 + kClHidden;
 constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
+// The three weight matrices again, in matrix-core fragment order (what the
+// MLP forward reads): fragment (tile, ks) of a [rows][K] matrix M is 64 lanes
+// x 4 bfloat16, lane l holding M[16 tile + l % 16][16 ks + 4 (l / 16) + t],
+// t = 0..3, so that one wavefront's operand load is 512 contiguous bytes.
+// W1 (16 x 2 fragments), W2 (16 x 16), W3 (2 x 16), back to back.
+constexpr int kFragElems = 64 * 4;
+constexpr int kFragW1 = 0;
+constexpr int kFragW2 = kFragW1 + (kClHidden / 16) * (kClModes / 16) * kFragElems;
+constexpr int kFragW3 = kFragW2 + (kClHidden / 16) * (kClHidden / 16) * kFragElems;
+constexpr int kClFrag = kFragW3 + (kClModes / 16) * (kClHidden / 16) * kFragElems;
 // per closure particle reduced quantities (red[16 * c + k])
 enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
        R_COS, R_SIN, R_ACTIVE, R_N };
@@ -181,6 +191,7 @@ struct MlpArgs {
     const double *q;           // inputs [*][32]
     const double *lam;         // [S][32]
     const uint16_t *wb;        // [S][kClParams] bfloat16 weights
+    const uint16_t *wfr;       // [S][kClFrag] the same in fragment order
     const float *wf;           // [S][kClParams] float32 weights (biases read here)
     const float *sig_q, *sig_r;  // [S][32]
     double *g;                 // out: -lambda q + sigma_r y, [rows][32] (or null)
@@ -188,8 +199,6 @@ struct MlpArgs {
     float *y;                  // [rows][32]
     uint16_t *xb, *h1, *h2;    // [rows][32], [rows][256], [rows][256]
     float *z1, *z2;            // [rows][256]
-    const int *on;             // [P] particle flags or null: rows of inactive particles are skipped
-    const int *cpart;          // [rows] particle of each row (with on)
 };
 
 struct ClState {
@@ -211,6 +220,7 @@ struct ClState {
     float *phiT = nullptr;     // [32][NT] float2
     double *tX = nullptr, *tY = nullptr;
     uint16_t *wb = nullptr;
+    uint16_t *wfr = nullptr;   // [S][kClFrag], repacked from wb after every change
     float *wf = nullptr, *sig_q = nullptr, *sig_r = nullptr;
     double *stats = nullptr;   // [4] device: sums of a check
     double *per = nullptr;     // [Pc][4] device: per-particle check results
@@ -365,6 +375,7 @@ hipError_t launch_colsum(const float *X, int rows, int cols, float *out, hipStre
 hipError_t launch_adam(float *w, uint16_t *wb, const float *g, float *m, float *v, int n, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_mlp_init(float *w, uint16_t *wb, uint64_t seed, hipStream_t s);
+hipError_t launch_mlp_pack(const uint16_t *wb, uint16_t *wfr, hipStream_t s);
 hipError_t launch_batch_idx(int *idx, int rows, int64_t n, uint64_t seed, int64_t it, hipStream_t s);
 hipError_t launch_norm_stats(const double *q, const double *g, const double *lam, int64_t n,
                              float *sig_q, float *sig_r, hipStream_t s);
