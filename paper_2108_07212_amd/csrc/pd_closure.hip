@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void k_rc_collect(DevArgs a, ClArgs c, const u
 
 // k_rc_update: the end of a reduced step after the MLP (learned closure)
 __global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list) {
-    rc_update_body(a, c, list);
+    rc_update_body(a, c, list, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

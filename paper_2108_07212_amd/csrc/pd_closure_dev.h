@@ -109,20 +109,19 @@ __device__ __forceinline__ int rc_write(const DevArgs &a, const ClArgs &c, int i
     return (isfinite(px) && isfinite(py) && isfinite(nvx) && isfinite(nvy)) ? 0 : kStNonfinite;
 }
 
-// rc_reduce_body (a step, after the contact forces of the active nodes):
-// positions of the reduced state advanced, then the external nodal forces
+// rc_reduce_body (a step of closure particle ci, one workgroup, after the
+// contact forces of its active nodes): positions of the reduced state advanced, then the external nodal forces
 // (contact and walls act only on active nodes) reduced to the total force,
 // the torque about the centroid (arms from the advanced nodal positions the
 // contact forces were evaluated at), the contact load and the modal force
 // Phi^T R(-phi) f; q goes to the MLP's input
-__device__ __forceinline__ void rc_reduce_body(const DevArgs &a, const ClArgs &c, int list) {
+__device__ __forceinline__ void rc_reduce_body(const DevArgs &a, const ClArgs &c, int list, int ci) {
     __shared__ double red[4 * 4];
     __shared__ double FB[2][kClMaxNodes];
     __shared__ double Q[kClModes];
     __shared__ double part[8][kClModes];
     __shared__ double Rg[3];
     if (replay_stale(a, list)) return;
-    const int ci = blockIdx.x;
     const int p = c.cpart[ci];
     double *RR = c.red + (size_t)ci * 16;
     if (!a.cl_on[p]) {
@@ -210,18 +209,18 @@ __device__ __forceinline__ void rc_reduce_body(const DevArgs &a, const ClArgs &c
     }
 }
 
-// rc_update_body (the end of a step): accelerations and rates of the reduced
+// rc_update_body (the end of a step of closure particle ci, one workgroup):
+// accelerations and rates of the reduced
 // state (F/M + g, tau/I, the closure's modal force plus the external one),
 // the gate, the reconstruction of the active nodes (every node of a particle
 // that leaves the closure) into the step's output state, and the bound on
 // every node's motion since the last list rebuild (the particle's next
 // position against its rebuild one, through centroid, angle and modes)
-__device__ __forceinline__ void rc_update_body(const DevArgs &a, const ClArgs &c, int list) {
+__device__ __forceinline__ void rc_update_body(const DevArgs &a, const ClArgs &c, int list, int ci) {
     __shared__ double Q[3][kClModes];
     __shared__ double Rn[16];
     __shared__ int fb;
     if (replay_stale(a, list)) return;
-    const int ci = blockIdx.x;
     const double *RR = c.red + (size_t)ci * 16;
     if (RR[R_ACTIVE] == 0.0) return;
     const int p = c.cpart[ci];

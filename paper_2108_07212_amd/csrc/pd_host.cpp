@@ -1126,7 +1126,7 @@ hipError_t cl_grad_batch(Ctx &c, int s, const double *q, const double *g, int ro
 // the force workgroups holding nodes of particles under the plain force
 pd_status cl_block_list(Ctx &c) {
     ClState &L = c.cl;
-    const int B = c.tune.block_nodes;
+    const int B = kSelBlockNodes;
     const int nb = (c.N + B - 1) / B;
     if (L.blk_cap < nb) {
         dfree(c, L.pd_blocks);
@@ -1816,7 +1816,6 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         TRY(build_grid(c, box.data()));
     }
     if (rewin) TRY(build_windows(c));
-    if (rewin && c.cl.mode) TRY(cl_block_list(c));
     invalidate_graph(c);
     return PD_OK;
 }

@@ -14,6 +14,9 @@ namespace pd {
 constexpr uint32_t kBroken = 0x80000000u;  // broken bit of a bond slot
 constexpr uint32_t kIndexMask = 0x7fffffffu;
 constexpr int kSlice = 16;                  // SELL slice height: the nodes of one wavefront (4 lanes each)
+// nodes per workgroup of the plain-force-only pass (modal closure on), whatever
+// the tuning (the unit of its workgroup list)
+constexpr int kSelBlockNodes = 64;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;

@@ -1115,10 +1115,10 @@ __global__ __launch_bounds__(256) void k_rc_step(DevArgs a, ClArgs c, int list, 
             cl_contact_node<R>(a, c.alist[(size_t)ci * c.max_n + k], sprev);
     }
     __syncthreads();  // this particle's cl_fx / cl_fy and advanced positions are written
-    rc_reduce_body(a, c, list);
+    rc_reduce_body(a, c, list, ci);
     if (fuse_update) {
         __syncthreads();
-        rc_update_body(a, c, list);
+        rc_update_body(a, c, list, ci);
     }
 }
 
@@ -1561,9 +1561,10 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     if (a.N == 0) return hipSuccess;
     if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
         return hipErrorInvalidValue;
-    const int B = a.block_nodes;  // nodes per workgroup, four lanes each
-    // the plain-force-only launch walks its list of workgroups with a stride
-    // of at most 1024 workgroups (four per compute unit) and stages nothing
+    // nodes per workgroup, four lanes each; the plain-force-only launch uses
+    // 64-node workgroups (its list's unit), walks the list with a stride of at
+    // most 1024 workgroups (four per compute unit) and stages nothing
+    const int B = sel ? kSelBlockNodes : a.block_nodes;
     const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * 5 * sizeof(double) : 0;
     const unsigned nb = (unsigned)grid_for(a.N, B);
     const dim3 g(sel ? std::min(nb, 1024u) : nb), b(4 * B);
