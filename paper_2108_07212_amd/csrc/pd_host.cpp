@@ -178,6 +178,10 @@ void set_state_ptrs(Ctx &c, int cur) {
     a.vy_o = c.V[nx][1];
     a.ax_o = c.Acc[nx][0];
     a.ay_o = c.Acc[nx][1];
+    a.unx = c.UN[cur][0];
+    a.uny = c.UN[cur][1];
+    a.unx_o = c.UN[nx][0];
+    a.uny_o = c.UN[nx][1];
 }
 
 int lds_cap(const Ctx &c) { return c.tune.use_lds ? force_lds_cap(c.max_win) : 0; }
@@ -1338,6 +1342,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
             TRY(dalloc(c, &c.U[b][d], N));
             TRY(dalloc(c, &c.V[b][d], N));
             TRY(dalloc(c, &c.Acc[b][d], N));
+            TRY(dalloc(c, &c.UN[b][d], N));
         }
     const double *init[4] = {p->u0x, p->u0y, p->v0x, p->v0y};
     double *dst[4] = {c.U[0][0], c.U[0][1], c.V[0][0], c.V[0][1]};

@@ -62,6 +62,12 @@ struct DevArgs {
     // state: read buffers (cur) and write buffers (nxt)
     const double *ux, *uy, *vx, *vy, *ax, *ay;
     double *ux_o, *uy_o, *vx_o, *vy_o, *ax_o, *ay_o;
+    // the displacement of the next position half-step, u + dt v + dt^2/2 a,
+    // as the list-mode step kernel wrote it beside the state (unx_o) and the
+    // next launch of the same replay reads it (unx) instead of evaluating it
+    // from u, v and a for the node and every partner (closure off only)
+    const double *unx, *uny;
+    double *unx_o, *uny_o;
     // contact grid
     uint32_t *keys;       // [N] cell key per node
     const uint32_t *skey; // [N] sorted keys
@@ -281,6 +287,7 @@ struct Ctx {
     // owned device buffers
     std::vector<void *> owned;
     double *U[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buf][comp]
+    double *UN[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // next displacement, [buf][comp]
     double *V[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     double *Acc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     uint32_t *keys_alt = nullptr;

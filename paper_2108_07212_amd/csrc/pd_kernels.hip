@@ -40,6 +40,20 @@ __device__ __forceinline__ void advanced_pos(const DevArgs &a, int j, bool adv, 
     py = a.y[j] + uy;
 }
 
+// the same advanced displacement and position, read from the previous launch
+// of the replay (un) or evaluated (bitwise the same value either way)
+__device__ __forceinline__ void advanced_pos_un(const DevArgs &a, int j, bool un, double &px,
+                                                double &py, double &ux, double &uy) {
+    if (un) {
+        ux = a.unx[j];
+        uy = a.uny[j];
+        px = a.x[j] + ux;
+        py = a.y[j] + uy;
+    } else {
+        advanced_pos(a, j, true, px, py, ux, uy);
+    }
+}
+
 __device__ __forceinline__ void cell_of(const DevArgs &a, int ag, double px, double py, int &cx,
                                         int &cy) {
     const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
@@ -643,7 +657,7 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                                             const double *Suy, const double *Sv, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
                                             R &fpy, int &nbrk, double &smx,
-                                            const SlotHead &h, int (&bj)[4]) {
+                                            const SlotHead &h, int (&bj)[4], bool un) {
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t base = h.base;
@@ -679,7 +693,10 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                     Vj = Sv[q];
                 } else {
                     double pxj, pyj;
-                    advanced_pos(a, j, adv, pxj, pyj, uxj, uyj);
+                    if (adv)
+                        advanced_pos_un(a, j, un, pxj, pyj, uxj, uyj);
+                    else
+                        advanced_pos(a, j, false, pxj, pyj, uxj, uyj);
                     xj = a.x[j];
                     yj = a.y[j];
                     Vj = a.vol[j];
@@ -750,7 +767,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                                                int sub, int pi, int ag, double xi, double yi,
                                                double pxi, double pyi, double vxi, double vyi,
                                                double Vi, double mi, R &fsx, R &fsy, R &fnx,
-                                               R &fny, int nc_pre = -1) {
+                                               R &fny, int nc_pre = -1, bool un = false) {
     if (LIST) {
         // candidates listed at the last rebuild (intact bonds excluded)
         // candidate j goes to lane j mod 4, in ascending j (the list is
@@ -768,7 +785,10 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                 const int j = js[t];
                 if (j < 0 || (j & 3) != sub) continue;
                 double pxj, pyj, ux, uy;
-                advanced_pos(a, j, adv, pxj, pyj, ux, uy);
+                if (adv)
+                    advanced_pos_un(a, j, un, pxj, pyj, ux, uy);
+                else
+                    advanced_pos(a, j, false, pxj, pyj, ux, uy);
                 const double ddx = pxj - pxi, ddy = pyj - pyi;
                 const double r2 = ddx * ddx + ddy * ddy;
                 if (!(r2 < a.Rc2)) continue;
@@ -838,8 +858,14 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     // staging loads (indices clamped: the loads of i >= N are discarded)
     const int ic = i < a.N ? i : a.N - 1;
     const double xi = a.x[ic], yi = a.y[ic];
+    // list-mode steps after the first of a replay (closure off) read the
+    // advanced displacements the previous launch wrote (uniform over the grid)
+    const bool un = LIST && adv && SEL == 0 && a.chunk_k > 0 && a.unx && !a.cl_on;
     double pxi, pyi, uxi, uyi;
-    advanced_pos(a, ic, adv, pxi, pyi, uxi, uyi);
+    if (adv)
+        advanced_pos_un(a, ic, un, pxi, pyi, uxi, uyi);
+    else
+        advanced_pos(a, ic, false, pxi, pyi, uxi, uyi);
     const double vxi = a.vx[ic], vyi = a.vy[ic];  // velocities of the previous step
     const double Vi = a.vol[ic], mi = a.mass[ic];
     const int pi = a.part[ic];
@@ -859,7 +885,10 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
             for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
                 const int j = lo + k;
                 double px, py, ux, uy;
-                advanced_pos(a, j, adv, px, py, ux, uy);
+                if (adv)
+                    advanced_pos_un(a, j, un, px, py, ux, uy);
+                else
+                    advanced_pos(a, j, false, px, py, ux, uy);
                 Sx[k] = a.x[j];
                 Sy[k] = a.y[j];
                 Sux[k] = ux;
@@ -895,11 +924,11 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     if constexpr (LIST) {
         if (!closure)
             staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj)
+                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un)
                    : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj);
+                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
-                                     fsx, fsy, fnx, fny, nc_pre);
+                                     fsx, fsy, fnx, fny, nc_pre, un);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
     } else {
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
@@ -907,9 +936,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
             staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj)
+                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false)
                    : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
-                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj);
+                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false);
     }
 
     // ---- combine the quad ------------------------------------------------------
@@ -1025,6 +1054,10 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                 // the next step's displacement against the one the list was built at
                 const double unx = (uxi + a.dt * vxn) + a.hdt2 * axn;
                 const double uny = (uyi + a.dt * vyn) + a.hdt2 * ayn;
+                if (a.unx_o) {  // for the next launch of the replay
+                    a.unx_o[i] = unx;
+                    a.uny_o[i] = uny;
+                }
                 const double ex = unx - ubxi, ey = uny - ubyi;
                 if (!(ex * ex + ey * ey <= a.move2))
                     atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
