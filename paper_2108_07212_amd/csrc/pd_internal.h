@@ -23,6 +23,7 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMaxLdsNodes = 1024;          // staged window limit (nodes)
+constexpr int kWin = 6;                      // doubles per staged window node: x, y, ux, uy, V, pad
 constexpr int kChunk = 64;                  // list-mode steps per graph replay
 
 // status bits raised by kernels

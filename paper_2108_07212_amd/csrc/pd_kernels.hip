@@ -652,9 +652,7 @@ __device__ __forceinline__ void slot_head(const DevArgs &a, int i, int sub, Slot
 // generic access).
 template <typename R, int MODE, bool STAGED>
 __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc, int i, int sub,
-                                            int lo, const double *Sx,
-                                            const double *Sy, const double *Sux,
-                                            const double *Suy, const double *Sv, double xi,
+                                            int lo, const double *S, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
                                             R &fpy, int &nbrk, double &smx,
                                             const SlotHead &h, int (&bj)[4], bool un) {
@@ -686,11 +684,16 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                 double xj, yj, uxj, uyj, Vj;
                 if constexpr (STAGED) {
                     const int q = j - lo;
-                    xj = Sx[q];
-                    yj = Sy[q];
-                    uxj = Sux[q];
-                    uyj = Suy[q];
-                    Vj = Sv[q];
+                    // node q of the window: (x, y), (ux, uy), (V, -) as three
+                    // aligned 16-byte LDS reads from one address
+                    const double *Sq = S + __umul24((unsigned)q, (unsigned)kWin);
+                    const double2 pxy = *reinterpret_cast<const double2 *>(Sq);
+                    const double2 puv = *reinterpret_cast<const double2 *>(Sq + 2);
+                    xj = pxy.x;
+                    yj = pxy.y;
+                    uxj = puv.x;
+                    uyj = puv.y;
+                    Vj = Sq[4];
                 } else {
                     double pxj, pyj;
                     if (adv)
@@ -845,8 +848,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
 template <typename R, int MODE, bool LIST, int SEL>
 __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int blk,
                                             long long sprev, double *lds) {
-    double *Sx = lds, *Sy = lds + lds_cap, *Sux = lds + 2 * lds_cap, *Suy = lds + 3 * lds_cap,
-           *Sv = lds + 4 * lds_cap;
+    double *S = lds;  // the window, kWin doubles per node
     constexpr bool adv = (MODE == M_STEP);
     const int sub = threadIdx.x & 3;
     const int i = blk * (blockDim.x >> 2) + (threadIdx.x >> 2);
@@ -889,11 +891,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                     advanced_pos_un(a, j, un, px, py, ux, uy);
                 else
                     advanced_pos(a, j, false, px, py, ux, uy);
-                Sx[k] = a.x[j];
-                Sy[k] = a.y[j];
-                Sux[k] = ux;
-                Suy[k] = uy;
-                Sv[k] = a.vol[j];
+                *reinterpret_cast<double2 *>(S + kWin * k) = make_double2(a.x[j], a.y[j]);
+                *reinterpret_cast<double2 *>(S + kWin * k + 2) = make_double2(ux, uy);
+                S[kWin * k + 4] = a.vol[j];
             }
         }
         __syncthreads();
@@ -923,9 +923,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     // step and the bond loop commits breaks.
     if constexpr (LIST) {
         if (!closure)
-            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, S, xi, yi, uxi,
                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un)
-                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, S, xi, yi, uxi,
                                                  uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un);
         contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
                                      fsx, fsy, fnx, fny, nc_pre, un);
@@ -935,9 +935,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                                      fsx, fsy, fnx, fny);
         wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
-            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, S, xi, yi, uxi,
                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false)
-                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, Sx, Sy, Sux, Suy, Sv, xi, yi, uxi,
+                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, S, xi, yi, uxi,
                                                  uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false);
     }
 
@@ -1598,7 +1598,7 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     // 64-node workgroups (its list's unit), walks the list with a stride of at
     // most 1024 workgroups (four per compute unit) and stages nothing
     const int B = sel ? kSelBlockNodes : a.block_nodes;
-    const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * 5 * sizeof(double) : 0;
+    const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * kWin * sizeof(double) : 0;
     const unsigned nb = (unsigned)grid_for(a.N, B);
     const dim3 g(sel ? std::min(nb, 1024u) : nb), b(4 * B);
     if (precision == PD_PREC_FP64)
