@@ -1067,6 +1067,17 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     if (st) atomicOr(a.status, st);
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup w to XCD
+// w mod 8), each XCD with its own L2.  Map them so that each XCD takes one
+// contiguous range of node blocks: neighbouring blocks share most of their
+// partner windows and contact partners, which then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int w, int nb) {
+    constexpr int kXcd = 8;
+    const int x = w % kXcd, r = w / kXcd;
+    const int q = nb / kXcd, rem = nb % kXcd;
+    return x * q + min(x, rem) + r;  // a bijection of [0, nb)
+}
+
 template <typename R, int MODE, bool LIST, int SEL = 0>
 __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     extern __shared__ double lds[];
@@ -1087,7 +1098,7 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         for (int slot = blockIdx.x; slot < nl; slot += gridDim.x)
             force_block<R, MODE, LIST, SEL>(a, 0, a.pd_blocks[slot], sprev, lds);
     } else {
-        force_block<R, MODE, LIST, SEL>(a, lds_cap, blockIdx.x, sprev, lds);
+        force_block<R, MODE, LIST, SEL>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x), sprev, lds);
     }
 }
 
