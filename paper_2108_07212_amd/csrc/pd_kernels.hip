@@ -659,25 +659,29 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t base = h.base;
-        const int W = h.W;
+        // the row width of the node's SELL-16 slice; a wavefront's 16 nodes are
+        // one slice, so it is uniform and the loop below branches on a scalar
+        const int W = __builtin_amdgcn_readfirstlane(h.W);
         const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
         const bool conic = mc.conic != 0;
         // this lane's slots k = sub + 4 t; their words are fetched in batches of
         // kBatch before any of them is used, so the loads overlap (the first
         // batch comes with the row head)
-        for (int k0 = sub; k0 < W; k0 += 4 * kBatch) {
+        for (int kb = 0; kb < W; kb += 4 * kBatch) {
+            const int k0 = kb + sub;
             uint32_t ev[kBatch];
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int k = k0 + 4 * t;
-                ev[t] = k0 == sub ? h.ev[t] : (k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken);
+                ev[t] = kb == 0 ? h.ev[t] : (k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken);
             }
             // fully unrolled, so that ev[t] is a register and not a select
-            // chain; a lane past its row's end (padding only) leaves the loop
+            // chain; the wavefront leaves at the row's end (a lane whose slot
+            // is past it holds a padding word, so it adds nothing)
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
                 const int k = k0 + 4 * t;
-                if (k >= W) break;
+                if (kb + 4 * t >= W) break;
                 const uint32_t e = ev[t];
                 const bool valid = (e & kBroken) == 0;
                 const int j = valid ? (int)e : i;
