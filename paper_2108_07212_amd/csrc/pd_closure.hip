@@ -363,7 +363,7 @@ __global__ __launch_bounds__(512) void k_cl_apply(DevArgs a, ClArgs c, int list)
         if (R[R_STRAIN] > c.gate_frac * c.s0[s] || R[R_CONTACT] > c.tau_c[s]) {
             const int p = c.cpart[first + q];
             a.cl_on[p] = 0;
-            list_particle_blocks(c, p);
+            list_particle_blocks(a, c, p);
             atomicAdd(c.fallbacks, 1ull);
         }
     }
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(256) void k_cl_check_part(DevArgs a, ClArgs c, doub
         const double scale = fmax(sqrt(n2), sqrt(q2));
         if (mx > c.gate_frac * c.s0[s] || sqrt(e2) > err_tol * scale) {
             a.cl_on[p] = 0;
-            list_particle_blocks(c, p);
+            list_particle_blocks(a, c, p);
             atomicAdd(c.fallbacks, 1ull);
         }
     }

@@ -26,11 +26,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
 }
 
 // a particle that leaves the closure: list the force workgroups holding its
-// nodes (each at most once) for the plain-force launch of the next step
-__device__ void list_particle_blocks(const ClArgs &c, int p) {
+// nodes (each at most once) for the plain-force launch of the next step; in a
+// replay without that launch, end the replay after this step (list mode)
+__device__ void list_particle_blocks(const DevArgs &a, const ClArgs &c, int p) {
     const int n0 = c.poff[p], n1 = c.poff[p + 1];
     for (int b = n0 / c.block_nodes; b <= (n1 - 1) / c.block_nodes; ++b)
         if (atomicExch(&c.blk_listed[b], 1) == 0) c.pd_blocks[atomicAdd(c.n_pd_blocks, 1)] = b;
+    if (c.stop_on_fallback) {
+        const long long sprev = *a.step_base + a.chunk_k;
+        atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
+    }
 }
 
 // list mode: a launch past the first stale step of a replay does nothing (the
@@ -277,7 +282,7 @@ __device__ __forceinline__ void rc_update_body(const DevArgs &a, const ClArgs &c
         if (RR[R_STRAIN] > c.gate_frac * c.s0[s] || RR[R_CONTACT] > c.tau_c[s]) {
             off = 1;
             a.cl_on[p] = 0;
-            list_particle_blocks(c, p);
+            list_particle_blocks(a, c, p);
             atomicAdd(c.fallbacks, 1ull);
         }
         fb = off;

@@ -310,10 +310,11 @@ void invalidate_graph(Ctx &c) {
             hipGraphExecDestroy(c.graph[k]);
             c.graph[k] = nullptr;
         }
-        if (c.lgraph[k]) {
-            hipGraphExecDestroy(c.lgraph[k]);
-            c.lgraph[k] = nullptr;
-        }
+        for (int w = 0; w < 2; ++w)
+            if (c.lgraph[w][k]) {
+                hipGraphExecDestroy(c.lgraph[w][k]);
+                c.lgraph[w][k] = nullptr;
+            }
     }
     c.graph_valid = false;
 }
@@ -342,14 +343,15 @@ hipError_t enqueue_closure(Ctx &c, bool list) {
 }
 
 // list-mode replay: n steps from buffer parity `start`
-hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
+hipError_t enqueue_list_launches(Ctx &c, int start, int n) {
     for (int k = 0; k < n; ++k) {
         set_state_ptrs(c, (start + k) & 1);
         c.a.chunk_k = k;
         hipError_t e;
         if (c.cl.mode) {
             // plain-force particles, then the closure particles' contact and walls
-            e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1);
+            e = c.cl.plain_launch ? launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 1)
+                                  : hipSuccess;
             // (the reduced form evaluates its contact inside its step kernel)
             if (e == hipSuccess && !c.cl.reduced) e = launch_cl_contact(c.a, c.precision, c.stream);
         } else {
@@ -361,6 +363,15 @@ hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
     }
     c.a.chunk_k = 0;
     return hipSuccess;
+}
+
+hipError_t enqueue_list_steps(Ctx &c, int start, int n) {
+    // (the closure kernels take their arguments by value at enqueue)
+    c.cl.ca.stop_on_fallback = (c.cl.mode && !c.cl.plain_launch) ? 1 : 0;
+    hipError_t e = enqueue_list_launches(c, start, n);
+    c.cl.ca.stop_on_fallback = 0;
+    c.a.chunk_k = 0;
+    return e;
 }
 
 pd_status capture_list_graph(Ctx &c, int start, int n, hipGraphExec_t *out) {
@@ -379,14 +390,15 @@ pd_status capture_list_graph(Ctx &c, int start, int n, hipGraphExec_t *out) {
 }
 
 pd_status ensure_list_graph(Ctx &c) {
+    hipGraphExec_t *g = c.lgraph[c.cl.plain_launch ? 1 : 0];
     for (int start = 0; start < 2; ++start)
-        if (!c.lgraph[start]) TRY(capture_list_graph(c, start, kChunk, &c.lgraph[start]));
+        if (!g[start]) TRY(capture_list_graph(c, start, kChunk, &g[start]));
     return PD_OK;
 }
 
 // a replay of n < kChunk steps (between periodic closure checks), captured once
 pd_status list_graph_n(Ctx &c, int start, int n, hipGraphExec_t *out) {
-    const long key = (long)start * 1000000L + n;
+    const long key = ((long)(c.cl.plain_launch ? 1 : 0) * 2 + start) * 1000000L + n;
     auto it = c.lgraph_n.find(key);
     if (it == c.lgraph_n.end()) {
         hipGraphExec_t g = nullptr;
@@ -551,6 +563,15 @@ pd_status step_lists(Ctx &c, int64_t n) {
             if (n_wall > 0 && c.step - c.cl.rb_step >= n_wall) c.list_valid = false;
         }
         if (!c.list_valid) TRY(rebuild_lists(c));
+        // closure on: the plain-force launch only while some particle is under
+        // the plain force (a particle leaving the closure ends a replay without it)
+        c.cl.plain_launch = true;
+        if (c.cl.mode) {
+            int npb = 1;
+            HIPCHK(hipMemcpyAsync(&npb, c.cl.n_pd_blocks, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipStreamSynchronize(c.stream));
+            c.cl.plain_launch = npb > 0;
+        }
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
                               c.stream));
@@ -561,7 +582,7 @@ pd_status step_lists(Ctx &c, int64_t n) {
         const int chunk = (int)lim;
         if (c.tune.use_graph && chunk == kChunk) {
             TRY(ensure_list_graph(c));
-            HIPCHK(hipGraphLaunch(c.lgraph[c.cur], c.stream));
+            HIPCHK(hipGraphLaunch(c.lgraph[c.cl.plain_launch ? 1 : 0][c.cur], c.stream));
         } else if (c.tune.use_graph && c.cl.mode) {
             hipGraphExec_t g = nullptr;
             TRY(list_graph_n(c, c.cur, chunk, &g));
@@ -585,6 +606,7 @@ pd_status step_lists(Ctx &c, int64_t n) {
         if (inv != ~0ull && (int64_t)inv <= c.step + 1) c.list_valid = false;
         if (st) return read_status(c);
     }
+    c.cl.plain_launch = true;
     set_state_ptrs(c, c.cur);
     TRY(set_device_step(c));
     return PD_OK;

@@ -175,6 +175,11 @@ struct ClArgs {
     // list of force workgroups with plain-force nodes, appended on fallback
     int *pd_blocks, *n_pd_blocks, *blk_listed;
     int block_nodes;
+    // 1 in replays captured without the plain-force launch (no particle was
+    // under the plain force at their start): a particle that leaves the
+    // closure ends the replay after its step, so that the next replay has
+    // that launch again
+    int stop_on_fallback;
     // reduced mode: the particle's state is (centroid, angle, modal
     // amplitudes) and their rates; a step handles only the particle's active
     // nodes (listed at the last list rebuild: nodes with contact candidates,
@@ -238,6 +243,7 @@ struct ClState {
     int max_n = 0;             // nodes of the largest closure shape
     // reduced mode
     bool reduced = false;
+    bool plain_launch = true;  // the replays being enqueued include the plain-force launch
     double *rs = nullptr, *qr = nullptr, *qv = nullptr, *qa = nullptr, *qrb = nullptr;
     int *alist = nullptr, *acnt = nullptr;   // active nodes per closure particle
     uint8_t *act = nullptr;                  // [N] active flags (rebuild time)
@@ -272,7 +278,8 @@ struct Ctx {
     pd_tuning tune{64, 1.0, 1, 1, 1.0};
     bool list_valid = false;     // candidate lists match the current state
     int64_t rebuilds = 0;
-    hipGraphExec_t lgraph[2] = {nullptr, nullptr};  // kChunk list-mode steps per parity
+    // kChunk list-mode steps, [with the plain-force launch (closure on)][parity]
+    hipGraphExec_t lgraph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::map<long, hipGraphExec_t> lgraph_n;          // shorter replays, by (parity, length)
     hipStream_t stream = nullptr;
     bool own_stream = false;
