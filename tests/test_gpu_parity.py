@@ -341,6 +341,26 @@ def test_damage_after_breaking(pdmod):
     assert nbg == nbo > 0 and np.array_equal(pg, po)
 
 
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_FP32_FORCE])
+def test_carried_displacement_is_bitwise(pdmod, prec):
+    """Launches after the first of a list-mode replay read the advanced
+    displacement the previous launch wrote; one-step replays evaluate it from
+    u, v and a every time.  Both give the same states bit for bit, with
+    contacts (a herd of particles driven together)."""
+    _say(f"case: carried displacement prec={prec}")
+    prob = _herd(_bed(10, 24, g=(0.0, -5000.0), precision=prec), 0.45, seed=24, dv=3.0)
+    long_, short = pdmod.PD(prob), pdmod.PD(prob)
+    long_.set_counting(True)
+    short.set_counting(True)
+    long_.step(160)
+    for _ in range(160):
+        short.step(1)
+    a, b = long_.get_state(), short.get_state()
+    for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
+        assert np.array_equal(a[k], b[k]), k
+    assert long_.counters()["inter"] > 0
+
+
 @pytest.mark.parametrize("skin", [1.0, 0.0])
 def test_determinism_graph_and_tuning(pdmod, skin):
     """Bitwise equal results: two runs; graph vs direct launches; every block
