@@ -1613,6 +1613,9 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     // 64-node workgroups (its list's unit), walks the list with a stride of at
     // most 1024 workgroups (four per compute unit) and stages nothing
     const int B = sel ? kSelBlockNodes : a.block_nodes;
+    // the bond loop takes a wavefront's 16 nodes to be one SELL-16 slice
+    static_assert(kSelBlockNodes % kSlice == 0, "plain-force workgroups hold whole slices");
+    if (B % kSlice != 0) return hipErrorInvalidValue;
     const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * kWin * sizeof(double) : 0;
     const unsigned nb = (unsigned)grid_for(a.N, B);
     const dim3 g(sel ? std::min(nb, 1024u) : nb), b(4 * B);
