@@ -67,23 +67,47 @@ def measured_traffic(kernel: str, workload: str, tuning: dict):
     return e.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """The host's core count and CPU model (the oracle's machine)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(prob, seconds: float, n_pairs: int):
-    """The FP64 oracle on the host cores, a bounded number of steps."""
+    """The FP64 oracle on the host cores, a bounded number of steps; then a
+    shorter single-thread run of the same steps."""
     from oracle import Oracle
+
+    def run(threads, secs):
+        o = Oracle(prob, contact_mode=1, n_threads=threads)
+        o.step(2)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            o.step(5)
+            n += 5
+            el = time.perf_counter() - t0
+            if el >= secs:
+                break
+        return n, el
+
     threads = min(os.cpu_count() or 1, 16)
-    o = Oracle(prob, contact_mode=1, n_threads=threads)
-    o.step(2)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.step(5)
-        n += 5
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    sps = n / el
+    n, el = run(threads, seconds)
+    n1, el1 = run(1, max(2.0, seconds / 3))
+    sps, sps1 = n / el, n1 / el1
     return {"value": n_pairs * sps, "unit": "bond interactions/s", "cores": threads,
             "kind": "oracle", "steps_per_s": sps,
+            "single_thread": {"value": n_pairs * sps1, "steps_per_s": sps1,
+                              "sample": f"{n1} steps, {el1:.1f} s"},
+            "host": host_cpu(),
             "sample": f"{n} steps of the same settling bed (FP64 oracle, bucket-grid contact, "
                       f"OpenMP over nodes), {el:.1f} s"}
 
@@ -507,6 +531,9 @@ def main():
         g.autotune(50)
     g.step(args.warmup)
     sps, rebuilds = timed(args.steps)
+    # the spread: five more windows of a fifth of the steps each (after the
+    # timed region, which stays the K steps above)
+    rep = sorted(timed(max(1, args.steps // 5))[0] for _ in range(5))
     # per-kernel mean launch time (HIP events on the library's stream)
     kt = g.time_kernels(args.kernel_steps)
     force_ms = kt["force"][0]
@@ -543,6 +570,9 @@ def main():
         "kernels_ms": {k: v[0] for k, v in kt.items()},
         "kernel_launches_per_step": {k: v[1] / args.kernel_steps for k, v in kt.items()},
         "list_rebuilds_per_1000_steps": 1000.0 * rebuilds / args.steps,
+        "repeats": {"n": 5, "steps_each": max(1, args.steps // 5),
+                    "steps_per_s_median": rep[2], "steps_per_s_min": rep[0],
+                    "steps_per_s_max": rep[4]},
         "every_step_search": {"value": n_pairs * sps0, "steps_per_s": sps0,
                               "note": "same step with the cell-key sort and cell search "
                                       "every step (skin 0)"},
