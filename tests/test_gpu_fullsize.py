@@ -1,0 +1,152 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times: 128 nodes per workgroup, LDS staging, candidate lists with
+skin 0.5, graph replays of 64 steps.
+
+Both start from the benchmark's inputs with seeded nodal noise added
+(displacements of 2 um, velocities of 0.05 m/s; the benchmark starts from
+rest, where every bond force is exactly zero for many steps):
+
+* The settling bed of 100 particles (30 075 nodes, 594 576 directed bonds):
+  the whole problem against the FP64 oracle -- reference bonds and contact
+  sets bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
+* The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), particles
+  also given seeded rigid velocities: aggregates never interact, so three
+  sampled aggregates (the smallest, the largest, the
+  first) are each run by the oracle alone and compared with their slice of
+  the batched run: bonds bit-exact; FP64 forces, 100-step trajectory to
+  1e-9; the FP32-force mode (the benchmark's) 100-step trajectory to 1e-5
+  (FP32 force rounding, about 3e-7 of the largest force per step, adds up
+  over the steps; measured 1e-7 to 7e-7) and, at its final state, per-term forces against
+  the oracle at that state to 2e-5, the FP32 force bar.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2108_07212_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BENCH_TUNING = dict(block_nodes=128, use_lds=1, use_graph=1, skin_factor=0.5)
+TERMS = (1, 2, 4, 8, 16)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pdmod():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2108_07212_amd import pd
+    pd.load_library()
+    return pd
+
+
+def _relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_settling_100_full_size(pdmod):
+    _say("case: settling bed, full size, benchmark tuning")
+    prob = W.perturb(W.settling(), 9, du=2e-6, dv=0.05)
+    g = pdmod.PD(prob)
+    g.set_tuning(**BENCH_TUNING)
+    o = Oracle(prob, contact_mode=1, n_threads=16)
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro) and np.array_equal(cg, co)
+    assert len(cg) == 594576
+    for t in TERMS:
+        gx, gy = g.forces(t)
+        ox, oy = o.forces(t)
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        if scale == 0.0:
+            assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0, t
+            continue
+        assert max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) <= 1e-12 * scale, t
+    assert np.abs(o.forces(1)[0]).max() > 0.0  # the noise strains the bonds
+    assert g.step(200, check=False) == o.step(200)
+    sg, so = g.get_state(), o.get_state()
+    for k in ("ux", "uy", "vx", "vy"):
+        assert _relerr(sg[k], so[k]) <= 1e-9, k
+    assert np.array_equal(sg["broken"], so["broken"])
+    cg_ = g.contacts()
+    co_ = o.contacts()
+    assert np.array_equal(cg_[0], co_[0]) and np.array_equal(cg_[1], co_[1])
+
+
+def _aggregate_ranges(prob):
+    pa = np.asarray(prob.particle_aggregate)
+    po = np.asarray(prob.particle_offset)
+    out = []
+    for a in range(prob.n_aggregates):
+        sel = np.nonzero(pa == a)[0]
+        out.append((int(po[sel[0]]), int(po[sel[-1] + 1])))
+    return out
+
+
+def test_batched_64_full_size_sampled(pdmod):
+    _say("case: 64 batched aggregates, full size, benchmark tuning, sampled aggregates")
+    prob = W.perturb(W.particle_velocities(W.batched(), 7, 3.0), 8, du=2e-6, dv=0.05)
+    ranges = _aggregate_ranges(prob)
+    sizes = [n1 - n0 for n0, n1 in ranges]
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0})
+    steps = 100
+    runs = {}
+    f32 = {}
+    for prec in (W.PREC_FP64, W.PREC_FP32_FORCE):
+        g = pdmod.PD(prob, precision=prec)
+        g.set_tuning(**BENCH_TUNING)
+        if prec == W.PREC_FP64:
+            rg, cg = g.bonds()
+        g.set_counting(True)
+        assert g.step(steps, check=False) == 0
+        runs[prec] = (g.get_state(), g.counters()["inter"])
+        if prec == W.PREC_FP32_FORCE:
+            for t in TERMS:
+                fx, fy = g.forces(t)
+                f32[t] = {a: (fx[ranges[a][0]:ranges[a][1]].copy(), fy[ranges[a][0]:ranges[a][1]].copy())
+                          for a in sample}
+        del g
+    for a in sample:
+        _say(f"  aggregate {a}: nodes {sizes[a]}")
+        n0, n1 = ranges[a]
+        sub = W.subproblem_aggregate(prob, a)
+        o = Oracle(sub, contact_mode=1, n_threads=16)
+        ro, co = o.bonds()
+        assert np.array_equal(cg[rg[n0]:rg[n1]] - n0, co), a
+        assert np.array_equal(rg[n0:n1 + 1] - rg[n0], ro), a
+        assert o.step(steps) == 0
+        so = o.get_state()
+        for prec, tol in ((W.PREC_FP64, 1e-9), (W.PREC_FP32_FORCE, 1e-5)):
+            sg = runs[prec][0]
+            for k in ("ux", "uy", "vx", "vy"):
+                e = _relerr(sg[k][n0:n1], so[k])
+                _say(f"    prec {prec} {k}: {e:.2e}")
+                assert e <= tol, (a, prec, k, e)
+            assert np.array_equal(sg["broken"][cg_slice(rg, n0, n1)], so["broken"]), (a, prec)
+        # FP32 forces at the FP32 run's own final state, against the oracle there
+        s32 = runs[W.PREC_FP32_FORCE][0]
+        st = {k: s32[k][n0:n1] for k in ("ux", "uy", "vx", "vy", "ax", "ay")}
+        st["broken"] = s32["broken"][cg_slice(rg, n0, n1)]
+        st["step"] = s32["step"]
+        o.set_state(st)
+        for t in TERMS:
+            ox, oy = o.forces(t)
+            gx, gy = f32[t][a]
+            scale = max(np.abs(ox).max(), np.abs(oy).max())
+            if scale == 0.0:
+                continue
+            e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
+            _say(f"    fp32 forces term {t}: {e:.2e}")
+            assert e < 2e-5, (a, t, e)
+        assert np.abs(f32[1][a][0]).max() > 0.0  # bond forces act
+
+
+def cg_slice(rg, n0, n1):
+    return slice(int(rg[n0]), int(rg[n1]))
