@@ -9,6 +9,8 @@ rest, where every bond force is exactly zero for many steps):
 * The settling bed of 100 particles (30 075 nodes, 594 576 directed bonds):
   the whole problem against the FP64 oracle -- reference bonds and contact
   sets bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
+* The compaction bed of 500 particles from a packed start (the FP32 / FP64
+  precision split's workload), whole against the oracle.
 * The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), particles
   also given seeded rigid velocities: aggregates never interact, so three
   sampled aggregates (the smallest, the largest, the
@@ -78,6 +80,68 @@ def test_settling_100_full_size(pdmod):
     cg_ = g.contacts()
     co_ = o.contacts()
     assert np.array_equal(cg_[0], co_[0]) and np.array_equal(cg_[1], co_[1])
+
+
+def test_compaction_500_full_size(pdmod):
+    """The precision-split workload (500 particles, about 245k nodes, packed
+    start, top wall at 0.1 m/s) in the benchmark's configuration (the
+    library's default tuning): FP64 against the oracle -- bonds and contact
+    sets bit-exact, per-term forces to 1e-12, 100 steps to 1e-9, broken bonds
+    equal.  The FP32-force mode: per-term forces against the oracle to 2e-5
+    at the start and at its own final state; its 100-step trajectory to
+    1e-3 only: this packed start amplifies any perturbation (about 2 million
+    contact evaluations in 100 steps, a third of them at the friction law's
+    stick/slip threshold) -- the FP64 oracle itself, with its start
+    accelerations perturbed by 3e-7 of their largest value, moves its
+    velocities by 1.6e-3 to 2.5e-3 in 100 steps; FP32 forces measured 1.5e-4
+    and 1.7e-4 against the oracle, displacements 2e-8."""
+    _say("case: compaction 500, full size, packed start")
+    import bench
+    prob = bench.herd(W.compaction(), 0.30)
+    prob.top_wall_speed = np.array([0.1])
+    o = Oracle(prob, contact_mode=1, n_threads=16)
+    g = pdmod.PD(prob, precision=W.PREC_FP64)
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro) and np.array_equal(cg, co)
+    for t in TERMS:
+        gx, gy = g.forces(t)
+        ox, oy = o.forces(t)
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        if scale == 0.0:
+            continue
+        assert max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) <= 1e-12 * scale, t
+    c0 = o.contacts()
+    assert len(c0[0]) > 0  # packed: contacts from the start
+    gc = g.contacts()
+    assert np.array_equal(gc[0], c0[0]) and np.array_equal(gc[1], c0[1])
+    g32 = pdmod.PD(prob, precision=W.PREC_FP32_FORCE)
+
+    def fp32_forces(label):
+        for t in TERMS:
+            gx, gy = g32.forces(t)
+            ox, oy = o.forces(t)
+            scale = max(np.abs(ox).max(), np.abs(oy).max())
+            if scale == 0.0:
+                continue
+            e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
+            _say(f"    fp32 forces {label} term {t}: {e:.2e}")
+            assert e < 2e-5, (label, t, e)
+
+    fp32_forces("start")
+    steps = 100
+    assert g.step(steps, check=False) == 0 and g32.step(steps, check=False) == 0
+    assert o.step(steps) == 0
+    so = o.get_state()
+    for gg, tol in ((g, 1e-9), (g32, 1e-3)):
+        sg = gg.get_state()
+        for k in ("ux", "uy", "vx", "vy"):
+            e = _relerr(sg[k], so[k])
+            _say(f"    {k}: {e:.2e}")
+            assert e <= tol, (k, e)
+    assert np.array_equal(g.get_state()["broken"], so["broken"])
+    o.set_state(g32.get_state())
+    fp32_forces("final")
 
 
 def _aggregate_ranges(prob):
