@@ -1,25 +1,27 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
-benchmark times: 128 nodes per workgroup, LDS staging, candidate lists with
-skin 0.5, graph replays of 64 steps.
+benchmark times for each workload (the headline and the batched run: 128
+nodes per workgroup, LDS staging, candidate lists with skin 0.5, graph
+replays of 64 steps; the precision split and the closure: the library's
+default tuning).
 
-Both start from the benchmark's inputs with seeded nodal noise added
-(displacements of 2 um, velocities of 0.05 m/s; the benchmark starts from
-rest, where every bond force is exactly zero for many steps):
-
-* The settling bed of 100 particles (30 075 nodes, 594 576 directed bonds):
-  the whole problem against the FP64 oracle -- reference bonds and contact
-  sets bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
+* The settling bed of 100 particles (30 075 nodes, 594 576 directed bonds),
+  with seeded nodal noise (displacements of 2 um, velocities of 0.05 m/s;
+  from rest every bond force stays exactly zero for many steps): the whole
+  problem against the FP64 oracle -- reference bonds and contact sets
+  bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
 * The compaction bed of 500 particles from a packed start (the FP32 / FP64
   precision split's workload), whole against the oracle.
-* The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), particles
-  also given seeded rigid velocities: aggregates never interact, so three
-  sampled aggregates (the smallest, the largest, the
+* The closure workload of 2 000 particles, reduced form, whole against the
+  oracle's reduced stepper.
+* The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), with the
+  same noise and seeded rigid particle velocities: aggregates never
+  interact, so three sampled aggregates (the smallest, the largest, the
   first) are each run by the oracle alone and compared with their slice of
-  the batched run: bonds bit-exact; FP64 forces, 100-step trajectory to
-  1e-9; the FP32-force mode (the benchmark's) 100-step trajectory to 1e-5
-  (FP32 force rounding, about 3e-7 of the largest force per step, adds up
-  over the steps; measured 1e-7 to 7e-7) and, at its final state, per-term forces against
-  the oracle at that state to 2e-5, the FP32 force bar.
+  the batched run: bonds bit-exact; FP64 100-step trajectory to 1e-9; the
+  FP32-force mode (the benchmark's) 100-step trajectory to 1e-5 (FP32 force
+  rounding, about 3e-7 of the largest force per step, adds up over the
+  steps; measured 1e-7 to 7e-7) and, at its final state, per-term forces
+  against the oracle at that state to 2e-5, the FP32 force bar.
 """
 import sys
 
@@ -214,3 +216,52 @@ def test_batched_64_full_size_sampled(pdmod):
 
 def cg_slice(rg, n0, n1):
     return slice(int(rg[n0]), int(rg[n1]))
+
+
+def test_closure_2000_full_size_reduced(pdmod):
+    """The closure workload (2 000 particles of four shapes, 781 500 nodes,
+    seeded rigid velocities) started in each particle's rigid + modal space,
+    reduced form, against the oracle's reduced stepper over 20 steps: the
+    linear closure to 1e-9, the learned closure with seeded network weights
+    to 1e-6 (the bars of the small-bed tests)."""
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import test_gpu_closure as TC
+    from oracle import closure as CL
+    _say("case: closure 2000 particles, full size, reduced form")
+    base = W.closure_bed(vmax=0.5)
+    o0 = Oracle(base, contact_mode=1, n_threads=16)
+    modes = TC.oracle_modes(base, o0)
+    s0 = float(o0.constants()["s0"][0])
+    del o0
+    S = len(modes)
+    steps = 20
+    learned = {s: TC.rand_params(70 + s) for s in modes}
+    for mode, tol, params in ((1, 1e-9, None), (2, 1e-6, learned)):
+        prob = TC.modal_deformation(W.closure_bed(vmax=0.5), modes, 69, (0.05, 0.3), s0)
+        sp = prob.meta["shape_of_particle"]
+        g = pdmod.PD(prob)
+        g.closure_setup(sp, gate_frac=0.5, tau_c=[TC.BIG] * S, check_every=0)
+        TC.load_modes(g, modes)
+        sq = sr = None
+        if params is not None:
+            qs = TC.initial_q(prob, modes)
+            sq = {s: np.sqrt((qs[s] ** 2).mean(0)).astype(np.float32).astype(np.float64) for s in modes}
+            sr = {s: (3e-2 * modes[s][1] * sq[s]).astype(np.float32).astype(np.float64) for s in modes}
+            for s in modes:
+                g.closure_load(s, params[s], sq[s], sr[s])
+        g.closure_enable(mode | pdmod.CLOSURE_REDUCED)
+        o = Oracle(prob, contact_mode=1, n_threads=16)
+        st = CL.ReducedStepper(o, prob, sp, modes, [s0] * S, [TC.BIG] * S, 0.5, params=params,
+                               sig_q=sq, sig_r=sr)
+        off = []
+        for _ in range(steps):
+            off += st.step()
+        assert g.step(steps, check=False) == 0
+        a, b = g.get_state(), o.get_state()
+        for k in ("ux", "uy", "vx", "vy"):
+            e = _relerr(a[k], b[k])
+            _say(f"    mode {mode} {k}: {e:.2e}")
+            assert e < tol, (mode, k, e)
+        assert g.closure_stats()["fallbacks"] == len(off)
+        del g, o, st
