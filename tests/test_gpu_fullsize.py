@@ -13,6 +13,8 @@ default tuning).
   precision split's workload), whole against the oracle.
 * The closure workload of 2 000 particles, reduced form, whole against the
   oracle's reduced stepper.
+* The notched impact at its benchmark resolution, whole against the oracle
+  through first contact and the bulk of the fractures.
 * The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), with the
   same noise and seeded rigid particle velocities: aggregates never
   interact, so three sampled aggregates (the smallest, the largest, the
@@ -265,3 +267,31 @@ def test_closure_2000_full_size_reduced(pdmod):
             assert e < tol, (mode, k, e)
         assert g.closure_stats()["fallbacks"] == len(off)
         del g, o, st
+
+
+@pytest.mark.parametrize("Gc", [135.0, 13.5])
+def test_notched_impact_full_size(pdmod, Gc):
+    """The three-particle impact at the benchmark's resolution (1 mm squares
+    of 40 x 40 nodes, 20 m/s, dt = 2 ns), whole against the oracle through
+    first contact (about step 600) and the bulk of the fractures: states to
+    1e-9 and broken flags bit-exact every 250 steps up to step 1 250, then
+    the fragment labels and the child counts from the same broken flags."""
+    from oracle import child_counts, components
+    _say(f"case: notched impact full size Gc={Gc}")
+    prob = W.notched_impact(Gc=Gc, n_side=40, dt=2e-9)
+    g, o = pdmod.PD(prob), Oracle(prob, contact_mode=1, n_threads=16)
+    row, col = o.bonds()
+    for k in range(5):
+        assert g.step(250, check=False) == o.step(250)
+        sg, so = g.get_state(), o.get_state()
+        eu = max(_relerr(sg["ux"], so["ux"]), _relerr(sg["uy"], so["uy"]))
+        ev = max(_relerr(sg["vx"], so["vx"]), _relerr(sg["vy"], so["vy"]))
+        nb = int(so["broken"].sum())
+        _say(f"    step {250 * (k + 1)}: eu={eu:.2e} ev={ev:.2e} broken={nb}")
+        assert eu <= 1e-9 and ev <= 1e-9, (k, eu, ev)
+        assert np.array_equal(sg["broken"], so["broken"]), k
+    assert nb > 1000
+    ref = components(row, col, so["broken"], prob.n_nodes)
+    lab, cnt, nc = g.fragments(min_nodes=1)
+    assert np.array_equal(lab, ref)
+    assert np.array_equal(cnt, child_counts(ref, prob.particle_offset, 1))
