@@ -130,12 +130,20 @@ __device__ __forceinline__ double orient(double ax, double ay, double bx, double
     return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
 }
 
+// A barrier segment that lies along the bond's line (both of its ends within
+// rounding of that line, e.g. a bond along the bisector ray of a cusp whose
+// vertex is the bond's end node) does not cross it properly; the signs of
+// such orientations are rounding noise and would differ between the two
+// directions of one bond.
 __device__ bool crosses_barrier(double ax, double ay, double bx, double by, const double *seg,
                                 int s0, int s1) {
+    const double lab = fabs(bx - ax) + fabs(by - ay);
     for (int s = s0; s < s1; ++s) {
         const double cx = seg[4 * s], cy = seg[4 * s + 1], dx = seg[4 * s + 2], dy = seg[4 * s + 3];
         const double o1 = orient(ax, ay, bx, by, cx, cy), o2 = orient(ax, ay, bx, by, dx, dy);
         if (!((o1 > 0.0 && o2 < 0.0) || (o1 < 0.0 && o2 > 0.0))) continue;
+        const double tol = 1e-10 * lab * (fabs(dx - cx) + fabs(dy - cy));
+        if (fabs(o1) <= tol && fabs(o2) <= tol) continue;  // collinear
         const double o3 = orient(cx, cy, dx, dy, ax, ay), o4 = orient(cx, cy, dx, dy, bx, by);
         if ((o3 > 0.0 && o4 < 0.0) || (o3 < 0.0 && o4 > 0.0)) return true;
     }

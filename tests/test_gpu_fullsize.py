@@ -15,6 +15,7 @@ default tuning).
   oracle's reduced stepper.
 * The notched impact at its benchmark resolution, whole against the oracle
   through first contact and the bulk of the fractures.
+* The four jammed shape beds of the settling study, whole against the oracle.
 * The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), with the
   same noise and seeded rigid particle velocities: aggregates never
   interact, so three sampled aggregates (the smallest, the largest, the
@@ -295,3 +296,29 @@ def test_notched_impact_full_size(pdmod, Gc):
     lab, cnt, nc = g.fragments(min_nodes=1)
     assert np.array_equal(lab, ref)
     assert np.array_equal(cnt, child_counts(ref, prob.particle_offset, 1))
+
+
+@pytest.mark.parametrize("shape", ["pdisk", "square", "plus", "ring"])
+def test_jammed_settling_full_size(pdmod, shape):
+    """The four shape beds of the benchmark (25 x 50 mm, jammed security-disk
+    start, 70k-142k nodes) with seeded rigid velocities in [-3, 3]^2 m/s plus
+    2 m/s downward and the nodal noise above: whole against the oracle over
+    300 steps, through the first contacts -- bond sets bit-exact, states to
+    1e-9, broken flags bit-exact."""
+    _say(f"case: jammed settling full size {shape}")
+    prob = W.perturb(W.particle_velocities(W.jammed_settling(shape), 9, 3.0), 10, du=2e-6, dv=0.05)
+    prob.v0y = prob.v0y - 2.0
+    g, o = pdmod.PD(prob), Oracle(prob, contact_mode=1, n_threads=16)
+    # bond sets bit-exact (the annulus's nodes lie on radial lines through the
+    # hole's vertices, so bonds run along the cusps' bisector rays)
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro) and np.array_equal(cg, co)
+    g.set_counting(True)
+    assert g.step(300, check=False) == o.step(300)
+    sg, so = g.get_state(), o.get_state()
+    eu = max(_relerr(sg["ux"], so["ux"]), _relerr(sg["uy"], so["uy"]))
+    ev = max(_relerr(sg["vx"], so["vx"]), _relerr(sg["vy"], so["vy"]))
+    _say(f"    nodes {prob.n_nodes}: eu={eu:.2e} ev={ev:.2e} contacts={g.counters()['inter']}")
+    assert eu <= 1e-9 and ev <= 1e-9, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
