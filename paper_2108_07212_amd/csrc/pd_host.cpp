@@ -580,9 +580,22 @@ pd_status step_lists(Ctx &c, int64_t n) {
             lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
         if (n_wall > 0) lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - c.cl.rb_step)));
         const int chunk = (int)lim;
+        int reps = 1;
         if (c.tune.use_graph && chunk == kChunk) {
             TRY(ensure_list_graph(c));
-            HIPCHK(hipGraphLaunch(c.lgraph[c.cl.plain_launch ? 1 : 0][c.cur], c.stream));
+            // plain steps: up to kReplaysPerSync replays per host round trip; a
+            // replay queued after one that went stale does nothing (the stale
+            // step stays recorded), and kChunk is even, so every replay starts
+            // at the same buffer parity
+            static_assert(kChunk % 2 == 0, "replays queued back to back share a parity");
+            if (!c.cl.mode) reps = (int)std::min<int64_t>(kReplaysPerSync, left / kChunk);
+            for (int r = 0; r < reps; ++r) {
+                if (r > 0)
+                    HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base,
+                                          (unsigned long long)(c.step + (int64_t)r * kChunk),
+                                          c.stream));
+                HIPCHK(hipGraphLaunch(c.lgraph[c.cl.plain_launch ? 1 : 0][c.cur], c.stream));
+            }
         } else if (c.tune.use_graph && c.cl.mode) {
             hipGraphExec_t g = nullptr;
             TRY(list_graph_n(c, c.cur, chunk, &g));
@@ -595,10 +608,11 @@ pd_status step_lists(Ctx &c, int64_t n) {
         HIPCHK(hipMemcpyAsync(&inv, c.a.invalid_step, sizeof(inv), hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipMemcpyAsync(&st, c.a.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
-        int64_t done = chunk;
+        const int64_t queued = (int64_t)chunk * reps;
+        int64_t done = queued;
         if (inv != ~0ull) {
             const int64_t lim = (int64_t)inv - 1 - c.step;  // steps that ran
-            done = std::max<int64_t>(0, std::min<int64_t>(chunk, lim));
+            done = std::max<int64_t>(0, std::min<int64_t>(queued, lim));
         }
         c.cur = (int)((c.cur + done) & 1);
         c.step += done;

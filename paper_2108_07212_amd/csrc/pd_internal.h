@@ -25,6 +25,7 @@ constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMaxLdsNodes = 1024;          // staged window limit (nodes)
 constexpr int kWin = 6;                      // doubles per staged window node: x, y, ux, uy, V, pad
 constexpr int kChunk = 64;                  // list-mode steps per graph replay
+constexpr int kReplaysPerSync = 4;          // plain replays queued per host round trip
 
 // status bits raised by kernels
 constexpr int kStEscaped = 1;
