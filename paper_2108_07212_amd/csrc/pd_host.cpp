@@ -567,10 +567,10 @@ pd_status step_lists(Ctx &c, int64_t n) {
         // the plain force (a particle leaving the closure ends a replay without it)
         c.cl.plain_launch = true;
         if (c.cl.mode) {
-            int npb = 1;
-            HIPCHK(hipMemcpyAsync(&npb, c.cl.n_pd_blocks, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipMemcpyAsync(&c.rb->npb, c.cl.n_pd_blocks, sizeof(int), hipMemcpyDeviceToHost,
+                                  c.stream));
             HIPCHK(hipStreamSynchronize(c.stream));
-            c.cl.plain_launch = npb > 0;
+            c.cl.plain_launch = c.rb->npb > 0;
         }
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
@@ -603,11 +603,12 @@ pd_status step_lists(Ctx &c, int64_t n) {
         } else {
             HIPCHK(enqueue_list_steps(c, c.cur, chunk));
         }
-        unsigned long long inv = 0;
-        int st = 0;
-        HIPCHK(hipMemcpyAsync(&inv, c.a.invalid_step, sizeof(inv), hipMemcpyDeviceToHost, c.stream));
-        HIPCHK(hipMemcpyAsync(&st, c.a.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipMemcpyAsync(&c.rb->inv, c.a.invalid_step, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipMemcpyAsync(&c.rb->st, c.a.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
+        const unsigned long long inv = c.rb->inv;
+        const int st = c.rb->st;
         const int64_t queued = (int64_t)chunk * reps;
         int64_t done = queued;
         if (inv != ~0ull) {
@@ -1227,6 +1228,7 @@ void pd_destroy(pd_ctx *ctx) {
     for (void *p : c.owned) hipFree(p);
     if (c.own_stream && c.stream) hipStreamDestroy(c.stream);
     if (c.caller_ev) hipEventDestroy(c.caller_ev);
+    if (c.rb) hipHostFree(c.rb);
     delete ctx;
 }
 
@@ -1285,6 +1287,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
         c.own_stream = true;
         HIPCHK(hipEventCreateWithFlags(&c.caller_ev, hipEventDisableTiming));
     }
+    HIPCHK(hipHostMalloc((void **)&c.rb, sizeof(Ctx::Readback), hipHostMallocDefault));
     // ---- host-side per node / particle data ----
     std::vector<int> part(N), pagg(P, 0);
     for (int q = 0; q < P; ++q) {

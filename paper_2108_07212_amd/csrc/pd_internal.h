@@ -295,6 +295,13 @@ struct Ctx {
     std::string err;
     // owned device buffers
     std::vector<void *> owned;
+    // pinned host words the step loop reads back after each round of
+    // replays: first stale step, status, plain-force workgroup count
+    struct Readback {
+        unsigned long long inv;
+        int st;
+        int npb;
+    } *rb = nullptr;
     double *U[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buf][comp]
     double *UN[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // next displacement, [buf][comp]
     double *V[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
