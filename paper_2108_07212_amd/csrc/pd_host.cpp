@@ -2013,14 +2013,17 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     const int blocks[3] = {256, 128, 64};
-    const double skins[4] = {0.0, 0.5, 1.0, 2.0};
+    // skin 0 (cell search every step) also tries cells of twice the contact
+    // radius: four times fewer cells can take a radix pass off the key sort
+    const double skins[5] = {0.0, 0.0, 0.5, 1.0, 2.0};
+    const double cells[5] = {1.0, 2.0, 1.0, 1.0, 1.0};
     pd_status result = PD_OK;
     for (int bi = 0; bi < 3 && result == PD_OK; ++bi)
-        for (int ci = 0; ci < 4 && result == PD_OK; ++ci)
+        for (int ci = 0; ci < 5 && result == PD_OK; ++ci)
             for (int li = 0; li < 2 && result == PD_OK; ++li) {
                 pd_tuning t = base;
                 t.block_nodes = blocks[bi];
-                t.cell_factor = 1.0;
+                t.cell_factor = cells[ci];
                 t.skin_factor = skins[ci];
                 t.use_lds = 1 - li;
                 if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
