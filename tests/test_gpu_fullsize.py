@@ -11,8 +11,8 @@ default tuning).
   bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
 * The compaction bed of 500 particles from a packed start (the FP32 / FP64
   precision split's workload), whole against the oracle.
-* The closure workload of 2 000 particles, reduced form, whole against the
-  oracle's reduced stepper.
+* The closure workload of 2 000 particles, reduced and nodal forms, whole
+  against the oracle's closure steppers.
 * The notched impact at its benchmark resolution, whole against the oracle
   through first contact and the bulk of the fractures.
 * The four jammed shape beds of the settling study, whole against the oracle.
@@ -224,9 +224,10 @@ def cg_slice(rg, n0, n1):
 def test_closure_2000_full_size_reduced(pdmod):
     """The closure workload (2 000 particles of four shapes, 781 500 nodes,
     seeded rigid velocities) started in each particle's rigid + modal space,
-    reduced form, against the oracle's reduced stepper over 20 steps: the
-    linear closure to 1e-9, the learned closure with seeded network weights
-    to 1e-6 (the bars of the small-bed tests)."""
+    against the oracle's closure steppers over 20 steps: the reduced form
+    with the linear closure to 1e-9 and with seeded network weights to 1e-6,
+    the nodal form with the linear closure to 1e-9 (the bars of the
+    small-bed tests)."""
     import os
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import test_gpu_closure as TC
@@ -240,7 +241,8 @@ def test_closure_2000_full_size_reduced(pdmod):
     S = len(modes)
     steps = 20
     learned = {s: TC.rand_params(70 + s) for s in modes}
-    for mode, tol, params in ((1, 1e-9, None), (2, 1e-6, learned)):
+    for reduced, mode, tol, params in ((True, 1, 1e-9, None), (True, 2, 1e-6, learned),
+                                       (False, 1, 1e-9, None)):
         prob = TC.modal_deformation(W.closure_bed(vmax=0.5), modes, 69, (0.05, 0.3), s0)
         sp = prob.meta["shape_of_particle"]
         g = pdmod.PD(prob)
@@ -253,10 +255,11 @@ def test_closure_2000_full_size_reduced(pdmod):
             sr = {s: (3e-2 * modes[s][1] * sq[s]).astype(np.float32).astype(np.float64) for s in modes}
             for s in modes:
                 g.closure_load(s, params[s], sq[s], sr[s])
-        g.closure_enable(mode | pdmod.CLOSURE_REDUCED)
+        g.closure_enable(mode | (pdmod.CLOSURE_REDUCED if reduced else 0))
         o = Oracle(prob, contact_mode=1, n_threads=16)
-        st = CL.ReducedStepper(o, prob, sp, modes, [s0] * S, [TC.BIG] * S, 0.5, params=params,
-                               sig_q=sq, sig_r=sr)
+        Stepper = CL.ReducedStepper if reduced else CL.ClosureStepper
+        st = Stepper(o, prob, sp, modes, [s0] * S, [TC.BIG] * S, 0.5, params=params,
+                     sig_q=sq, sig_r=sr)
         off = []
         for _ in range(steps):
             off += st.step()
@@ -264,7 +267,7 @@ def test_closure_2000_full_size_reduced(pdmod):
         a, b = g.get_state(), o.get_state()
         for k in ("ux", "uy", "vx", "vy"):
             e = _relerr(a[k], b[k])
-            _say(f"    mode {mode} {k}: {e:.2e}")
+            _say(f"    {'reduced' if reduced else 'nodal'} mode {mode} {k}: {e:.2e}")
             assert e < tol, (mode, k, e)
         assert g.closure_stats()["fallbacks"] == len(off)
         del g, o, st
