@@ -473,8 +473,8 @@ def main():
                     help="only run a plain 256 MiB device copy (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
-              "multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step loop has "
+              "no multi-GPU form (its sharding is a design only)", file=sys.stderr)
         sys.exit(2)
 
     import torch
