@@ -234,10 +234,17 @@ __global__ __launch_bounds__(kSortBlock) void k_hist(const uint32_t *keys, int N
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int base = blockIdx.x * kSortTile;
+    // the tile's keys, all loaded before the first count (one memory round trip)
+    uint32_t kr[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int idx = base + r * kSortBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+        kr[r] = idx < N ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int idx = base + r * kSortBlock + threadIdx.x;
+        if (idx < N) atomicAdd(&cnt[(kr[r] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     hist[threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
@@ -268,18 +275,31 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(const uint32_t *kin, con
     __shared__ uint32_t wc[4][kRadix];
     __shared__ uint32_t sh[4];
     const int t = threadIdx.x, w = t >> 6;
+    const int base = blockIdx.x * kSortTile;
+    // the tile's keys and payloads, loaded up front: the rounds below are
+    // serialised by barriers, so loads issued inside them would cost one
+    // memory round trip each
+    uint32_t kr[kSortItems];
+    int vr[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int idx = base + r * kSortBlock + t;
+        const bool valid = idx < N;
+        kr[r] = valid ? kin[idx] : 0u;
+        vr[r] = valid ? (vin ? vin[idx] : idx) : 0;
+    }
     uint32_t tot;
     const uint32_t dbase = block_excl_scan256(dtotal[t], &tot, sh);
     run[t] = dbase + hist[t * G + blockIdx.x];
     wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
     __syncthreads();
     const uint64_t lt = __lanemask_lt();
-    const int base = blockIdx.x * kSortTile;
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int idx = base + r * kSortBlock + t;
         const bool valid = idx < N;
-        const uint32_t key = valid ? kin[idx] : 0u;
-        const int val = valid ? (vin ? vin[idx] : idx) : 0;
+        const uint32_t key = kr[r];
+        const int val = vr[r];
         const uint32_t d = (key >> shift) & (kRadix - 1);
         // lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(valid);
