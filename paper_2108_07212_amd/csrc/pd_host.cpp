@@ -1471,8 +1471,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     TRY(dalloc(c, &c.skey_buf, N));
     TRY(dalloc(c, &c.perm_buf, N));
     TRY(dalloc(c, &c.perm_alt, N));
-    const int G = (N + kSortTile - 1) / kSortTile;
-    TRY(dalloc(c, &c.hist, (size_t)kRadix * G));
+    TRY(dalloc(c, &c.hist, (size_t)kRadix * sort_tiles_max(N)));
     TRY(dalloc(c, &c.dtotal, kRadix));
     a.skey = c.skey_buf;
     a.perm = c.perm_buf;

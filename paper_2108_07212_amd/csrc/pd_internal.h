@@ -20,8 +20,24 @@ constexpr int kSelBlockNodes = 64;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr int kSortItemsMax = 8;
+// Keys per thread of a radix pass: one up to 64k keys (a workgroup of 256 keys
+// each, one scatter round), more for larger sorts (at most kSortItemsMax), so
+// that the per-digit scan over tiles stays short.
+inline int sort_items(int N) {
+    const int per = (N + 65535) / 65536;
+    return per < 1 ? 1 : (per > kSortItemsMax ? kSortItemsMax : per);
+}
+inline int sort_tiles(int N) {
+    const int tile = kSortBlock * sort_items(N);
+    return (N + tile - 1) / tile;
+}
+// tiles of any sort of at most N keys (the hist buffer's size): up to 256 while
+// the items grow, then those of N itself
+inline int sort_tiles_max(int N) {
+    const int t = sort_tiles(N);
+    return t > 256 ? t : 256;
+}
 constexpr int kMaxLdsNodes = 1024;          // staged window limit (nodes)
 constexpr int kWin = 6;                      // doubles per staged window node: x, y, ux, uy, V, pad
 constexpr int kChunk = 64;                  // list-mode steps per graph replay

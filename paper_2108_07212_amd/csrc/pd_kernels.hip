@@ -229,22 +229,22 @@ __global__ void k_keys(DevArgs a, int adv) {
 // radix sort: histogram, per-digit scan over tiles, stable scatter
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortBlock) void k_hist(const uint32_t *keys, int N, int shift,
-                                                     uint32_t *hist, int G) {
+                                                     uint32_t *hist, int G, int items) {
     __shared__ uint32_t cnt[kRadix];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int base = blockIdx.x * kSortTile;
+    const int base = blockIdx.x * kSortBlock * items;
     // the tile's keys, all loaded before the first count (one memory round trip)
-    uint32_t kr[kSortItems];
+    uint32_t kr[kSortItemsMax];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kSortItemsMax; ++r) {
         const int idx = base + r * kSortBlock + threadIdx.x;
-        kr[r] = idx < N ? keys[idx] : 0u;
+        kr[r] = (r < items && idx < N) ? keys[idx] : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kSortItemsMax; ++r) {
         const int idx = base + r * kSortBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&cnt[(kr[r] >> shift) & (kRadix - 1)], 1u);
+        if (r < items && idx < N) atomicAdd(&cnt[(kr[r] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     hist[threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
@@ -270,21 +270,21 @@ __global__ __launch_bounds__(kSortBlock) void k_digit_scan(uint32_t *hist, int G
 __global__ __launch_bounds__(kSortBlock) void k_scatter(const uint32_t *kin, const int *vin,
                                                         uint32_t *kout, int *vout, int N,
                                                         int shift, const uint32_t *hist, int G,
-                                                        const uint32_t *dtotal) {
+                                                        const uint32_t *dtotal, int items) {
     __shared__ uint32_t run[kRadix];
     __shared__ uint32_t wc[4][kRadix];
     __shared__ uint32_t sh[4];
     const int t = threadIdx.x, w = t >> 6;
-    const int base = blockIdx.x * kSortTile;
+    const int base = blockIdx.x * kSortBlock * items;
     // the tile's keys and payloads, loaded up front: the rounds below are
     // serialised by barriers, so loads issued inside them would cost one
     // memory round trip each
-    uint32_t kr[kSortItems];
-    int vr[kSortItems];
+    uint32_t kr[kSortItemsMax];
+    int vr[kSortItemsMax];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kSortItemsMax; ++r) {
         const int idx = base + r * kSortBlock + t;
-        const bool valid = idx < N;
+        const bool valid = r < items && idx < N;
         kr[r] = valid ? kin[idx] : 0u;
         vr[r] = valid ? (vin ? vin[idx] : idx) : 0;
     }
@@ -295,7 +295,8 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(const uint32_t *kin, con
     __syncthreads();
     const uint64_t lt = __lanemask_lt();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kSortItemsMax; ++r) {
+        if (r >= items) break;  // uniform: a kernel argument
         const int idx = base + r * kSortBlock + t;
         const bool valid = idx < N;
         const uint32_t key = kr[r];
@@ -1593,14 +1594,14 @@ hipError_t launch_keys(const DevArgs &a, int adv, hipStream_t s) {
 hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int N,
                             int shift, uint32_t *hist, uint32_t *dtotal, hipStream_t s,
                             hipEvent_t *ev) {
-    const int G = (int)grid_for(N, kSortTile);
+    const int items = sort_items(N), G = sort_tiles(N);
     if (ev) hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_hist, dim3(G), dim3(kSortBlock), 0, s, kin, N, shift, hist, G);
+    hipLaunchKernelGGL(k_hist, dim3(G), dim3(kSortBlock), 0, s, kin, N, shift, hist, G, items);
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_digit_scan, dim3(kRadix), dim3(kSortBlock), 0, s, hist, G, dtotal);
     if (ev) hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(kSortBlock), 0, s, kin, vin, kout, vout, N, shift,
-                       hist, G, dtotal);
+                       hist, G, dtotal, items);
     if (ev) hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
