@@ -186,8 +186,9 @@ void set_state_ptrs(Ctx &c, int cur) {
 
 int lds_cap(const Ctx &c) { return c.tune.use_lds ? force_lds_cap(c.max_win) : 0; }
 
-// radix sort of c.a.keys into skey/perm
-hipError_t enqueue_sort(Ctx &c, hipEvent_t *ev) {
+// radix sort of c.a.keys into skey/perm (hist_done: the first pass's digit
+// counts are already in c.hist)
+hipError_t enqueue_sort(Ctx &c, hipEvent_t *ev, bool hist_done) {
     const int P = c.a.radix_passes;
     const uint32_t *kin = c.a.keys;
     const int *vin = nullptr;
@@ -196,7 +197,7 @@ hipError_t enqueue_sort(Ctx &c, hipEvent_t *ev) {
         uint32_t *kout = last_parity ? c.skey_buf : c.keys_alt;
         int *vout = last_parity ? c.perm_buf : c.perm_alt;
         hipError_t e = launch_sort_pass(kin, vin, kout, vout, c.N, kRadixBits * p, c.hist, c.dtotal,
-                                        c.stream, ev ? ev + 4 * p : nullptr);
+                                        c.stream, ev ? ev + 4 * p : nullptr, hist_done && p == 0);
         if (e != hipSuccess) return e;
         kin = kout;
         vin = vout;
@@ -204,13 +205,24 @@ hipError_t enqueue_sort(Ctx &c, hipEvent_t *ev) {
     return hipSuccess;
 }
 
+// cell keys and their radix sort; ev: null, or the keys' two events then the
+// sort's four per pass.  With one key per thread the keys kernel also counts
+// the first pass's digits (its workgroups are that pass's tiles).
+hipError_t enqueue_keys_sort(Ctx &c, int adv, hipEvent_t *ev) {
+    const bool fuse = c.a.radix_passes > 0 && sort_items(c.N) == 1;
+    hipError_t e = ev ? hipEventRecord(ev[0], c.stream) : hipSuccess;
+    if (e != hipSuccess) return e;
+    e = launch_keys(c.a, adv, fuse ? c.hist : nullptr, sort_tiles(c.N), c.stream);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], c.stream)) != hipSuccess) return e;
+    return enqueue_sort(c, ev ? ev + 2 : nullptr, fuse);
+}
+
 // positions -> keys -> sort -> cells, at the current (adv = 0) or advanced
 // (adv = 1) positions of buffer cur
 hipError_t enqueue_search(Ctx &c, int cur, int adv, int advance_step) {
     set_state_ptrs(c, cur);
-    hipError_t e = launch_keys(c.a, adv, c.stream);
-    if (e != hipSuccess) return e;
-    e = enqueue_sort(c, nullptr);
+    hipError_t e = enqueue_keys_sort(c, adv, nullptr);
     if (e != hipSuccess) return e;
     return launch_cells(c.a, adv, advance_step, c.stream);
 }
@@ -512,10 +524,7 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIPCHK(hipMemsetAsync(c.a.overflow, 0, sizeof(int), c.stream));
         set_state_ptrs(c, c.cur);
-        if (ev) HIPCHK(hipEventRecord(ev[0], c.stream));
-        HIPCHK(launch_keys(c.a, 1, c.stream));
-        if (ev) HIPCHK(hipEventRecord(ev[1], c.stream));
-        HIPCHK(enqueue_sort(c, ev ? ev + 2 : nullptr));
+        HIPCHK(enqueue_keys_sort(c, 1, ev));
         const int b = 2 + 4 * c.a.radix_passes;
         if (ev) HIPCHK(hipEventRecord(ev[b], c.stream));
         HIPCHK(launch_cells(c.a, 1, 0, c.stream));
@@ -1951,10 +1960,7 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
             if (inv != ~0ull && (int64_t)inv <= c.step + 1) c.list_valid = false;
         } else {
             set_state_ptrs(c, c.cur);
-            HIPCHK(hipEventRecord(ev[0], c.stream));
-            HIPCHK(launch_keys(c.a, 1, c.stream));
-            HIPCHK(hipEventRecord(ev[1], c.stream));
-            HIPCHK(enqueue_sort(c, ev.data() + 2));
+            HIPCHK(enqueue_keys_sort(c, 1, ev.data()));
             const int b = 2 + 4 * P;
             HIPCHK(hipEventRecord(ev[b], c.stream));
             HIPCHK(launch_cells(c.a, 1, 1, c.stream));

@@ -373,10 +373,10 @@ hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, hipStream_t s);
 hipError_t launch_bonds_fill(const BondArgs &b, uint32_t *col, const uint32_t *slice_ptr,
                              hipStream_t s);
 hipError_t launch_windows(const DevArgs &a, int *win_lo, int *win_hi, hipStream_t s);
-hipError_t launch_keys(const DevArgs &a, int adv, hipStream_t s);
+hipError_t launch_keys(const DevArgs &a, int adv, uint32_t *hist, int G, hipStream_t s);
 hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int N,
                             int shift, uint32_t *hist, uint32_t *dtotal, hipStream_t s,
-                            hipEvent_t *ev);
+                            hipEvent_t *ev, bool hist_done);
 hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t s);
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,

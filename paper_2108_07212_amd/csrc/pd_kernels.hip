@@ -214,15 +214,30 @@ __global__ void k_windows(const uint32_t *col, const uint32_t *slice_ptr, const 
 // ---------------------------------------------------------------------------
 // cell keys
 // ---------------------------------------------------------------------------
-__global__ void k_keys(DevArgs a, int adv) {
+// With `hist` set, the workgroup also counts the low digit of its 256 keys:
+// when the radix sort takes one key per thread, these workgroups are exactly
+// the first pass's tiles, and that pass needs no histogram launch of its own.
+static_assert(kRadix == 256, "k_keys counts one digit per thread of a 256-thread workgroup");
+__global__ __launch_bounds__(256) void k_keys(DevArgs a, int adv, uint32_t *hist, int G) {
+    __shared__ uint32_t cnt[kRadix];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    double px, py, ux, uy;
-    advanced_pos(a, i, adv != 0, px, py, ux, uy);
-    const int ag = a.pagg[a.part[i]];
-    int cx, cy;
-    cell_of(a, ag, px, py, cx, cy);
-    a.keys[i] = a.agg_cell0[ag] + (uint32_t)cy * (uint32_t)a.agg_ncx[ag] + (uint32_t)cx;
+    if (hist) cnt[threadIdx.x] = 0;
+    uint32_t key = 0;
+    if (i < a.N) {
+        double px, py, ux, uy;
+        advanced_pos(a, i, adv != 0, px, py, ux, uy);
+        const int ag = a.pagg[a.part[i]];
+        int cx, cy;
+        cell_of(a, ag, px, py, cx, cy);
+        key = a.agg_cell0[ag] + (uint32_t)cy * (uint32_t)a.agg_ncx[ag] + (uint32_t)cx;
+        a.keys[i] = key;
+    }
+    if (hist) {  // uniform: a kernel argument
+        __syncthreads();
+        if (i < a.N) atomicAdd(&cnt[key & (kRadix - 1)], 1u);
+        __syncthreads();
+        hist[threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1585,18 +1600,21 @@ hipError_t launch_windows(const DevArgs &a, int *win_lo, int *win_hi, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const DevArgs &a, int adv, hipStream_t s) {
+hipError_t launch_keys(const DevArgs &a, int adv, uint32_t *hist, int G, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a, adv);
+    const unsigned g = grid_for(a.N, 256);
+    if (hist && (sort_items(a.N) != 1 || (int)g != G)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_keys, dim3(g), dim3(256), 0, s, a, adv, hist, G);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int N,
                             int shift, uint32_t *hist, uint32_t *dtotal, hipStream_t s,
-                            hipEvent_t *ev) {
+                            hipEvent_t *ev, bool hist_done) {
     const int items = sort_items(N), G = sort_tiles(N);
     if (ev) hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_hist, dim3(G), dim3(kSortBlock), 0, s, kin, N, shift, hist, G, items);
+    if (!hist_done)
+        hipLaunchKernelGGL(k_hist, dim3(G), dim3(kSortBlock), 0, s, kin, N, shift, hist, G, items);
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_digit_scan, dim3(kRadix), dim3(kSortBlock), 0, s, hist, G, dtotal);
     if (ev) hipEventRecord(ev[2], s);
