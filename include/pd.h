@@ -197,15 +197,18 @@ pd_status pd_set_tuning(pd_ctx *c, const pd_tuning *t);
  * fastest.  chosen may be NULL. */
 pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
 
-/* Kernel timing: runs n_steps steps with direct launches and records HIP
- * events on the context's stream; ms[k] receives the mean duration per
- * launch of kernel class k and launches[k] the number of launches timed:
- *   0 cell keys, 1 radix histogram, 2 radix digit scan, 3 radix scatter,
+/* Kernel timing: runs n_steps steps and records HIP events on the
+ * context's stream; ms[k] receives the mean duration per launch of kernel
+ * class k and launches[k] the number of launches timed:
+ *   0 cell keys (with one key per thread also the first radix pass's digit
+ *   count), 1 radix histogram, 2 radix digit scan, 3 radix scatter,
  *   4 cell starts, 5 force + integrate (one per step), 6 candidate-list
  *   build.
  * Search kernels are bracketed one by one.  With candidate lists (skin > 0)
- * the force kernel is timed over runs of up to 64 back-to-back launches
- * (events at the ends of each run), so its mean excludes event overhead.
+ * the force kernel is timed over runs of up to 64 steps issued as pd_step
+ * issues them (one graph replay when the tuning's use_graph is set, else
+ * back-to-back launches), events at the ends of each run: its mean is the
+ * replay's time per step and excludes per-launch event overhead.
  * (n_out >= 7) */
 pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out);
 
