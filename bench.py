@@ -2,17 +2,22 @@
 """Throughput of the PeriDEM step loop on one MI355X.
 
 One step is one pass of the whole hot path (velocity-Verlet position update,
-cell-key radix sort and cell starts, contact + walls + bond forces + velocity
-update) over the settling bed of 100 particles (equal thirds of disks, plus
-shapes and rings, R ~ U[0.8, 1.2] mm, h = 0.0904 mm, horizon 3h, contact
-radius 0.95h, 30 x 60 mm box, gravity 9.81 m/s^2, dt = 1e-7 s, plain FP64),
-with all inputs resident in device memory.
+contact candidates (cell-key radix sort when a list goes stale), contact +
+walls + bond forces with breaking, velocity update) over 64 independent
+settling aggregates of 50-400 particles each (disks, plus shapes and rings,
+R ~ U[0.8, 1.2] mm, h = 0.078 mm, horizon 3h, contact radius 0.95h,
+gravity 9.81 m/s^2, dt = 1e-7 s): 6.4M nodes and 130M directed bonds in
+plain FP64, with all inputs resident in device memory.
 
 Prints one JSON line: bond interactions/s (unordered reference bonds x
 steps/s) as the value, steps/s beside it, the roofline of the dominant
-kernel (force kernel: algorithmic bytes per launch / mean launch time from
-HIP events on the library's stream) and the FP64 CPU oracle timed on the
-host cores over a bounded sample of the same workload.
+kernel (force kernel: algorithmic bytes per launch / its mean duration in
+graph replays, HIP events on the library's stream) and the FP64 CPU oracle
+timed on the host cores over one aggregate of the same workload.  Secondary
+legs: the 30k-node settling bed (FP64; also with the cell search every
+step), the FP32-force split on the compaction bed, the batch with FP32
+forces against its aggregates run one by one, the modal closure, the
+notched-square impact and the jammed shape beds.
 """
 from __future__ import annotations
 
@@ -23,12 +28,17 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_NODE_FORCE = 16 + 16 + 16 + 16 + 48  # x, u, v, a read; u, v, a written
-BYTES_PER_BOND = 4  # one 32-bit slot per directed bond (partner index + broken bit)
+# algorithmic bytes of one step: per node x, u, v, a read (64 B), u, v, a
+# written (48 B), cell key and permutation (16 B); FP32 force split: a in
+# FP32 (16 B less); per directed bond one 32-bit slot (partner + broken bit)
+BYTES_PER_NODE = {0: 128, 1: 112}
+BYTES_PER_BOND = 4
 
 
 def kernel_source_hash() -> str:
@@ -81,13 +91,16 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(prob, seconds: float, n_pairs: int):
-    """The FP64 oracle on the host cores, a bounded number of steps; then a
-    shorter single-thread run of the same steps."""
+def cpu_baseline(prob, seconds: float, sample: str):
+    """The FP64 oracle on the host cores (OpenMP over nodes, up to 16
+    threads), a bounded number of steps of `prob`; then a shorter
+    single-thread run.  Rates in bond interactions/s (the sample's unordered
+    bonds x its steps/s), which are comparable across problem sizes."""
     from oracle import Oracle
 
     def run(threads, secs):
         o = Oracle(prob, contact_mode=1, n_threads=threads)
+        n_pairs = len(o.bonds()[1]) // 2
         o.step(2)
         t0 = time.perf_counter()
         n = 0
@@ -97,34 +110,19 @@ def cpu_baseline(prob, seconds: float, n_pairs: int):
             el = time.perf_counter() - t0
             if el >= secs:
                 break
-        return n, el
+        return n, el, n_pairs
 
     threads = min(os.cpu_count() or 1, 16)
-    n, el = run(threads, seconds)
-    n1, el1 = run(1, max(2.0, seconds / 3))
+    n, el, n_pairs = run(threads, seconds)
+    n1, el1, _ = run(1, max(2.0, seconds / 3))
     sps, sps1 = n / el, n1 / el1
     return {"value": n_pairs * sps, "unit": "bond interactions/s", "cores": threads,
             "kind": "oracle", "steps_per_s": sps,
             "single_thread": {"value": n_pairs * sps1, "steps_per_s": sps1,
                               "sample": f"{n1} steps, {el1:.1f} s"},
             "host": host_cpu(),
-            "sample": f"{n} steps of the same settling bed (FP64 oracle, bucket-grid contact, "
-                      f"OpenMP over nodes), {el:.1f} s"}
-
-
-def herd(prob, alpha):
-    """Translate every particle rigidly toward the bed centre by the fraction
-    alpha of its distance: a synthetic packed state with contacts at once."""
-    import numpy as np
-    cx, cy = prob.x.mean(), prob.y.mean()
-    po = prob.particle_offset
-    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
-    for p in range(prob.n_particles):
-        sl = slice(po[p], po[p + 1])
-        ux[sl] = -alpha * (prob.x[sl].mean() - cx)
-        uy[sl] = -alpha * (prob.y[sl].mean() - cy)
-    prob.u0x, prob.u0y = ux, uy
-    return prob
+            "sample": f"{sample}: {prob.n_nodes} nodes, {n_pairs} unordered bonds, {n} steps "
+                      f"in {el:.1f} s (FP64 oracle, bucket-grid contact, OpenMP over nodes)"}
 
 
 def precision_split(pd, W, torch, steps):
@@ -133,7 +131,7 @@ def precision_split(pd, W, torch, steps):
     state: throughput of both modes, the per-step force error of FP32 against
     FP64 at identical states, and broken-bond counts after `steps` steps."""
     import numpy as np
-    prob = herd(W.compaction(), 0.30)
+    prob = W.herd(W.compaction(), 0.30)
     prob.top_wall_speed = np.array([0.1])
     g64 = pd.PD(prob, precision=0)
     g32 = pd.PD(prob, precision=1)
@@ -172,13 +170,136 @@ def precision_split(pd, W, torch, steps):
     return res
 
 
-def batched(pd, W, torch, steps, tuning_fixed=None):
-    """64 independent settling aggregates of 50-400 particles (about 6.4M
-    nodes) in one problem, FP64 state and FP32 forces: steps/s of the batch,
-    the roofline of its force kernel, and the time of the same 64 aggregates
-    run one after another, each in a context of its own."""
-    prob = W.batched()
+def timed_steps(g, torch, steps):
+    """steps/s of exactly `steps` steps of context g (the stream drained on
+    both sides), and the candidate-list rebuilds among them."""
+    torch.cuda.synchronize()
+    r0 = g.sizes()["list_rebuilds"]
+    t0 = time.perf_counter()
+    g.step(steps)  # returns after the stream is drained
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0), g.sizes()["list_rebuilds"] - r0
+
+
+def force_roofline(g, kernel_steps, precision, workload, name):
+    """Roofline of the force kernel: algorithmic bytes per launch over its
+    mean duration in graph replays (HIP events on the library's stream)."""
+    sizes = g.sizes()
+    kt = g.time_kernels(kernel_steps)
+    ms = kt["force"][0]
+    fb = BYTES_PER_NODE[precision] * sizes["nodes"] + BYTES_PER_BOND * sizes["bonds"]
+    ach = fb / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic("force", workload, g.tuning()),
+            "bytes_per_launch": fb, "mean_launch_ms": ms,
+            "bytes_per_node": BYTES_PER_NODE[precision], "bytes_per_directed_bond": BYTES_PER_BOND,
+            "timed_launches": kt["force"][1]}, kt
+
+
+def headline(pd, W, torch, args, prob):
+    """The 64 batched settling aggregates (6.4M nodes) in plain FP64: the
+    library's autotuner, W warmup steps and one untimed pass of K steps
+    (captures the K-step replay), then exactly K timed steps; five more
+    windows of K steps for the spread; the force kernel's roofline."""
+    g = pd.PD(prob, precision=0)
+    sizes = g.sizes()
+    g.step(min(args.warmup, 20) if args.warmup > 0 else 0)
+    t0 = time.perf_counter()
+    if args.tuning:
+        g.set_tuning(**parse_tuning(args.tuning))
+    else:
+        g.autotune(10)
+    t_tune = time.perf_counter() - t0
+    if args.warmup > 0:
+        g.step(args.warmup)
+    g.step(args.steps)
+    sps, rebuilds = timed_steps(g, torch, args.steps)
+    rep = sorted(timed_steps(g, torch, args.steps)[0] for _ in range(5))
+    roof, kt = force_roofline(g, args.kernel_steps, 0, "batched_64_fp64", "k_force<double,M_STEP>")
+    n_pairs = sizes["bonds"] // 2
+    out = {
+        "metric": "PD bond interactions/s (plain FP64, 64 batched settling aggregates)",
+        "value": n_pairs * sps,
+        "unit": "bond interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 / sps,
+        "steps_per_s": sps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded aggregates, lattice nodes, RSA placement)",
+        "config": {"workload": "batched_64", "aggregates": prob.n_aggregates,
+                   "particles": prob.n_particles, "nodes": sizes["nodes"],
+                   "directed_bonds": sizes["bonds"], "unordered_bonds": n_pairs, "dt": prob.dt,
+                   "gravity": prob.gravity[1], "precision": "fp64", "tuning": g.tuning(),
+                   "autotune_s": t_tune},
+        "roofline": roof,
+        "kernels_ms": {k: v[0] for k, v in kt.items()},
+        "kernel_launches_per_step": {k: v[1] / args.kernel_steps for k, v in kt.items()},
+        "list_rebuilds_in_timed_steps": rebuilds,
+        "repeats": {"n": 5, "steps_each": args.steps, "steps_per_s_median": rep[2],
+                    "steps_per_s_min": rep[0], "steps_per_s_max": rep[4]},
+        "bond_evaluations_per_s": sizes["bonds"] * sps,
+    }
+    del g
+    return out
+
+
+def settling_leg(pd, W, torch, args):
+    """The 30k-node settling bed (100 particles, plain FP64): candidate lists
+    with the autotuner's skin, then the cell search every step (skin 0, the
+    cell size chosen among 1, 2 and 3 contact radii)."""
+    prob = W.settling()
     g = pd.PD(prob)
+    sizes = g.sizes()
+    n_pairs = sizes["bonds"] // 2
+    g.step(100)
+    if args.tuning:
+        g.set_tuning(**parse_tuning(args.tuning))
+    else:
+        g.autotune(50)
+    steps = args.settling_steps
+    g.step(500)
+    g.step(steps)
+    sps, rebuilds = timed_steps(g, torch, steps)
+    rep = sorted(timed_steps(g, torch, max(1, steps // 5))[0] for _ in range(5))
+    roof, kt = force_roofline(g, 512, 0, "settling_100", "k_force<double,M_STEP>")
+    tun = g.tuning()
+    best0 = None
+    for cf in (1.0, 2.0, 3.0):
+        g.set_tuning(skin_factor=0.0, cell_factor=cf)
+        g.step(50)
+        s_cf, _ = timed_steps(g, torch, max(100, steps // 50))
+        if best0 is None or s_cf > best0[1]:
+            best0 = (cf, s_cf)
+    g.set_tuning(skin_factor=0.0, cell_factor=best0[0])
+    sps0, _ = timed_steps(g, torch, max(100, steps // 10))
+    g.set_tuning(**tun)
+    res = {"workload": "settling_100", "nodes": sizes["nodes"], "directed_bonds": sizes["bonds"],
+           "steps": steps, "steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+           "ms_per_step": 1e3 / sps, "tuning": tun, "roofline": roof,
+           "kernels_ms": {k: v[0] for k, v in kt.items()},
+           "list_rebuilds_per_1000_steps": 1000.0 * rebuilds / steps,
+           "repeats": {"n": 5, "steps_each": max(1, steps // 5), "steps_per_s_median": rep[2],
+                       "steps_per_s_min": rep[0], "steps_per_s_max": rep[4]},
+           "every_step_search": {"bond_interactions_per_s": n_pairs * sps0, "steps_per_s": sps0,
+                                 "cell_factor": best0[0],
+                                 "note": "the same step with the cell-key sort and cell search "
+                                         "every step (skin 0)"}}
+    del g
+    return res
+
+
+def batched_fp32(pd, W, torch, steps, prob, tuning_fixed=None):
+    """The 64 aggregates with FP32 force arithmetic (FP64 state and break
+    decisions): steps/s of the batch, the roofline of its force kernel, and
+    the time of the same 64 aggregates run one after another, each in a
+    context of its own."""
+    g = pd.PD(prob, precision=1)
     g.step(20)
     t0 = time.perf_counter()
     if tuning_fixed:
@@ -188,29 +309,23 @@ def batched(pd, W, torch, steps, tuning_fixed=None):
         tuning = g.autotune(10)
     t_tune = time.perf_counter() - t0
     g.step(20)
-    sizes = g.sizes()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     g.step(steps)
-    torch.cuda.synchronize()
-    sps = steps / (time.perf_counter() - t0)
-    kt = g.time_kernels(128)
-    fb = BYTES_PER_NODE_FORCE * sizes["nodes"] + BYTES_PER_BOND * sizes["bonds"]
-    ach = fb / (kt["force"][0] * 1e-3) / 1e9
-    res = {"workload": "batched_64", "aggregates": prob.n_aggregates, "nodes": sizes["nodes"],
-           "tuning": tuning, "autotune_s": t_tune,
+    sizes = g.sizes()
+    sps, _ = timed_steps(g, torch, steps)
+    roof, _ = force_roofline(g, 128, 1, "batched_64", "k_force<float,M_STEP>")
+    res = {"workload": "batched_64", "precision": "fp32_force", "aggregates": prob.n_aggregates,
+           "nodes": sizes["nodes"], "tuning": tuning, "autotune_s": t_tune,
            "directed_bonds": sizes["bonds"], "steps_per_s": sps,
            "bond_interactions_per_s": sizes["bonds"] // 2 * sps,
-           "force_kernel": {"mean_launch_ms": kt["force"][0], "bytes_per_launch": fb,
-                            "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS,
-                            "traffic": measured_traffic("force", "batched_64", tuning)}}
+           "force_kernel": roof}
     del g
     seq = 0.0
     sub_steps = max(20, steps // 2)
     for a in range(prob.n_aggregates):
-        ga = pd.PD(W.subproblem_aggregate(prob, a))
+        ga = pd.PD(W.subproblem_aggregate(prob, a), precision=1)
         ga.set_tuning(**tuning)
         ga.step(5)
+        ga.step(sub_steps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ga.step(sub_steps)
@@ -448,27 +563,29 @@ def copy_calibration(torch, mib=256, reps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps of the headline (the 64 batched aggregates, FP64)")
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=500)
+    ap.add_argument("--kernel-steps", type=int, default=128)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--settling-steps", type=int, default=20000)
     ap.add_argument("--split-steps", type=int, default=400)
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--impact-us", type=float, default=40.0)
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning instead of the autotuner for the headline and batched "
-                         "runs, e.g. block_nodes=128,use_lds=1,skin_factor=0.5 (profiling runs)")
+                    help="fixed tuning instead of the autotuner for the run's contexts, e.g. "
+                         "block_nodes=128,use_lds=1,skin_factor=0.5 (profiling runs)")
     ap.add_argument("--settle-us", type=float, default=10000.0)
     ap.add_argument("--settle-every-us", type=float, default=1000.0)
-    ap.add_argument("--workload", choices=("settling", "compaction", "batched", "closure",
-                                           "fragmentation", "settle_shapes"),
-                    default="settling",
-                    help="settling: the headline line (plus the variants unless "
-                         "--no-variants); compaction / batched: only that variant")
+    ap.add_argument("--workload", choices=("batched", "settling", "compaction", "batched_fp32",
+                                           "closure", "fragmentation", "settle_shapes"),
+                    default="batched",
+                    help="batched: the headline line (plus the secondary legs unless "
+                         "--no-variants); any other: only that leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (profiler calibration)")
     args = ap.parse_args()
@@ -485,116 +602,39 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    fixed = parse_tuning(args.tuning) if args.tuning else None
     if args.copy_calibration:
         print(json.dumps(copy_calibration(torch)), flush=True)
         return
-    if args.workload == "compaction":
-        print(json.dumps({"precision_split": precision_split(pd, W, torch, args.split_steps)}),
-              flush=True)
-        return
-    if args.workload == "batched":
-        print(json.dumps({"batched": batched(pd, W, torch, args.batched_steps,
-                                             parse_tuning(args.tuning) if args.tuning else None)}),
-              flush=True)
-        return
-    if args.workload == "closure":
-        print(json.dumps({"closure": closure(pd, W, torch, args.closure_steps, args.train_iters)}),
-              flush=True)
-        return
-    if args.workload == "settle_shapes":
-        print(json.dumps({"settle_shapes": settle_shapes(pd, W, torch, args.settle_us,
-                                                         args.settle_every_us)}), flush=True)
-        return
-    if args.workload == "fragmentation":
-        print(json.dumps({"fragmentation": fragmentation(pd, W, torch, args.impact_us)}), flush=True)
-        return
-    prob = W.settling()
-    g = pd.PD(prob)
-    sizes = g.sizes()
-    N, n_dir = sizes["nodes"], sizes["bonds"]
-    n_pairs = n_dir // 2
-    def timed(steps):
-        torch.cuda.synchronize()
-        r0 = g.sizes()["list_rebuilds"]
-        t0 = time.perf_counter()
-        g.step(steps)  # returns after the stream is drained
-        torch.cuda.synchronize()
-        return steps / (time.perf_counter() - t0), g.sizes()["list_rebuilds"] - r0
-
-    # the library's own autotuner (nodes per workgroup, skin, LDS staging),
-    # then the contact set evaluated from exact distances every step, over
-    # the candidate lists (rebuilt by the cell-key radix sort when stale)
-    g.step(min(args.warmup, 100))
-    if args.tuning:
-        g.set_tuning(**parse_tuning(args.tuning))
-    else:
-        g.autotune(50)
-    g.step(args.warmup)
-    sps, rebuilds = timed(args.steps)
-    # the spread: five more windows of a fifth of the steps each (after the
-    # timed region, which stays the K steps above)
-    rep = sorted(timed(max(1, args.steps // 5))[0] for _ in range(5))
-    # per-kernel mean launch time (HIP events on the library's stream)
-    kt = g.time_kernels(args.kernel_steps)
-    force_ms = kt["force"][0]
-    # the same loop with the cell search run every step (skin 0), the cell
-    # size chosen among 1, 2 and 3 contact radii (fewer cells can take a pass
-    # off the radix sort, larger cells hold more candidates)
-    tun = g.tuning()
-    best0 = None
-    for cf in (1.0, 2.0, 3.0):
-        g.set_tuning(skin_factor=0.0, cell_factor=cf)
-        g.step(max(10, args.warmup // 10))
-        s_cf, _ = timed(max(100, args.steps // 50))
-        if best0 is None or s_cf > best0[1]:
-            best0 = (cf, s_cf)
-    g.set_tuning(skin_factor=0.0, cell_factor=best0[0])
-    sps0, _ = timed(max(100, args.steps // 10))
-    cf0 = best0[0]
-    g.set_tuning(**tun)
-    force_bytes = BYTES_PER_NODE_FORCE * N + BYTES_PER_BOND * n_dir
-    achieved = force_bytes / (force_ms * 1e-3) / 1e9
-    traffic = measured_traffic("force", "settling_100", g.tuning())
-    out = {
-        "metric": "PD bond interactions/s (plain FP64, settling bed)",
-        "value": n_pairs * sps,
-        "unit": "bond interactions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 / sps,
-        "steps_per_s": sps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded settling bed, lattice nodes, RSA placement)",
-        "config": {"workload": "settling_100", "particles": prob.n_particles, "nodes": N,
-                   "directed_bonds": n_dir, "unordered_bonds": n_pairs, "dt": prob.dt,
-                   "gravity": prob.gravity[1], "precision": "fp64", "tuning": g.tuning()},
-        "roofline": {"bound": "hbm", "kernel": "k_force<double,M_STEP>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": force_bytes,
-                     "mean_launch_ms": force_ms},
-        "kernels_ms": {k: v[0] for k, v in kt.items()},
-        "kernel_launches_per_step": {k: v[1] / args.kernel_steps for k, v in kt.items()},
-        "list_rebuilds_per_1000_steps": 1000.0 * rebuilds / args.steps,
-        "repeats": {"n": 5, "steps_each": max(1, args.steps // 5),
-                    "steps_per_s_median": rep[2], "steps_per_s_min": rep[0],
-                    "steps_per_s_max": rep[4]},
-        "every_step_search": {"value": n_pairs * sps0, "steps_per_s": sps0, "cell_factor": cf0,
-                              "note": "same step with the cell-key sort and cell search "
-                                      "every step (skin 0)"},
+    legs = {
+        "settling": lambda: settling_leg(pd, W, torch, args),
+        "compaction": lambda: precision_split(pd, W, torch, args.split_steps),
+        "batched_fp32": lambda: batched_fp32(pd, W, torch, args.batched_steps,
+                                             W.batched(precision=1), fixed),
+        "closure": lambda: closure(pd, W, torch, args.closure_steps, args.train_iters),
+        "fragmentation": lambda: fragmentation(pd, W, torch, args.impact_us),
+        "settle_shapes": lambda: settle_shapes(pd, W, torch, args.settle_us, args.settle_every_us),
     }
-    del g
+    if args.workload != "batched":
+        print(json.dumps({args.workload: legs[args.workload]()}), flush=True)
+        return
+    prob = W.batched(precision=0)
+    out = headline(pd, W, torch, args, prob)
     if not args.no_variants:
-        out["precision_split"] = precision_split(pd, W, torch, args.split_steps)
-        out["batched"] = batched(pd, W, torch, args.batched_steps)
-        out["closure"] = closure(pd, W, torch, args.closure_steps, args.train_iters)
-        out["fragmentation"] = fragmentation(pd, W, torch, args.impact_us)
-        out["settle_shapes"] = settle_shapes(pd, W, torch, args.settle_us, args.settle_every_us)
+        out["settling_100"] = legs["settling"]()
+        out["precision_split"] = legs["compaction"]()
+        out["batched_fp32"] = batched_fp32(pd, W, torch, args.batched_steps, prob, fixed)
+        out["closure"] = legs["closure"]()
+        out["fragmentation"] = legs["fragmentation"]()
+        out["settle_shapes"] = legs["settle_shapes"]()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.settling(), args.cpu_seconds, n_pairs)
+        # one aggregate of the same batch, of about the batch's mean size
+        sizes = np.diff(prob.particle_offset)
+        agg_nodes = np.bincount(prob.particle_aggregate, weights=sizes)
+        k = int(np.argmin(np.abs(agg_nodes - agg_nodes.mean())))
+        out["cpu_baseline"] = cpu_baseline(
+            W.subproblem_aggregate(prob, k), args.cpu_seconds,
+            f"aggregate {k} of the 64 batched settling aggregates (of mean size)")
     print(json.dumps(out), flush=True)
 
 

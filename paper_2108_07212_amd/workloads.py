@@ -123,29 +123,34 @@ def polygon_area(loops: list) -> float:
 
 
 def _inside_even_odd(px: np.ndarray, py: np.ndarray, loops: list) -> np.ndarray:
+    """Even-odd rule: crossings of the horizontal ray to +x with every edge
+    (all edges of a loop at once, the same expressions per edge)."""
     inside = np.zeros(px.shape, dtype=bool)
+    qx, qy = px[:, None], py[:, None]
     for lp in loops:
         a = lp
         b = np.roll(lp, -1, axis=0)
-        for (ax, ay), (bx, by) in zip(a, b):
-            cond = (ay > py) != (by > py)
-            with np.errstate(divide="ignore", invalid="ignore"):
-                xint = ax + (py - ay) * (bx - ax) / (by - ay)
-            inside ^= cond & (px < xint)
+        ax, ay, bx, by = a[:, 0], a[:, 1], b[:, 0], b[:, 1]
+        cond = (ay > qy) != (by > qy)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xint = ax + (qy - ay) * (bx - ax) / (by - ay)
+        inside ^= (np.count_nonzero(cond & (qx < xint), axis=1) & 1).astype(bool)
     return inside
 
 
 def _dist_to_loops(px: np.ndarray, py: np.ndarray, loops: list) -> np.ndarray:
+    """Distance of each point to the nearest edge of the loops."""
     d = np.full(px.shape, np.inf)
+    qx0, qy0 = px[:, None], py[:, None]
     for lp in loops:
         a = lp
         b = np.roll(lp, -1, axis=0)
-        for (ax, ay), (bx, by) in zip(a, b):
-            ex, ey = bx - ax, by - ay
-            L2 = ex * ex + ey * ey
-            t = np.clip(((px - ax) * ex + (py - ay) * ey) / L2, 0.0, 1.0)
-            qx, qy = ax + t * ex - px, ay + t * ey - py
-            d = np.minimum(d, np.sqrt(qx * qx + qy * qy))
+        ax, ay = a[:, 0], a[:, 1]
+        ex, ey = b[:, 0] - ax, b[:, 1] - ay
+        L2 = ex * ex + ey * ey
+        t = np.minimum(np.maximum(((qx0 - ax) * ex + (qy0 - ay) * ey) / L2, 0.0), 1.0)
+        qx, qy = ax + t * ex - qx0, ay + t * ey - qy0
+        d = np.minimum(d, np.sqrt(qx * qx + qy * qy).min(axis=1))
     return d
 
 
@@ -176,8 +181,14 @@ def loop_nodes(loops: list, R: float, h: float, margin: float = 1e-3) -> np.ndar
     jj, iig = np.meshgrid(ii, ii, indexing="ij")
     px = (iig * h).ravel().astype(np.float64)
     py = (jj * h).ravel().astype(np.float64)
-    keep = _inside_even_odd(px, py, loops)
-    keep &= _dist_to_loops(px, py, loops) > margin * h
+    # points beyond the circle through the farthest vertex are outside; the
+    # rest get the even-odd test, and the points inside the distance test
+    rmax = max(float(np.sqrt((lp * lp).sum(axis=1)).max()) for lp in loops)
+    keep = px * px + py * py <= (1.001 * rmax) ** 2
+    idx = np.nonzero(keep)[0]
+    keep[idx] = _inside_even_odd(px[idx], py[idx], loops)
+    idx = np.nonzero(keep)[0]
+    keep[idx] = _dist_to_loops(px[idx], py[idx], loops) > margin * h
     return np.stack([px[keep], py[keep]], axis=1)
 
 
@@ -490,6 +501,21 @@ def subproblem_aggregate(prob: Problem, a: int) -> Problem:
         u0x=cut(prob.u0x), u0y=cut(prob.u0y), v0x=cut(prob.v0x), v0y=cut(prob.v0y),
         meta=dict(prob.meta, aggregate=a),
     )
+
+
+def herd(prob: Problem, alpha: float) -> Problem:
+    """Translate every particle rigidly toward the bed centre by the fraction
+    alpha of its distance: a synthetic packed state with contacts (and
+    overlaps) at t = 0, a stress case for contact and breaking."""
+    cx, cy = prob.x.mean(), prob.y.mean()
+    po = prob.particle_offset
+    ux, uy = np.zeros(prob.n_nodes), np.zeros(prob.n_nodes)
+    for p in range(prob.n_particles):
+        sl = slice(po[p], po[p + 1])
+        ux[sl] = -alpha * (prob.x[sl].mean() - cx)
+        uy[sl] = -alpha * (prob.y[sl].mean() - cy)
+    prob.u0x, prob.u0y = ux, uy
+    return prob
 
 
 def single_node_particles(points, velocities, vol: float, box, *, contact_radius: float,

@@ -101,8 +101,7 @@ def test_compaction_500_full_size(pdmod):
     velocities by 1.6e-3 to 2.5e-3 in 100 steps; FP32 forces measured 1.5e-4
     and 1.7e-4 against the oracle, displacements 2e-8."""
     _say("case: compaction 500, full size, packed start")
-    import bench
-    prob = bench.herd(W.compaction(), 0.30)
+    prob = W.herd(W.compaction(), 0.30)
     prob.top_wall_speed = np.array([0.1])
     o = Oracle(prob, contact_mode=1, n_threads=16)
     g = pdmod.PD(prob, precision=W.PREC_FP64)
