@@ -464,85 +464,182 @@ static void contact_node(or_ctx *c, int i, const double *vx, const double *vy, i
     c->F[T_NBR][1][i] = fny;
 }
 
-/* phi - sin(phi) for phi in [0, 2 pi), without cancellation for small phi */
-static double phi_minus_sin(double phi) {
-    if (phi < 0.5) {
-        /* Taylor series: sum_k (-1)^k phi^(2k+3) / (2k+3)! */
-        double p2 = phi * phi, term = phi * p2 / 6.0, s = 0.0;
-        for (int k = 0; k < 8; ++k) {
-            s += term;
-            term *= -p2 / ((2.0 * k + 4.0) * (2.0 * k + 5.0));
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.5 wall regions by quadrature of their defining integrals           */
+/* ------------------------------------------------------------------------ */
+/* The regions are parts of the contact disk of radius Rc about the node: the
+ * circular segment beyond one wall and the intersection of two such segments
+ * at a corner.  Their areas and first moments are integrals over the region,
+ * evaluated here by Gauss-Legendre quadrature on vertical strips: in the
+ * frame of the node with the wall (or the two walls) beyond x = da (and
+ * y = db), a strip at abscissa x = Rc cos(theta) runs from its lower end
+ * (the line y = db, or the circle) to the circle y = Rc sin(theta), and
+ * dx = Rc sin(theta) dtheta.  The integrands are smooth in theta, so a
+ * 20-point rule is exact to rounding; each panel is checked against its two
+ * halves and halved until they agree to 1e-15. */
+#define GL_N 20
+static double gl_x[GL_N], gl_w[GL_N];
+static int gl_ready = 0;
+
+/* nodes and weights of the n-point Gauss-Legendre rule on [-1, 1]: roots of
+ * the Legendre polynomial P_n by Newton's method (P_n and P_n' from the
+ * three-term recurrence), weights 2 / ((1 - x^2) P_n'(x)^2) */
+static void gl_init(void) {
+    if (gl_ready) return;
+    const int n = GL_N;
+    for (int k = 0; k < n; ++k) {
+        double x = cos(M_PI * (k + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int m = 2; m <= n; ++m) {
+                const double p2 = ((2.0 * m - 1.0) * x * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-17) break;
         }
-        return s;
+        gl_x[k] = x;
+        gl_w[k] = 2.0 / ((1.0 - x * x) * dp * dp);
     }
-    return phi - sin(phi);
+    gl_ready = 1;
+}
+
+/* the strip integrands at angle theta (abscissa x = Rc cos theta, top
+ * Rc sin theta), times dx/dtheta: area, moment along x, moment along y, and
+ * the integral of (Rc - x), with Rc - x = 2 Rc sin^2(theta/2) */
+#define NQ 4
+typedef struct {
+    double Rc, db;
+    int circle; /* lower end: 0 the line y = db, 1 the circle y = -Rc sin theta */
+} strip_args;
+
+/* out[NQ..2NQ-1]: the same products with |top| + |bot| for the strip's
+ * length and absolute values elsewhere, the scale of their rounding errors
+ * (top - bot and top + bot cancel where the strip is short or its ends are
+ * nearly opposite) */
+static void strip(const strip_args *s, double th, double out[2 * NQ]) {
+    const double R = s->Rc;
+    const double sn = sin(th), x = R * cos(th), top = R * sn, sh = sin(0.5 * th);
+    const double bot = s->circle ? -top : s->db;
+    const double jac = R * sn; /* dx / dtheta */
+    const double len = top - bot;
+    out[0] = len * jac;
+    out[1] = x * len * jac;
+    out[2] = 0.5 * (top - bot) * (top + bot) * jac;
+    out[3] = 2.0 * R * sh * sh * len * jac;
+    const double span = fabs(top) + fabs(bot); /* |len| before cancellation */
+    out[NQ + 0] = span * fabs(jac);
+    out[NQ + 1] = fabs(x) * span * fabs(jac);
+    out[NQ + 2] = 0.5 * span * span * fabs(jac);
+    out[NQ + 3] = 2.0 * R * sh * sh * span * fabs(jac);
+}
+
+/* the rule on one panel: integrals out[0..NQ-1] and the integrals of the
+ * absolute products out[NQ..2NQ-1] */
+static void gl_panel(const strip_args *s, double a, double b, double out[2 * NQ]) {
+    const double m = 0.5 * (a + b), r = 0.5 * (b - a);
+    for (int q = 0; q < 2 * NQ; ++q) out[q] = 0.0;
+    for (int k = 0; k < GL_N; ++k) {
+        double f[2 * NQ];
+        strip(s, m + r * gl_x[k], f);
+        for (int q = 0; q < 2 * NQ; ++q) out[q] += gl_w[k] * f[q];
+    }
+    for (int q = 0; q < 2 * NQ; ++q) out[q] *= r;
+}
+
+/* the panel [a, b] whose one-panel value is `whole`: accepted when its two
+ * halves agree with it to 1e-13 of the integral of the absolute products,
+ * else each half in turn (at most 8 halvings).  The integrands are smooth,
+ * so the 20-point rule is exact to rounding on any panel here; the two
+ * evaluations then differ only by the rounding of the abscissae (sin theta
+ * near 0 or pi magnifies it by |cot theta|), far below this bound. */
+static void gl_adapt(const strip_args *s, double a, double b, const double whole[2 * NQ],
+                     int depth, double out[NQ]) {
+    const double m = 0.5 * (a + b);
+    double l[2 * NQ], r[2 * NQ];
+    gl_panel(s, a, m, l);
+    gl_panel(s, m, b, r);
+    int ok = 1;
+    for (int q = 0; q < NQ; ++q)
+        if (fabs((l[q] + r[q]) - whole[q]) > 1e-13 * (l[NQ + q] + r[NQ + q])) ok = 0;
+    if (ok || depth >= 8) {
+        for (int q = 0; q < NQ; ++q) out[q] = l[q] + r[q];
+        return;
+    }
+    double lo[NQ], hi[NQ];
+    gl_adapt(s, a, m, l, depth + 1, lo);
+    gl_adapt(s, m, b, r, depth + 1, hi);
+    for (int q = 0; q < NQ; ++q) out[q] = lo[q] + hi[q];
+}
+
+/* adds the strips of angles [a, b] (0 <= a <= b <= pi) to acc */
+static void strips(double Rc, double db, int circle, double a, double b, double acc[NQ]) {
+    if (!(b > a)) return;
+    gl_init();
+    const strip_args s = {Rc, db, circle};
+    double whole[2 * NQ], out[NQ];
+    gl_panel(&s, a, b, whole);
+    gl_adapt(&s, a, b, whole, 0, out);
+    for (int q = 0; q < NQ; ++q) acc[q] += out[q];
+}
+
+/* angle theta in [0, pi] of the abscissa x = Rc cos(theta), from
+ * 1 - cos(theta) = 2 sin^2(theta/2): well conditioned as x -> Rc */
+static double theta_of(double Rc, double x) { return 2.0 * asin(sqrt((Rc - x) / (2.0 * Rc))); }
+
+/* Region {x > da, y > db, x^2 + y^2 < Rc^2} (a corner; db <= -Rc: the
+ * segment beyond x = da alone): area and first moments about the node. */
+static void region_integrals(double Rc, double da, double db, double acc[NQ]) {
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    const double tda = theta_of(Rc, da); /* strips x in (da, Rc): theta in [0, tda) */
+    if (db <= -Rc) {                     /* no lower wall: whole chords */
+        strips(Rc, 0.0, 1, 0.0, tda, acc);
+    } else if (db >= 0.0) {
+        /* the line y = db is the lower end where the circle is above it:
+         * sin(theta) > db / Rc */
+        const double tb = asin(db / Rc);
+        strips(Rc, db, 0, tb, fmin(tda, M_PI - tb), acc);
+    } else {
+        /* the line is the lower end where it lies above the lower circle,
+         * sin(theta) > -db / Rc; whole chords elsewhere */
+        const double tc = asin(-db / Rc);
+        strips(Rc, db, 1, 0.0, fmin(tc, tda), acc);
+        strips(Rc, db, 0, tc, fmin(tda, M_PI - tc), acc);
+        strips(Rc, db, 1, M_PI - tc, tda, acc);
+    }
 }
 
 /* Sec. 4.5: circular segment of the contact disk beyond one wall at signed
- * distance d (-Rc < d < Rc).  The printed area Rc^2 (pi/2 - asin(d/Rc)) -
- * d sqrt(Rc^2 - d^2) equals (Rc^2/2)(phi - sin phi) with phi = 2 acos(d/Rc)
- * = 4 asin(sqrt((Rc - d)/(2 Rc))); this form has no cancellation as d -> Rc,
- * where the printed one loses every digit.  Centroid distance as printed:
- * (2/3) (Rc^2 - d^2)^(3/2) / |S|. */
+ * distance d (-Rc < d < Rc): its area |S| and the distance of its centroid
+ * from the node (the printed closed forms are the pins of these integrals) */
 void or_wall_segment(double Rc, double d, double *area, double *centroid_dist) {
-    double q = (Rc - d) * (Rc + d);
-    double phi = 4.0 * asin(sqrt((Rc - d) / (2.0 * Rc)));
-    double A = 0.5 * Rc * Rc * phi_minus_sin(phi);
-    *area = A;
-    *centroid_dist = (2.0 / 3.0) * (q * sqrt(q)) / A;
+    double q[NQ];
+    region_integrals(Rc, d, -2.0 * Rc, q);
+    *area = q[0];
+    *centroid_dist = q[0] > 0.0 ? q[1] / q[0] : Rc;
 }
 
-/* Rc |S| - (2/3)(Rc^2 - d^2)^(3/2) = |S| (Rc - |c - p|): the factor of the
- * single-wall repulsion (Sec. 4.5).  With d = Rc cos(phi/2) it equals
- * Rc^3 [(phi - sin phi)/2 - (2/3) sin^3(phi/2)], whose Taylor series starts
- * at phi^5/160; the series avoids the cancellation of the two terms as
- * d -> Rc, where both vanish. */
+/* |S| (Rc - |c - p|) = integral over S of (Rc - x) dA: the factor of the
+ * single-wall repulsion (Sec. 4.5), whose integrand is positive, so that it
+ * keeps its precision as d -> Rc, where |S| and Rc - |c - p| both vanish */
 double or_wall_segment_gap(double Rc, double d) {
-    const double phi = 4.0 * asin(sqrt((Rc - d) / (2.0 * Rc)));
-    double h;
-    if (phi < 2.0) {
-        double pw = phi * phi * phi * phi * phi / 120.0, a = 0.5 * 0.5 * 0.5 * 0.5 * 0.5,
-               b = 1.5 * 1.5 * 1.5 * 1.5 * 1.5;
-        h = 0.0;
-        for (int k = 2; k < 18; ++k) {
-            const double ck = -0.5 - 0.5 * a + b / 6.0;
-            h += (k % 2 ? -ck : ck) * pw;
-            pw *= phi * phi / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
-            a *= 0.25;
-            b *= 2.25;
-        }
-    } else {
-        const double sh = sin(0.5 * phi);
-        h = 0.5 * (phi - sin(phi)) - (2.0 / 3.0) * sh * sh * sh;
-    }
-    return Rc * Rc * Rc * h;
+    double q[NQ];
+    region_integrals(Rc, d, -2.0 * Rc, q);
+    return q[3];
 }
 
 /* Sec. 4.5: the part of the contact disk beyond two adjacent walls at signed
- * distances da, db (da^2 + db^2 < Rc^2), and its first moments Ix (toward
- * wall a) and Iy (toward wall b) about the node.  Evaluated as the right
- * triangle V P2 P1 (V = (da, db), P2 = (sqrt(Rc^2 - db^2), db),
- * P1 = (da, sqrt(Rc^2 - da^2))) plus the circular segment on the chord
- * P2 P1; this equals the printed area and moments (test-pinned) without
- * their cancellation when the region is small. */
+ * distances da, db (the intersection of the two segments), and its first
+ * moments Ix (toward wall a) and Iy (toward wall b) about the node */
 void or_wall_corner(double Rc, double da, double db, double *area, double *Ix, double *Iy) {
-    const double x2 = sqrt((Rc - db) * (Rc + db)); /* P2 = (x2, db) */
-    const double y1 = sqrt((Rc - da) * (Rc + da)); /* P1 = (da, y1) */
-    const double D = (Rc - da) * (Rc + da) - db * db; /* Rc^2 - da^2 - db^2 > 0 */
-    const double wx = da > 0.0 ? D / (x2 + da) : x2 - da; /* x2 - da */
-    const double wy = db > 0.0 ? D / (y1 + db) : y1 - db; /* y1 - db */
-    const double At = 0.5 * wx * wy;                      /* triangle V P2 P1 */
-    const double chord = sqrt(wx * wx + wy * wy);
-    const double half = asin(chord / (2.0 * Rc)); /* half the central angle */
-    const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
-    /* segment moment about the disk centre: (2/3) Rc^3 sin^3(half) along the
-     * chord normal pointing away from V */
-    const double sh = sin(half);
-    const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
-    const double nx = wy / chord, ny = wx / chord;
-    *area = At + As;
-    *Ix = At * (da + (da + wx) + da) / 3.0 + ms * nx;
-    *Iy = At * (db + db + (db + wy)) / 3.0 + ms * ny;
+    double q[NQ];
+    region_integrals(Rc, da, db, q);
+    *area = q[0];
+    *Ix = q[1];
+    *Iy = q[2];
 }
 
 /* one wall region (segment or corner) acting on node i: repulsion of
@@ -584,10 +681,11 @@ static int wall_node_split(or_ctx *c, int i, double t, const double *vx, const d
         if (!(d[w] > -Rc)) st = OR_E_ESCAPED;
         if (d[w] < Rc && d[w] > -Rc) {
             /* F = -K_n (Rc - |c_l - p|) V_i |S_l| e_l, with |S_l| (Rc - |c_l - p|)
-             * evaluated without cancellation */
-            double A, g;
-            or_wall_segment(Rc, d[w], &A, &g);
-            const double Frmag = Kn * c->vol[i] * or_wall_segment_gap(Rc, d[w]);
+             * the integral of (Rc - x) over S_l (no cancellation as d -> Rc) */
+            double q[NQ];
+            region_integrals(Rc, d[w], -2.0 * Rc, q);
+            const double A = q[0];
+            const double Frmag = Kn * c->vol[i] * q[3];
             if (A > 0.0) {
                 double rx = 0.0, ry = 0.0;
                 wall_region(c, i, Kn, A, Frmag, nx[w], ny[w], 0.0, wv[w], vx, vy, +1.0, &rx, &ry,
@@ -606,7 +704,11 @@ static int wall_node_split(or_ctx *c, int i, double t, const double *vx, const d
     for (int k = 0; k < 4; ++k) {
         int wa = pa[k], wb = pb[k];
         double da = d[wa], db = d[wb];
-        if (da > -Rc && db > -Rc && da * da + db * db < Rc * Rc) {
+        /* S_a and S_b overlap iff the point of the quadrant beyond both
+         * walls nearest to the node lies within Rc (for da, db >= 0 the
+         * printed condition da^2 + db^2 < Rc^2) */
+        const double qa = da > 0.0 ? da : 0.0, qb = db > 0.0 ? db : 0.0;
+        if (da > -Rc && db > -Rc && qa * qa + qb * qb < Rc * Rc) {
             double A, Ix, Iy;
             or_wall_corner(Rc, da, db, &A, &Ix, &Iy);
             if (!(A > 0.0)) continue;
@@ -753,6 +855,7 @@ static void *dup(const void *p, size_t n) {
 }
 
 int or_create(const or_problem *p, or_ctx **out) {
+    gl_init(); /* the quadrature rule, before any parallel region reads it */
     *out = NULL;
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     if (!c) return OR_E_NOMEM;

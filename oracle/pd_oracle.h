@@ -103,10 +103,13 @@ int or_counters(const or_ctx *c, int64_t out[8]);
 int or_segment_in_particle(const or_ctx *c, int32_t particle, double ax, double ay,
                            double bx, double by);
 
-/* wall helpers exposed for tests (closed forms of Sec. 4.5) */
+/* wall helpers exposed for tests: the regions of Sec. 4.5 by Gauss-Legendre
+ * quadrature of their defining integrals (the printed closed forms pin them) */
 void or_wall_segment(double Rc, double d, double *area, double *centroid_dist);
+/* the intersection of the segments beyond two adjacent walls at signed
+ * distances da, db and its first moments toward each wall */
 void or_wall_corner(double Rc, double da, double db, double *area, double *Ix, double *Iy);
-/* |S| (Rc - |c - p|) of a single wall at signed distance d */
+/* |S| (Rc - |c - p|) = integral over S of (Rc - x) dA, single wall at d */
 double or_wall_segment_gap(double Rc, double d);
 
 #ifdef __cplusplus

@@ -418,14 +418,18 @@ def test_wall_repulsion_factor_vs_quadrature(d):
 
 
 @pytest.mark.parametrize("da,db", [(0.0, 0.0), (0.2, 0.3), (0.5, 0.5), (0.6, 0.1), (-0.3, 0.4),
-                                   (0.5, -0.6), (-0.5, -0.5), (0.69, 0.7)])
+                                   (0.5, -0.6), (-0.5, -0.5), (0.69, 0.7),
+                                   (-0.5, 0.9), (0.95, -0.4), (-0.75, -0.75), (-0.2, 0.999)])
 def test_wall_corner_vs_quadrature(da, db):
+    """The intersection of the two segments, S_a and S_b (Sec. 4.5), against
+    scipy's adaptive quadrature of its definition, including nodes beyond
+    a wall whose corner lies outside the contact disk (the last four)."""
     Rc = 1.0
     A, Ix, Iy = wall_corner(Rc, da, db)
     Aq, Mx, My = _quad_region(Rc, da, db)
-    assert A == pytest.approx(Aq, rel=1e-9)
-    assert Ix == pytest.approx(Mx, rel=1e-8, abs=1e-13)
-    assert Iy == pytest.approx(My, rel=1e-8, abs=1e-13)
+    assert A == pytest.approx(Aq, rel=1e-10)
+    assert Ix == pytest.approx(Mx, rel=1e-9, abs=1e-13)
+    assert Iy == pytest.approx(My, rel=1e-9, abs=1e-13)
     if da >= 0 and db >= 0:
         q = math.sqrt
         Ap = (-0.5 * math.asin(da) + 0.5 * math.asin(q(1 - db * db)) + da * db
@@ -444,6 +448,27 @@ def test_wall_special_values_printed_in_paper():
     A, Ix, Iy = wall_corner(Rc, 0.0, 0.0)
     assert A == pytest.approx(g["corner_area_at_0_over_Rc2"] * Rc * Rc, rel=1e-15)
     assert Ix / A == pytest.approx(g["corner_centroid_at_0_over_Rc"] * Rc, rel=1e-14)
+
+
+def test_wall_force_continuous_as_a_node_crosses_a_wall_near_a_corner():
+    """A node near the floor's contact zone edge crossing the left wall's
+    line: the corner correction (the overlap of the two segments) must not
+    switch off at d_left = 0, so the wall force is continuous there."""
+    h = 1e-4
+    Rc = 0.95 * h
+    e = 1e-10 * Rc
+    db = 0.99 * Rc
+    pts = [(e, db), (-e, db), (-0.3 * Rc, db), (-0.3 * Rc, 1.2 * Rc)]
+    prob = W.single_node_particles(pts, [(0, 0)] * 4, h * h, [0, 1e-2, 0, 1e-2],
+                                   contact_radius=Rc, h=h)
+    fx, fy = Oracle(prob).forces(T_WALL)
+    assert fx[0] == pytest.approx(fx[1], rel=1e-6) and fy[0] == pytest.approx(fy[1], rel=1e-6)
+    # beyond the left wall with the floor's segment wholly inside the left
+    # one, the corner term cancels the floor's own: only the left wall acts
+    fx1, fy1 = Oracle(W.single_node_particles(pts[3:], [(0, 0)], h * h, [0, 1e-2, 0, 1e-2],
+                                              contact_radius=Rc, h=h)).forces(T_WALL)
+    assert fy[2] == pytest.approx(0.0, abs=1e-9 * abs(fx[2]))
+    assert fx[2] == pytest.approx(fx1[0], rel=1e-12)
 
 
 def test_wall_force_pushes_node_away():
