@@ -489,22 +489,49 @@ __device__ void wall_parts(const DevArgs &a, int ag, int part, double px, double
     const int pa[4] = {0, 2, 1, 3}, pb[4] = {2, 1, 3, 0};
     const int wa = pa[part], wb = pb[part];
     const double da = d[wa], db = d[wb];
-    if (!(da > -Rc && db > -Rc && da * da + db * db < Rc * Rc)) return;
-    // triangle (da,db)-(x2,db)-(da,y1) plus the circular segment on its hypotenuse
-    const double x2 = sqrt((Rc - db) * (Rc + db)), y1 = sqrt((Rc - da) * (Rc + da));
-    const double D = (Rc - da) * (Rc + da) - db * db;
-    const double wx = da > 0.0 ? D / (x2 + da) : x2 - da;
-    const double wy = db > 0.0 ? D / (y1 + db) : y1 - db;
-    const double At = 0.5 * wx * wy;
-    const double chord = sqrt(wx * wx + wy * wy);
-    const double half = asin(chord / (2.0 * Rc));
-    const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
-    const double sh = sin(half);
-    const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
-    const double A = At + As;
-    if (!(A > 0.0)) return;
-    const double Ix = At * (da + (da + wx) + da) / 3.0 + ms * (wy / chord);
-    const double Iy = At * (db + db + (db + wy)) / 3.0 + ms * (wx / chord);
+    // the two segments overlap iff the quadrant beyond both walls comes
+    // within Rc of the node (for da, db >= 0: da^2 + db^2 < Rc^2)
+    const double qa = da > 0.0 ? da : 0.0, qb = db > 0.0 ? db : 0.0;
+    if (!(da > -Rc && db > -Rc && qa * qa + qb * qb < Rc * Rc)) return;
+    double A, Ix, Iy;
+    if (da * da + db * db < Rc * Rc) {
+        // the corner (da, db) inside the disk: triangle (da,db)-(x2,db)-(da,y1)
+        // plus the circular segment on its hypotenuse
+        const double x2 = sqrt((Rc - db) * (Rc + db)), y1 = sqrt((Rc - da) * (Rc + da));
+        const double D = (Rc - da) * (Rc + da) - db * db;
+        const double wx = da > 0.0 ? D / (x2 + da) : x2 - da;
+        const double wy = db > 0.0 ? D / (y1 + db) : y1 - db;
+        const double At = 0.5 * wx * wy;
+        const double chord = sqrt(wx * wx + wy * wy);
+        const double half = asin(chord / (2.0 * Rc));
+        const double As = 0.5 * Rc * Rc * phi_minus_sin(2.0 * half);
+        const double sh = sin(half);
+        const double ms = (2.0 / 3.0) * Rc * Rc * Rc * sh * sh * sh;
+        A = At + As;
+        if (!(A > 0.0)) return;
+        Ix = At * (da + (da + wx) + da) / 3.0 + ms * (wy / chord);
+        Iy = At * (db + db + (db + wy)) / 3.0 + ms * (wx / chord);
+    } else if (da < 0.0 && db < 0.0) {
+        // node beyond both walls, corner outside the disk: the disk minus the
+        // two disjoint caps on the near sides of the walls
+        const double pa2 = 4.0 * asin(sqrt((Rc + da) / (2.0 * Rc)));
+        const double pb2 = 4.0 * asin(sqrt((Rc + db) / (2.0 * Rc)));
+        const double qa2 = (Rc - da) * (Rc + da), qb2 = (Rc - db) * (Rc + db);
+        A = Rc * Rc * M_PI - 0.5 * Rc * Rc * (phi_minus_sin(pa2) + phi_minus_sin(pb2));
+        Ix = (2.0 / 3.0) * qa2 * sqrt(qa2);
+        Iy = (2.0 / 3.0) * qb2 * sqrt(qb2);
+    } else {
+        // node beyond one wall, whose line misses the other wall's segment:
+        // the overlap is that whole segment
+        const double dd = da < 0.0 ? db : da;
+        const double ph = 4.0 * asin(sqrt((Rc - dd) / (2.0 * Rc)));
+        const double q2 = (Rc - dd) * (Rc + dd);
+        A = 0.5 * Rc * Rc * phi_minus_sin(ph);
+        if (!(A > 0.0)) return;
+        const double m = (2.0 / 3.0) * q2 * sqrt(q2);
+        Ix = da < 0.0 ? 0.0 : m;
+        Iy = da < 0.0 ? m : 0.0;
+    }
     const double cx = (Ix * nx[wa] + Iy * nx[wb]) / A, cy = (Ix * ny[wa] + Iy * ny[wb]) / A;
     const double dist = sqrt(cx * cx + cy * cy);
     const double wvy = (wa == 3 || wb == 3) ? -vtop : 0.0;

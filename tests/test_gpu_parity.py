@@ -179,6 +179,80 @@ def test_forces_walls_and_corners(pdmod, vtop):
     assert np.count_nonzero(wx) + np.count_nonzero(wy) > 100
 
 
+def test_forces_corner_overlap_beyond_one_wall(pdmod):
+    """Nodes beyond one wall near a corner whose other segment the first
+    wall's line misses (the overlap is that whole segment), and beyond both
+    walls with the corner outside the contact disk (the disk minus two caps):
+    the two segments overlap although d_a^2 + d_b^2 >= R_c^2."""
+    _say("case: forces corner overlap beyond a wall")
+    h = 1e-4
+    Rc = 0.95 * h
+    L = 4e-3
+    pts = []
+    for da, db in [(-0.3, 0.97), (-0.5, 0.9), (-0.2, 0.99), (0.95, -0.4), (-0.75, -0.75),
+                   (-0.6, -0.85), (-0.72, -0.7), (-0.05, 0.999)]:
+        da, db = da * Rc, db * Rc
+        pts += [(da, db), (L - da, db), (L - da, L - db), (da, L - db)]
+    rng = np.random.default_rng(7)
+    vel = [tuple(v) for v in rng.uniform(-0.5, 0.5, (len(pts), 2))]
+    prob = W.single_node_particles(pts, vel, h * h, [0, L, 0, L], contact_radius=Rc, h=h,
+                                   friction_mu=0.4, damping_ratio=0.6, dt=1e-8)
+    _check_forces(pdmod.PD(prob), Oracle(prob), "corner-overlap")
+
+
+def _two_material_bed(seed, kn_mode=W.KN_SELF_CONSISTENT, dt=1e-7, conic=True, alpha=0.45):
+    """A herded bed whose particles alternate between two materials: the
+    configs' material (constant micromodulus) and a stiffer, denser one with
+    the conic micromodulus (Table tab:2d-peri) and a larger horizon."""
+    h = 0.12e-3
+    parts, bx = W.mixed_bed(10, h, 14e-3, 14e-3, seed)
+    for k, p in enumerate(parts):
+        p.material = k % 2
+    mats = [W.Material(horizon=3 * h),
+            W.Material(rho=2400.0, bulk_k=6.0e7, Gc=80.0, horizon=3.5 * h,
+                       micro=W.MICRO_CONIC if conic else W.MICRO_CONST)]
+    prob = W.assemble(parts, h, mats, bx, contact_radius=0.95 * h, friction_mu=0.5,
+                      damping_ratio=0.8, dt=dt, gravity=(0.0, -5000.0), kn_mode=kn_mode)
+    return _herd(prob, alpha, seed=seed, dv=0.5)
+
+
+@pytest.mark.parametrize("seed", [61, 62])
+def test_two_materials_conic(pdmod, seed):
+    """Two materials, one with the conic micromodulus: per-term forces (the
+    harmonic-mean stiffness of Sec. 4.1 between particles of the two
+    materials), bond sets and a 100-step trajectory with breaking."""
+    _say(f"case: two materials, conic micromodulus seed={seed}")
+    prob = _two_material_bed(seed)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    _check_bonds(g, o, "two-materials")
+    g.set_counting(True)
+    _check_forces(g, o, "two-materials t0")
+    eu, ev, sg, so = _traj(g, o, 100)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert np.array_equal(sg["broken"], so["broken"])
+    assert o.counters()["inter"] > 0
+    g.set_state(so)
+    _check_forces(g, o, "two-materials t100")
+
+
+def test_kn_paper_3d(pdmod):
+    """K_n = 18 k / (pi eps^5) as printed (Sec. 4.1), at a step small enough
+    for its stiffness (dt = 1e-8 s), with two materials: forces and a 100-step
+    trajectory against the oracle (particles pushed together less than in the
+    other beds: this stiffness turns the same overlaps into ~1000x the
+    force)."""
+    _say("case: K_n as printed (3-D)")
+    prob = _two_material_bed(63, kn_mode=W.KN_PAPER_3D, dt=1e-8, conic=False, alpha=0.15)
+    g, o = pdmod.PD(prob), Oracle(prob)
+    c = o.constants()
+    assert c["Kn"][0] == pytest.approx(18 * 2.16e7 / (math.pi * prob.materials[0].horizon ** 5),
+                                       rel=1e-14)
+    _check_forces(g, o, "kn3d t0")
+    eu, ev, sg, so = _traj(g, o, 100)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    assert o.counters()["inter"] > 0
+
+
 def _traj(g, o, steps):
     assert g.step(steps, check=False) == o.step(steps)
     sg, so = g.get_state(), o.get_state()
