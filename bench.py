@@ -546,18 +546,24 @@ def settle_shapes(pd, W, torch, micro_s, every_us):
     return res
 
 
-def copy_calibration(torch, mib=256, reps=10):
-    """A plain device-to-device copy of known size, for scaling the HBM
-    byte counters of a profiler run: the counters of this run divided by
-    `reps` x `mib` MiB give the counter's bytes per true byte."""
+def hbm_probe(pd, torch, mib=1024, reps=10):
+    """The library's streaming probe (hand-written read-only and copy
+    kernels) over buffers of `mib` MiB, four times the 256 MB on-package
+    cache: the device's achievable bandwidth, and the known traffic that
+    scales a profiler's byte counters (a read pass moves `mib` MiB, a copy
+    twice that)."""
     n = mib * 1024 * 1024
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    return {"copy_calibration": {"bytes_read_per_copy": n, "bytes_written_per_copy": n,
-                                 "copies": reps}}
+    pd.stream_probe(0, src, dst, 2)
+    pd.stream_probe(1, src, dst, 2)
+    ms_r = pd.stream_probe(0, src, dst, reps)
+    ms_c = pd.stream_probe(1, src, dst, reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": n, "passes": reps,
+            "read_ms": ms_r, "read_GBs": n / (ms_r * 1e-3) / 1e9,
+            "copy_ms": ms_c, "copy_GBs": 2 * n / (ms_c * 1e-3) / 1e9}
 
 
 def main():
@@ -586,8 +592,9 @@ def main():
                     default="batched",
                     help="batched: the headline line (plus the secondary legs unless "
                          "--no-variants); any other: only that leg")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 256 MiB device copy (profiler calibration)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only run the streaming probe (1 GiB read-only and copy passes): "
+                         "achievable bandwidth and profiler counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step loop has "
@@ -603,8 +610,8 @@ def main():
         sys.exit(3)
     torch.cuda.set_device(0)
     fixed = parse_tuning(args.tuning) if args.tuning else None
-    if args.copy_calibration:
-        print(json.dumps(copy_calibration(torch)), flush=True)
+    if args.hbm_probe:
+        print(json.dumps({"hbm_probe": hbm_probe(pd, torch)}), flush=True)
         return
     legs = {
         "settling": lambda: settling_leg(pd, W, torch, args),
@@ -620,6 +627,7 @@ def main():
         return
     prob = W.batched(precision=0)
     out = headline(pd, W, torch, args, prob)
+    out["hbm_measured"] = hbm_probe(pd, torch)
     if not args.no_variants:
         out["settling_100"] = legs["settling"]()
         out["precision_split"] = legs["compaction"]()

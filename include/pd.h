@@ -212,6 +212,17 @@ pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
  * (n_out >= 7) */
 pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out);
 
+/* Streaming probe of known traffic (no context; for measuring the device's
+ * achievable memory bandwidth and for scaling a profiler's byte counters):
+ * mode 0 reads all `bytes` of src once (16-byte loads) and writes 4 bytes
+ * per workgroup of its 4096 to dst (at least 16 KiB); mode 1 copies src to
+ * dst.  Runs `reps` times back to back on the given stream (hipStream_t or
+ * NULL) and returns the mean time per pass in *ms.  src, dst: device
+ * buffers, 16-byte aligned; bytes a positive multiple of 16.
+ * Errors: PD_E_INVALID (arguments), PD_E_DEVICE. */
+pd_status pd_stream_probe(int32_t mode, const void *src, void *dst, int64_t bytes, int32_t reps,
+                          void *hip_stream, double *ms);
+
 /* Sizes: [0] nodes, [1] directed bonds, [2] padded bond slots, [3] cells,
  * [4] radix passes, [5] particles, [6] aggregates, [7] max LDS window,
  * [8] candidate-list rebuilds so far, [9] candidate slots per node. */

@@ -19,7 +19,7 @@ HIP_FLAGS = [
 ]
 
 
-SOURCES = ("pd_kernels.hip", "pd_closure.hip", "pd_host.cpp", "pd_eig.cpp")
+SOURCES = ("pd_kernels.hip", "pd_closure.hip", "pd_host.cpp", "pd_eig.cpp", "pd_probe.hip")
 
 
 def build(verbose: bool = False) -> str:

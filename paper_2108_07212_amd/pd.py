@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     L.pd_autotune.argtypes = [vp, C.c_int32, C.POINTER(Tuning)]
     L.pd_time_kernels.argtypes = [vp, C.c_int64, _dp, _ip, C.c_int32]
     L.pd_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.pd_stream_probe.argtypes = [C.c_int32, vp, vp, C.c_int64, C.c_int32, vp, _dp]
     L.pd_observables.argtypes = [vp, _dp]
     L.pd_particle_damage.argtypes = [vp, vp, C.c_int32]
     L.pd_fragments.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -129,6 +130,21 @@ def load_library(path: str = LIB_PATH):
 CLOSURE_MODES = 32
 CLOSURE_PARAMS = 82464
 CLOSURE_REDUCED = 4  # pd_closure_enable flag: reduced rigid + modal state
+
+
+def stream_probe(mode: int, src, dst, reps: int = 10, stream=None) -> float:
+    """pd_stream_probe over torch device tensors: mean ms per pass of reading
+    (mode 0) or copying (mode 1) all of src."""
+    import torch
+    L = load_library()
+    s = torch.cuda.current_stream() if stream is None else stream
+    ms = C.c_double()
+    st = L.pd_stream_probe(mode, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                           src.numel() * src.element_size(), reps, C.c_void_p(s.cuda_stream),
+                           C.byref(ms))
+    if st != PD_OK:
+        raise PDError(st, "pd_stream_probe")
+    return ms.value
 
 
 def _p(a, t):
