@@ -159,6 +159,21 @@ pd_status pd_step(pd_ctx *c, int64_t n_steps);
  * [n_nodes], host or device (on_device = 1). */
 pd_status pd_forces(pd_ctx *c, uint32_t term_mask, double *fx, double *fy, int32_t on_device);
 
+/* pd_forces for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same evaluation and the same results as pd_forces(..., on_device = 1),
+ * with the per-term workspace in a fixed array of 32 MiB that each device
+ * the library runs on holds from its first pd_setup until the process ends
+ * (10 doubles per node: at most 419 430 nodes).  The call allocates nothing.
+ * fx, fy: [n_nodes] device buffers on the context's device.
+ * Errors: PD_E_INVALID for a null output or a problem with more nodes than
+ * the workspace holds (nothing is launched), PD_E_DEVICE.
+ * Every call on one device shares that device's workspace, which keeps the
+ * last call's contents (each call writes every entry it reads): calls that
+ * overlap on one device, from contexts on different streams or threads,
+ * race and must be serialised by the caller. */
+pd_status pd_forces_noalloc(pd_ctx *c, uint32_t term_mask, double *fx, double *fy);
+
 /* Damage of each node (Sec. 3.1): broken bonds / reference bonds, and the
  * number of broken directed bonds.  phi: [n_nodes] host or device, or NULL. */
 pd_status pd_damage(pd_ctx *c, double *phi, int64_t *n_broken_directed, int32_t on_device);

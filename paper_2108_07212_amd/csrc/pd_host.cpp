@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -17,6 +18,38 @@ using namespace pd;
 struct pd_ctx {
     Ctx c;
 };
+
+// Workspace of pd_forces_noalloc: the per-term force densities of one
+// evaluation, 10 doubles per node.  Every device the library runs on holds
+// its own copy until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol: its device address, per device, comes from
+// hipGetSymbolAddress at pd_setup and is the only handle host code uses.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (the device must be current)
+hipError_t scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+    return hipSuccess;
+}
+
+double *scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -1291,7 +1324,9 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     c.A = A;
     c.M = M;
     c.precision = p->precision;
-    // ---- stream ----
+    // ---- device, its workspace of pd_forces_noalloc, stream ----
+    HIPCHK(hipGetDevice(&c.device));
+    HIPCHK(scratch_init(c.device));
     if (p->hip_stream) {
         c.stream = (hipStream_t)p->hip_stream;
     } else {
@@ -1568,6 +1603,32 @@ pd_status pd_forces(pd_ctx *ctx, uint32_t mask, double *fx, double *fy, int32_t 
         HIPCHK(hipMemcpyAsync(fx, ox, c.N * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipMemcpyAsync(fy, oy, c.N * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PD_OK;
+}
+
+pd_status pd_forces_noalloc(pd_ctx *ctx, uint32_t mask, double *fx, double *fy) {
+    if (!ctx) return PD_E_INVALID;
+    Ctx &c = ctx->c;
+    if (!fx || !fy) return fail(c, PD_E_INVALID, "pd_forces_noalloc: null output");
+    const size_t need = (size_t)10 * (size_t)c.N * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(c, PD_E_INVALID,
+                    "pd_forces_noalloc: " + std::to_string(c.N) + " nodes need " +
+                        std::to_string(need) + " bytes of workspace, more than its " +
+                        std::to_string(kScratchBytes) + " (at most " +
+                        std::to_string(kScratchBytes / (10 * sizeof(double))) + " nodes)");
+    double *ws = scratch_of(c.device);
+    if (!ws) return fail(c, PD_E_STATE, "pd_forces_noalloc: no workspace on this device");
+    TRY(after_caller(c));
+    TRY(rc_sync(c));
+    HIPCHK(enqueue_search(c, c.cur, 0, 0));
+    set_state_ptrs(c, c.cur);
+    DevArgs a = c.a;
+    a.terms = ws;       // every entry is written by the force kernel
+    a.smax = nullptr;
+    HIPCHK(launch_force(a, c.precision, M_FORCES, lds_cap(c), c.stream));
+    HIPCHK(launch_sum_terms(a, mask, fx, fy, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     return PD_OK;
 }

@@ -299,6 +299,7 @@ struct Ctx {
     hipGraphExec_t lgraph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::map<long, hipGraphExec_t> lgraph_n;          // shorter replays, by (parity, length)
     hipStream_t stream = nullptr;
+    int device = 0;              // the HIP device current at setup
     bool own_stream = false;
     hipEvent_t caller_ev = nullptr;  // with an own stream: orders it after the legacy default stream
     int precision = 0;

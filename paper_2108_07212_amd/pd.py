@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.pd_last_error.restype = C.c_char_p
     L.pd_step.argtypes = [vp, C.c_int64]
     L.pd_forces.argtypes = [vp, C.c_uint32, vp, vp, C.c_int32]
+    L.pd_forces_noalloc.argtypes = [vp, C.c_uint32, vp, vp]
     L.pd_damage.argtypes = [vp, vp, C.POINTER(C.c_int64), C.c_int32]
     L.pd_n_bonds.argtypes = [vp]
     L.pd_n_bonds.restype = C.c_int64
@@ -231,6 +232,12 @@ class PD:
         fy = np.zeros(self.N)
         self._chk(self.lib.pd_forces(self.h, mask, C.c_void_p(fx.ctypes.data),
                                      C.c_void_p(fy.ctypes.data), 0))
+        return fx, fy
+
+    def forces_noalloc(self, fx, fy, mask: int = TERM_ALL):
+        """pd_forces_noalloc into caller-owned device tensors fx, fy (float64, n_nodes)."""
+        self._chk(self.lib.pd_forces_noalloc(self.h, mask, C.c_void_p(fx.data_ptr()),
+                                             C.c_void_p(fy.data_ptr())))
         return fx, fy
 
     def damage(self):
