@@ -117,8 +117,9 @@ typedef struct {
 
 /* Tuning of the launch configuration.  Results are bitwise identical for
  * every block size, staging and graph choice, and equal within rounding for
- * every cell factor and skin (the contact set itself never changes: it is
- * evaluated from exact distances every step). */
+ * every cell factor, skin and lane count (the contact set itself never
+ * changes: it is evaluated from exact distances every step; the lane count
+ * changes the order of the per-node sums). */
 typedef struct {
     int32_t block_nodes;  /* nodes per workgroup of the force kernel: 64, 128 or 256 */
     double cell_factor;   /* cell side / search radius, >= 1 */
@@ -127,6 +128,9 @@ typedef struct {
     double skin_factor;   /* contact candidates within R_c (1 + skin_factor) are listed per node
                              and the list is rebuilt (cell-key radix sort) when a node has moved
                              half the skin or a bond broke; 0: search the cells every step */
+    int32_t lanes_per_node; /* threads per node of the step kernel with candidate lists: 4 (short
+                               chains of dependent work, small problems), 2 or 1 (per-node work
+                               done once, large problems); other evaluations use 4 */
 } pd_tuning;
 
 /* Builds the context: validates the problem, copies it to the device,

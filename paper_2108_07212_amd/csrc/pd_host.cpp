@@ -571,6 +571,10 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
         HIPCHK(hipStreamSynchronize(c.stream));
         if (over == 0) {
             c.list_valid = true;
+            const double gap = (double)(c.step - c.last_rebuild_step);
+            if (c.rebuilds > 0 && gap > 0.0)
+                c.rebuild_interval = c.rebuild_interval > 1e8 ? gap : 0.5 * (c.rebuild_interval + gap);
+            c.last_rebuild_step = c.step;
             ++c.rebuilds;
             return rc_activate(c);
         }
@@ -619,6 +623,16 @@ pd_status step_lists(Ctx &c, int64_t n) {
         HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
                               c.stream));
         int64_t lim = std::min<int64_t>(left, kChunk);
+        // lists that go stale every few steps: replays of about twice the
+        // usual interval (a power of two, at least 8 steps), one per round
+        // trip, so that few launches run as no-ops after a stale step
+        bool short_runs = false;
+        if (c.rebuild_interval < 0.5 * kChunk) {
+            int64_t len = 8;
+            while (len < 2.0 * c.rebuild_interval && len < kChunk) len *= 2;
+            short_runs = len < kChunk;
+            lim = std::min<int64_t>(lim, len);
+        }
         if (c.cl.mode && c.cl.check_every > 0)
             lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
         if (n_wall > 0) lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - c.cl.rb_step)));
@@ -631,7 +645,8 @@ pd_status step_lists(Ctx &c, int64_t n) {
             // step stays recorded), and kChunk is even, so every replay starts
             // at the same buffer parity
             static_assert(kChunk % 2 == 0, "replays queued back to back share a parity");
-            if (!c.cl.mode) reps = (int)std::min<int64_t>(kReplaysPerSync, left / kChunk);
+            if (!c.cl.mode && !short_runs)
+                reps = (int)std::min<int64_t>(kReplaysPerSync, left / kChunk);
             for (int r = 0; r < reps; ++r) {
                 if (r > 0)
                     HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base,
@@ -1541,6 +1556,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     c.step = 0;
     TRY(set_device_step(c));
     a.use_lds = c.tune.use_lds;
+    a.lanes = c.tune.lanes_per_node;
     TRY(build_windows(c));
     // ---- t = 0: forces at u0, v0 with the break rule; a0 = F / (rho V) + g ----
     HIPCHK(enqueue_search(c, 0, 0, 0));
@@ -1864,6 +1880,8 @@ pd_status pd_set_state(pd_ctx *ctx, const double *ux, const double *uy, const do
     HIPCHK(hipStreamSynchronize(c.stream));
     c.status = 0;
     c.list_valid = false;
+    c.rebuild_interval = 1e9;
+    c.last_rebuild_step = step;
     set_state_ptrs(c, 0);
     if (c.cl.ready && c.cl.mode && c.cl.reduced) {
         // the reduced state of the closure particles from the loaded nodes,
@@ -1904,6 +1922,8 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
     Ctx &c = ctx->c;
     if (!(t->block_nodes == 64 || t->block_nodes == 128 || t->block_nodes == 256))
         return fail(c, PD_E_INVALID, "block_nodes must be 64, 128 or 256");
+    if (!(t->lanes_per_node == 1 || t->lanes_per_node == 2 || t->lanes_per_node == 4))
+        return fail(c, PD_E_INVALID, "lanes_per_node must be 1, 2 or 4");
     if (!(t->cell_factor >= 1.0) || t->cell_factor > 64.0)
         return fail(c, PD_E_INVALID, "cell_factor must be in [1, 64]");
     if (!(t->skin_factor >= 0.0) || t->skin_factor > 16.0)
@@ -1917,7 +1937,9 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
     c.tune.use_lds = t->use_lds ? 1 : 0;
     c.tune.use_graph = t->use_graph ? 1 : 0;
     c.a.use_lds = c.tune.use_lds;
+    c.a.lanes = c.tune.lanes_per_node;
     c.list_valid = false;
+    c.rebuild_interval = 1e9;  // the skin may have changed
     set_list_params(c);
     if (regrid) {
         std::vector<double> box(4 * (size_t)c.A);
@@ -2103,38 +2125,41 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     const int blocks[3] = {256, 128, 64};
+    const int lanes[3] = {4, 2, 1};
     // skin 0 (cell search every step) also tries cells of twice the contact
     // radius: four times fewer cells can take a radix pass off the key sort
     const double skins[5] = {0.0, 0.0, 0.5, 1.0, 2.0};
     const double cells[5] = {1.0, 2.0, 1.0, 1.0, 1.0};
     pd_status result = PD_OK;
-    for (int bi = 0; bi < 3 && result == PD_OK; ++bi)
-        for (int ci = 0; ci < 5 && result == PD_OK; ++ci)
-            for (int li = 0; li < 2 && result == PD_OK; ++li) {
-                pd_tuning t = base;
-                t.block_nodes = blocks[bi];
-                t.cell_factor = cells[ci];
-                t.skin_factor = skins[ci];
-                t.use_lds = 1 - li;
-                if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
-                // restore and warm up
-                for (int k = 0; k < 6; ++k)
-                    HIPCHK(hipMemcpyAsync(src[k], save + k * c.N, nb, hipMemcpyDeviceToDevice, c.stream));
-                c.cur = cur0;
-                c.step = step0;
-                TRY(set_device_step(c));
-                if ((result = pd_step(ctx, 2)) != PD_OK) break;
-                HIPCHK(hipEventRecord(e0, c.stream));
-                if ((result = pd_step(ctx, steps)) != PD_OK) break;
-                HIPCHK(hipEventRecord(e1, c.stream));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
-                }
-            }
+    for (int trial = 0; trial < 3 * 5 * 2 * 3 && result == PD_OK; ++trial) {
+        const int bi = trial / 30, ci = (trial / 6) % 5, li = (trial / 3) % 2, ni = trial % 3;
+        // the lane count matters to the list-mode step only
+        if (skins[ci] == 0.0 && ni > 0) continue;
+        pd_tuning t = base;
+        t.block_nodes = blocks[bi];
+        t.cell_factor = cells[ci];
+        t.skin_factor = skins[ci];
+        t.use_lds = 1 - li;
+        t.lanes_per_node = skins[ci] > 0.0 ? lanes[ni] : 4;
+        if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
+        // restore and warm up
+        for (int k = 0; k < 6; ++k)
+            HIPCHK(hipMemcpyAsync(src[k], save + k * c.N, nb, hipMemcpyDeviceToDevice, c.stream));
+        c.cur = cur0;
+        c.step = step0;
+        TRY(set_device_step(c));
+        if ((result = pd_step(ctx, 2)) != PD_OK) break;
+        HIPCHK(hipEventRecord(e0, c.stream));
+        if ((result = pd_step(ctx, steps)) != PD_OK) break;
+        HIPCHK(hipEventRecord(e1, c.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     pd_status s2 = pd_set_tuning(ctx, &best);

@@ -77,6 +77,7 @@ struct DevArgs {
     const int *win_lo, *win_hi;  // per force block
     int block_nodes;
     int use_lds;
+    int lanes;               // lanes per node of the list-mode step kernel (1, 2 or 4)
     // state: read buffers (cur) and write buffers (nxt)
     const double *ux, *uy, *vx, *vy, *ax, *ay;
     double *ux_o, *uy_o, *vx_o, *vy_o, *ax_o, *ay_o;
@@ -292,9 +293,14 @@ struct ClState {
 struct Ctx {
     DevArgs a{};
     ClState cl;
-    pd_tuning tune{64, 1.0, 1, 1, 1.0};
+    pd_tuning tune{64, 1.0, 1, 1, 1.0, 4};
     bool list_valid = false;     // candidate lists match the current state
     int64_t rebuilds = 0;
+    // steps between candidate-list rebuilds, running average (list mode): a
+    // replay is made no longer than about this, so that a bed whose lists go
+    // stale often does not queue launches that a stale step turns into no-ops
+    double rebuild_interval = 1e9;
+    int64_t last_rebuild_step = 0;
     // kChunk list-mode steps, [with the plain-force launch (closure on)][parity]
     hipGraphExec_t lgraph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::map<long, hipGraphExec_t> lgraph_n;          // shorter replays, by (parity, length)

@@ -460,6 +460,16 @@ __device__ void wall_forces(const DevArgs &a, int ag, int part, double px, doubl
     fy += cry;
 }
 
+// whether node p is within R_c of a wall of its aggregate, or beyond one
+// (the same test as the quick exit of wall_parts)
+__device__ __forceinline__ bool near_wall(const DevArgs &a, int ag, double px, double py,
+                                          double t) {
+    const double Rc = a.Rc;
+    const double *b = a.box + 4 * ag;
+    return !(px - b[0] >= Rc && b[1] - px >= Rc && py - b[2] >= Rc &&
+             (b[3] - a.vtop[ag] * t) - py >= Rc);
+}
+
 __device__ void wall_parts(const DevArgs &a, int ag, int part, double px, double py, double vxi,
                            double vyi, double mi, double Vi, double Kn, double t, double &fx,
                            double &fy, double &crx, double &cry, int &st) {
@@ -689,6 +699,42 @@ __device__ __forceinline__ T quad_sum(T v) {
     return v;
 }
 
+// the same over the LPN lanes of a node (LPN = 1, 2 or 4 consecutive lanes;
+// quad_xor<1> swaps the lanes of each pair): (l0 + l1) + (l2 + l3)
+template <int LPN, typename T>
+__device__ __forceinline__ T lanes_sum(T v) {
+    if constexpr (LPN >= 2) v += quad_xor<1>(v);
+    if constexpr (LPN == 4) v += quad_xor<2>(v);
+    return v;
+}
+template <int LPN>
+__device__ __forceinline__ int lanes_or(int v) {
+    if constexpr (LPN >= 2) v |= quad_xor<1>(v);
+    if constexpr (LPN == 4) v |= quad_xor<2>(v);
+    return v;
+}
+template <int LPN>
+__device__ __forceinline__ double lanes_max(double v) {
+    if constexpr (LPN >= 2) v = fmax(v, quad_xor<1>(v));
+    if constexpr (LPN == 4) v = fmax(v, quad_xor<2>(v));
+    return v;
+}
+
+// The largest SELL-16 row width among the slices of a wavefront's nodes
+// (64 / LPN nodes: one slice at LPN 4, two at 2, four at 1), uniform over
+// the wavefront so that the slot loop exits on a scalar branch.
+template <int LPN>
+__device__ __forceinline__ int wave_row_width(int w) {
+    if constexpr (LPN == 4) {
+        return __builtin_amdgcn_readfirstlane(w);
+    } else if constexpr (LPN == 2) {
+        return max(__builtin_amdgcn_readlane(w, 0), __builtin_amdgcn_readlane(w, 32));
+    } else {
+        return max(max(__builtin_amdgcn_readlane(w, 0), __builtin_amdgcn_readlane(w, 16)),
+                   max(__builtin_amdgcn_readlane(w, 32), __builtin_amdgcn_readlane(w, 48)));
+    }
+}
+
 // The start of node i's SELL-16 row for lane `sub`: slice base, row width and
 // the lane's first batch of slot words, loaded early (before the workgroup's
 // LDS staging) so that these dependent loads overlap the staging loads.
@@ -699,6 +745,7 @@ struct SlotHead {
     uint32_t ev[kBatch];
 };
 
+template <int LPN>
 __device__ __forceinline__ void slot_head(const DevArgs &a, int i, int sub, SlotHead &h) {
     const uint32_t sl = (uint32_t)i / kSlice;
     const uint32_t p0 = a.slice_ptr[sl], p1 = a.slice_ptr[sl + 1];
@@ -706,22 +753,33 @@ __device__ __forceinline__ void slot_head(const DevArgs &a, int i, int sub, Slot
     h.W = (int)((p1 - p0) / kSlice);
 #pragma unroll
     for (int t = 0; t < kBatch; ++t) {
-        const int k = sub + 4 * t;
+        const int k = sub + LPN * t;
         h.ev[t] = k < h.W ? a.col[h.base + (uint32_t)k * kSlice] : kBroken;
     }
 }
 
-// Bond forces of node i from the slots k = sub, sub + 4, ... of its SELL-16
-// row (lane `sub` of the node's quad).  Every slot runs the same branch-free
-// arithmetic (padding and broken slots are masked), so consecutive slots form
-// independent chains the compiler can interleave.  A bond whose approximate
-// stretch comes within 1e-10 (FP64) or 2e-6 (FP32) of s0 is re-decided with
-// the stretch evaluated in IEEE FP64 (correctly rounded square roots and
-// division), the exact decision of Sec. 3.1.
+// The exact decision of Sec. 3.1 for bond (i, j): the stretch evaluated in
+// IEEE FP64 (correctly rounded square roots and division, no contraction:
+// the expression the oracle evaluates, bit for bit).
+__device__ __forceinline__ bool exact_break(double X, double Y, double EX, double EY, double DX,
+                                         double DY, double s0) {
+    const double l0x = __dsqrt_rn(__dadd_rn(__dmul_rn(X, X), __dmul_rn(Y, Y)));
+    const double lx = __dsqrt_rn(__dadd_rn(__dmul_rn(DX, DX), __dmul_rn(DY, DY)));
+    const double nm = __dadd_rn(__dmul_rn(EX, __dadd_rn(DX, X)), __dmul_rn(EY, __dadd_rn(DY, Y)));
+    const double sx = __ddiv_rn(nm, __dmul_rn(l0x, __dadd_rn(lx, l0x)));
+    return fabs(sx) > s0;
+}
+
+// Bond forces of node i from the slots k = sub, sub + LPN, ... of its
+// SELL-16 row (lane `sub` of the node's LPN lanes).  Every slot runs the
+// same branch-free arithmetic (padding and broken slots are masked), so
+// consecutive slots form independent chains the compiler can interleave.  A
+// bond whose approximate stretch comes within 1e-10 (FP64) or 2e-6 (FP32) of
+// s0 is re-decided by exact_break.
 // STAGED: partner data from the workgroup's LDS window (a separate
 // instantiation, so that no load merges LDS and global addresses into one
 // generic access).
-template <typename R, int MODE, bool STAGED>
+template <typename R, int MODE, bool STAGED, int LPN>
 __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc, int i, int sub,
                                             int lo, const double *S, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
@@ -730,29 +788,34 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t base = h.base;
-        // the row width of the node's SELL-16 slice; a wavefront's 16 nodes are
-        // one slice, so it is uniform and the loop below branches on a scalar
-        const int W = __builtin_amdgcn_readfirstlane(h.W);
-        const double cw = mc.cw, s0 = mc.s0, inv_eps = 1.0 / mc.eps;
-        const bool conic = mc.conic != 0;
-        // this lane's slots k = sub + 4 t; their words are fetched in batches of
-        // kBatch before any of them is used, so the loads overlap (the first
-        // batch comes with the row head)
-        for (int kb = 0; kb < W; kb += 4 * kBatch) {
+        const int Wi = h.W;  // this node's slice
+        // the widest slice of the wavefront's nodes: the loop below branches on
+        // a scalar; a lane past its own row holds padding words (kBroken)
+        const int W = wave_row_width<LPN>(Wi);
+        const double s0 = mc.s0, s0m = mc.s0 * (1.0 - 1e-10);
+        // per node: c_w V_i; the conic weight 1 - l0/eps as fma(-l0, ie, 1)
+        // with ie = 0 for the constant micromodulus (w = 1 exactly)
+        const double cVi = mc.cw * Vi;
+        const double ie = mc.conic != 0 ? 1.0 / mc.eps : 0.0;
+        // this lane's slots k = sub + LPN t; their words are fetched in batches
+        // of kBatch before any of them is used, so the loads overlap (the
+        // first batch comes with the row head)
+        constexpr int NB = LPN == 4 ? kBatch : kBatch / 2;
+        for (int kb = 0; kb < W; kb += LPN * NB) {
             const int k0 = kb + sub;
-            uint32_t ev[kBatch];
+            uint32_t ev[NB];
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                const int k = k0 + 4 * t;
-                ev[t] = kb == 0 ? h.ev[t] : (k < W ? a.col[base + (uint32_t)k * kSlice] : kBroken);
+            for (int t = 0; t < NB; ++t) {
+                const int k = k0 + LPN * t;
+                ev[t] = (kb == 0 && t < kBatch) ? h.ev[t < kBatch ? t : 0]
+                                                 : (k < Wi ? a.col[base + (uint32_t)k * kSlice] : kBroken);
             }
             // fully unrolled, so that ev[t] is a register and not a select
-            // chain; the wavefront leaves at the row's end (a lane whose slot
-            // is past it holds a padding word, so it adds nothing)
+            // chain; the wavefront leaves at the row's end
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                const int k = k0 + 4 * t;
-                if (kb + 4 * t >= W) break;
+            for (int t = 0; t < NB; ++t) {
+                const int k = k0 + LPN * t;
+                if (kb + LPN * t >= W) break;
                 const uint32_t e = ev[t];
                 const bool valid = (e & kBroken) == 0;
                 const int j = valid ? (int)e : i;
@@ -786,61 +849,60 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                 const double X = xj - xi, Y = yj - yi;
                 const double EX = uxj - uxi, EY = uyj - uyi;
                 const double DX = X + EX, DY = Y + EY;
+                // padding slots (j = i) have X = Y = EX = EY = 0: the floors keep
+                // their arithmetic finite and their coefficient is zero, as is
+                // that of a broken bond
                 bool cand;
                 R g, DXr, DYr;
                 if constexpr (sizeof(R) == 8) {
-                    const double l0s = valid ? X * X + Y * Y : 1.0;
-                    const double ls = valid ? DX * DX + DY * DY : 1.0;
+                    const double l0s = fmax(fma(X, X, Y * Y), 1e-200);
+                    const double ls = fmax(fma(DX, DX, DY * DY), 1e-200);
                     const double r0 = rsq_nr(l0s), rl = rsq_nr(ls);
                     const double l0 = l0s * r0, l = ls * rl;
-                    const double num = EX * (DX + X) + EY * (DY + Y);
+                    const double num = fma(EX, DX + X, EY * (DY + Y));
                     const double s = num * rcp_nr(l0 * (l + l0));
-                    cand = valid && fabs(s) > s0 * (1.0 - 1e-10);
+                    cand = valid && fabs(s) > s0m;
                     if (MODE == M_FORCES && valid) smx = fmax(smx, fabs(s));
-                    const double w = conic ? 1.0 - l0 * inv_eps : 1.0;
-                    const double f = valid ? cw * w * s * Vi * Vj : 0.0;
-                    g = f * rl;
+                    const double cf = valid ? cVi * Vj : 0.0;
+                    g = (cf * fma(-l0, ie, 1.0)) * s * rl;
                     DXr = DX;
                     DYr = DY;
                 } else {
                     const float Xf = (float)X, Yf = (float)Y, DXf = (float)DX, DYf = (float)DY;
                     const float EXf = (float)EX, EYf = (float)EY;
-                    const float l0s = valid ? Xf * Xf + Yf * Yf : 1.0f;
-                    const float ls = valid ? DXf * DXf + DYf * DYf : 1.0f;
+                    const float l0s = fmaxf(fmaf(Xf, Xf, Yf * Yf), 1e-30f);
+                    const float ls = fmaxf(fmaf(DXf, DXf, DYf * DYf), 1e-30f);
                     const float r0 = __builtin_amdgcn_rsqf(l0s), rl = __builtin_amdgcn_rsqf(ls);
                     const float l0 = l0s * r0, l = ls * rl;
-                    const float num = EXf * (DXf + Xf) + EYf * (DYf + Yf);
+                    const float num = fmaf(EXf, DXf + Xf, EYf * (DYf + Yf));
                     const float s = num * __builtin_amdgcn_rcpf(l0 * (l + l0));
                     cand = valid && fabsf(s) > (float)(s0 - 2e-6);
                     if (MODE == M_FORCES && valid) smx = fmax(smx, (double)fabsf(s));
-                    const float w = conic ? 1.0f - l0 * (float)inv_eps : 1.0f;
-                    const float f = valid ? (float)cw * w * s * (float)Vi * (float)Vj : 0.0f;
-                    g = f * rl;
+                    const float cf = valid ? (float)cVi * (float)Vj : 0.0f;
+                    g = (cf * fmaf(-l0, (float)ie, 1.0f)) * s * rl;
                     DXr = DXf;
                     DYr = DYf;
                 }
-                if (cand) {  // rare: the exact decision (Sec. 3.1, broken for good)
-                    const double l0x = sqrt(X * X + Y * Y), lx = sqrt(DX * DX + DY * DY);
-                    const double sx = (EX * (DX + X) + EY * (DY + Y)) / (l0x * (lx + l0x));
-                    if (fabs(sx) > s0) {
-                        if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
-                        if (nbrk < 4) bj[nbrk] = j;  // partners for the candidate list
-                        ++nbrk;
-                        g = 0;
-                    }
+                if (cand && exact_break(X, Y, EX, EY, DX, DY, s0)) {
+                    // rare: broken for good (Sec. 3.1)
+                    if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
+                    if (nbrk < 4) bj[nbrk] = j;  // partners for the candidate list
+                    ++nbrk;
+                    g = 0;
                 }
-                fpx += g * DXr;
-                fpy += g * DYr;
+                fpx = fma(g, DXr, fpx);
+                fpy = fma(g, DYr, fpy);
             }
         }
     }
 }
 
-// Contact forces of node i (lane `sub` of its quad): with candidate lists
-// (LIST), the listed candidates j with j mod 4 = sub; otherwise the nodes of the cells
-// sub, sub + 4, sub + 8 of the 3 x 3 neighbourhood.  Pairs closer than R_c
-// act; an intact bond replaces contact between nodes of one particle.
-template <typename R, bool LIST, bool adv>
+// Contact forces of node i (lane `sub` of its LPN lanes): with candidate
+// lists (LIST), the listed candidates j with j mod LPN = sub; otherwise (LPN
+// 4) the nodes of the cells sub, sub + 4, sub + 8 of the 3 x 3
+// neighbourhood.  Pairs closer than R_c act; an intact bond replaces contact
+// between nodes of one particle.
+template <typename R, bool LIST, bool adv, int LPN = 4>
 __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst &mc, int i,
                                                int sub, int pi, int ag, double xi, double yi,
                                                double pxi, double pyi, double vxi, double vyi,
@@ -848,7 +910,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                                                R &fny, int nc_pre = -1, bool un = false) {
     if (LIST) {
         // candidates listed at the last rebuild (intact bonds excluded)
-        // candidate j goes to lane j mod 4, in ascending j (the list is
+        // candidate j goes to lane j mod LPN, in ascending j (the list is
         // sorted): a lane's sum then depends only on the pairs within R_c,
         // not on which extra candidates the list holds (it is a superset that
         // depends on when it was built)
@@ -861,7 +923,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                 js[t] = q0 + t < nc ? (int)a.clist[(size_t)(q0 + t) * a.N + i] : -1;
             for (int t = 0; t < kCB; ++t) {
                 const int j = js[t];
-                if (j < 0 || (j & 3) != sub) continue;
+                if (j < 0 || (j & (LPN - 1)) != sub) continue;
                 double pxj, pyj, ux, uy;
                 if (adv)
                     advanced_pos_un(a, j, un, pxj, pyj, ux, uy);
@@ -880,6 +942,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
             }
         }
     } else {
+        static_assert(LIST || LPN == 4, "the cell search runs with four lanes per node");
         // nodes of the 3 x 3 neighbouring cells, cells sub, sub + 4, sub + 8
         int cx, cy;
         cell_of(a, ag, pxi, pyi, cx, cy);
@@ -911,22 +974,27 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
     }
 }
 
-// Four lanes per node: lane `sub` of node i takes the bond slots k = sub,
-// sub + 4, ... of the node's SELL-16 row, every fourth contact candidate, one
-// wall and one corner; the quad then combines its partial sums in a fixed
-// order and lane 0 integrates.  LDS holds the block's window of bond partners
-// (reference and current positions, volumes).
+// LPN lanes per node (1, 2 or 4): lane `sub` of node i takes the bond slots
+// k = sub, sub + LPN, ... of the node's SELL-16 row, every LPN-th contact
+// candidate and the walls and corners sub, sub + LPN, ...; the node's lanes
+// then combine their partial sums in a fixed order and lane 0 integrates.
+// Four lanes keep the chain of dependent work per wavefront short (small
+// problems, where latency bounds a launch); one lane does the per-node work
+// (walls, candidates, reductions, integration) once instead of four times
+// (large problems, bound by instruction issue).  LDS holds the block's window
+// of bond partners (reference and current positions, volumes).
 // The step (or force evaluation) of the nodes of force workgroup `blk`.
 // SEL (step mode with the modal closure on): 0 every node; 1 only the nodes
 // of particles under the plain bond force (closure nodes are left to
 // k_cl_contact and the closure kernels).
-template <typename R, int MODE, bool LIST, int SEL>
+template <typename R, int MODE, bool LIST, int SEL, int LPN>
 __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int blk,
                                             long long sprev, double *lds) {
+    static_assert(LPN == 1 || LPN == 2 || LPN == 4, "1, 2 or 4 lanes per node");
     double *S = lds;  // the window, kWin doubles per node
     constexpr bool adv = (MODE == M_STEP);
-    const int sub = threadIdx.x & 3;
-    const int i = blk * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    const int sub = threadIdx.x & (LPN - 1);
+    const int i = blk * (blockDim.x / LPN) + (threadIdx.x / LPN);
     if (SEL == 1) {
         const int mine = (i < a.N && !a.cl_on[a.part[i]]) ? 1 : 0;
         if (!__syncthreads_or(mine)) return;
@@ -947,11 +1015,18 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     const double Vi = a.vol[ic], mi = a.mass[ic];
     const int pi = a.part[ic];
     SlotHead head;
-    slot_head(a, ic, sub, head);
+    slot_head<LPN>(a, ic, sub, head);
     const int nc_pre = LIST ? a.clist_n[ic] : -1;
-    // the epilogue's own-node loads, issued now rather than at the end
-    const double axi = a.ax[ic], ayi = a.ay[ic];
-    const double ubxi = LIST ? (double)a.ubx[ic] : 0.0, ubyi = LIST ? (double)a.uby[ic] : 0.0;
+    // the epilogue's own-node loads: with four lanes, issued now rather than
+    // at the end (the launch is latency-bound); with fewer, at the end (the
+    // registers they would hold through the bond loop are scarcer there)
+    double axi = 0.0, ayi = 0.0, ubxi = 0.0, ubyi = 0.0;
+    if constexpr (LPN == 4) {
+        axi = a.ax[ic];
+        ayi = a.ay[ic];
+        ubxi = LIST ? (double)a.ubx[ic] : 0.0;
+        ubyi = LIST ? (double)a.uby[ic] : 0.0;
+    }
     int lo = 0;
     bool staged = false;
     if (SEL == 0 && a.use_lds) {
@@ -973,7 +1048,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         }
         __syncthreads();
     }
-    if (i >= a.N) return;  // whole quads leave together
+    if (i >= a.N) return;  // a node's lanes leave together
 
     const int mt = a.pmat[pi];
     const int ag = a.pagg[pi];
@@ -990,48 +1065,55 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     // a particle under the modal closure: no bond forces here; its external
     // nodal force goes to the closure kernels, which integrate its nodes
     const bool closure = MODE == M_STEP && a.cl_on && a.cl_on[pi];
-    if (SEL == 1 && closure) return;   // whole quads leave together
+    if (SEL == 1 && closure) return;   // a node's lanes leave together
     // List mode runs the bond loop first (its contact candidates never
     // involve intact bonds, so the order does not matter there), which keeps
     // fewer partial sums live through the loop.  Otherwise contact comes
     // first, because self-contact needs the bonds intact at the start of the
     // step and the bond loop commits breaks.
+    // (list mode: the walls come after the lanes' sums and the list appends
+    // below, where fewer values are live)
     if constexpr (LIST) {
         if (!closure)
-            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un)
-                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un);
-        contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
-                                     fsx, fsy, fnx, fny, nc_pre, un);
-        wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+            staged ? bond_forces<R, MODE, true, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
+                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un)
+                   : bond_forces<R, MODE, false, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
+                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un);
+        contact_forces<R, LIST, adv, LPN>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi,
+                                          mi, fsx, fsy, fnx, fny, nc_pre, un);
     } else {
-        contact_forces<R, LIST, adv>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
-                                     fsx, fsy, fnx, fny);
-        wall_forces(a, ag, sub, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+        contact_forces<R, LIST, adv, LPN>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi,
+                                          mi, fsx, fsy, fnx, fny);
+#pragma unroll 1
+        for (int part = sub; part < 4; part += LPN)
+            wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
-            staged ? bond_forces<R, MODE, true>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false)
-                   : bond_forces<R, MODE, false>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                 uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false);
+            staged ? bond_forces<R, MODE, true, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
+                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false)
+                   : bond_forces<R, MODE, false, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
+                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false);
     }
 
-    // ---- combine the quad ------------------------------------------------------
-    fpx = quad_sum(fpx);
-    fpy = quad_sum(fpy);
-    fsx = quad_sum(fsx);
-    fsy = quad_sum(fsy);
-    fnx = quad_sum(fnx);
-    fny = quad_sum(fny);
-    fwx = quad_sum(fwx);
-    fwy = quad_sum(fwy);
+    // ---- combine the node's lanes -----------------------------------------------
+    fpx = lanes_sum<LPN>(fpx);
+    fpy = lanes_sum<LPN>(fpy);
+    fsx = lanes_sum<LPN>(fsx);
+    fsy = lanes_sum<LPN>(fsy);
+    fnx = lanes_sum<LPN>(fnx);
+    fny = lanes_sum<LPN>(fny);
+    if constexpr (LPN != 4) {
+        axi = a.ax[i];
+        ayi = a.ay[i];
+        ubxi = LIST ? (double)a.ubx[i] : 0.0;
+        ubyi = LIST ? (double)a.uby[i] : 0.0;
+    }
     // list mode: a bond that broke makes its pair a self-contact candidate
     // from the next step on; if the pair was within the list radius at the
     // last rebuild (build-time positions, with a margin), this lane appends it
     // to the node's own candidate list, in lane order; a full list means a
     // rebuild instead
     bool relist = false;
-    // (skipped by a wavefront without a break: all its quads have nothing to append)
+    // (skipped by a wavefront without a break: none of its nodes has anything to append)
     if (LIST && MODE == M_STEP && __any(nbrk > 0)) {
         int keep = 0;
         uint32_t kj[4];
@@ -1046,25 +1128,21 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
             }
         }
         for (int t = keep; t < 4; ++t) kj[t] = 0xffffffffu;
-        int over = nbrk > 4 ? 1 : 0;
-        over |= quad_xor<1>(over);
-        over |= quad_xor<2>(over);
-        int tot = keep;
-        tot += quad_xor<1>(tot);
-        tot += quad_xor<2>(tot);
-        // lane 0 gathers the quad's partners and merges them into the node's
-        // sorted list
-        uint32_t nj[16];
-        const int q0 = (int)(threadIdx.x & ~3u);
+        const int over = lanes_or<LPN>(nbrk > 4 ? 1 : 0);
+        const int tot = lanes_sum<LPN>(keep);
+        // lane 0 gathers the partners of the node's lanes and merges them into
+        // the node's sorted list
+        uint32_t nj[4 * LPN];
+        const int q0 = (int)(threadIdx.x & ~(unsigned)(LPN - 1));
 #pragma unroll
-        for (int l = 0; l < 4; ++l)
+        for (int l = 0; l < LPN; ++l)
 #pragma unroll
             for (int t = 0; t < 4; ++t) nj[4 * l + t] = __shfl(kj[t], q0 + l, 64);
         if (over || nc_pre + tot > a.maxc) {
             relist = true;
         } else if (sub == 0 && tot) {
             int n = nc_pre;
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < 4 * LPN; ++e) {
                 const uint32_t v = nj[e];
                 if (v == 0xffffffffu) continue;
                 int m = n - 1;
@@ -1078,13 +1156,19 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
             a.clist_n[i] = n;
         }
     }
-    nbrk = quad_sum(nbrk);
-    st |= quad_xor<1>(st);
-    st |= quad_xor<2>(st);
-    if (MODE == M_FORCES) {
-        smx = fmax(smx, quad_xor<1>(smx));
-        smx = fmax(smx, quad_xor<2>(smx));
+    if constexpr (LIST) {
+        // (most nodes are far from every wall: the loop is the cold path)
+        if (__builtin_expect(near_wall(a, ag, pxi, pyi, t), 0)) {
+#pragma unroll
+            for (int part = sub; part < 4; part += LPN)
+                wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
+        }
     }
+    fwx = lanes_sum<LPN>(fwx);
+    fwy = lanes_sum<LPN>(fwy);
+    nbrk = lanes_sum<LPN>(nbrk);
+    st = lanes_or<LPN>(st);
+    if (MODE == M_FORCES) smx = lanes_max<LPN>(smx);
     if (sub != 0) return;
     if (MODE != M_FORCES) count(a, C_BROKEN, (unsigned long long)nbrk);
     if (LIST && relist) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
@@ -1153,7 +1237,7 @@ __device__ __forceinline__ int xcd_block(int w, int nb) {
     return x * q + min(x, rem) + r;  // a bijection of [0, nb)
 }
 
-template <typename R, int MODE, bool LIST, int SEL = 0>
+template <typename R, int MODE, bool LIST, int SEL = 0, int LPN = 4>
 __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     extern __shared__ double lds[];
     // list mode: this launch computes step sprev + 1 of a replay that started
@@ -1171,9 +1255,10 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         // LDS staging.  The list cannot grow during this launch.
         const int nl = *a.n_pd_blocks;
         for (int slot = blockIdx.x; slot < nl; slot += gridDim.x)
-            force_block<R, MODE, LIST, SEL>(a, 0, a.pd_blocks[slot], sprev, lds);
+            force_block<R, MODE, LIST, SEL, LPN>(a, 0, a.pd_blocks[slot], sprev, lds);
     } else {
-        force_block<R, MODE, LIST, SEL>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x), sprev, lds);
+        force_block<R, MODE, LIST, SEL, LPN>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x), sprev,
+                                             lds);
     }
 }
 
@@ -1661,11 +1746,15 @@ int force_lds_cap(int max_win) { return max_win > kMaxLdsNodes ? 0 : max_win; }
 
 template <typename R>
 static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b, size_t shm,
-                           hipStream_t s, int lds_cap, int sel) {
+                           hipStream_t s, int lds_cap, int sel, int lpn) {
     if (mode == M_STEP) {
         if (list) {
             if (sel == 1)
                 hipLaunchKernelGGL((k_force<R, M_STEP, true, 1>), g, b, 0, s, a, lds_cap);
+            else if (lpn == 1)
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 0, 1>), g, b, shm, s, a, lds_cap);
+            else if (lpn == 2)
+                hipLaunchKernelGGL((k_force<R, M_STEP, true, 0, 2>), g, b, shm, s, a, lds_cap);
             else
                 hipLaunchKernelGGL((k_force<R, M_STEP, true, 0>), g, b, shm, s, a, lds_cap);
         } else {
@@ -1683,20 +1772,23 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     if (a.N == 0) return hipSuccess;
     if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
         return hipErrorInvalidValue;
-    // nodes per workgroup, four lanes each; the plain-force-only launch uses
-    // 64-node workgroups (its list's unit), walks the list with a stride of at
-    // most 1024 workgroups (four per compute unit) and stages nothing
+    // nodes per workgroup, LPN lanes each (the tuning's lanes for list-mode
+    // steps, four otherwise); the plain-force-only launch uses 64-node
+    // workgroups (its list's unit), walks the list with a stride of at most
+    // 1024 workgroups (four per compute unit) and stages nothing
     const int B = sel ? kSelBlockNodes : a.block_nodes;
-    // the bond loop takes a wavefront's 16 nodes to be one SELL-16 slice
+    const int lpn = (mode == M_STEP && list && !sel) ? a.lanes : 4;
+    if (!(lpn == 1 || lpn == 2 || lpn == 4) || lpn * B > 1024) return hipErrorInvalidValue;
+    // the bond loop takes a wavefront's 64 / LPN nodes to be whole SELL-16 slices
     static_assert(kSelBlockNodes % kSlice == 0, "plain-force workgroups hold whole slices");
-    if (B % kSlice != 0) return hipErrorInvalidValue;
+    if (B % kSlice != 0 || (64 / lpn) % kSlice != 0) return hipErrorInvalidValue;
     const size_t shm = (a.use_lds && !sel) ? (size_t)lds_cap * kWin * sizeof(double) : 0;
     const unsigned nb = (unsigned)grid_for(a.N, B);
-    const dim3 g(sel ? std::min(nb, 1024u) : nb), b(4 * B);
+    const dim3 g(sel ? std::min(nb, 1024u) : nb), b(lpn * B);
     if (precision == PD_PREC_FP64)
-        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel);
+        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn);
     else
-        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap, sel);
+        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn);
     return hipGetLastError();
 }
 

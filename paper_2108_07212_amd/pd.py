@@ -55,11 +55,13 @@ class Problem(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block_nodes", C.c_int32), ("cell_factor", C.c_double),
-                ("use_lds", C.c_int32), ("use_graph", C.c_int32), ("skin_factor", C.c_double)]
+                ("use_lds", C.c_int32), ("use_graph", C.c_int32), ("skin_factor", C.c_double),
+                ("lanes_per_node", C.c_int32)]
 
     def as_dict(self):
         return dict(block_nodes=self.block_nodes, cell_factor=self.cell_factor,
-                    use_lds=self.use_lds, use_graph=self.use_graph, skin_factor=self.skin_factor)
+                    use_lds=self.use_lds, use_graph=self.use_graph, skin_factor=self.skin_factor,
+                    lanes_per_node=self.lanes_per_node)
 
 
 _lib = None

@@ -407,7 +407,9 @@ def test_reduced_moving_wall_and_restart_match_oracle(setup_bed):
         st.step()
     g.step(30)
     _compare_states(g, o, 1e-9)
-    mid = g.get_state()
+    # both restart from the oracle's state (inputs flow from the oracle to
+    # the library, never back)
+    mid = o.get_state()
     g.set_state(mid)
     o.set_state(mid)
     st = CL.ReducedStepper(o, prob, sp, modes, [s0] * S, [BIG] * S, BIG, active=st.active)

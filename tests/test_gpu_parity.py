@@ -281,15 +281,18 @@ def test_trajectory_two_disks_contact_1000(pdmod):
     assert np.array_equal(sg["broken"], so["broken"])
 
 
-def test_breaks_during_list_steps(pdmod):
+@pytest.mark.parametrize("lanes", [4, 1])
+def test_breaks_during_list_steps(pdmod, lanes):
     """A 40 m/s head-on impact breaks bonds while the candidate lists are in
     use: each broken pair joins its nodes' lists in the step it breaks (no
     rebuild).  The first 75 steps (bonds break, fragments touch) follow the
     oracle; after that, contact onsets near ties make any rounding difference
     grow about a thousandfold per 25 steps, in the oracle as well, so the
     remaining check is the list path against the every-step cell search on
-    the GPU, which must give the same states and broken bonds."""
-    _say("case: breaks during list steps")
+    the GPU (with fewer lanes per node, whose sums run in another order,
+    against lists of a wider skin), which must give the same states and
+    broken bonds."""
+    _say(f"case: breaks during list steps, {lanes} lanes per node")
 
     def impact():
         prob = W.two_disks(contact_active=True)
@@ -300,6 +303,7 @@ def test_breaks_during_list_steps(pdmod):
 
     prob = impact()
     g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_tuning(lanes_per_node=lanes)
     assert g.tuning()["skin_factor"] > 0
     for k in range(3):
         eu, ev, sg, so = _traj(g, o, 25)
@@ -307,8 +311,15 @@ def test_breaks_during_list_steps(pdmod):
         assert np.array_equal(sg["broken"], so["broken"]), k
     assert int(so["broken"].sum()) > 50
     assert o.counters()["self_"] > 0
+    # against the cell search every step (four lanes per node); with fewer
+    # lanes, whose per-node sums run in another order, against the same lane
+    # count with a four times wider skin (other lists, other rebuild steps)
     lst, srch = pdmod.PD(impact()), pdmod.PD(impact())
-    srch.set_tuning(skin_factor=0.0)
+    lst.set_tuning(lanes_per_node=lanes)
+    if lanes == 4:
+        srch.set_tuning(skin_factor=0.0)
+    else:
+        srch.set_tuning(lanes_per_node=lanes, skin_factor=4 * lst.tuning()["skin_factor"])
     r0 = lst.sizes()["list_rebuilds"]
     for k in range(3):
         lst.step(50)
@@ -325,13 +336,15 @@ def test_breaks_during_list_steps(pdmod):
     assert lst.sizes()["list_rebuilds"] - r0 < 40
 
 
-@pytest.mark.parametrize("seed", [11, 12])
-def test_trajectory_bed_100(pdmod, seed):
+@pytest.mark.parametrize("seed,lanes", [(11, 4), (12, 4), (11, 1), (12, 2)])
+def test_trajectory_bed_100(pdmod, seed, lanes):
     """A herded bed with gravity 5000 m/s^2: contact, friction, damping,
-    walls and bond breaking over 100 steps."""
-    _say(f"case: trajectory bed seed={seed}")
+    walls and bond breaking over 100 steps, with 4, 2 or 1 lanes per node in
+    the list-mode step."""
+    _say(f"case: trajectory bed seed={seed} lanes={lanes}")
     prob = _herd(_bed(10, seed, g=(0.0, -5000.0)), 0.45, seed=seed, dv=0.5)
     g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_tuning(lanes_per_node=lanes)
     eu, ev, sg, so = _traj(g, o, 100)
     assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
     assert np.array_equal(sg["broken"], so["broken"])
@@ -438,22 +451,33 @@ def test_carried_displacement_is_bitwise(pdmod, prec):
 @pytest.mark.parametrize("skin", [1.0, 0.0])
 def test_determinism_graph_and_tuning(pdmod, skin):
     """Bitwise equal results: two runs; graph vs direct launches; every block
-    size and LDS staging choice (for a fixed skin)."""
+    size and LDS staging choice (for a fixed skin and lane count).  Lane
+    counts (list mode) change only the order of the per-node sums: their
+    trajectories agree to 1e-9 and their broken bonds exactly."""
     _say(f"case: determinism skin={skin}")
     prob = _herd(_bed(10, 21, g=(0.0, -5000.0)), 0.45, seed=21, dv=0.5)
-    ref = None
-    for bn in (256, 128, 64):
-        for lds in (1, 0):
-            for graph in (1, 0):
-                g = pdmod.PD(prob)
-                g.set_tuning(block_nodes=bn, use_lds=lds, use_graph=graph, skin_factor=skin)
-                g.step(137)
-                s = g.get_state()
-                if ref is None:
-                    ref = s
-                else:
-                    for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
-                        assert np.array_equal(ref[k], s[k]), (bn, lds, graph, k)
+    first = None
+    for lanes in ((4, 2, 1) if skin > 0 else (4,)):
+        ref = None
+        for bn in (256, 128, 64):
+            for lds in (1, 0):
+                for graph in (1, 0):
+                    g = pdmod.PD(prob)
+                    g.set_tuning(block_nodes=bn, use_lds=lds, use_graph=graph, skin_factor=skin,
+                                 lanes_per_node=lanes)
+                    g.step(137)
+                    s = g.get_state()
+                    if ref is None:
+                        ref = s
+                    else:
+                        for k in ("ux", "uy", "vx", "vy", "ax", "ay", "broken"):
+                            assert np.array_equal(ref[k], s[k]), (lanes, bn, lds, graph, k)
+        if first is None:
+            first = ref
+        else:
+            assert np.array_equal(first["broken"], ref["broken"]), lanes
+            for k in ("ux", "uy", "vx", "vy"):
+                assert _relerr(ref[k], first[k]) <= TRAJ_TOL, (lanes, k)
 
 
 @pytest.mark.parametrize("skin", [0.0, 0.25, 2.0])
