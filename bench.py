@@ -49,7 +49,7 @@ def kernel_source_hash() -> str:
 
 
 def tuning_key(t: dict) -> str:
-    return f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}"
+    return f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}_lpn{int(t.get('lanes_per_node', 4))}"
 
 
 def parse_tuning(text: str) -> dict:
@@ -290,6 +290,35 @@ def settling_leg(pd, W, torch, args):
                                  "cell_factor": best0[0],
                                  "note": "the same step with the cell-key sort and cell search "
                                          "every step (skin 0)"}}
+    del g
+    return res
+
+
+def settling_g5000(pd, W, torch, args):
+    """The settling bed at the paper's gravity of 5000 m/s^2 (Sec. 7.3):
+    after 2 ms of fall the lower particles pile up on the floor, contacts
+    are everywhere and the candidate lists go stale every few steps.  Steps/s
+    with the lists, rebuilds per 1000 steps, contact pairs per step."""
+    prob = W.settling(gravity=-5000.0)
+    g = pd.PD(prob)
+    sizes = g.sizes()
+    n_pairs = sizes["bonds"] // 2
+    g.step(100)
+    if args.tuning:
+        g.set_tuning(**parse_tuning(args.tuning))
+    else:
+        g.autotune(50)
+    g.step(20000)
+    g.set_counting(True)
+    c0 = g.counters()
+    steps = max(1000, args.settling_steps // 4)
+    sps, rebuilds = timed_steps(g, torch, steps)
+    c1 = g.counters()
+    res = {"workload": "settling_100_g5000", "gravity": -5000.0, "t_start_ms": 2.0,
+           "steps": steps, "steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
+           "ms_per_step": 1e3 / sps, "tuning": g.tuning(),
+           "list_rebuilds_per_1000_steps": 1000.0 * rebuilds / steps,
+           "contact_pairs_per_step": float(c1["inter"] - c0["inter"] + c1["self_"] - c0["self_"]) / steps}
     del g
     return res
 
@@ -587,7 +616,8 @@ def main():
                          "block_nodes=128,use_lds=1,skin_factor=0.5 (profiling runs)")
     ap.add_argument("--settle-us", type=float, default=10000.0)
     ap.add_argument("--settle-every-us", type=float, default=1000.0)
-    ap.add_argument("--workload", choices=("batched", "settling", "compaction", "batched_fp32",
+    ap.add_argument("--workload", choices=("batched", "settling", "settling_g5000", "compaction",
+                                           "batched_fp32",
                                            "closure", "fragmentation", "settle_shapes"),
                     default="batched",
                     help="batched: the headline line (plus the secondary legs unless "
@@ -615,6 +645,7 @@ def main():
         return
     legs = {
         "settling": lambda: settling_leg(pd, W, torch, args),
+        "settling_g5000": lambda: settling_g5000(pd, W, torch, args),
         "compaction": lambda: precision_split(pd, W, torch, args.split_steps),
         "batched_fp32": lambda: batched_fp32(pd, W, torch, args.batched_steps,
                                              W.batched(precision=1), fixed),
@@ -630,6 +661,7 @@ def main():
     out["hbm_measured"] = hbm_probe(pd, torch)
     if not args.no_variants:
         out["settling_100"] = legs["settling"]()
+        out["settling_g5000"] = legs["settling_g5000"]()
         out["precision_split"] = legs["compaction"]()
         out["batched_fp32"] = batched_fp32(pd, W, torch, args.batched_steps, prob, fixed)
         out["closure"] = legs["closure"]()
