@@ -126,47 +126,82 @@ def cpu_baseline(prob, seconds: float, sample: str):
 
 
 def precision_split(pd, W, torch, steps):
-    """FP32 force arithmetic with FP64 state and FP64 break decisions, on the
-    compaction bed of 500 particles (about 245k nodes) started from a packed
-    state: throughput of both modes, the per-step force error of FP32 against
-    FP64 at identical states, and broken-bond counts after `steps` steps."""
+    """The compaction run with damage (Sec. 7.4), FP32 force arithmetic
+    (FP64 state and FP64 break decisions) against plain FP64: 509 mixed
+    particles (178k nodes) from the jammed start of Sec. 7.1; the top wall
+    comes down at 1 m/s (the paper's compaction speed) for 5 mm, and from that
+    checkpoint at 0.1 m/s until the bonds break.  Along the 0.1 m/s run, at
+    every sample: the FP32 force error at the FP64 run's state (max-norm,
+    relative), broken bonds of the FP64 and FP32 runs, the top-wall force
+    and the volume fraction; the step rates of both.  Then the same error on
+    the herded compaction bed (particles pushed into each other at t = 0),
+    a stress case."""
     import numpy as np
-    prob = W.herd(W.compaction(), 0.30)
-    prob.top_wall_speed = np.array([0.1])
-    g64 = pd.PD(prob, precision=0)
-    g32 = pd.PD(prob, precision=1)
-    res = {"workload": "compaction_500 (packed start)", "nodes": prob.n_nodes}
-    errs = []
-    for k in range(4):
-        s = g64.get_state()
-        g32.set_state(s)
-        f64 = g64.forces(pd.TERM_ALL)
-        f32 = g32.forces(pd.TERM_ALL)
+    pre_steps = 50000
+    prob = W.jammed_compaction(wall_speed=1.0)
+    g = pd.PD(prob, precision=0)
+    g.step(20)
+    tun = g.autotune(10)
+    t0 = time.perf_counter()
+    g.step(pre_steps - 20)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    ck = g.get_state()
+    wall = float(g.observables()["top_wall_y"][0])
+    del g
+    run = W.restart_with_wall(prob, ck, wall, 0.1)
+    ck0 = dict(ck, step=0)
+    ctx = {}
+    for prec in (0, 1):
+        c = pd.PD(run, precision=prec)
+        c.set_tuning(**tun)
+        c.set_state(ck0)
+        ctx[prec] = c
+    probe = pd.PD(run, precision=1)
+    probe.set_tuning(**tun)
+    series, t_run = [], {0: 0.0, 1: 0.0}
+    chunk, done, first = 10000, 0, None
+    while done < steps:
+        for prec in (0, 1):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx[prec].step(chunk)
+            torch.cuda.synchronize()
+            t_run[prec] += time.perf_counter() - t1
+        done += chunk
+        s64 = ctx[0].get_state()
+        probe.set_state(s64)
+        f64 = ctx[0].forces(pd.TERM_ALL)
+        f32 = probe.forces(pd.TERM_ALL)
         scale = max(np.abs(f64[0]).max(), np.abs(f64[1]).max())
-        errs.append(float(max(np.abs(f32[0] - f64[0]).max(), np.abs(f32[1] - f64[1]).max()) / scale))
-        g64.step(steps // 4)
-    g32b = pd.PD(prob, precision=1)
-    series = []
-    for k in range(8):
-        g32b.step(steps // 8)
-        ob = g32b.observables()
-        series.append({"step": (k + 1) * (steps // 8),
+        ob = ctx[0].observables()
+        nb64, nb32 = int(ctx[0].damage()[1]), int(ctx[1].damage()[1])
+        series.append({"step": done, "wall_travel_mm": 1e3 * (run.box[0, 3] - float(ob["top_wall_y"][0])),
+                       "force_rel_err_fp32": float(max(np.abs(f32[0] - f64[0]).max(),
+                                                       np.abs(f32[1] - f64[1]).max()) / scale),
+                       "broken_directed_fp64": nb64, "broken_directed_fp32": nb32,
                        "top_wall_force_y": float(ob["wall_force"][0, 3, 1]),
-                       "volume_fraction": float(ob["volume_fraction"][0]),
-                       "damage": float(ob["broken"][0] / ob["reference"][0])})
-    res["fp32_observables"] = series
-    res["force_rel_err_fp32_vs_fp64_max_norm"] = errs
-    res["broken_directed_fp64"] = int(g64.damage()[1])
-    res["broken_directed_fp32"] = int(g32b.damage()[1])
-    for name, g in (("fp64", g64), ("fp32", g32b)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.step(steps)
-        torch.cuda.synchronize()
-        sps = steps / (time.perf_counter() - t0)
-        n_pairs = g.sizes()["bonds"] // 2
-        res[name] = {"steps_per_s": sps, "bond_interactions_per_s": n_pairs * sps,
-                     "force_kernel_ms": g.time_kernels(128)["force"][0]}
+                       "volume_fraction": float(ob["volume_fraction"][0])})
+        if nb64 > 0 and first is None:
+            first = done
+        if first is not None and done >= first + 3 * chunk:
+            break
+    n_pairs = ctx[0].sizes()["bonds"] // 2
+    res = {"workload": "jammed_compaction (509 particles, 40 x 40 mm, h = 0.070 mm)",
+           "nodes": prob.n_nodes, "tuning": tun,
+           "precompaction": {"wall_speed": 1.0, "steps": pre_steps, "seconds": t_pre},
+           "wall_speed": 0.1, "steps": done, "first_break_step": first, "series": series,
+           "fp64": {"steps_per_s": done / t_run[0], "bond_interactions_per_s": n_pairs * done / t_run[0]},
+           "fp32": {"steps_per_s": done / t_run[1], "bond_interactions_per_s": n_pairs * done / t_run[1]},
+           "max_force_rel_err_fp32": max(e["force_rel_err_fp32"] for e in series)}
+    del ctx, probe
+    herd = W.herd(W.compaction(), 0.30)
+    g64, g32 = pd.PD(herd, precision=0), pd.PD(herd, precision=1)
+    f64, f32 = g64.forces(pd.TERM_ALL), g32.forces(pd.TERM_ALL)
+    scale = max(np.abs(f64[0]).max(), np.abs(f64[1]).max())
+    res["herded_stress_case"] = {
+        "nodes": herd.n_nodes,
+        "force_rel_err_fp32": float(max(np.abs(f32[0] - f64[0]).max(), np.abs(f32[1] - f64[1]).max()) / scale)}
     return res
 
 
@@ -606,7 +641,9 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=128)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--settling-steps", type=int, default=20000)
-    ap.add_argument("--split-steps", type=int, default=400)
+    ap.add_argument("--split-steps", type=int, default=600000,
+                    help="most steps of the 0.1 m/s compaction run (it stops 30k steps after "
+                         "the first break)")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--train-iters", type=int, default=2000)

@@ -838,6 +838,62 @@ def jammed_disks(width: float, height: float, mesh_size: float, seed: int, shrin
     return centres, radii[keep], stats, origin
 
 
+def jammed_compaction(width: float = 40e-3, height: float = 40e-3, mesh_size: float = 3.2e-3,
+                      seed: int = 3, h: float = 0.070e-3, r_min: float = 0.4e-3,
+                      wall_speed: float = 0.1, dt: float = 1e-7,
+                      precision: int = PREC_FP64) -> Problem:
+    """Compaction of mixed particles from a jammed start (Sec. 7.4 with the
+    initial configuration of Sec. 7.1): security disks of jammed_disks over
+    the container inset by R_c / 2, shrunk by R_c / 2 and kept if of radius
+    >= r_min (510 in a 40 x 40 mm box with mesh size 3.2 mm); in each an
+    equal-thirds mix of disks, plus shapes (half-length R, arm width R/2) and
+    rings (inner radius R/2) whose farthest point lies on the disk's circle,
+    randomly oriented;
+    h = 0.070 mm, horizon 3h, R_c = 0.95 h, the configs' material (G_c =
+    50 J/m^2), mu = 0.5, r_d = 0.8, no gravity, the top wall moving down at
+    wall_speed.
+
+    Draw order: the mesh jitter (default_rng(seed)), then default_rng(seed +
+    1) for the shape list's shuffle and the orientations."""
+    Rc = 0.95 * h
+    centres, radii, st, _ = jammed_disks(width - Rc, height - Rc, mesh_size, seed,
+                                         shrink=0.5 * Rc, x0=0.5 * Rc, y0=0.5 * Rc)
+    keep = radii >= r_min
+    centres, radii = centres[keep], radii[keep]
+    n = len(radii)
+    rng = np.random.default_rng(seed + 1)
+    kinds = [("disk", "plus", "ring")[k % 3] for k in range(n)]
+    kinds = [kinds[i] for i in rng.permutation(n)]
+    th = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    # a plus of half-length R reaches sqrt(1 + 1/16) R at its arm corners:
+    # scaled so that its farthest point lies on the disk's circle
+    reach = {"disk": 1.0, "ring": 1.0, "plus": math.sqrt(1.0 + 1.0 / 16.0)}
+    parts = [Particle(kinds[k], float(radii[k]) / reach[kinds[k]],
+                      (float(centres[k, 0]), float(centres[k, 1])), float(th[k])) for k in range(n)]
+    return assemble(parts, h, [_material(h)], [0.0, width, 0.0, height], contact_radius=Rc,
+                    friction_mu=0.5, damping_ratio=0.8, dt=dt, gravity=(0.0, 0.0),
+                    top_wall_speed=[wall_speed], precision=precision,
+                    meta=dict(name="jammed_compaction", seed=seed, packing=st,
+                              dropped_small=int((~keep).sum())))
+
+
+def restart_with_wall(prob: Problem, state: dict, wall_y: float, speed: float) -> Problem:
+    """The same nodes, particles and materials, with the displacement and
+    velocity of `state` as the initial condition and the top wall of the
+    (single) aggregate at height wall_y moving down at `speed`: a run that
+    continues from a checkpoint with a new wall motion (the checkpoint's
+    accelerations and broken bonds are loaded with pd_set_state)."""
+    import copy
+    out = copy.copy(prob)
+    out.box = prob.box.copy()
+    out.box[0, 3] = wall_y
+    out.top_wall_speed = np.array([speed], dtype=np.float64)
+    out.u0x, out.u0y = np.asarray(state["ux"]).copy(), np.asarray(state["uy"]).copy()
+    out.v0x, out.v0y = np.asarray(state["vx"]).copy(), np.asarray(state["vy"]).copy()
+    out.meta = dict(prob.meta, restart=True)
+    return out
+
+
 SETTLE_SHAPES = ("pdisk", "square", "plus", "ring")
 
 
