@@ -11,11 +11,12 @@
 //   k_cl_apply    nodal accelerations of the rigid + modal motion,
 //                 velocity-Verlet velocity update, the per-step gate
 // Reduced form (centroid, angle and modal amplitudes integrated directly):
-//   k_rc_init, k_rc_sync, k_rc_collect, k_rc_reduce, k_rc_update
+//   k_rc_init, k_rc_sync, k_rc_collect here; the step itself is one kernel,
+//   k_rc_fused, beside the force kernel (it evaluates contact)
 // Both:
 //   k_mlp_fwd     the 32 -> 256 -> 256 -> 32 SiLU MLP on 16-row blocks, eight
 //                 wavefronts splitting the columns, bfloat16 operands and
-//                 float32 accumulation on the matrix cores (v_mfma 16x16x16
+//                 float32 accumulation on the matrix cores (v_mfma 16x16x32
 //                 bf16), weights read in fragment order, hidden activations
 //                 in LDS
 //   k_mlp_pack    a shape's weights into that fragment order (after every
@@ -32,39 +33,9 @@
 #include <math.h>
 
 #include "pd_closure_dev.h"
+#include "pd_mlp_dev.h"
 
 namespace pd {
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// float -> bfloat16, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
-
-__device__ __forceinline__ float dsilu_f(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
-    return s * (1.0f + z * (1.0f - s));
-}
-
-// four consecutive bfloat16 values as one MFMA operand
-__device__ __forceinline__ bf16x4 load4(const uint16_t *p) {
-    const uint2 v = *reinterpret_cast<const uint2 *>(p);
-    bf16x4 r;
-    r[0] = (short)(v.x & 0xffffu);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xffffu);
-    r[3] = (short)(v.y >> 16);
-    return r;
-}
 
 __device__ __forceinline__ double block_max(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -541,11 +512,6 @@ __global__ __launch_bounds__(256) void k_rc_collect(DevArgs a, ClArgs c, const u
     if (threadIdx.x < kClModes) c.qrb[ci * kClModes + threadIdx.x] = c.qr[ci * kClModes + threadIdx.x];
 }
 
-// k_rc_update: the end of a reduced step after the MLP (learned closure)
-__global__ __launch_bounds__(256) void k_rc_update(DevArgs a, ClArgs c, int list) {
-    rc_update_body(a, c, list, blockIdx.x);
-}
-
 // ---------------------------------------------------------------------------
 // periodic check against the plain bond force: per particle, the modal force
 // of the closure vs the modal PD force (in c.gext after a mode-1 projection),
@@ -612,27 +578,22 @@ __global__ __launch_bounds__(256) void k_cl_check_sum(const double *per, int Pc,
 }
 
 // ---------------------------------------------------------------------------
-// the MLP forward: one workgroup per 16-row block; its eight wavefronts split
-// the output columns of each layer (32 of the 256 hidden units each; the two
-// 16-column tiles of the last layer go to waves 0 and 1), and the layers meet
-// in LDS.  The launch is latency-bound (2 000 rows are 125 workgroups), so
-// the loads are issued at the start in the order they are needed, with no
-// branch between them: the block's inputs first, then every weight fragment
-// (fragment order: 512 contiguous bytes per wavefront load) and bias of the
-// wave's three layers.  Every row of the block is computed and written,
-// also those of particles that are off (their consumers skip them; rows are
-// independent); a replay that has gone stale computes but writes nothing.
-// MFMA operand layout
-// (v_mfma_f32_16x16x16 bf16): lane l holds A[l % 16][4 (l / 16) + t] and
-// B[4 (l / 16) + t][l % 16], t = 0..3, and receives D[4 (l / 16) + t][l % 16].
+// the MLP forward (training, checks, snapshots): one workgroup of eight
+// wavefronts per 16-row block.  The launch is latency-bound (2 000 rows are
+// 125 workgroups), so the loads are issued at the start in the order they
+// are needed, with no branch between them: the block's inputs, then every
+// weight fragment and bias of the wave's three layers.  Every row of the
+// block is computed and written, also those of particles that are off
+// (their consumers skip them; rows are independent); a replay that has gone
+// stale computes but writes nothing.
 // ---------------------------------------------------------------------------
 constexpr int kMlpWaves = 8;
 
 __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a, int list) {
     static_assert(16 * kClModes == 64 * kMlpWaves, "one input element per thread");
-    __shared__ uint16_t Xs[16 * kClModes];
-    __shared__ uint16_t H1[16 * kClHidden];
-    __shared__ uint16_t H2[16 * kClHidden];
+    __shared__ __align__(16) uint16_t Xs[16 * kXsStride];
+    __shared__ __align__(16) uint16_t H1[16 * kHStride];
+    __shared__ __align__(16) uint16_t H2[16 * kHStride];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int rb = blockIdx.x;
     int s = m.shape, first = 16 * rb, cnt;
@@ -643,12 +604,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
     } else {
         cnt = min(16, m.rows - first);
     }
-    const uint16_t *F = m.wfr + (size_t)s * kClFrag;
-    const float *Wf = m.wf + (size_t)s * kClParams;
     const int r = l & 15, kq = 4 * (l >> 4);
-    constexpr int TPW = kClHidden / 16 / kMlpWaves;  // column tiles per wave
-    // lane l's part of fragment f of a matrix
-    auto frag = [&](int base, int f) { return load4(F + base + f * kFragElems + 4 * l); };
     // ---- this thread's input element (row, col) = (tid / 32, tid % 32) ---------
     // (indices clamped to the block's rows, so that no load waits on a branch)
     const int xrow = threadIdx.x / kClModes, xcol = threadIdx.x % kClModes;
@@ -656,117 +612,43 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpArgs m, DevArgs a
     const double qin = m.q[(size_t)(m.idx ? m.idx[first + xr] : first + xr) * kClModes + xcol];
     const float sq = m.sig_q[s * kClModes + xcol];
     // ---- the wave's weights and biases --------------------------------------
-    bf16x4 w1[TPW][2], w2[TPW][16], w3[16];
-    float b1[TPW], b2[TPW];
-#pragma unroll
-    for (int jj = 0; jj < TPW; ++jj) {
-        const int n = 16 * (TPW * wv + jj) + r;
-        const int tile = TPW * wv + jj;
-        w1[jj][0] = frag(kFragW1, tile * (kClModes / 16));
-        w1[jj][1] = frag(kFragW1, tile * (kClModes / 16) + 1);
-        b1[jj] = Wf[kOffB1 + n];
-    }
-#pragma unroll
-    for (int jj = 0; jj < TPW; ++jj) {
-        const int n = 16 * (TPW * wv + jj) + r;
-        const int tile = TPW * wv + jj;
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) w2[jj][ks] = frag(kFragW2, tile * (kClHidden / 16) + ks);
-        b2[jj] = Wf[kOffB2 + n];
-    }
+    MlpWave<kMlpWaves> W;
+    mlp_load<kMlpWaves>(W, m.wfr + (size_t)s * kClFrag, m.wf + (size_t)s * kClParams, wv, l);
     const bool last = wv < kClModes / 16;  // waves of the last layer
     const int n3 = 16 * (last ? wv : 0) + r;
-    float b3 = 0.0f, sr3 = 0.0f;
+    float sr3 = 0.0f;
     double lam3 = 0.0, q3[4] = {0.0, 0.0, 0.0, 0.0};
-    if (last) {
+    if (last && m.g) {
+        lam3 = m.lam[s * kClModes + n3];
+        sr3 = m.sig_r[s * kClModes + n3];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) w3[ks] = frag(kFragW3, wv * (kClHidden / 16) + ks);
-        b3 = Wf[kOffB3 + n3];
-        if (m.g) {
-            lam3 = m.lam[s * kClModes + n3];
-            sr3 = m.sig_r[s * kClModes + n3];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = min(kq + t, cnt - 1);
-                q3[t] = m.q[(size_t)(m.idx ? m.idx[first + row] : first + row) * kClModes + n3];
-            }
+        for (int t = 0; t < 4; ++t) {
+            const int row = min(kq + t, cnt - 1);
+            q3[t] = m.q[(size_t)(m.idx ? m.idx[first + row] : first + row) * kClModes + n3];
         }
     }
     // ---- inputs, bfloat16 -----------------------------------------------------
     {
         const float xv = xrow < cnt ? (float)(qin / (double)sq) : 0.0f;  // padding rows: 0
         const uint16_t b = f2bf(xv);
-        Xs[threadIdx.x] = b;
+        Xs[xrow * kXsStride + xcol] = b;
         if (m.xb && xrow < cnt) m.xb[(size_t)(first + xrow) * kClModes + xcol] = b;
     }
     __syncthreads();
-    // ---- layer 1: x (16 x 32) W1^T, columns 32 wv .. 32 wv + 31 -----------------
-    {
-        const bf16x4 a0 = load4(Xs + r * kClModes + kq), a1 = load4(Xs + r * kClModes + 16 + kq);
-#pragma unroll
-        for (int jj = 0; jj < TPW; ++jj) {
-            const int n = 16 * (TPW * wv + jj) + r;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, w1[jj][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, w1[jj][1], acc, 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = kq + t;
-                const float z = acc[t] + b1[jj];
-                const uint16_t h = f2bf(silu_f(z));
-                H1[row * kClHidden + n] = h;
-                if (m.z1 && row < cnt) {
-                    m.z1[(size_t)(first + row) * kClHidden + n] = z;
-                    m.h1[(size_t)(first + row) * kClHidden + n] = h;
-                }
-            }
-        }
-    }
+    mlp_hidden(Xs, kXsStride, W.w1, W.b1, H1, wv, l, first, cnt, m.z1, m.h1);
     __syncthreads();
-    // ---- layer 2: h1 (16 x 256) W2^T, columns 32 wv .. 32 wv + 31 ---------------
-    {
-        bf16x4 ah[16];
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H1 + r * kClHidden + 16 * ks + kq);
-#pragma unroll
-        for (int jj = 0; jj < TPW; ++jj) {
-            const int n = 16 * (TPW * wv + jj) + r;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], w2[jj][ks], acc, 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = kq + t;
-                const float z = acc[t] + b2[jj];
-                const uint16_t h = f2bf(silu_f(z));
-                H2[row * kClHidden + n] = h;
-                if (m.z2 && row < cnt) {
-                    m.z2[(size_t)(first + row) * kClHidden + n] = z;
-                    m.h2[(size_t)(first + row) * kClHidden + n] = h;
-                }
-            }
-        }
-    }
+    mlp_hidden(H1, kHStride, W.w2, W.b2, H2, wv, l, first, cnt, m.z2, m.h2);
     __syncthreads();
-    // ---- layer 3: h2 (16 x 256) W3^T, column tile wv (waves 0 and 1) -----------
     if (last) {
         const bool stale = list && replay_stale(a, true);
-        bf16x4 ah[16];
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) ah[ks] = load4(H2 + r * kClHidden + 16 * ks + kq);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[ks], w3[ks], acc, 0, 0, 0);
+        const f32x4 y = mlp_out<kMlpWaves>(H2, W, l);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int row = kq + t;
             if (stale || row >= cnt) continue;
-            const float y = acc[t] + b3;
-            if (m.y) m.y[(size_t)(first + row) * kClModes + n3] = y;
+            if (m.y) m.y[(size_t)(first + row) * kClModes + n3] = y[t];
             if (m.g)
-                m.g[(size_t)(first + row) * kClModes + n3] = -lam3 * q3[t] + (double)sr3 * (double)y;
+                m.g[(size_t)(first + row) * kClModes + n3] = -lam3 * q3[t] + (double)sr3 * (double)y[t];
         }
     }
 }
@@ -788,18 +670,18 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     const int tile = blockIdx.x * 4 + wv;
     if (tile >= tn * tm) return;
     const int m0 = 16 * (tile / tn), n0 = 16 * (tile % tn);
-    const int r = l & 15, kq = 4 * (l >> 4);
+    const int r = l & 15, kq = 4 * (l >> 4), k8 = 8 * (l >> 4);
     const int am = m0 + r, bn = n0 + r;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 av, bv;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        uint16_t av[8], bv[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = k0 + kq + t;
-            av[t] = (short)((am < M && k < K) ? A[(long)am * sam + (long)k * sak] : 0);
-            bv[t] = (short)((bn < N && k < K) ? B[(long)k * sbk + (long)bn * sbn] : 0);
+        for (int t = 0; t < 8; ++t) {
+            const int k = k0 + k8 + t;
+            av[t] = (am < M && k < K) ? A[(long)am * sam + (long)k * sak] : (uint16_t)0;
+            bv[t] = (bn < N && k < K) ? B[(long)k * sbk + (long)bn * sbn] : (uint16_t)0;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        acc = mfma32(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -898,9 +780,9 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const uint16_t *wb, uint16_t *
     } else {
         off = kOffW3, K = kClHidden, f = (o - kFragW3) / kFragElems;
     }
-    const int l = (o / 4) % 64, t = o % 4;
-    const int tile = f / (K / 16), ks = f % (K / 16);
-    const int n = 16 * tile + l % 16, k = 16 * ks + 4 * (l / 16) + t;
+    const int l = (o / 8) % 64, t = o % 8;
+    const int tile = f / (K / 32), ks = f % (K / 32);
+    const int n = 16 * tile + l % 16, k = 32 * ks + 8 * (l / 16) + t;
     wfr[o] = wb[off + n * K + k];
 }
 
@@ -1002,13 +884,6 @@ hipError_t launch_rc_collect(const DevArgs &a, const ClArgs &c, const uint8_t *a
     if (c.Pc <= 0) return hipSuccess;
     if (!rc_ready(a, c) || !act) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rc_collect, dim3(c.Pc), dim3(256), 0, s, a, c, act);
-    return hipGetLastError();
-}
-
-hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s) {
-    if (c.Pc <= 0) return hipSuccess;
-    if (!rc_ready(a, c)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rc_update, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0);
     return hipGetLastError();
 }
 

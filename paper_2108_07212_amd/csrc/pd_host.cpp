@@ -369,14 +369,9 @@ void invalidate_graph(Ctx &c) {
 hipError_t enqueue_closure(Ctx &c, bool list) {
     if (c.cl.mode == 0) return hipSuccess;
     if (c.cl.reduced) {
-        // reduced state: contact of the active nodes, advance and reduction,
-        // then (learned) the MLP and the update, or (linear) the update in
-        // the same kernel
-        if (c.cl.mode == 1) return launch_rc_step(c.a, c.cl.ca, c.precision, list, true, c.stream);
-        hipError_t e = launch_rc_step(c.a, c.cl.ca, c.precision, list, false, c.stream);
-        if (e == hipSuccess) e = launch_mlp_forward(c.cl.ma, c.a, list, c.stream);
-        if (e == hipSuccess) e = launch_rc_update(c.a, c.cl.ca, list, c.stream);
-        return e;
+        // reduced state: one launch (contact of the active nodes, advance
+        // and reduction, the MLP of the learned closure, the update)
+        return launch_rc_fused(c.a, c.cl.ca, c.cl.ma, c.precision, c.cl.mode == 2, list, c.stream);
     }
     hipError_t e = launch_cl_project(c.a, c.cl.ca, list, 0, c.cl.max_n, c.stream);
     if (e != hipSuccess) return e;

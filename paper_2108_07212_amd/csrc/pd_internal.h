@@ -149,14 +149,15 @@ constexpr int kOffW3 = kOffB2 + kClHidden;
 constexpr int kOffB3 = kOffW3 + kClModes * kClHidden;
 // The three weight matrices again, in matrix-core fragment order (what the
 // MLP forward reads): fragment (tile, ks) of a [rows][K] matrix M is 64 lanes
-// x 4 bfloat16, lane l holding M[16 tile + l % 16][16 ks + 4 (l / 16) + t],
-// t = 0..3, so that one wavefront's operand load is 512 contiguous bytes.
-// W1 (16 x 2 fragments), W2 (16 x 16), W3 (2 x 16), back to back.
-constexpr int kFragElems = 64 * 4;
+// x 8 bfloat16, lane l holding M[16 tile + l % 16][32 ks + 8 (l / 16) + t],
+// t = 0..7 (the B operand of v_mfma_f32_16x16x32_bf16 for the columns of the
+// tile), so that one wavefront's operand load is 1 KB contiguous.
+// W1 (16 x 1 fragments), W2 (16 x 8), W3 (2 x 8), back to back.
+constexpr int kFragElems = 64 * 8;
 constexpr int kFragW1 = 0;
-constexpr int kFragW2 = kFragW1 + (kClHidden / 16) * (kClModes / 16) * kFragElems;
-constexpr int kFragW3 = kFragW2 + (kClHidden / 16) * (kClHidden / 16) * kFragElems;
-constexpr int kClFrag = kFragW3 + (kClModes / 16) * (kClHidden / 16) * kFragElems;
+constexpr int kFragW2 = kFragW1 + (kClHidden / 16) * (kClModes / 32) * kFragElems;
+constexpr int kFragW3 = kFragW2 + (kClHidden / 16) * (kClHidden / 32) * kFragElems;
+constexpr int kClFrag = kFragW3 + (kClModes / 16) * (kClHidden / 32) * kFragElems;
 // per closure particle reduced quantities (red[16 * c + k])
 enum { R_M = 0, R_CX, R_CY, R_VCX, R_VCY, R_PHI, R_I, R_OM, R_FX, R_FY, R_TAU, R_STRAIN, R_CONTACT,
        R_COS, R_SIN, R_ACTIVE, R_N };
@@ -389,8 +390,10 @@ int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
-hipError_t launch_rc_step(const DevArgs &a, const ClArgs &c, int precision, bool list, bool fuse_update,
-                          hipStream_t s);
+// the reduced closure's step in one launch (contact, reduction, MLP when
+// learned, update), one workgroup per block of <= 16 particles of one shape
+hipError_t launch_rc_fused(const DevArgs &a, const ClArgs &c, const MlpArgs &m, int precision,
+                           bool learned, bool list, hipStream_t s);
 hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStream_t s);
 hipError_t launch_observables(const DevArgs &a, double *split, const int *agg_pstart,
                               const int *agg_parts, const int *poff, double *out, hipStream_t s);
@@ -411,7 +414,6 @@ hipError_t launch_cl_apply(const DevArgs &a, const ClArgs &c, bool list, hipStre
 hipError_t launch_rc_init(const DevArgs &a, const ClArgs &c, hipStream_t s);
 hipError_t launch_rc_sync(const DevArgs &a, const ClArgs &c, hipStream_t s);
 hipError_t launch_rc_collect(const DevArgs &a, const ClArgs &c, const uint8_t *act, hipStream_t s);
-hipError_t launch_rc_update(const DevArgs &a, const ClArgs &c, bool list, hipStream_t s);
 hipError_t launch_cl_check(const DevArgs &a, const ClArgs &c, double err_tol, double *per,
                            double *stats, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpArgs &m, const DevArgs &a, bool list, hipStream_t s);

@@ -22,6 +22,7 @@
 
 #include "pd_internal.h"
 #include "pd_closure_dev.h"
+#include "pd_mlp_dev.h"
 
 namespace pd {
 
@@ -84,6 +85,14 @@ __device__ __forceinline__ double rcp_nr(double x) {
 __device__ __forceinline__ double rsq_nr(double x) {
     const double r = __builtin_amdgcn_rsq(x);
     return fma(r, fma(-0.5 * x * r, r, 0.5), r);
+}
+
+// sqrt(x) from the 1/sqrt estimate r: h = x r, refined by one Newton step
+// for the square root, h + (h / 2)(1 - h r) (same accuracy as above)
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double r = __builtin_amdgcn_rsq(x);
+    const double h = x * r;
+    return fma(0.5 * h, fma(-h, r, 1.0), h);
 }
 
 // inclusive scan across a 64-lane wavefront
@@ -791,10 +800,11 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
         // a scalar; a lane past its own row holds padding words (kBroken)
         const int W = wave_row_width<LPN>(Wi);
         const double s0 = mc.s0, s0m = mc.s0 * (1.0 - 1e-10);
-        // per node: c_w V_i; the conic weight 1 - l0/eps as fma(-l0, ie, 1)
-        // with ie = 0 for the constant micromodulus (w = 1 exactly)
+        // per node: c_w V_i and c_w V_i / eps; the bond's c_w V_i V_j w with
+        // the conic weight w = 1 - l0/eps is V_j (c_w V_i - l0 c_w V_i / eps),
+        // and c_w V_i V_j for the constant micromodulus (cVie = 0)
         const double cVi = mc.cw * Vi;
-        const double ie = mc.conic != 0 ? 1.0 / mc.eps : 0.0;
+        const double cVie = mc.conic != 0 ? cVi / mc.eps : 0.0;
         // this lane's slots k = sub + LPN t; their words are fetched in batches
         // of kBatch before any of them is used, so the loads overlap (the
         // first batch comes with the row head)
@@ -852,32 +862,34 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                 // that of a broken bond
                 bool cand;
                 R g, DXr, DYr;
+                // (the 1e-200 / 1e-30 added under the squares keeps padding
+                // finite and is far below an ulp of any bond's length)
                 if constexpr (sizeof(R) == 8) {
-                    const double l0s = fmax(fma(X, X, Y * Y), 1e-200);
-                    const double ls = fmax(fma(DX, DX, DY * DY), 1e-200);
-                    const double r0 = rsq_nr(l0s), rl = rsq_nr(ls);
-                    const double l0 = l0s * r0, l = ls * rl;
+                    const double l0s = fma(X, X, fma(Y, Y, 1e-200));
+                    const double ls = fma(DX, DX, fma(DY, DY, 1e-200));
+                    const double l0 = sqrt_nr(l0s), rl = rsq_nr(ls);
+                    const double l = ls * rl;
                     const double num = fma(EX, DX + X, EY * (DY + Y));
                     const double s = num * rcp_nr(l0 * (l + l0));
                     cand = valid && fabs(s) > s0m;
                     if (MODE == M_FORCES && valid) smx = fmax(smx, fabs(s));
-                    const double cf = valid ? cVi * Vj : 0.0;
-                    g = (cf * fma(-l0, ie, 1.0)) * s * rl;
+                    const double vj = valid ? Vj : 0.0;
+                    g = (vj * fma(-l0, cVie, cVi)) * s * rl;
                     DXr = DX;
                     DYr = DY;
                 } else {
                     const float Xf = (float)X, Yf = (float)Y, DXf = (float)DX, DYf = (float)DY;
                     const float EXf = (float)EX, EYf = (float)EY;
-                    const float l0s = fmaxf(fmaf(Xf, Xf, Yf * Yf), 1e-30f);
-                    const float ls = fmaxf(fmaf(DXf, DXf, DYf * DYf), 1e-30f);
+                    const float l0s = fmaf(Xf, Xf, fmaf(Yf, Yf, 1e-30f));
+                    const float ls = fmaf(DXf, DXf, fmaf(DYf, DYf, 1e-30f));
                     const float r0 = __builtin_amdgcn_rsqf(l0s), rl = __builtin_amdgcn_rsqf(ls);
                     const float l0 = l0s * r0, l = ls * rl;
                     const float num = fmaf(EXf, DXf + Xf, EYf * (DYf + Yf));
                     const float s = num * __builtin_amdgcn_rcpf(l0 * (l + l0));
                     cand = valid && fabsf(s) > (float)(s0 - 2e-6);
                     if (MODE == M_FORCES && valid) smx = fmax(smx, (double)fabsf(s));
-                    const float cf = valid ? (float)cVi * (float)Vj : 0.0f;
-                    g = (cf * fmaf(-l0, (float)ie, 1.0f)) * s * rl;
+                    const float vj = valid ? (float)Vj : 0.0f;
+                    g = (vj * fmaf(-l0, (float)cVie, (float)cVi)) * s * rl;
                     DXr = DXf;
                     DYr = DYf;
                 }
@@ -1264,8 +1276,12 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
 // Contact and wall forces of a node of a particle under the modal closure
 // (list mode): every candidate and every wall and corner region in turn.
 // The closure kernels integrate these nodes.
+struct ClNode {
+    double fx, fy, ux, uy;  // external force, advanced displacement
+};
+
 template <typename R>
-__device__ __forceinline__ void cl_contact_node(const DevArgs &a, int i, long long sprev) {
+__device__ __forceinline__ ClNode cl_contact_node(const DevArgs &a, int i, long long sprev) {
     const int pi = a.part[i];
     const double xi = a.x[i], yi = a.y[i];
     double pxi, pyi, uxi, uyi;
@@ -1285,12 +1301,15 @@ __device__ __forceinline__ void cl_contact_node(const DevArgs &a, int i, long lo
 #pragma unroll 1
     for (int part = 0; part < 4; ++part)
         wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
-    a.cl_fx[i] = ((double)fsx + (double)fnx) + fwx;
-    a.cl_fy[i] = ((double)fsy + (double)fny) + fwy;
+    const double fx = ((double)fsx + (double)fnx) + fwx;
+    const double fy = ((double)fsy + (double)fny) + fwy;
+    a.cl_fx[i] = fx;
+    a.cl_fy[i] = fy;
     a.ux_o[i] = uxi;
     a.uy_o[i] = uyi;
     if (!(isfinite(uxi) && isfinite(uyi))) st |= kStNonfinite;
     if (st) atomicOr(a.status, st);
+    return ClNode{fx, fy, uxi, uyi};
 }
 
 // every node of the closure particles, a thread per node
@@ -1303,25 +1322,255 @@ __global__ __launch_bounds__(256) void k_cl_contact(DevArgs a) {
     cl_contact_node<R>(a, i, sprev);
 }
 
-// reduced closure, one workgroup per closure particle: the contact and wall
-// forces of its active nodes, then (same workgroup) the reduction of the
-// reduced step, and with fuse_update (linear closure: nothing between) the
-// update as well
-template <typename R>
-__global__ __launch_bounds__(256) void k_rc_step(DevArgs a, ClArgs c, int list, int fuse_update) {
+// ---------------------------------------------------------------------------
+// the step of the reduced closure in one launch: one workgroup per block of
+// at most 16 closure particles of one shape (the MLP's row block) and NW
+// wavefronts, each taking the block's particles wv, wv + NW, ...  Per
+// particle, on its wavefront: the reduced positions advanced, the contact and
+// wall forces of its active nodes and their total force, torque about the
+// centroid, contact load and modal force (nodes lane, lane + 64, ... of the
+// active list on each lane, summed by butterflies: a fixed order).  Then, for
+// the learned closure, the MLP on the block's 16 rows of modal amplitudes,
+// all NW wavefronts on the matrix cores (rows of particles that are off or
+// past the block are zero).  Then per particle the rates, the gate, the
+// reconstruction of the active nodes (every node of a particle that leaves
+// the closure) and the motion bound since the last list rebuild.  What a
+// particle's first part leaves for its last (modal amplitudes and forces,
+// the advanced centroid and angle, the sums) stays in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRcWaves = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// LDS written by some lanes of a wavefront and then read by others of it
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+enum { RW_CX = 0, RW_CY, RW_PH, RW_FX, RW_FY, RW_TAU, RW_CONTACT, RW_STRAIN, RW_BQ, RW_N };
+
+template <typename R, bool LEARNED, int NW>
+__global__ __launch_bounds__(64 * NW) void k_rc_fused(DevArgs a, ClArgs c, MlpArgs m, int list) {
+    __shared__ __align__(16) uint16_t Xs[16 * kXsStride];
+    __shared__ __align__(16) uint16_t H1[LEARNED ? 16 * kHStride : 8];
+    __shared__ __align__(16) uint16_t H2[LEARNED ? 16 * kHStride : 8];
+    __shared__ double Gh[LEARNED ? 16 : 1][kClModes];
+    __shared__ double Ge[16][kClModes];
+    __shared__ double Qs[16][3][kClModes];
+    __shared__ double Rw[16][RW_N];
+    __shared__ double FB[NW][2][64];
     if (replay_stale(a, list != 0)) return;
-    const int ci = blockIdx.x;
-    if (a.cl_on[c.cpart[ci]]) {
-        const long long sprev = *a.step_base + a.chunk_k;
-        const int n = c.acnt[ci];
-        for (int k = threadIdx.x; k < n; k += blockDim.x)
-            cl_contact_node<R>(a, c.alist[(size_t)ci * c.max_n + k], sprev);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int rb = blockIdx.x;
+    const int s = c.rb_shape[rb], first = c.rb_first[rb], cnt = c.rb_count[rb];
+    const long long sprev = *a.step_base + a.chunk_k;
+    const int t0 = c.toff[s];
+    const int k = l & 31;  // this lane's mode (lanes k and k + 32 hold the same one)
+    // ---- per particle: advance, contact, sums ------------------------------------
+#pragma unroll 1
+    for (int row = wv; row < 16; row += NW) {
+        const int ci = first + min(row, cnt - 1);
+        const int p = c.cpart[ci];
+        const bool on = row < cnt && a.cl_on[p] != 0;  // the same on every lane of the wave
+        if (!on) {
+            if (LEARNED && l < kClModes) Xs[row * kXsStride + k] = 0;
+            continue;
+        }
+        const int n0 = c.poff[p];
+        const int *al = c.alist + (size_t)ci * c.max_n;
+        double *RS = c.rs + (size_t)ci * 16;
+        const size_t qk = (size_t)ci * kClModes + k;
+        const double q = (c.qr[qk] + a.dt * c.qv[qk]) + a.hdt2 * c.qa[qk];
+        const double cx = (RS[RS_CX] + a.dt * RS[RS_VX]) + a.hdt2 * RS[RS_AX];
+        const double cy = (RS[RS_CY] + a.dt * RS[RS_VY]) + a.hdt2 * RS[RS_AY];
+        const double ph = (RS[RS_PHI] + a.dt * RS[RS_OM]) + a.hdt2 * RS[RS_AL];
+        if (l < kClModes) {
+            c.qr[qk] = q;
+            c.q[qk] = q;
+            Qs[row][0][k] = q;
+        }
+        if (l == 0) {
+            RS[RS_CX] = cx;
+            RS[RS_CY] = cy;
+            RS[RS_PHI] = ph;
+        }
+        const double cp = cos(ph), sp = sin(ph);
+        // contact and walls of the active nodes, and their sums
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, g = 0.0;
+        const int na = c.acnt[ci];
+        for (int b0 = 0; b0 < na; b0 += 64) {
+            const int b = b0 + l;
+            double fbx = 0.0, fby = 0.0;
+            if (b < na) {
+                const int i = al[b];
+                const ClNode f = cl_contact_node<R>(a, i, sprev);
+                const double Yx = (a.x[i] + f.ux) - cx, Yy = (a.y[i] + f.uy) - cy;
+                v0 += f.fx;
+                v1 += f.fy;
+                v2 += Yx * f.fy - Yy * f.fx;
+                v3 += sqrt(f.fx * f.fx + f.fy * f.fy);
+                fbx = cp * f.fx + sp * f.fy;  // in the body frame
+                fby = -sp * f.fx + cp * f.fy;
+            }
+            FB[wv][0][l] = fbx;
+            FB[wv][1][l] = fby;
+            wave_lds_sync();
+            // modal force: lane k + 32 h takes the chunk's nodes h, h + 2, ...
+            const int nb = min(64, na - b0);
+            for (int u = l >> 5; u < nb; u += 2) {
+                const int t = t0 + (al[b0 + u] - n0);
+                const float px = c.phi[((size_t)t * kClModes + k) * 2];
+                const float py = c.phi[((size_t)t * kClModes + k) * 2 + 1];
+                g += (double)px * FB[wv][0][u] + (double)py * FB[wv][1][u];
+            }
+            wave_lds_sync();
+        }
+        v0 = wave_sum(v0);
+        v1 = wave_sum(v1);
+        v2 = wave_sum(v2);
+        v3 = wave_sum(v3);
+        const double ge = g + __shfl_xor(g, 32, 64);
+        double sb = fabs(q) * c.sig[s * kClModes + k];
+        double bq = 2.0 * c.bvec[s * kClModes + k] * q + q * q;
+        for (int o = 16; o > 0; o >>= 1) {  // over the 32 modes
+            sb += __shfl_xor(sb, o, 64);
+            bq += __shfl_xor(bq, o, 64);
+        }
+        if (l < kClModes) {
+            c.gext[qk] = ge;
+            Ge[row][k] = ge;
+            if (LEARNED)
+                Xs[row * kXsStride + k] = f2bf((float)(q / (double)m.sig_q[s * kClModes + k]));
+        }
+        if (l == 0) {
+            Rw[row][RW_CX] = cx;
+            Rw[row][RW_CY] = cy;
+            Rw[row][RW_PH] = ph;
+            Rw[row][RW_FX] = v0;
+            Rw[row][RW_FY] = v1;
+            Rw[row][RW_TAU] = v2;
+            Rw[row][RW_CONTACT] = v3;
+            Rw[row][RW_STRAIN] = sb;
+            Rw[row][RW_BQ] = bq;
+        }
     }
-    __syncthreads();  // this particle's cl_fx / cl_fy and advanced positions are written
-    rc_reduce_body(a, c, list, ci);
-    if (fuse_update) {
+    // ---- the MLP on the block's rows ----------------------------------------------
+    if constexpr (LEARNED) {
+        MlpWave<NW> W;
+        mlp_load<NW>(W, m.wfr + (size_t)s * kClFrag, m.wf + (size_t)s * kClParams, wv, l);
         __syncthreads();
-        rc_update_body(a, c, list, ci);
+        mlp_hidden(Xs, kXsStride, W.w1, W.b1, H1, wv, l, 0, 0, nullptr, nullptr);
+        __syncthreads();
+        mlp_hidden(H1, kHStride, W.w2, W.b2, H2, wv, l, 0, 0, nullptr, nullptr);
+        __syncthreads();
+        if (wv < kClModes / 16) {
+            const f32x4 y = mlp_out<NW>(H2, W, l);
+            const int n3 = 16 * wv + (l & 15), kq = 4 * (l >> 4);
+            const double lam3 = m.lam[s * kClModes + n3];
+            const double sr3 = (double)m.sig_r[s * kClModes + n3];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = kq + t;
+                if (row < cnt) Gh[row][n3] = -lam3 * Qs[row][0][n3] + sr3 * (double)y[t];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- per particle: rates, gate, reconstruction, motion bound -------------------
+#pragma unroll 1
+    for (int row = wv; row < cnt; row += NW) {
+        const int ci = first + row;
+        const int p = c.cpart[ci];
+        if (a.cl_on[p] == 0) continue;  // off before this step (nothing above changes it)
+        const int n0 = c.poff[p];
+        const int *al = c.alist + (size_t)ci * c.max_n;
+        double *RS = c.rs + (size_t)ci * 16;
+        const size_t qk = (size_t)ci * kClModes + k;
+        const double q = Qs[row][0][k];
+        const double gk = LEARNED ? Gh[row][k] : -c.lam[s * kClModes + k] * q;
+        const double qa = gk + Ge[row][k];
+        const double qv = c.qv[qk] + a.hdt * (c.qa[qk] + qa);
+        if (l < kClModes) {
+            c.qv[qk] = qv;
+            c.qa[qk] = qa;
+            Qs[row][1][k] = qv;
+            Qs[row][2][k] = qa;
+        }
+        const double pm = c.phimax[s * kClModes + k];
+        const double qb = c.qrb[qk];
+        double dq = fabs(((q + a.dt * qv) + a.hdt2 * qa) - qb) * pm;
+        double zq = fabs(qb) * pm;
+        for (int o = 16; o > 0; o >>= 1) {
+            dq += __shfl_xor(dq, o, 64);
+            zq += __shfl_xor(zq, o, 64);
+        }
+        const double cx = Rw[row][RW_CX], cy = Rw[row][RW_CY], ph = Rw[row][RW_PH];
+        const double M = c.Mt[s];
+        const double ax = Rw[row][RW_FX] / M + a.gx, ay = Rw[row][RW_FY] / M + a.gy;
+        const double alp = Rw[row][RW_TAU] / (c.I0[s] + Rw[row][RW_BQ]);
+        const double vx = RS[RS_VX] + a.hdt * (RS[RS_AX] + ax);
+        const double vy = RS[RS_VY] + a.hdt * (RS[RS_AY] + ay);
+        const double om = RS[RS_OM] + a.hdt * (RS[RS_AL] + alp);
+        const double rbx = RS[RS_RBX], rby = RS[RS_RBY], rbphi = RS[RS_RBPHI];
+        // the gate for the next step: past gate_frac s0 on the stretch bound or
+        // past tau_c on the contact load, the particle leaves the closure with
+        // every node reconstructed now
+        const bool off = Rw[row][RW_STRAIN] > c.gate_frac * c.s0[s] ||
+                         Rw[row][RW_CONTACT] > c.tau_c[s];
+        wave_lds_sync();  // Qs complete; every lane has read a.cl_on[p]
+        if (l == 0) {
+            RS[RS_VX] = vx;
+            RS[RS_VY] = vy;
+            RS[RS_AX] = ax;
+            RS[RS_AY] = ay;
+            RS[RS_OM] = om;
+            RS[RS_AL] = alp;
+            if (off) {
+                a.cl_on[p] = 0;
+                list_particle_blocks(a, c, p);
+                atomicAdd(c.fallbacks, 1ull);
+            }
+        }
+        RcRigid r;
+        r.cx = cx;
+        r.cy = cy;
+        r.vx = vx;
+        r.vy = vy;
+        r.ax = ax;
+        r.ay = ay;
+        r.cp = cos(ph);
+        r.sp = sin(ph);
+        r.om = om;
+        r.al = alp;
+        const int cntn = off ? c.poff[p + 1] - n0 : c.acnt[ci];
+        int st = 0, stale = 0;
+        for (int b = l; b < cntn; b += 64) {
+            const int i = off ? n0 + b : al[b];
+            st |= rc_write(a, c, i, t0 + (i - n0), r, Qs[row][0], Qs[row][1], Qs[row][2], a.ux_o,
+                           a.uy_o, a.vx_o, a.vy_o, a.ax_o, a.ay_o);
+            if (list && off) {  // a particle leaving the closure: its nodes' own check
+                const double unx = (a.ux_o[i] + a.dt * a.vx_o[i]) + a.hdt2 * a.ax_o[i];
+                const double uny = (a.uy_o[i] + a.dt * a.vy_o[i]) + a.hdt2 * a.ay_o[i];
+                const double ex = unx - (double)a.ubx[i], ey = uny - (double)a.uby[i];
+                if (!(ex * ex + ey * ey <= a.move2)) stale = 1;
+            }
+        }
+        if (list && !off) {
+            // |c' - c_rb| + |phi' - phi_rb| (r_max + sum |q_rb| phimax) + sum |q' - q_rb| phimax
+            // bounds every node's displacement since the rebuild, at the next step
+            const double cxn = (cx + a.dt * vx) + a.hdt2 * ax;
+            const double cyn = (cy + a.dt * vy) + a.hdt2 * ay;
+            const double phn = (ph + a.dt * om) + a.hdt2 * alp;
+            const double B = hypot(cxn - rbx, cyn - rby) + fabs(phn - rbphi) * (c.rmax[s] + zq) + dq;
+            if (!(B * B <= a.move2)) stale = 1;
+        }
+        if (st) atomicOr(a.status, st);
+        if (__any(stale) && l == 0) atomicMin(a.invalid_step, (unsigned long long)(sprev + 2));
     }
 }
 
@@ -1336,18 +1585,27 @@ hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rc_step(const DevArgs &a, const ClArgs &c, int precision, bool list, bool fuse_update,
-                          hipStream_t s) {
+hipError_t launch_rc_fused(const DevArgs &a, const ClArgs &c, const MlpArgs &m, int precision,
+                           bool learned, bool list, hipStream_t s) {
     if (c.Pc <= 0) return hipSuccess;
     if (!(a.cl_on && a.cl_fx && a.cl_fy && c.rs && c.qr && c.qv && c.qa && c.qrb && c.alist && c.acnt &&
-          c.Mt && c.I0 && c.bvec && c.phimax && c.rmax))
+          c.Mt && c.I0 && c.bvec && c.phimax && c.rmax && c.rb_shape && c.rb_first && c.rb_count &&
+          c.n_rb > 0))
         return hipErrorInvalidValue;
-    if (precision == PD_PREC_FP64)
-        hipLaunchKernelGGL(k_rc_step<double>, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0,
-                           fuse_update ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_rc_step<float>, dim3(c.Pc), dim3(256), 0, s, a, c, list ? 1 : 0,
-                           fuse_update ? 1 : 0);
+    if (learned && !(m.wfr && m.wf && m.sig_q && m.sig_r && m.lam)) return hipErrorInvalidValue;
+    const dim3 g((unsigned)c.n_rb), b(64 * kRcWaves);
+    const int li = list ? 1 : 0;
+    if (precision == PD_PREC_FP64) {
+        if (learned)
+            hipLaunchKernelGGL((k_rc_fused<double, true, kRcWaves>), g, b, 0, s, a, c, m, li);
+        else
+            hipLaunchKernelGGL((k_rc_fused<double, false, kRcWaves>), g, b, 0, s, a, c, m, li);
+    } else {
+        if (learned)
+            hipLaunchKernelGGL((k_rc_fused<float, true, kRcWaves>), g, b, 0, s, a, c, m, li);
+        else
+            hipLaunchKernelGGL((k_rc_fused<float, false, kRcWaves>), g, b, 0, s, a, c, m, li);
+    }
     return hipGetLastError();
 }
 
