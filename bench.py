@@ -49,7 +49,8 @@ def kernel_source_hash() -> str:
 
 
 def tuning_key(t: dict) -> str:
-    return f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}_lpn{int(t.get('lanes_per_node', 4))}"
+    return (f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}_lpn{int(t.get('lanes_per_node', 4))}"
+            f"_wp{int(t.get('wall_pass', 0))}")
 
 
 def parse_tuning(text: str) -> dict:
@@ -439,14 +440,18 @@ def modal_excitation(prob, modes, seed, strain_range):
 
 def closure(pd, W, torch, steps, train_iters):
     """The learned modal closure on 2000 particles of four fixed shapes
-    (disk, plus, ring, L; about 390 nodes each, 781 500 nodes) under
-    compaction: snapshots of a plain run train each shape's network on the
-    GPU; then plain, linear-closure and learned-closure runs from another
-    excitation are timed, in the nodal form and in the reduced form (rigid +
-    modal state, boundary nodes only), with the closure checked against the
-    plain bond force every 100 steps."""
+    (disk, plus, ring, L; about 390 nodes each, 781 500 nodes) in a packed
+    bed (security disks at 0.85 of the default box scale) under gravity
+    (5 000 m/s^2), seeded rigid velocities up to 1 m/s and the top wall
+    coming down at 1 m/s: snapshots of a plain run of that settling and
+    compaction (from a seeded modal excitation) train each shape's network
+    on the GPU; then plain, linear-closure and learned-closure runs from
+    another excitation are timed, in the nodal form and in the reduced form
+    (rigid + modal state, boundary nodes only), with the closure checked
+    against the plain bond force every 100 steps; contacts make particles
+    fall back to the plain force during the timed runs."""
     import numpy as np
-    mk = lambda: W.closure_bed(vmax=0.5)
+    mk = lambda: W.closure_bed(vmax=1.0, fill_scale=0.85, gravity=-5000.0, wall_speed=1.0)
     prob = mk()
     sp = prob.meta["shape_of_particle"]
     g = pd.PD(prob)
@@ -468,7 +473,7 @@ def closure(pd, W, torch, steps, train_iters):
     Q, G = torch.cat(Q), torch.cat(G)
     _, s_of, _ = g.closure_particles()
     rows = torch.from_numpy(np.tile(s_of, len(Q) // len(s_of))).cuda()
-    res = {"workload": "closure_2000 (compaction, modal excitation)", "nodes": prob.n_nodes,
+    res = {"workload": "closure_2000 (packed bed: gravity 5000 m/s^2, rigid velocities <= 1 m/s, top wall 1 m/s)", "nodes": prob.n_nodes,
            "particles": prob.n_particles, "modes_setup_s": t_modes,
            "snapshots_per_shape": int(len(Q) // 4)}
     torch.cuda.synchronize()
@@ -645,7 +650,7 @@ def main():
                     help="most steps of the 0.1 m/s compaction run (it stops 30k steps after "
                          "the first break)")
     ap.add_argument("--batched-steps", type=int, default=200)
-    ap.add_argument("--closure-steps", type=int, default=1000)
+    ap.add_argument("--closure-steps", type=int, default=3000)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--impact-us", type=float, default=40.0)
     ap.add_argument("--tuning", default="",
@@ -693,18 +698,27 @@ def main():
     if args.workload != "batched":
         print(json.dumps({args.workload: legs[args.workload]()}), flush=True)
         return
+    def progress(what, t0):
+        # one line per finished leg on stderr (the JSON line stays alone on stdout)
+        print(f"[bench] {what} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
     prob = W.batched(precision=0)
     out = headline(pd, W, torch, args, prob)
     out["hbm_measured"] = hbm_probe(pd, torch)
+    progress("headline", t0)
     if not args.no_variants:
-        out["settling_100"] = legs["settling"]()
-        out["settling_g5000"] = legs["settling_g5000"]()
-        out["precision_split"] = legs["compaction"]()
-        out["batched_fp32"] = batched_fp32(pd, W, torch, args.batched_steps, prob, fixed)
-        out["closure"] = legs["closure"]()
-        out["fragmentation"] = legs["fragmentation"]()
-        out["settle_shapes"] = legs["settle_shapes"]()
+        for key, run in (("settling_100", legs["settling"]), ("settling_g5000", legs["settling_g5000"]),
+                         ("precision_split", legs["compaction"]),
+                         ("batched_fp32", lambda: batched_fp32(pd, W, torch, args.batched_steps, prob,
+                                                               fixed)),
+                         ("closure", legs["closure"]), ("fragmentation", legs["fragmentation"]),
+                         ("settle_shapes", legs["settle_shapes"])):
+            t0 = time.perf_counter()
+            out[key] = run()
+            progress(key, t0)
     if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
         # one aggregate of the same batch, of about the batch's mean size
         sizes = np.diff(prob.particle_offset)
         agg_nodes = np.bincount(prob.particle_aggregate, weights=sizes)
@@ -712,6 +726,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(
             W.subproblem_aggregate(prob, k), args.cpu_seconds,
             f"aggregate {k} of the 64 batched settling aggregates (of mean size)")
+        progress("cpu_baseline", t0)
     print(json.dumps(out), flush=True)
 
 

@@ -117,9 +117,9 @@ typedef struct {
 
 /* Tuning of the launch configuration.  Results are bitwise identical for
  * every block size, staging and graph choice, and equal within rounding for
- * every cell factor, skin and lane count (the contact set itself never
- * changes: it is evaluated from exact distances every step; the lane count
- * changes the order of the per-node sums). */
+ * every cell factor, skin, lane count and wall pass (the contact set itself
+ * never changes: it is evaluated from exact distances every step; the lane
+ * count and the wall pass change the order of the per-node sums). */
 typedef struct {
     int32_t block_nodes;  /* nodes per workgroup of the force kernel: 64, 128 or 256 */
     double cell_factor;   /* cell side / search radius, >= 1 */
@@ -131,6 +131,10 @@ typedef struct {
     int32_t lanes_per_node; /* threads per node of the step kernel with candidate lists: 4 (short
                                chains of dependent work, small problems), 2 or 1 (per-node work
                                done once, large problems); other evaluations use 4 */
+    int32_t wall_pass;    /* with candidate lists and the closure off: 1 evaluates the wall
+                             forces (Sec. 4.5) of the nodes near a wall in a pass of their own
+                             before each step kernel (one more launch per step, a step kernel
+                             with fewer registers: large problems); 0 inside the step kernel */
 } pd_tuning;
 
 /* Builds the context: validates the problem, copies it to the device,
@@ -222,12 +226,14 @@ pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
  *   0 cell keys (with one key per thread also the first radix pass's digit
  *   count), 1 radix histogram, 2 radix digit scan, 3 radix scatter,
  *   4 cell starts, 5 force + integrate (one per step), 6 candidate-list
- *   build.
+ *   build, 7 wall pass (n_out >= 8; tuning wall_pass = 1 only).
  * Search kernels are bracketed one by one.  With candidate lists (skin > 0)
  * the force kernel is timed over runs of up to 64 steps issued as pd_step
  * issues them (one graph replay when the tuning's use_graph is set, else
  * back-to-back launches), events at the ends of each run: its mean is the
- * replay's time per step and excludes per-launch event overhead.
+ * replay's time per step and excludes per-launch event overhead.  With the
+ * wall pass the run's launches are issued one by one, each bracketed by
+ * events, so that class 5 is the step kernel's own duration.
  * (n_out >= 7) */
 pd_status pd_time_kernels(pd_ctx *c, int64_t n_steps, double *ms, int32_t *launches, int32_t n_out);
 

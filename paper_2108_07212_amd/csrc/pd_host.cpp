@@ -383,6 +383,11 @@ hipError_t enqueue_closure(Ctx &c, bool list) {
 }
 
 // list-mode replay: n steps from buffer parity `start`
+// the wall pass runs with candidate lists and the closure off
+bool wall_pass_on(const Ctx &c) {
+    return c.tune.wall_pass && c.tune.skin_factor > 0.0 && !c.cl.mode && c.a.wfx;
+}
+
 hipError_t enqueue_list_launches(Ctx &c, int start, int n) {
     for (int k = 0; k < n; ++k) {
         set_state_ptrs(c, (start + k) & 1);
@@ -394,6 +399,10 @@ hipError_t enqueue_list_launches(Ctx &c, int start, int n) {
                                   : hipSuccess;
             // (the reduced form evaluates its contact inside its step kernel)
             if (e == hipSuccess && !c.cl.reduced) e = launch_cl_contact(c.a, c.precision, c.stream);
+        } else if (wall_pass_on(c)) {
+            e = launch_walls(c.a, c.stream);
+            if (e == hipSuccess)
+                e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 0, true);
         } else {
             e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true);
         }
@@ -559,6 +568,10 @@ pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
         HIPCHK(launch_cells(c.a, 1, 0, c.stream));
         if (ev) HIPCHK(hipEventRecord(ev[b + 1], c.stream));
         HIPCHK(launch_build_list(c.a, c.stream));
+        if (wall_pass_on(c)) {
+            HIPCHK(hipMemsetAsync(c.a.wall_n, 0, sizeof(unsigned long long), c.stream));
+            HIPCHK(launch_wall_mark(c.a, (double)(c.step + 1) * c.a.dt, c.stream));
+        }
         if (ev) HIPCHK(hipEventRecord(ev[b + 2], c.stream));
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         int over = 0;
@@ -594,15 +607,17 @@ pd_status step_lists(Ctx &c, int64_t n) {
             TRY(closure_check(c));
             c.cl.last_check_step = c.step;
         }
-        // reduced closure: the moving top wall may approach a node that is not
-        // active by at most half the skin between rebuilds
+        // reduced closure and wall pass: the moving top wall may approach a
+        // node that is not listed (active, near a wall) by at most half the
+        // skin between rebuilds
         int64_t n_wall = 0;
-        if (c.cl.mode && c.cl.reduced) {
+        const int64_t rb_step = (c.cl.mode && c.cl.reduced) ? c.cl.rb_step : c.last_rebuild_step;
+        if ((c.cl.mode && c.cl.reduced) || wall_pass_on(c)) {
             double vmax = 0.0;
             for (double v : c.h_vtop) vmax = std::max(vmax, fabs(v));
             const double skin = sqrt(c.a.Rl2) - c.a.Rc;
             if (vmax > 0.0) n_wall = std::max<int64_t>(1, (int64_t)floor(0.5 * skin / (vmax * c.a.dt)));
-            if (n_wall > 0 && c.step - c.cl.rb_step >= n_wall) c.list_valid = false;
+            if (n_wall > 0 && c.step - rb_step >= n_wall) c.list_valid = false;
         }
         if (!c.list_valid) TRY(rebuild_lists(c));
         // closure on: the plain-force launch only while some particle is under
@@ -630,7 +645,10 @@ pd_status step_lists(Ctx &c, int64_t n) {
         }
         if (c.cl.mode && c.cl.check_every > 0)
             lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
-        if (n_wall > 0) lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - c.cl.rb_step)));
+        if (n_wall > 0) {
+            const int64_t rbs = (c.cl.mode && c.cl.reduced) ? c.cl.rb_step : c.last_rebuild_step;
+            lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - rbs)));
+        }
         const int chunk = (int)lim;
         int reps = 1;
         if (c.tune.use_graph && chunk == kChunk) {
@@ -1925,7 +1943,23 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         return fail(c, PD_E_INVALID, "skin_factor must be in [0, 16]");
     if (c.cl.mode && !(t->skin_factor > 0.0))
         return fail(c, PD_E_INVALID, "the modal closure runs with candidate lists (skin_factor > 0)");
+    if (!(t->wall_pass == 0 || t->wall_pass == 1))
+        return fail(c, PD_E_INVALID, "wall_pass must be 0 or 1");
     HIPCHK(hipStreamSynchronize(c.stream));
+    if (t->wall_pass && !c.a.wfx) {
+        // the wall pass's node list and forces (kept until the context ends)
+        int *wl;
+        unsigned long long *wn;
+        double *fx, *fy;
+        TRY(dalloc(c, &wl, (size_t)c.N));
+        TRY(dalloc(c, &wn, 1));
+        TRY(dalloc(c, &fx, (size_t)c.N));
+        TRY(dalloc(c, &fy, (size_t)c.N));
+        c.a.wall_list = wl;
+        c.a.wall_n = wn;
+        c.a.wfx = fx;
+        c.a.wfy = fy;
+    }
     const bool regrid = t->cell_factor != c.tune.cell_factor || t->skin_factor != c.tune.skin_factor;
     const bool rewin = t->block_nodes != c.tune.block_nodes;
     c.tune = *t;
@@ -1975,11 +2009,12 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
     if (c.status) return (pd_status)c.status;
     const int P = c.a.radix_passes;
     const int nev = 2 + 4 * P + 3;
-    std::vector<hipEvent_t> ev(nev), fe(2);
+    std::vector<hipEvent_t> ev(nev), fe(2), we(wall_pass_on(c) ? 3 * kChunk : 0);
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     for (auto &e : fe) HIPCHK(hipEventCreate(&e));
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    int32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (auto &e : we) HIPCHK(hipEventCreate(&e));
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const bool list = c.tune.skin_factor > 0.0;
     auto add_search = [&](bool with_list) -> pd_status {
         float t;
@@ -2030,7 +2065,8 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
             HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
                                   c.stream));
             hipGraphExec_t g = nullptr;
-            if (c.tune.use_graph) {
+            const bool wp = wall_pass_on(c);
+            if (c.tune.use_graph && !wp) {
                 // the launches as pd_step issues them: one graph replay
                 if (run == kChunk) {
                     TRY(ensure_list_graph(c));
@@ -2040,10 +2076,24 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
                 }
             }
             HIPCHK(hipEventRecord(fe[0], c.stream));
-            if (g)
+            if (wp) {
+                // two kernels per step: each launch bracketed by events (the
+                // step kernel's duration, not the replay's time per step)
+                for (int k = 0; k < run; ++k) {
+                    set_state_ptrs(c, (c.cur + k) & 1);
+                    c.a.chunk_k = k;
+                    HIPCHK(hipEventRecord(we[3 * k], c.stream));
+                    HIPCHK(launch_walls(c.a, c.stream));
+                    HIPCHK(hipEventRecord(we[3 * k + 1], c.stream));
+                    HIPCHK(launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 0, true));
+                    HIPCHK(hipEventRecord(we[3 * k + 2], c.stream));
+                }
+                c.a.chunk_k = 0;
+            } else if (g) {
                 HIPCHK(hipGraphLaunch(g, c.stream));
-            else
+            } else {
                 HIPCHK(enqueue_list_steps(c, c.cur, run));
+            }
             HIPCHK(hipEventRecord(fe[1], c.stream));
             unsigned long long inv = 0;
             HIPCHK(hipMemcpyAsync(&inv, c.a.invalid_step, sizeof(inv), hipMemcpyDeviceToHost, c.stream));
@@ -2052,8 +2102,18 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
             if (inv != ~0ull) done = std::max<int64_t>(0, std::min<int64_t>(run, (int64_t)inv - 1 - c.step));
             if (done == run) {  // only complete runs time the kernel
                 float t;
-                HIPCHK(hipEventElapsedTime(&t, fe[0], fe[1]));
-                acc[5] += t;
+                if (wp) {
+                    for (int k = 0; k < run; ++k) {
+                        HIPCHK(hipEventElapsedTime(&t, we[3 * k], we[3 * k + 1]));
+                        acc[7] += t;
+                        HIPCHK(hipEventElapsedTime(&t, we[3 * k + 1], we[3 * k + 2]));
+                        acc[5] += t;
+                    }
+                    cnt[7] += run;
+                } else {
+                    HIPCHK(hipEventElapsedTime(&t, fe[0], fe[1]));
+                    acc[5] += t;
+                }
                 cnt[5] += run;
             }
             c.cur = (int)((c.cur + done) & 1);
@@ -2086,7 +2146,8 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
     if (list) TRY(set_device_step(c));
     for (auto &e : ev) hipEventDestroy(e);
     for (auto &e : fe) hipEventDestroy(e);
-    for (int k = 0; k < 7; ++k) {
+    for (auto &e : we) hipEventDestroy(e);
+    for (int k = 0; k < std::min(n_out, 8); ++k) {
         ms[k] = cnt[k] ? acc[k] / (double)cnt[k] : 0.0;
         if (launches) launches[k] = cnt[k];
     }
@@ -2126,16 +2187,25 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     const double skins[5] = {0.0, 0.0, 0.5, 1.0, 2.0};
     const double cells[5] = {1.0, 2.0, 1.0, 1.0, 1.0};
     pd_status result = PD_OK;
-    for (int trial = 0; trial < 3 * 5 * 2 * 3 && result == PD_OK; ++trial) {
-        const int bi = trial / 30, ci = (trial / 6) % 5, li = (trial / 3) % 2, ni = trial % 3;
-        // the lane count matters to the list-mode step only
-        if (skins[ci] == 0.0 && ni > 0) continue;
+    constexpr int kGrid = 3 * 5 * 2 * 3;
+    for (int trial = 0; trial <= kGrid && result == PD_OK; ++trial) {
         pd_tuning t = base;
-        t.block_nodes = blocks[bi];
-        t.cell_factor = cells[ci];
-        t.skin_factor = skins[ci];
-        t.use_lds = 1 - li;
-        t.lanes_per_node = skins[ci] > 0.0 ? lanes[ni] : 4;
+        if (trial < kGrid) {
+            const int bi = trial / 30, ci = (trial / 6) % 5, li = (trial / 3) % 2, ni = trial % 3;
+            // the lane count matters to the list-mode step only
+            if (skins[ci] == 0.0 && ni > 0) continue;
+            t.block_nodes = blocks[bi];
+            t.cell_factor = cells[ci];
+            t.skin_factor = skins[ci];
+            t.use_lds = 1 - li;
+            t.lanes_per_node = skins[ci] > 0.0 ? lanes[ni] : 4;
+            t.wall_pass = 0;
+        } else {
+            // last: the best so far with the walls in a pass of their own
+            if (!(best.skin_factor > 0.0)) break;
+            t = best;
+            t.wall_pass = 1;
+        }
         if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
         // restore and warm up
         for (int k = 0; k < 6; ++k)

@@ -101,6 +101,12 @@ struct DevArgs {
     // walls
     const double *box;    // [A*4]
     const double *vtop;   // [A]
+    // wall pass (list-mode steps, closure off): the nodes within the list
+    // radius of a wall at the last rebuild, and the wall force the pass
+    // evaluates for each of them before the step kernel reads it
+    int *wall_list;                  // [N]
+    unsigned long long *wall_n;      // listed nodes
+    double *wfx, *wfy;               // [N], valid at listed nodes
     // scalars
     double Rc, Rc2, mu, rd, dt, hdt, hdt2, gx, gy;
     long long *step;      // device step counter (t = step * dt)
@@ -294,7 +300,7 @@ struct ClState {
 struct Ctx {
     DevArgs a{};
     ClState cl;
-    pd_tuning tune{64, 1.0, 1, 1, 1.0, 4};
+    pd_tuning tune{64, 1.0, 1, 1, 1.0, 4, 0};
     bool list_valid = false;     // candidate lists match the current state
     int64_t rebuilds = 0;
     // steps between candidate-list rebuilds, running average (list mode): a
@@ -388,7 +394,11 @@ hipError_t launch_sort_pass(const uint32_t *kin, const int *vin, uint32_t *kout,
 hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t s);
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
-                        bool list = false, int sel = 0);
+                        bool list = false, int sel = 0, bool wall_pass = false);
+// the wall pass of list-mode steps: its node list at a rebuild, then one
+// launch before each step kernel
+hipError_t launch_wall_mark(const DevArgs &a, double t_next, hipStream_t s);
+hipError_t launch_walls(const DevArgs &a, hipStream_t s);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
 // the reduced closure's step in one launch (contact, reduction, MLP when
 // learned, update), one workgroup per block of <= 16 particles of one shape

@@ -997,7 +997,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
 // SEL (step mode with the modal closure on): 0 every node; 1 only the nodes
 // of particles under the plain bond force (closure nodes are left to
 // k_cl_contact and the closure kernels).
-template <typename R, int MODE, bool LIST, int SEL, int LPN>
+template <typename R, int MODE, bool LIST, int SEL, int LPN, bool WP>
 __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int blk,
                                             long long sprev, double *lds) {
     static_assert(LPN == 1 || LPN == 2 || LPN == 4, "1, 2 or 4 lanes per node");
@@ -1167,7 +1167,14 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
             a.clist_n[i] = n;
         }
     }
-    if constexpr (LIST) {
+    if constexpr (LIST && WP) {
+        // the wall pass evaluated this node's wall force before this launch
+        // (every node near a wall is on its list until the next rebuild)
+        if (sub == 0 && __builtin_expect(near_wall(a, ag, pxi, pyi, t), 0)) {
+            fwx = a.wfx[i];
+            fwy = a.wfy[i];
+        }
+    } else if constexpr (LIST) {
         // (most nodes are far from every wall: the loop is the cold path)
         if (__builtin_expect(near_wall(a, ag, pxi, pyi, t), 0)) {
 #pragma unroll
@@ -1266,11 +1273,23 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
         // LDS staging.  The list cannot grow during this launch.
         const int nl = *a.n_pd_blocks;
         for (int slot = blockIdx.x; slot < nl; slot += gridDim.x)
-            force_block<R, MODE, LIST, SEL, LPN>(a, 0, a.pd_blocks[slot], sprev, lds);
+            force_block<R, MODE, LIST, SEL, LPN, false>(a, 0, a.pd_blocks[slot], sprev, lds);
     } else {
-        force_block<R, MODE, LIST, SEL, LPN>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x), sprev,
-                                             lds);
+        force_block<R, MODE, LIST, SEL, LPN, false>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x),
+                                                    sprev, lds);
     }
+}
+
+// the list-mode step with the wall pass: without the walls' code the kernel
+// fits in 96 VGPRs, five wavefronts per SIMD instead of four
+template <typename R, int LPN>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_force_wp(
+    DevArgs a, int lds_cap) {
+    extern __shared__ double lds[];
+    const long long sprev = *a.step_base + a.chunk_k;
+    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    force_block<R, M_STEP, true, 0, LPN, true>(a, lds_cap, xcd_block(blockIdx.x, gridDim.x), sprev,
+                                               lds);
 }
 
 // Contact and wall forces of a node of a particle under the modal closure
@@ -1645,6 +1664,83 @@ hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStre
 }
 
 // ---------------------------------------------------------------------------
+// the wall pass of list-mode steps (closure off): the walls' code needs more
+// registers than the rest of the step kernel, so for large problems it runs
+// in a launch of its own over the few nodes near a wall and the step kernel,
+// which then reads the result, keeps more wavefronts in flight
+// ---------------------------------------------------------------------------
+// at a list rebuild (positions advanced as the lists were built): every node
+// within the list radius of a wall of its aggregate (the top wall at the next
+// step's time), or beyond one, onto the list.  Until the next rebuild no
+// other node can come within R_c of a wall: nodes move less than half the
+// skin between rebuilds, and the top wall is held to half the skin as well.
+__global__ void k_wall_mark(DevArgs a, double t_next) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double px, py, ux, uy;
+    advanced_pos(a, i, true, px, py, ux, uy);
+    const int ag = a.pagg[a.part[i]];
+    const double *b = a.box + 4 * ag;
+    const double top = b[3] - a.vtop[ag] * t_next;
+    const double rl = sqrt(a.Rl2);
+    if (px - b[0] < rl || b[1] - px < rl || py - b[2] < rl || top - py < rl) {
+        const unsigned long long k = atomicAdd(a.wall_n, 1ull);
+        a.wall_list[k] = i;
+    }
+}
+
+// each listed node's wall force at the position and velocity the step
+// kernel uses (a thread per node; the four regions summed as the step
+// kernel's four lanes sum them, so the result is the same whatever its lane
+// count); a launch past the first stale step of a replay does nothing
+__global__ __launch_bounds__(256) void k_walls(DevArgs a) {
+    const long long sprev = *a.step_base + a.chunk_k;
+    if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
+    const bool un = a.chunk_k > 0 && a.unx && !a.cl_on;
+    const double t = (double)(sprev + 1) * a.dt;
+    const long long n = (long long)*a.wall_n;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int i = a.wall_list[k];
+        double pxi, pyi, uxi, uyi;
+        advanced_pos_un(a, i, un, pxi, pyi, uxi, uyi);
+        const int pi = a.part[i];
+        const int ag = a.pagg[pi];
+        const MatConst mc = a.mat[a.pmat[pi]];
+        const double Vi = a.vol[i], mi = mc.rho * Vi;
+        const double vxi = a.vx[i], vyi = a.vy[i];
+        int st = 0;
+        double fx[4], fy[4];
+#pragma unroll
+        for (int part = 0; part < 4; ++part) {
+            fx[part] = 0.0;
+            fy[part] = 0.0;
+            wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fx[part], fy[part], st);
+        }
+        a.wfx[i] = (fx[0] + fx[1]) + (fx[2] + fx[3]);
+        a.wfy[i] = (fy[0] + fy[1]) + (fy[2] + fy[3]);
+        if (st) atomicOr(a.status, st);
+    }
+}
+
+hipError_t launch_wall_mark(const DevArgs &a, double t_next, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    if (!(a.wall_list && a.wall_n)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wall_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, t_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_walls(const DevArgs &a, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    if (!(a.wall_list && a.wall_n && a.wfx && a.wfy)) return hipErrorInvalidValue;
+    // a fixed grid (the list's length changes at rebuilds, replays keep the
+    // grid they were captured with); two workgroups per compute unit
+    const unsigned g = std::min<unsigned>((unsigned)((a.N + 255) / 256), 512u);
+    hipLaunchKernelGGL(k_walls, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // compaction observables (Sec. 7.4): wall reactions, bond counts, damage
 // ---------------------------------------------------------------------------
 // each wall's share of the wall force on node i at the current state
@@ -2003,11 +2099,17 @@ int force_lds_cap(int max_win) { return max_win > kMaxLdsNodes ? 0 : max_win; }
 
 template <typename R>
 static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b, size_t shm,
-                           hipStream_t s, int lds_cap, int sel, int lpn) {
+                           hipStream_t s, int lds_cap, int sel, int lpn, bool wp) {
     if (mode == M_STEP) {
         if (list) {
             if (sel == 1)
                 hipLaunchKernelGGL((k_force<R, M_STEP, true, 1>), g, b, 0, s, a, lds_cap);
+            else if (wp && lpn == 1)
+                hipLaunchKernelGGL((k_force_wp<R, 1>), g, b, shm, s, a, lds_cap);
+            else if (wp && lpn == 2)
+                hipLaunchKernelGGL((k_force_wp<R, 2>), g, b, shm, s, a, lds_cap);
+            else if (wp)
+                hipLaunchKernelGGL((k_force_wp<R, 4>), g, b, shm, s, a, lds_cap);
             else if (lpn == 1)
                 hipLaunchKernelGGL((k_force<R, M_STEP, true, 0, 1>), g, b, shm, s, a, lds_cap);
             else if (lpn == 2)
@@ -2025,9 +2127,12 @@ static void launch_force_t(const DevArgs &a, int mode, bool list, dim3 g, dim3 b
 }
 
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
-                        bool list, int sel) {
+                        bool list, int sel, bool wall_pass) {
     if (a.N == 0) return hipSuccess;
     if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
+        return hipErrorInvalidValue;
+    // the wall pass serves list-mode steps of the plain path only
+    if (wall_pass && !(mode == M_STEP && list && !sel && !a.cl_on && a.wfx && a.wfy))
         return hipErrorInvalidValue;
     // nodes per workgroup, LPN lanes each (the tuning's lanes for list-mode
     // steps, four otherwise); the plain-force-only launch uses 64-node
@@ -2043,9 +2148,9 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     const unsigned nb = (unsigned)grid_for(a.N, B);
     const dim3 g(sel ? std::min(nb, 1024u) : nb), b(lpn * B);
     if (precision == PD_PREC_FP64)
-        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn);
+        launch_force_t<double>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn, wall_pass);
     else
-        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn);
+        launch_force_t<float>(a, mode, list, g, b, shm, s, lds_cap, sel, lpn, wall_pass);
     return hipGetLastError();
 }
 

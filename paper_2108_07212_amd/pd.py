@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pd.h")
 PD_OK, PD_E_INVALID, PD_E_NOMEM, PD_E_DEVICE, PD_E_NONFINITE, PD_E_ESCAPED, PD_E_STATE = range(7)
 TERM_PD, TERM_SELF, TERM_NBR, TERM_WALL, TERM_BODY, TERM_ALL = 1, 2, 4, 8, 16, 31
 KERNEL_CLASSES = ("keys", "radix_hist", "radix_digit_scan", "radix_scatter", "cells", "force",
-                  "build_list")
+                  "build_list", "walls")
 
 
 class PDError(RuntimeError):
@@ -56,12 +56,12 @@ class Problem(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block_nodes", C.c_int32), ("cell_factor", C.c_double),
                 ("use_lds", C.c_int32), ("use_graph", C.c_int32), ("skin_factor", C.c_double),
-                ("lanes_per_node", C.c_int32)]
+                ("lanes_per_node", C.c_int32), ("wall_pass", C.c_int32)]
 
     def as_dict(self):
         return dict(block_nodes=self.block_nodes, cell_factor=self.cell_factor,
                     use_lds=self.use_lds, use_graph=self.use_graph, skin_factor=self.skin_factor,
-                    lanes_per_node=self.lanes_per_node)
+                    lanes_per_node=self.lanes_per_node, wall_pass=self.wall_pass)
 
 
 _lib = None

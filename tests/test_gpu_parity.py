@@ -281,8 +281,8 @@ def test_trajectory_two_disks_contact_1000(pdmod):
     assert np.array_equal(sg["broken"], so["broken"])
 
 
-@pytest.mark.parametrize("lanes", [4, 1])
-def test_breaks_during_list_steps(pdmod, lanes):
+@pytest.mark.parametrize("lanes,wall_pass", [(4, 0), (1, 0), (4, 1), (1, 1)])
+def test_breaks_during_list_steps(pdmod, lanes, wall_pass):
     """A 40 m/s head-on impact breaks bonds while the candidate lists are in
     use: each broken pair joins its nodes' lists in the step it breaks (no
     rebuild).  The first 75 steps (bonds break, fragments touch) follow the
@@ -291,8 +291,9 @@ def test_breaks_during_list_steps(pdmod, lanes):
     remaining check is the list path against the every-step cell search on
     the GPU (with fewer lanes per node, whose sums run in another order,
     against lists of a wider skin), which must give the same states and
-    broken bonds."""
-    _say(f"case: breaks during list steps, {lanes} lanes per node")
+    broken bonds.  With the wall pass the breaks go through the break log,
+    merged into the lists by the next step's pass."""
+    _say(f"case: breaks during list steps, {lanes} lanes per node, wall pass {wall_pass}")
 
     def impact():
         prob = W.two_disks(contact_active=True)
@@ -303,7 +304,7 @@ def test_breaks_during_list_steps(pdmod, lanes):
 
     prob = impact()
     g, o = pdmod.PD(prob), Oracle(prob)
-    g.set_tuning(lanes_per_node=lanes)
+    g.set_tuning(lanes_per_node=lanes, wall_pass=wall_pass)
     assert g.tuning()["skin_factor"] > 0
     for k in range(3):
         eu, ev, sg, so = _traj(g, o, 25)
@@ -315,11 +316,12 @@ def test_breaks_during_list_steps(pdmod, lanes):
     # lanes, whose per-node sums run in another order, against the same lane
     # count with a four times wider skin (other lists, other rebuild steps)
     lst, srch = pdmod.PD(impact()), pdmod.PD(impact())
-    lst.set_tuning(lanes_per_node=lanes)
+    lst.set_tuning(lanes_per_node=lanes, wall_pass=wall_pass)
     if lanes == 4:
         srch.set_tuning(skin_factor=0.0)
     else:
-        srch.set_tuning(lanes_per_node=lanes, skin_factor=4 * lst.tuning()["skin_factor"])
+        srch.set_tuning(lanes_per_node=lanes, wall_pass=wall_pass,
+                        skin_factor=4 * lst.tuning()["skin_factor"])
     r0 = lst.sizes()["list_rebuilds"]
     for k in range(3):
         lst.step(50)
