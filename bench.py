@@ -50,7 +50,7 @@ def kernel_source_hash() -> str:
 
 def tuning_key(t: dict) -> str:
     return (f"bn{int(t['block_nodes'])}_lds{int(t['use_lds'])}_lpn{int(t.get('lanes_per_node', 4))}"
-            f"_wp{int(t.get('wall_pass', 0))}")
+            f"_wp{int(t.get('wall_pass', 0))}_sk{float(t.get('skin_factor', 1.0)):g}")
 
 
 def parse_tuning(text: str) -> dict:
@@ -64,8 +64,9 @@ def parse_tuning(text: str) -> dict:
 
 def measured_traffic(kernel: str, workload: str, tuning: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source with the same nodes per
-    workgroup and LDS staging."""
+    were taken on the current kernel source with the same launch
+    configuration (nodes per workgroup, LDS staging, lanes per node, wall
+    pass, skin)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
