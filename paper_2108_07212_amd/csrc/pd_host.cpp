@@ -328,20 +328,23 @@ pd_status build_grid(Ctx &c, const double *box) {
     c.a.radix_passes = (bits + kRadixBits - 1) / kRadixBits;
     double *gx0, *gy0;
     int *ncx, *ncy;
-    uint32_t *cell0, *cs_buf;
+    uint32_t *cell0, *cs_buf, *ce_buf;
     TRY(upload(c, &gx0, c.h_gx0.data(), c.A));
     TRY(upload(c, &gy0, c.h_gy0.data(), c.A));
     TRY(upload(c, &ncx, c.h_ncx.data(), c.A));
     TRY(upload(c, &ncy, c.h_ncy.data(), c.A));
     TRY(upload(c, &cell0, c.h_cell0.data(), c.A));
     TRY(dalloc(c, &cs_buf, (size_t)nc));
+    TRY(dalloc(c, &ce_buf, (size_t)nc));
     HIPCHK(launch_fill_u32(cs_buf, 0u, (int64_t)nc, c.stream));
+    HIPCHK(launch_fill_u32(ce_buf, 0u, (int64_t)nc, c.stream));
     c.a.agg_gx0 = gx0;
     c.a.agg_gy0 = gy0;
     c.a.agg_ncx = ncx;
     c.a.agg_ncy = ncy;
     c.a.agg_cell0 = cell0;
     c.a.cell_start = cs_buf;
+    c.a.cell_end = ce_buf;
     c.a.cell = cs;
     c.a.inv_cell = 1.0 / cs;
     return PD_OK;
@@ -459,6 +462,35 @@ pd_status list_graph_n(Ctx &c, int start, int n, hipGraphExec_t *out) {
     return PD_OK;
 }
 
+hipError_t enqueue_rebuild(Ctx &c, hipEvent_t *ev);
+
+// plain list mode: a rebuild of the lists, the replay's arming (no steps run
+// if a list did not fit its slots) and n steps from buffer parity `start`
+// (the current one), captured once per length and parity
+pd_status rebuild_graph_n(Ctx &c, int start, int n, hipGraphExec_t *out) {
+    const long key = (4L + start) * 1000000L + n;
+    auto it = c.lgraph_n.find(key);
+    if (it == c.lgraph_n.end()) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+        hipError_t e1 = enqueue_rebuild(c, nullptr);
+        if (e1 == hipSuccess) e1 = launch_arm_replay(c.a, c.stream);
+        if (e1 == hipSuccess) e1 = enqueue_list_steps(c, start, n);
+        hipError_t e2 = hipStreamEndCapture(c.stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(c, PD_E_DEVICE, "graph capture failed");
+        }
+        hipGraphExec_t x = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(c, PD_E_DEVICE, "graph instantiate failed");
+        it = c.lgraph_n.emplace(key, x).first;
+    }
+    *out = it->second;
+    return PD_OK;
+}
+
 pd_status ensure_graph(Ctx &c) {
     if (c.graph_valid) return PD_OK;
     invalidate_graph(c);
@@ -520,6 +552,9 @@ pd_status eval_terms(Ctx &c) {
 }
 
 pd_status alloc_lists(Ctx &c, int maxc) {
+    if (maxc > kBlMaxc)
+        return fail(c, PD_E_DEVICE, "a node has more than " + std::to_string(kBlMaxc) +
+                                        " contact candidates");
     if (c.a.clist) {
         hipFree(c.a.clist);
         c.owned.erase(std::remove(c.owned.begin(), c.owned.end(), (void *)c.a.clist), c.owned.end());
@@ -556,39 +591,53 @@ pd_status rc_activate(Ctx &c) {
 }
 
 // candidate lists at the advanced positions of the current state: keys, radix
-// sort and cell starts there, then the per-node lists
+// sort and cell starts there, then the per-node lists (enqueued only, after
+// a round start with its rebuild flag, which clears the counters they fill;
+// no memset, so that replays can capture it)
+hipError_t enqueue_rebuild(Ctx &c, hipEvent_t *ev) {
+    set_state_ptrs(c, c.cur);
+    hipError_t e = enqueue_keys_sort(c, 1, ev);
+    if (e != hipSuccess) return e;
+    const int b = 2 + 4 * c.a.radix_passes;
+    if (ev && (e = hipEventRecord(ev[b], c.stream)) != hipSuccess) return e;
+    if ((e = launch_cells(c.a, 1, 0, c.stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[b + 1], c.stream)) != hipSuccess) return e;
+    if ((e = launch_build_list(c.a, c.stream)) != hipSuccess) return e;
+    if (wall_pass_on(c) && (e = launch_wall_mark(c.a, c.stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[b + 2], c.stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// a rebuild at the current step whose lists fit their slots
+pd_status rebuild_done(Ctx &c) {
+    c.list_valid = true;
+    const double gap = (double)(c.step - c.last_rebuild_step);
+    if (c.rebuilds > 0 && gap > 0.0)
+        c.rebuild_interval = c.rebuild_interval > 1e8 ? gap : 0.5 * (c.rebuild_interval + gap);
+    c.last_rebuild_step = c.step;
+    ++c.rebuilds;
+    return rc_activate(c);
+}
+
+// lists too short for a node's candidates: twice as many slots, until they fit
+pd_status grow_lists(Ctx &c, int over) {
+    int m = c.a.maxc;
+    while (m < over) m *= 2;
+    return alloc_lists(c, m);
+}
+
+// the lists rebuilt and checked before returning
 pd_status rebuild_lists(Ctx &c, hipEvent_t *ev = nullptr, float *ms = nullptr) {
     TRY(rc_sync(c));
     for (int attempt = 0; attempt < 4; ++attempt) {
-        HIPCHK(hipMemsetAsync(c.a.overflow, 0, sizeof(int), c.stream));
-        set_state_ptrs(c, c.cur);
-        HIPCHK(enqueue_keys_sort(c, 1, ev));
-        const int b = 2 + 4 * c.a.radix_passes;
-        if (ev) HIPCHK(hipEventRecord(ev[b], c.stream));
-        HIPCHK(launch_cells(c.a, 1, 0, c.stream));
-        if (ev) HIPCHK(hipEventRecord(ev[b + 1], c.stream));
-        HIPCHK(launch_build_list(c.a, c.stream));
-        if (wall_pass_on(c)) {
-            HIPCHK(hipMemsetAsync(c.a.wall_n, 0, sizeof(unsigned long long), c.stream));
-            HIPCHK(launch_wall_mark(c.a, (double)(c.step + 1) * c.a.dt, c.stream));
-        }
-        if (ev) HIPCHK(hipEventRecord(ev[b + 2], c.stream));
+        HIPCHK(launch_round_start(c.a, c.step, true, c.stream));
+        HIPCHK(enqueue_rebuild(c, ev));
         HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
         int over = 0;
         HIPCHK(hipMemcpyAsync(&over, c.a.overflow, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
-        if (over == 0) {
-            c.list_valid = true;
-            const double gap = (double)(c.step - c.last_rebuild_step);
-            if (c.rebuilds > 0 && gap > 0.0)
-                c.rebuild_interval = c.rebuild_interval > 1e8 ? gap : 0.5 * (c.rebuild_interval + gap);
-            c.last_rebuild_step = c.step;
-            ++c.rebuilds;
-            return rc_activate(c);
-        }
-        int m = c.a.maxc;
-        while (m < over) m *= 2;
-        TRY(alloc_lists(c, m));
+        if (over == 0) return rebuild_done(c);
+        TRY(grow_lists(c, over));
     }
     return fail(c, PD_E_DEVICE, "candidate lists keep overflowing");
 }
@@ -619,7 +668,16 @@ pd_status step_lists(Ctx &c, int64_t n) {
             if (vmax > 0.0) n_wall = std::max<int64_t>(1, (int64_t)floor(0.5 * skin / (vmax * c.a.dt)));
             if (n_wall > 0 && c.step - rb_step >= n_wall) c.list_valid = false;
         }
-        if (!c.list_valid) TRY(rebuild_lists(c));
+        // plain steps queue the rebuild ahead of the replay (one graph), whose
+        // steps run only if every list fit its slots (checked with the
+        // replay's results)
+        bool queued_rebuild = false;
+        if (!c.list_valid) {
+            if (c.cl.mode)
+                TRY(rebuild_lists(c));
+            else
+                queued_rebuild = true;
+        }
         // closure on: the plain-force launch only while some particle is under
         // the plain force (a particle leaving the closure ends a replay without it)
         c.cl.plain_launch = true;
@@ -629,37 +687,49 @@ pd_status step_lists(Ctx &c, int64_t n) {
             HIPCHK(hipStreamSynchronize(c.stream));
             c.cl.plain_launch = c.rb->npb > 0;
         }
-        HIPCHK(launch_invalidate(c.a, ~0ull, c.stream));
-        HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base, (unsigned long long)c.step,
-                              c.stream));
+        HIPCHK(launch_round_start(c.a, c.step, queued_rebuild, c.stream));
         int64_t lim = std::min<int64_t>(left, kChunk);
-        // lists that go stale every few steps: replays of about twice the
-        // usual interval (a power of two, at least 8 steps), one per round
-        // trip, so that few launches run as no-ops after a stale step
-        bool short_runs = false;
-        if (c.rebuild_interval < 0.5 * kChunk) {
-            int64_t len = 8;
-            while (len < 2.0 * c.rebuild_interval && len < kChunk) len *= 2;
-            short_runs = len < kChunk;
-            lim = std::min<int64_t>(lim, len);
+        // lists that go stale within a replay: replays of about 1.5 times the
+        // usual interval (a multiple of 8 steps), so that few launches run as
+        // no-ops after a stale step
+        if (c.rebuild_interval < kChunk) {
+            const int64_t len = 8 * (int64_t)ceil(1.5 * c.rebuild_interval / 8.0);
+            lim = std::min<int64_t>(lim, std::max<int64_t>(8, len));
         }
         if (c.cl.mode && c.cl.check_every > 0)
             lim = std::min<int64_t>(lim, c.cl.check_every - c.step % c.cl.check_every);
         if (n_wall > 0) {
-            const int64_t rbs = (c.cl.mode && c.cl.reduced) ? c.cl.rb_step : c.last_rebuild_step;
+            // (a rebuild queued ahead of this replay is at the current step)
+            const int64_t rbs = queued_rebuild                   ? c.step
+                                : (c.cl.mode && c.cl.reduced) ? c.cl.rb_step
+                                                              : c.last_rebuild_step;
             lim = std::min<int64_t>(lim, std::max<int64_t>(1, n_wall - (c.step - rbs)));
         }
         const int chunk = (int)lim;
         int reps = 1;
-        if (c.tune.use_graph && chunk == kChunk) {
+        if (queued_rebuild) {
+            if (c.tune.use_graph) {
+                hipGraphExec_t g = nullptr;
+                TRY(rebuild_graph_n(c, c.cur, chunk, &g));
+                HIPCHK(hipGraphLaunch(g, c.stream));
+            } else {
+                HIPCHK(enqueue_rebuild(c, nullptr));
+                HIPCHK(launch_arm_replay(c.a, c.stream));
+                HIPCHK(enqueue_list_steps(c, c.cur, chunk));
+            }
+        } else if (c.tune.use_graph && chunk == kChunk) {
             TRY(ensure_list_graph(c));
             // plain steps: up to kReplaysPerSync replays per host round trip; a
             // replay queued after one that went stale does nothing (the stale
             // step stays recorded), and kChunk is even, so every replay starts
             // at the same buffer parity
             static_assert(kChunk % 2 == 0, "replays queued back to back share a parity");
-            if (!c.cl.mode && !short_runs)
-                reps = (int)std::min<int64_t>(kReplaysPerSync, left / kChunk);
+            // (as many as the lists are expected to outlast)
+            if (!c.cl.mode) {
+                const double fit = std::floor(c.rebuild_interval / kChunk);
+                reps = (int)std::min<double>({(double)kReplaysPerSync, (double)(left / kChunk),
+                                              std::max(1.0, fit)});
+            }
             for (int r = 0; r < reps; ++r) {
                 if (r > 0)
                     HIPCHK(launch_set_u64((unsigned long long *)c.a.step_base,
@@ -676,12 +746,19 @@ pd_status step_lists(Ctx &c, int64_t n) {
         } else {
             HIPCHK(enqueue_list_steps(c, c.cur, chunk));
         }
-        HIPCHK(hipMemcpyAsync(&c.rb->inv, c.a.invalid_step, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, c.stream));
-        HIPCHK(hipMemcpyAsync(&c.rb->st, c.a.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipMemcpyAsync(&c.rb->ctl, c.ctl, sizeof(Ctx::Ctl), hipMemcpyDeviceToHost,
+                              c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
-        const unsigned long long inv = c.rb->inv;
-        const int st = c.rb->st;
+        const unsigned long long inv = c.rb->ctl.inv;
+        const int st = c.rb->ctl.st;
+        if (queued_rebuild) {
+            // lists too short: the replay did nothing; longer lists, rebuilt
+            if (c.rb->ctl.over > 0) {
+                TRY(grow_lists(c, c.rb->ctl.over));
+                continue;
+            }
+            TRY(rebuild_done(c));
+        }
         const int64_t queued = (int64_t)chunk * reps;
         int64_t done = queued;
         if (inv != ~0ull) {
@@ -1554,15 +1631,17 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     TRY(dalloc(c, &a.spy, N));
     TRY(dalloc(c, &a.spart, N));
     TRY(dalloc(c, &a.step, 1));
-    TRY(dalloc(c, &a.step_base, 1));
-    TRY(dalloc(c, &a.invalid_step, 1));
-    TRY(dalloc(c, &a.overflow, 1));
+    TRY(dalloc(c, &c.ctl, 1));
+    a.invalid_step = &c.ctl->inv;
+    a.step_base = &c.ctl->base;
+    a.status = &c.ctl->st;
+    a.overflow = &c.ctl->over;
+    HIPCHK(hipMemsetAsync(c.ctl, 0, sizeof(Ctx::Ctl), c.stream));
     TRY(dalloc(c, &a.clist_n, N));
     TRY(dalloc(c, &a.ubx, N));
     TRY(dalloc(c, &a.uby, N));
     TRY(alloc_lists(c, 16));
     HIPCHK(launch_invalidate(a, ~0ull, c.stream));
-    TRY(dalloc(c, &a.status, 1));
     TRY(dalloc(c, &a.counters, C_N));
     HIPCHK(hipMemsetAsync(a.status, 0, sizeof(int), c.stream));
     HIPCHK(hipMemsetAsync(a.counters, 0, sizeof(unsigned long long) * C_N, c.stream));
@@ -1975,7 +2054,7 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         HIPCHK(hipMemcpy(box.data(), c.a.box, box.size() * sizeof(double), hipMemcpyDeviceToHost));
         // release the old grid arrays
         const void *old[] = {c.a.agg_gx0, c.a.agg_gy0, c.a.agg_ncx, c.a.agg_ncy, c.a.agg_cell0,
-                             c.a.cell_start};
+                             c.a.cell_start, c.a.cell_end};
         for (const void *q : old) {
             hipFree((void *)q);
             c.owned.erase(std::remove(c.owned.begin(), c.owned.end(), q), c.owned.end());

@@ -14,6 +14,8 @@ namespace pd {
 constexpr uint32_t kBroken = 0x80000000u;  // broken bit of a bond slot
 constexpr uint32_t kIndexMask = 0x7fffffffu;
 constexpr int kSlice = 16;                  // SELL slice height: the nodes of one wavefront (4 lanes each)
+constexpr int kBlLanes = 16;   // lanes per node of the candidate-list build
+constexpr int kBlMaxc = 2048;  // longest candidate list (the build gathers it in LDS)
 // nodes per workgroup of the plain-force-only pass (modal closure on), whatever
 // the tuning (the unit of its workgroup list)
 constexpr int kSelBlockNodes = 64;
@@ -92,6 +94,7 @@ struct DevArgs {
     const uint32_t *skey; // [N] sorted keys
     const int *perm;      // [N] sorted position -> node
     uint32_t *cell_start; // [ncells]
+    uint32_t *cell_end;   // [ncells] one past the cell's last sorted entry
     double *spx, *spy;    // [N] positions in sorted order
     int *spart;           // [N] particle of sorted position
     const double *agg_gx0, *agg_gy0;  // grid origin per aggregate
@@ -325,11 +328,19 @@ struct Ctx {
     std::string err;
     // owned device buffers
     std::vector<void *> owned;
-    // pinned host words the step loop reads back after each round of
-    // replays: first stale step, status, plain-force workgroup count
-    struct Readback {
+    // device control words of the list-mode steps, one block so that a round
+    // of replays reads them back in one copy: first stale step, the steps
+    // completed before the replay, status, and the longest candidate list of
+    // a rebuild queued with the replay when it did not fit (else 0)
+    struct Ctl {
         unsigned long long inv;
+        long long base;
         int st;
+        int over;
+    } *ctl = nullptr;
+    // pinned host copy of the control words, and the plain-force workgroup count
+    struct Readback {
+        Ctl ctl;
         int npb;
     } *rb = nullptr;
     double *U[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buf][comp]
@@ -397,7 +408,7 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
                         bool list = false, int sel = 0, bool wall_pass = false);
 // the wall pass of list-mode steps: its node list at a rebuild, then one
 // launch before each step kernel
-hipError_t launch_wall_mark(const DevArgs &a, double t_next, hipStream_t s);
+hipError_t launch_wall_mark(const DevArgs &a, hipStream_t s);
 hipError_t launch_walls(const DevArgs &a, hipStream_t s);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
 // the reduced closure's step in one launch (contact, reduction, MLP when
@@ -414,6 +425,8 @@ hipError_t launch_cc_count(const DevArgs &a, const int *L, int *size, int min_no
                            int *stats, hipStream_t s);
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s);
 hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s);
+hipError_t launch_arm_replay(const DevArgs &a, hipStream_t s);
+hipError_t launch_round_start(const DevArgs &a, long long step, bool rebuild, hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 hipError_t launch_sum_terms(const DevArgs &a, uint32_t mask, double *fx, double *fy, hipStream_t s);
 hipError_t launch_damage(const DevArgs &a, double *phi, unsigned long long *nb, hipStream_t s);

@@ -357,6 +357,7 @@ __global__ void k_cells(DevArgs a, int adv, int advance_step) {
     if (k >= a.N) return;
     const uint32_t key = a.skey[k];
     if (k == 0 || a.skey[k - 1] != key) a.cell_start[key] = (uint32_t)k;
+    if (k == a.N - 1 || a.skey[k + 1] != key) a.cell_end[key] = (uint32_t)k + 1u;
     const int j = a.perm[k];
     double px, py, ux, uy;
     advanced_pos(a, j, adv != 0, px, py, ux, uy);
@@ -557,16 +558,23 @@ __device__ void wall_parts(const DevArgs &a, int ag, int part, double px, double
 }
 
 // bond (i, j) is in the reference set and intact (scan of i's own row)
+// is j an intact bond partner of i?  Bond rows are in ascending partner
+// order: a binary search of the row.
 __device__ __forceinline__ bool bonded_intact(const DevArgs &a, int i, int j) {
     const uint32_t base = a.slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
     const int n = a.rowlen[i];
-    for (int k = 0; k < n; ++k) {
-        const uint32_t e = a.col[base + (uint32_t)k * kSlice];
-        const int jj = (int)(e & kIndexMask);
-        if (jj == j) return (e & kBroken) == 0;
-        if (jj > j) break;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int jj = (int)(a.col[base + (uint32_t)mid * kSlice] & kIndexMask);
+        if (jj < j)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    return false;
+    if (lo == n) return false;
+    const uint32_t e = a.col[base + (uint32_t)lo * kSlice];
+    return (int)(e & kIndexMask) == j && (e & kBroken) == 0;
 }
 
 
@@ -574,24 +582,26 @@ __device__ __forceinline__ bool bonded_intact(const DevArgs &a, int i, int j) {
 // r2 = |p_j - p_i|^2 < R_c^2, r2 > 0: repulsion (Sec. 4.1 for other
 // particles, Sec. 4.4 for unbonded nodes of the same particle), damping and
 // friction.  Accumulates into the self or the inter-particle term.
+// The partner's reference position (xj, yj), volume Vj and velocity come in
+// loaded; its material's stiffness is read only with several materials.
 template <typename R>
-__device__ __forceinline__ void contact_pair(const DevArgs &a, const MatConst &mc, int i, int j,
-                                             bool same, int pj, double xi, double yi, double ddx,
-                                             double ddy, double r2, double vxi, double vyi,
-                                             double vxj, double vyj, double Vi, double mi,
-                                             R &fsx, R &fsy, R &fnx, R &fny) {
+__device__ __forceinline__ void contact_pair_d(const DevArgs &a, const MatConst &mc, bool same,
+                                               int pj, double xi, double yi, double xj, double yj,
+                                               double Vj, double ddx, double ddy, double r2,
+                                               double vxi, double vyi, double vxj, double vyj,
+                                               double Vi, double mi, R &fsx, R &fsy, R &fnx,
+                                               R &fny) {
     const double d = sqrt(r2);
     const double ex = ddx / d, ey = ddy / d;
-    const double Vj = a.vol[j];
     double coef, Kd;
     if (!same) {
-        const double Ka = mc.Kn, Kb = a.mat[a.pmat[pj]].Kn;
+        const double Ka = mc.Kn, Kb = a.M == 1 ? mc.Kn : a.mat[a.pmat[pj]].Kn;
         const double Kn = (2.0 * Ka * Kb) / (Ka + Kb);  // harmonic mean (Sec. 4.1)
         coef = -Kn * (a.Rc - d);
         Kd = Kn;
         count(a, C_INTER);
     } else {
-        const double X = a.x[j] - xi, Y = a.y[j] - yi;
+        const double X = xj - xi, Y = yj - yi;
         const double L = sqrt(X * X + Y * Y);  // reference distance |xi|
         if (L < a.Rc)
             coef = (d < L) ? mc.cw * (d - L) / L : 0.0;
@@ -613,63 +623,135 @@ __device__ __forceinline__ void contact_pair(const DevArgs &a, const MatConst &m
     }
 }
 
+template <typename R>
+__device__ __forceinline__ void contact_pair(const DevArgs &a, const MatConst &mc, int i, int j,
+                                             bool same, int pj, double xi, double yi, double ddx,
+                                             double ddy, double r2, double vxi, double vyi,
+                                             double vxj, double vyj, double Vi, double mi,
+                                             R &fsx, R &fsy, R &fnx, R &fny) {
+    contact_pair_d<R>(a, mc, same, pj, xi, yi, a.x[j], a.y[j], a.vol[j], ddx, ddy, r2, vxi, vyi,
+                      vxj, vyj, Vi, mi, fsx, fsy, fnx, fny);
+}
+
+// LDS written by some lanes of a wavefront and then read by others of it
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Contact candidate list of every node at its advanced position: nodes of
 // the 3 x 3 neighbouring cells (cell side >= list radius) closer than the
-// list radius, except intact bonds, in cell order.  Also records the
-// displacement at which the list was built.
-__global__ void k_build_list(DevArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
+// list radius, except intact bonds, in ascending partner index.  Also
+// records the displacement at which the list was built.
+//
+// kBlLanes lanes per node, one wavefront per workgroup.  The three cells of
+// a row have consecutive keys, so they are one range of the cell-sorted
+// arrays; the lanes take the entries of the three ranges in turn, gather
+// the accepted partners in LDS (a wavefront ballot gives each its slot) and
+// then write each one at its rank among them.
+__global__ __launch_bounds__(64) void k_build_list(DevArgs a) {
+    extern __shared__ uint32_t bl_lds[];
+    constexpr int kNodes = 64 / kBlLanes;
+    const int g = threadIdx.x / kBlLanes, l = threadIdx.x % kBlLanes;
+    const int i = blockIdx.x * kNodes + g;
+    const bool live = i < a.N;
+    const int ic = live ? i : a.N - 1;
+    const int maxc = a.maxc;
+    uint32_t *L = bl_lds + (size_t)g * maxc;
     double pxi, pyi, uxi, uyi;
-    advanced_pos(a, i, true, pxi, pyi, uxi, uyi);
-    const int pi = a.part[i];
+    advanced_pos(a, ic, true, pxi, pyi, uxi, uyi);
+    const int pi = a.part[ic];
     const int ag = a.pagg[pi];
     int cx, cy;
     cell_of(a, ag, pxi, pyi, cx, cy);
     const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
     const uint32_t c0 = a.agg_cell0[ag];
-    int n = 0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = cy + dy;
-        if (yy < 0 || yy >= ncy) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int xx = cx + dx;
-            if (xx < 0 || xx >= ncx) continue;
-            const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
-            const uint32_t s = a.cell_start[c];
-            if (s >= (uint32_t)a.N || a.skey[s] != c) continue;
-            for (uint32_t k = s; k < (uint32_t)a.N && a.skey[k] == c; ++k) {
-                const int j = a.perm[k];
-                if (j == i) continue;
-                const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
-                if (!(ddx * ddx + ddy * ddy < a.Rl2)) continue;
-                if (a.spart[k] == pi && bonded_intact(a, i, j)) continue;
-                if (n < a.maxc) a.clist[(size_t)n * a.N + i] = (uint32_t)j;
-                ++n;
+    const int xlo = max(cx - 1, 0), xhi = min(cx + 1, ncx - 1);
+    uint32_t beg[3], cnt[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int yy = cy + r - 1;
+        uint32_t b = 0xffffffffu, e = 0u;
+        if (live && yy >= 0 && yy < ncy) {
+            for (int xx = xlo; xx <= xhi; ++xx) {
+                const uint32_t c = c0 + (uint32_t)yy * (uint32_t)ncx + (uint32_t)xx;
+                const uint32_t s = a.cell_start[c];
+                if (s < (uint32_t)a.N && a.skey[s] == c) {
+                    b = min(b, s);
+                    e = max(e, a.cell_end[c]);
+                }
             }
         }
+        beg[r] = b;
+        cnt[r] = e > b ? e - b : 0u;
     }
-    if (n > a.maxc) {
-        atomicMax(a.overflow, n);
-        n = a.maxc;
+    const int T = (int)(cnt[0] + cnt[1] + cnt[2]);
+    const unsigned long long gmask = ((1ull << kBlLanes) - 1ull) << (g * kBlLanes);
+    const unsigned long long below = (1ull << (threadIdx.x)) - 1ull;
+    int n = 0;
+    for (int t0 = 0; __any(t0 < T); t0 += kBlLanes) {
+        const int t = t0 + l;
+        bool acc = false;
+        uint32_t j = 0;
+        if (t < T) {
+            const uint32_t k = t < (int)cnt[0] ? beg[0] + (uint32_t)t
+                               : t < (int)(cnt[0] + cnt[1]) ? beg[1] + (uint32_t)(t - (int)cnt[0])
+                                                           : beg[2] + (uint32_t)(t - (int)(cnt[0] + cnt[1]));
+            j = (uint32_t)a.perm[k];
+            if ((int)j != i) {
+                const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
+                acc = ddx * ddx + ddy * ddy < a.Rl2;
+                if (acc && a.spart[k] == pi) acc = !bonded_intact(a, i, (int)j);
+            }
+        }
+        const unsigned long long bal = __ballot(acc) & gmask;
+        const int pos = n + __popcll(bal & below);
+        if (acc && pos < maxc) L[pos] = j;
+        n += __popcll(bal);
+    }
+    wave_lds_sync();
+    if (!live) return;
+    if (n > maxc) {
+        if (l == 0) atomicMax(a.overflow, n);
+        n = maxc;
     }
     // ascending partner index: the order contact sums run in does not depend
     // on how the list came about (a rebuild or appends after breaks)
-    for (int k = 1; k < n; ++k) {
-        const uint32_t v = a.clist[(size_t)k * a.N + i];
-        int m = k - 1;
-        while (m >= 0 && a.clist[(size_t)m * a.N + i] > v) {
-            a.clist[(size_t)(m + 1) * a.N + i] = a.clist[(size_t)m * a.N + i];
-            --m;
-        }
-        a.clist[(size_t)(m + 1) * a.N + i] = v;
+    for (int e = l; e < n; e += kBlLanes) {
+        const uint32_t v = L[e];
+        int rank = 0;
+        for (int m = 0; m < n; ++m) rank += L[m] < v ? 1 : 0;
+        a.clist[(size_t)rank * a.N + i] = v;
     }
-    a.clist_n[i] = n;
-    a.ubx[i] = (float)uxi;
-    a.uby[i] = (float)uyi;
+    if (l == 0) {
+        a.clist_n[i] = n;
+        a.ubx[i] = (float)uxi;
+        a.uby[i] = (float)uyi;
+    }
 }
 
 __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
+// the first stale step before a replay: none, or every step of the replay
+// when the candidate lists it follows did not fit their slots
+__global__ void k_arm_replay(unsigned long long *inv, const int *overflow) {
+    *inv = *overflow ? 0ull : ~0ull;
+}
+
+// the start of a round of list-mode steps after `step` completed steps: the
+// step base, and either no stale step yet, or (a rebuild ahead of the
+// replay) the counters the rebuild fills cleared; k_arm_replay then sets
+// the stale step
+__global__ void k_round_start(DevArgs a, long long step, int rebuild) {
+    *a.step_base = step;
+    if (rebuild) {
+        *a.overflow = 0;
+        if (a.wall_n) *a.wall_n = 0ull;
+    } else {
+        *a.invalid_step = ~0ull;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // the force kernel
@@ -919,21 +1001,50 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                                                double Vi, double mi, R &fsx, R &fsy, R &fnx,
                                                R &fny, int nc_pre = -1, bool un = false) {
     if (LIST) {
-        // candidates listed at the last rebuild (intact bonds excluded)
-        // candidate j goes to lane j mod LPN, in ascending j (the list is
-        // sorted): a lane's sum then depends only on the pairs within R_c,
-        // not on which extra candidates the list holds (it is a superset that
-        // depends on when it was built)
+        // Candidates listed at the last rebuild (intact bonds excluded), in
+        // ascending j, taken in batches of kCB list entries.  First the
+        // node's lanes split a batch by position and test the distances (a
+        // lane's kPer candidates loaded together: one memory round trip, not
+        // one per candidate); then each pair closer than R_c goes to lane
+        // j mod LPN, in ascending j, so a lane's sum depends only on the
+        // pairs within R_c, not on which extra candidates the list holds (a
+        // superset that depends on when it was built).
         const int nc = nc_pre >= 0 ? nc_pre : a.clist_n[i];
-        constexpr int kCB = 8;  // list entries fetched together
+        constexpr int kPer = 4;
+        constexpr int kCB = kPer * LPN;
+        static_assert(kCB <= 32, "a batch's mask is one word");
         for (int q0 = 0; q0 < nc; q0 += kCB) {
-            int js[kCB];
+            int jq[kPer];
 #pragma unroll
-            for (int t = 0; t < kCB; ++t)
-                js[t] = q0 + t < nc ? (int)a.clist[(size_t)(q0 + t) * a.N + i] : -1;
-            for (int t = 0; t < kCB; ++t) {
-                const int j = js[t];
-                if (j < 0 || (j & (LPN - 1)) != sub) continue;
+            for (int m = 0; m < kPer; ++m) {
+                const int q = q0 + sub + m * LPN;
+                jq[m] = q < nc ? (int)a.clist[(size_t)q * a.N + i] : -1;
+            }
+            double pxq[kPer], pyq[kPer];
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const int j = jq[m] >= 0 ? jq[m] : i;
+                double ux, uy;
+                if (adv)
+                    advanced_pos_un(a, j, un, pxq[m], pyq[m], ux, uy);
+                else
+                    advanced_pos(a, j, false, pxq[m], pyq[m], ux, uy);
+            }
+            int hit = 0;
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const double ddx = pxq[m] - pxi, ddy = pyq[m] - pyi;
+                if (jq[m] >= 0 && ddx * ddx + ddy * ddy < a.Rc2) hit |= 1 << (sub + m * LPN);
+            }
+            hit = lanes_or<LPN>(hit);  // the node's pairs within R_c in this batch
+            while (hit) {
+                const int t = __builtin_ctz((unsigned)hit);
+                hit &= hit - 1;
+                const int j = (int)a.clist[(size_t)(q0 + t) * a.N + i];
+                if ((j & (LPN - 1)) != sub) continue;
+                const double xj = a.x[j], yj = a.y[j];
+                const double vxj = a.vx[j], vyj = a.vy[j], Vj = a.vol[j];
+                const int pj = a.part[j];
                 double pxj, pyj, ux, uy;
                 if (adv)
                     advanced_pos_un(a, j, un, pxj, pyj, ux, uy);
@@ -941,14 +1052,12 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                     advanced_pos(a, j, false, pxj, pyj, ux, uy);
                 const double ddx = pxj - pxi, ddy = pyj - pyi;
                 const double r2 = ddx * ddx + ddy * ddy;
-                if (!(r2 < a.Rc2)) continue;
                 if (r2 == 0.0) {
                     count(a, C_COINC);
                     continue;
                 }
-                const int pj = a.part[j];
-                contact_pair<R>(a, mc, i, j, pj == pi, pj, xi, yi, ddx, ddy, r2, vxi, vyi,
-                                a.vx[j], a.vy[j], Vi, mi, fsx, fsy, fnx, fny);
+                contact_pair_d<R>(a, mc, pj == pi, pj, xi, yi, xj, yj, Vj, ddx, ddy, r2, vxi, vyi,
+                                  vxj, vyj, Vi, mi, fsx, fsy, fnx, fny);
             }
         }
     } else {
@@ -1364,12 +1473,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// LDS written by some lanes of a wavefront and then read by others of it
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 enum { RW_CX = 0, RW_CY, RW_PH, RW_FX, RW_FY, RW_TAU, RW_CONTACT, RW_STRAIN, RW_BQ, RW_N };
 
@@ -1670,13 +1773,14 @@ hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStre
 // which then reads the result, keeps more wavefronts in flight
 // ---------------------------------------------------------------------------
 // at a list rebuild (positions advanced as the lists were built): every node
-// within the list radius of a wall of its aggregate (the top wall at the next
-// step's time), or beyond one, onto the list.  Until the next rebuild no
+// within the list radius of a wall of its aggregate (the top wall at the time
+// of the step after *step_base, the rebuild's step), or beyond one, onto the list.  Until the next rebuild no
 // other node can come within R_c of a wall: nodes move less than half the
 // skin between rebuilds, and the top wall is held to half the skin as well.
-__global__ void k_wall_mark(DevArgs a, double t_next) {
+__global__ void k_wall_mark(DevArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
+    const double t_next = (double)(*a.step_base + 1) * a.dt;
     double px, py, ux, uy;
     advanced_pos(a, i, true, px, py, ux, uy);
     const int ag = a.pagg[a.part[i]];
@@ -1723,10 +1827,10 @@ __global__ __launch_bounds__(256) void k_walls(DevArgs a) {
     }
 }
 
-hipError_t launch_wall_mark(const DevArgs &a, double t_next, hipStream_t s) {
+hipError_t launch_wall_mark(const DevArgs &a, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
     if (!(a.wall_list && a.wall_n)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_wall_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a, t_next);
+    hipLaunchKernelGGL(k_wall_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -2156,7 +2260,11 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
 
 hipError_t launch_build_list(const DevArgs &a, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_list, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+    if (a.maxc < 1 || a.maxc > kBlMaxc) return hipErrorInvalidValue;
+    constexpr int kNodes = 64 / kBlLanes;
+    const size_t shm = (size_t)kNodes * (size_t)a.maxc * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_build_list, dim3((unsigned)((a.N + kNodes - 1) / kNodes)), dim3(64), shm,
+                       s, a);
     return hipGetLastError();
 }
 
@@ -2167,6 +2275,16 @@ hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream
 
 hipError_t launch_invalidate(const DevArgs &a, unsigned long long v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, a.invalid_step, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_start(const DevArgs &a, long long step, bool rebuild, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_start, dim3(1), dim3(1), 0, s, a, step, rebuild ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_arm_replay(const DevArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_arm_replay, dim3(1), dim3(1), 0, s, a.invalid_step, a.overflow);
     return hipGetLastError();
 }
 

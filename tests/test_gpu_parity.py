@@ -485,7 +485,8 @@ def test_determinism_graph_and_tuning(pdmod, skin):
 @pytest.mark.parametrize("skin", [0.0, 0.25, 2.0])
 def test_trajectory_skins(pdmod, skin):
     """Every skin (0: cell search every step) gives the oracle trajectory;
-    a small skin forces many candidate-list rebuilds."""
+    a small skin forces many candidate-list rebuilds, a wide one lists longer
+    than their initial slots."""
     _say(f"case: trajectory skin={skin}")
     prob = _herd(_bed(10, 13, g=(0.0, -5000.0)), 0.45, seed=13, dv=2.0)
     g, o = pdmod.PD(prob), Oracle(prob)
@@ -495,6 +496,10 @@ def test_trajectory_skins(pdmod, skin):
     assert np.array_equal(sg["broken"], so["broken"])
     if skin == 0.25:
         assert g.sizes()["list_rebuilds"] > 3
+    if skin == 2.0:
+        # some node has more candidates than the 16 initial slots: the lists
+        # grew after a rebuild queued ahead of a replay overflowed them
+        assert g.sizes()["list_slots"] > 16
 
 
 def test_autotune_keeps_state(pdmod):
