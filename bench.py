@@ -218,20 +218,35 @@ def timed_steps(g, torch, steps):
     return steps / (time.perf_counter() - t0), g.sizes()["list_rebuilds"] - r0
 
 
-def force_roofline(g, kernel_steps, precision, workload, name):
-    """Roofline of the force kernel: algorithmic bytes per launch over its
-    mean duration in graph replays (HIP events on the library's stream)."""
+def step_kernel_name(tuning: dict, precision: int) -> str:
+    """The step kernel a tuning launches (list mode: with or without the pass
+    of walls and contact candidates before it)."""
+    r = "double" if precision == 0 else "float"
+    if tuning.get("wall_pass") and tuning.get("skin_factor", 0.0) > 0.0:
+        return f"k_force_wp<{r},{tuning['lanes_per_node']}>"
+    if tuning.get("skin_factor", 0.0) > 0.0:
+        return f"k_force<{r},M_STEP,list,{tuning['lanes_per_node']}>"
+    return f"k_force<{r},M_STEP>"
+
+
+def force_roofline(g, kernel_steps, precision, workload):
+    """Roofline of the step kernel: algorithmic bytes per launch over its
+    mean duration in graph replays (HIP events on the library's stream).
+    With the pass of walls and contact candidates, that pass is a launch of
+    its own before each step kernel (kernels_ms.pass): inside ms_per_step,
+    outside this kernel's time."""
     sizes = g.sizes()
+    tun = g.tuning()
     kt = g.time_kernels(kernel_steps)
     ms = kt["force"][0]
     fb = BYTES_PER_NODE[precision] * sizes["nodes"] + BYTES_PER_BOND * sizes["bonds"]
     ach = fb / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS,
-            "traffic": measured_traffic("force", workload, g.tuning()),
+    return {"bound": "hbm", "kernel": step_kernel_name(tun, precision), "achieved": ach,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic("force", workload, tun),
             "bytes_per_launch": fb, "mean_launch_ms": ms,
             "bytes_per_node": BYTES_PER_NODE[precision], "bytes_per_directed_bond": BYTES_PER_BOND,
-            "timed_launches": kt["force"][1]}, kt
+            "timed_launches": kt["force"][1], "pass_ms": kt["pass"][0]}, kt
 
 
 def headline(pd, W, torch, args, prob):
@@ -253,7 +268,7 @@ def headline(pd, W, torch, args, prob):
     g.step(args.steps)
     sps, rebuilds = timed_steps(g, torch, args.steps)
     rep = sorted(timed_steps(g, torch, args.steps)[0] for _ in range(5))
-    roof, kt = force_roofline(g, args.kernel_steps, 0, "batched_64_fp64", "k_force<double,M_STEP>")
+    roof, kt = force_roofline(g, args.kernel_steps, 0, "batched_64_fp64")
     n_pairs = sizes["bonds"] // 2
     out = {
         "metric": "PD bond interactions/s (plain FP64, 64 batched settling aggregates)",
@@ -304,7 +319,7 @@ def settling_leg(pd, W, torch, args):
     g.step(steps)
     sps, rebuilds = timed_steps(g, torch, steps)
     rep = sorted(timed_steps(g, torch, max(1, steps // 5))[0] for _ in range(5))
-    roof, kt = force_roofline(g, 512, 0, "settling_100", "k_force<double,M_STEP>")
+    roof, kt = force_roofline(g, 512, 0, "settling_100")
     tun = g.tuning()
     best0 = None
     for cf in (1.0, 2.0, 3.0):
@@ -384,7 +399,7 @@ def batched_fp32(pd, W, torch, steps, prob, tuning_fixed=None):
     g.step(steps)
     sizes = g.sizes()
     sps, _ = timed_steps(g, torch, steps)
-    roof, _ = force_roofline(g, 128, 1, "batched_64", "k_force<float,M_STEP>")
+    roof, _ = force_roofline(g, 128, 1, "batched_64")
     res = {"workload": "batched_64", "precision": "fp32_force", "aggregates": prob.n_aggregates,
            "nodes": sizes["nodes"], "tuning": tuning, "autotune_s": t_tune,
            "directed_bonds": sizes["bonds"], "steps_per_s": sps,

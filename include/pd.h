@@ -119,7 +119,8 @@ typedef struct {
  * every block size, staging and graph choice, and equal within rounding for
  * every cell factor, skin, lane count and wall pass (the contact set itself
  * never changes: it is evaluated from exact distances every step; the lane
- * count and the wall pass change the order of the per-node sums). */
+ * count changes the order of the per-node sums, and so does the wall pass
+ * for a node's wall regions at one or two lanes per node). */
 typedef struct {
     int32_t block_nodes;  /* nodes per workgroup of the force kernel: 64, 128 or 256 */
     double cell_factor;   /* cell side / search radius, >= 1 */
@@ -132,7 +133,8 @@ typedef struct {
                                chains of dependent work, small problems), 2 or 1 (per-node work
                                done once, large problems); other evaluations use 4 */
     int32_t wall_pass;    /* with candidate lists and the closure off: 1 evaluates the wall
-                             forces (Sec. 4.5) of the nodes near a wall in a pass of their own
+                             forces (Sec. 4.5) of the nodes near a wall and the contact forces
+                             (Sec. 4.1-4.4) of the nodes with candidates in a pass of their own
                              before each step kernel (one more launch per step, a step kernel
                              with fewer registers: large problems); 0 inside the step kernel */
 } pd_tuning;
@@ -226,7 +228,8 @@ pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
  *   0 cell keys (with one key per thread also the first radix pass's digit
  *   count), 1 radix histogram, 2 radix digit scan, 3 radix scatter,
  *   4 cell starts, 5 force + integrate (one per step), 6 candidate-list
- *   build, 7 wall pass (n_out >= 8; tuning wall_pass = 1 only).
+ *   build, 7 the pass of walls and contact candidates before each step
+ *   kernel (n_out >= 8; tuning wall_pass = 1 only).
  * Search kernels are bracketed one by one.  With candidate lists (skin > 0)
  * the force kernel is timed over runs of up to 64 steps issued as pd_step
  * issues them (one graph replay when the tuning's use_graph is set, else

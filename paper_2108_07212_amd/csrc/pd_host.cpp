@@ -403,7 +403,7 @@ hipError_t enqueue_list_launches(Ctx &c, int start, int n) {
             // (the reduced form evaluates its contact inside its step kernel)
             if (e == hipSuccess && !c.cl.reduced) e = launch_cl_contact(c.a, c.precision, c.stream);
         } else if (wall_pass_on(c)) {
-            e = launch_walls(c.a, c.stream);
+            e = launch_pass(c.a, c.precision, c.stream);
             if (e == hipSuccess)
                 e = launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 0, true);
         } else {
@@ -603,7 +603,7 @@ hipError_t enqueue_rebuild(Ctx &c, hipEvent_t *ev) {
     if ((e = launch_cells(c.a, 1, 0, c.stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[b + 1], c.stream)) != hipSuccess) return e;
     if ((e = launch_build_list(c.a, c.stream)) != hipSuccess) return e;
-    if (wall_pass_on(c) && (e = launch_wall_mark(c.a, c.stream)) != hipSuccess) return e;
+    if (wall_pass_on(c) && (e = launch_pass_mark(c.a, c.stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[b + 2], c.stream)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -1638,6 +1638,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     a.overflow = &c.ctl->over;
     HIPCHK(hipMemsetAsync(c.ctl, 0, sizeof(Ctx::Ctl), c.stream));
     TRY(dalloc(c, &a.clist_n, N));
+    TRY(dalloc(c, &a.brk_log, (size_t)16 * N));
     TRY(dalloc(c, &a.ubx, N));
     TRY(dalloc(c, &a.uby, N));
     TRY(alloc_lists(c, 16));
@@ -2026,18 +2027,25 @@ pd_status pd_set_tuning(pd_ctx *ctx, const pd_tuning *t) {
         return fail(c, PD_E_INVALID, "wall_pass must be 0 or 1");
     HIPCHK(hipStreamSynchronize(c.stream));
     if (t->wall_pass && !c.a.wfx) {
-        // the wall pass's node list and forces (kept until the context ends)
-        int *wl;
-        unsigned long long *wn;
-        double *fx, *fy;
+        // the pass's node lists, wall forces and contact sums (kept until the
+        // context ends)
+        int *wl, *cl;
+        unsigned long long *wn, *cn;
+        double *fx, *fy, *cs;
         TRY(dalloc(c, &wl, (size_t)c.N));
         TRY(dalloc(c, &wn, 1));
         TRY(dalloc(c, &fx, (size_t)c.N));
         TRY(dalloc(c, &fy, (size_t)c.N));
+        TRY(dalloc(c, &cl, (size_t)c.N));
+        TRY(dalloc(c, &cn, 1));
+        TRY(dalloc(c, &cs, (size_t)4 * c.N));
         c.a.wall_list = wl;
         c.a.wall_n = wn;
         c.a.wfx = fx;
         c.a.wfy = fy;
+        c.a.cont_list = cl;
+        c.a.cont_n = cn;
+        c.a.csum = cs;
     }
     const bool regrid = t->cell_factor != c.tune.cell_factor || t->skin_factor != c.tune.skin_factor;
     const bool rewin = t->block_nodes != c.tune.block_nodes;
@@ -2162,7 +2170,7 @@ pd_status pd_time_kernels(pd_ctx *ctx, int64_t n_steps, double *ms, int32_t *lau
                     set_state_ptrs(c, (c.cur + k) & 1);
                     c.a.chunk_k = k;
                     HIPCHK(hipEventRecord(we[3 * k], c.stream));
-                    HIPCHK(launch_walls(c.a, c.stream));
+                    HIPCHK(launch_pass(c.a, c.precision, c.stream));
                     HIPCHK(hipEventRecord(we[3 * k + 1], c.stream));
                     HIPCHK(launch_force(c.a, c.precision, M_STEP, lds_cap(c), c.stream, true, 0, true));
                     HIPCHK(hipEventRecord(we[3 * k + 2], c.stream));

@@ -110,6 +110,9 @@ struct DevArgs {
     int *wall_list;                  // [N]
     unsigned long long *wall_n;      // listed nodes
     double *wfx, *wfy;               // [N], valid at listed nodes
+    int *cont_list;                  // [N] nodes with contact candidates
+    unsigned long long *cont_n;      // listed nodes
+    double *csum;                    // [N][4] their contact sums (self x, y; other x, y)
     // scalars
     double Rc, Rc2, mu, rd, dt, hdt, hdt2, gx, gy;
     long long *step;      // device step counter (t = step * dt)
@@ -122,6 +125,7 @@ struct DevArgs {
     // intact bonds excluded), slot k of node i at clist[k * N + i]
     uint32_t *clist;
     int *clist_n;
+    uint32_t *brk_log;         // [N][4 lanes][4] partners of the bonds a step broke
     float *ubx, *uby;          // displacement at list build
     int maxc;                  // slots per node
     double Rl2;                // list radius squared, (R_c + skin)^2
@@ -408,8 +412,8 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
                         bool list = false, int sel = 0, bool wall_pass = false);
 // the wall pass of list-mode steps: its node list at a rebuild, then one
 // launch before each step kernel
-hipError_t launch_wall_mark(const DevArgs &a, hipStream_t s);
-hipError_t launch_walls(const DevArgs &a, hipStream_t s);
+hipError_t launch_pass_mark(const DevArgs &a, hipStream_t s);
+hipError_t launch_pass(const DevArgs &a, int precision, hipStream_t s);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);
 // the reduced closure's step in one launch (contact, reduction, MLP when
 // learned, update), one workgroup per block of <= 16 particles of one shape

@@ -748,6 +748,7 @@ __global__ void k_round_start(DevArgs a, long long step, int rebuild) {
     if (rebuild) {
         *a.overflow = 0;
         if (a.wall_n) *a.wall_n = 0ull;
+        if (a.cont_n) *a.cont_n = 0ull;
     } else {
         *a.invalid_step = ~0ull;
     }
@@ -868,12 +869,18 @@ __device__ __forceinline__ bool exact_break(double X, double Y, double EX, doubl
 // STAGED: partner data from the workgroup's LDS window (a separate
 // instantiation, so that no load merges LDS and global addresses into one
 // generic access).
+// slot t < 4 of the break log of node i's lane sub: the partners of bonds
+// that lane broke in this step
+__device__ __forceinline__ size_t brk_slot(int i, int sub, int t) {
+    return (((size_t)i << 2) + (size_t)sub) * 4 + (size_t)t;
+}
+
 template <typename R, int MODE, bool STAGED, int LPN>
 __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc, int i, int sub,
                                             int lo, const double *S, double xi,
                                             double yi, double uxi, double uyi, double Vi, R &fpx,
                                             R &fpy, int &nbrk, double &smx,
-                                            const SlotHead &h, int (&bj)[4], bool un) {
+                                            const SlotHead &h, bool un) {
     constexpr bool adv = (MODE == M_STEP);
     {
         const uint32_t base = h.base;
@@ -978,7 +985,9 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
                 if (cand && exact_break(X, Y, EX, EY, DX, DY, s0)) {
                     // rare: broken for good (Sec. 3.1)
                     if (MODE != M_FORCES) a.col[base + (uint32_t)k * kSlice] = e | kBroken;
-                    if (nbrk < 4) bj[nbrk] = j;  // partners for the candidate list
+                    // partners for the candidate list, logged in memory
+                    // rather than held in registers through the loop
+                    if (MODE == M_STEP && nbrk < 4) a.brk_log[brk_slot(i, sub, nbrk)] = (uint32_t)j;
                     ++nbrk;
                     g = 0;
                 }
@@ -1180,7 +1189,6 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     R fsx = 0, fsy = 0, fnx = 0, fny = 0, fpx = 0, fpy = 0;
     double fwx = 0.0, fwy = 0.0;
     int nbrk = 0;
-    int bj[4] = {0, 0, 0, 0};
     double smx = 0.0;
     // a particle under the modal closure: no bond forces here; its external
     // nodal force goes to the closure kernels, which integrate its nodes
@@ -1196,11 +1204,13 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     if constexpr (LIST) {
         if (!closure)
             staged ? bond_forces<R, MODE, true, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un)
+                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, un)
                    : bond_forces<R, MODE, false, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, bj, un);
-        contact_forces<R, LIST, adv, LPN>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi,
-                                          mi, fsx, fsy, fnx, fny, nc_pre, un);
+                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, un);
+        // (with the pass, the candidates were evaluated before this launch)
+        if constexpr (!WP)
+            contact_forces<R, LIST, adv, LPN>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi,
+                                              Vi, mi, fsx, fsy, fnx, fny, nc_pre, un);
     } else {
         contact_forces<R, LIST, adv, LPN>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi,
                                           mi, fsx, fsy, fnx, fny);
@@ -1209,9 +1219,9 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
             wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);
         if (!closure)
             staged ? bond_forces<R, MODE, true, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false)
+                                                     uyi, Vi, fpx, fpy, nbrk, smx, head, false)
                    : bond_forces<R, MODE, false, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
-                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, bj, false);
+                                                      uyi, Vi, fpx, fpy, nbrk, smx, head, false);
     }
 
     // ---- combine the node's lanes -----------------------------------------------
@@ -1221,6 +1231,17 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
     fsy = lanes_sum<LPN>(fsy);
     fnx = lanes_sum<LPN>(fnx);
     fny = lanes_sum<LPN>(fny);
+    if constexpr (LIST && WP) {
+        // the pass's sums over this node's candidates (its lanes, its order)
+        if (sub == 0 && nc_pre > 0) {
+            const double2 c0 = *reinterpret_cast<const double2 *>(a.csum + 4 * (size_t)i);
+            const double2 c1 = *reinterpret_cast<const double2 *>(a.csum + 4 * (size_t)i + 2);
+            fsx = (R)c0.x;
+            fsy = (R)c0.y;
+            fnx = (R)c1.x;
+            fny = (R)c1.y;
+        }
+    }
     if constexpr (LPN != 4) {
         axi = a.ax[i];
         ayi = a.ay[i];
@@ -1241,7 +1262,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         if (nb) {
             const double bxi = xi + ubxi, byi = yi + ubyi;
             for (int t = 0; t < nb; ++t) {
-                const int j = bj[t];
+                const int j = (int)a.brk_log[brk_slot(i, sub, t)];
                 const double dx = (a.x[j] + (double)a.ubx[j]) - bxi;
                 const double dy = (a.y[j] + (double)a.uby[j]) - byi;
                 if (dx * dx + dy * dy < a.Rl2 * (1.0 + 1e-6)) kj[keep++] = (uint32_t)j;
@@ -1274,6 +1295,8 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                 ++n;
             }
             a.clist_n[i] = n;
+            // with the pass: a node's first candidates put it on its list
+            if (WP && nc_pre == 0) a.cont_list[atomicAdd(a.cont_n, 1ull)] = i;
         }
     }
     if constexpr (LIST && WP) {
@@ -1389,10 +1412,11 @@ __global__ __launch_bounds__(1024) void k_force(DevArgs a, int lds_cap) {
     }
 }
 
-// the list-mode step with the wall pass: without the walls' code the kernel
-// fits in 96 VGPRs, five wavefronts per SIMD instead of four
+// the list-mode step with the pass of walls and contact candidates: without
+// their code the kernel fits in 80 VGPRs at one or two lanes per node (six
+// wavefronts per SIMD instead of four) and in 96 at four (five)
 template <typename R, int LPN>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_force_wp(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LPN == 4 ? 5 : 6, 8))) void k_force_wp(
     DevArgs a, int lds_cap) {
     extern __shared__ double lds[];
     const long long sprev = *a.step_base + a.chunk_k;
@@ -1774,10 +1798,13 @@ hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStre
 // ---------------------------------------------------------------------------
 // at a list rebuild (positions advanced as the lists were built): every node
 // within the list radius of a wall of its aggregate (the top wall at the time
-// of the step after *step_base, the rebuild's step), or beyond one, onto the list.  Until the next rebuild no
-// other node can come within R_c of a wall: nodes move less than half the
-// skin between rebuilds, and the top wall is held to half the skin as well.
-__global__ void k_wall_mark(DevArgs a) {
+// of the step after *step_base, the rebuild's step), or beyond one, onto the
+// wall list; every node with contact candidates onto the contact list (a
+// node that gets its first candidates from a broken bond later joins it from
+// the step kernel).  Until the next rebuild no other node can come within
+// R_c of a wall: nodes move less than half the skin between rebuilds, and
+// the top wall is held to half the skin as well.
+__global__ void k_pass_mark(DevArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     const double t_next = (double)(*a.step_base + 1) * a.dt;
@@ -1791,20 +1818,28 @@ __global__ void k_wall_mark(DevArgs a) {
         const unsigned long long k = atomicAdd(a.wall_n, 1ull);
         a.wall_list[k] = i;
     }
+    if (a.clist_n[i] > 0) a.cont_list[atomicAdd(a.cont_n, 1ull)] = i;
 }
 
-// each listed node's wall force at the position and velocity the step
-// kernel uses (a thread per node; the four regions summed as the step
-// kernel's four lanes sum them, so the result is the same whatever its lane
-// count); a launch past the first stale step of a replay does nothing
-__global__ __launch_bounds__(256) void k_walls(DevArgs a) {
+// The pass before each list-mode step kernel: at the position and velocity
+// the step kernel uses, each listed node's wall force (a thread per node; the
+// four regions summed as the step kernel's four lanes sum them, so the result
+// is the same whatever its lane count), then each listed node's contact
+// forces over its candidates (LPN lanes per node, the step kernel's lanes and
+// order: the same bits).  A launch past the first stale step of a replay does
+// nothing.
+template <typename R, int LPN>
+__global__ __launch_bounds__(256) void k_pass(DevArgs a) {
     const long long sprev = *a.step_base + a.chunk_k;
     if ((unsigned long long)(sprev + 1) >= *a.invalid_step) return;
     const bool un = a.chunk_k > 0 && a.unx && !a.cl_on;
     const double t = (double)(sprev + 1) * a.dt;
-    const long long n = (long long)*a.wall_n;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    // even workgroups take the wall list, odd ones the contact list (the two
+    // chains of dependent work side by side rather than one after the other)
+    const long long stride = (long long)(gridDim.x / 2) * blockDim.x;
+    const long long tid = (long long)(blockIdx.x / 2) * blockDim.x + threadIdx.x;
+    const long long n = (blockIdx.x & 1) ? 0 : (long long)*a.wall_n;
+    for (long long k = tid; k < n; k += stride) {
         const int i = a.wall_list[k];
         double pxi, pyi, uxi, uyi;
         advanced_pos_un(a, i, un, pxi, pyi, uxi, uyi);
@@ -1825,22 +1860,61 @@ __global__ __launch_bounds__(256) void k_walls(DevArgs a) {
         a.wfy[i] = (fy[0] + fy[1]) + (fy[2] + fy[3]);
         if (st) atomicOr(a.status, st);
     }
+    const long long nc = (blockIdx.x & 1) ? (long long)*a.cont_n : 0;
+    const int sub = (int)(threadIdx.x & (LPN - 1));
+    for (long long k = tid / LPN; k < nc; k += stride / LPN) {
+        const int i = a.cont_list[k];
+        const int pi = a.part[i];
+        const MatConst mc = a.mat[a.pmat[pi]];
+        const double xi = a.x[i], yi = a.y[i];
+        double pxi, pyi, uxi, uyi;
+        advanced_pos_un(a, i, un, pxi, pyi, uxi, uyi);
+        const double vxi = a.vx[i], vyi = a.vy[i];
+        const double Vi = a.vol[i], mi = mc.rho * Vi;
+        R fsx = 0, fsy = 0, fnx = 0, fny = 0;
+        contact_forces<R, true, true, LPN>(a, mc, i, sub, pi, a.pagg[pi], xi, yi, pxi, pyi, vxi,
+                                           vyi, Vi, mi, fsx, fsy, fnx, fny, a.clist_n[i], un);
+        fsx = lanes_sum<LPN>(fsx);
+        fsy = lanes_sum<LPN>(fsy);
+        fnx = lanes_sum<LPN>(fnx);
+        fny = lanes_sum<LPN>(fny);
+        if (sub == 0) {
+            *reinterpret_cast<double2 *>(a.csum + 4 * (size_t)i) = make_double2(fsx, fsy);
+            *reinterpret_cast<double2 *>(a.csum + 4 * (size_t)i + 2) = make_double2(fnx, fny);
+        }
+    }
 }
 
-hipError_t launch_wall_mark(const DevArgs &a, hipStream_t s) {
+hipError_t launch_pass_mark(const DevArgs &a, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    if (!(a.wall_list && a.wall_n)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_wall_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
+    if (!(a.wall_list && a.wall_n && a.cont_list && a.cont_n)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pass_mark, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_walls(const DevArgs &a, hipStream_t s) {
+template <typename R>
+static void launch_pass_t(const DevArgs &a, int lpn, unsigned g, hipStream_t s) {
+    if (lpn == 1)
+        hipLaunchKernelGGL((k_pass<R, 1>), dim3(g), dim3(256), 0, s, a);
+    else if (lpn == 2)
+        hipLaunchKernelGGL((k_pass<R, 2>), dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pass<R, 4>), dim3(g), dim3(256), 0, s, a);
+}
+
+hipError_t launch_pass(const DevArgs &a, int precision, hipStream_t s) {
     if (a.N == 0) return hipSuccess;
-    if (!(a.wall_list && a.wall_n && a.wfx && a.wfy)) return hipErrorInvalidValue;
-    // a fixed grid (the list's length changes at rebuilds, replays keep the
-    // grid they were captured with); two workgroups per compute unit
-    const unsigned g = std::min<unsigned>((unsigned)((a.N + 255) / 256), 512u);
-    hipLaunchKernelGGL(k_walls, dim3(g), dim3(256), 0, s, a);
+    if (!(a.wall_list && a.wall_n && a.wfx && a.wfy && a.cont_list && a.cont_n && a.csum))
+        return hipErrorInvalidValue;
+    if (!(a.lanes == 1 || a.lanes == 2 || a.lanes == 4)) return hipErrorInvalidValue;
+    // a fixed grid (the lists' lengths change at rebuilds and appends,
+    // replays keep the grid they were captured with), an even number of
+    // workgroups (half for each list), two per compute unit
+    const unsigned g = 2u * std::min<unsigned>((unsigned)((a.N + 511) / 512), 256u);
+    if (precision == PD_PREC_FP64)
+        launch_pass_t<double>(a, a.lanes, g, s);
+    else
+        launch_pass_t<float>(a, a.lanes, g, s);
     return hipGetLastError();
 }
 

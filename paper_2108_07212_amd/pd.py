@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pd.h")
 PD_OK, PD_E_INVALID, PD_E_NOMEM, PD_E_DEVICE, PD_E_NONFINITE, PD_E_ESCAPED, PD_E_STATE = range(7)
 TERM_PD, TERM_SELF, TERM_NBR, TERM_WALL, TERM_BODY, TERM_ALL = 1, 2, 4, 8, 16, 31
 KERNEL_CLASSES = ("keys", "radix_hist", "radix_digit_scan", "radix_scatter", "cells", "force",
-                  "build_list", "walls")
+                  "build_list", "pass")
 
 
 class PDError(RuntimeError):

@@ -291,8 +291,9 @@ def test_breaks_during_list_steps(pdmod, lanes, wall_pass):
     remaining check is the list path against the every-step cell search on
     the GPU (with fewer lanes per node, whose sums run in another order,
     against lists of a wider skin), which must give the same states and
-    broken bonds.  With the wall pass the breaks go through the break log,
-    merged into the lists by the next step's pass."""
+    broken bonds.  With the wall pass the contacts of the nodes with
+    candidates are evaluated in the pass before each step kernel, and a node
+    whose first candidates come from a break joins the pass's list."""
     _say(f"case: breaks during list steps, {lanes} lanes per node, wall pass {wall_pass}")
 
     def impact():
@@ -336,6 +337,32 @@ def test_breaks_during_list_steps(pdmod, lanes, wall_pass):
     # rebuilds come from motion (a node moving half the skin), not from the
     # hundreds of steps with a break
     assert lst.sizes()["list_rebuilds"] - r0 < 40
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_contact_pass_matches_inline_contacts(pdmod, lanes):
+    """The pass before the step kernel (tuning wall_pass = 1) evaluates the
+    contact forces of the nodes with candidates on the step kernel's lanes
+    and in its order: a herded bed away from the walls (contacts, friction,
+    damping, bonds breaking and their pairs joining the lists) gives the same
+    states bit for bit as contact inside the step kernel, at every lane
+    count."""
+    _say(f"case: contact pass against inline contacts, {lanes} lane(s) per node")
+    prob = _herd(_bed(10, 13), 0.45, seed=13, dv=2.0)
+    out, cnt = {}, {}
+    for wp in (0, 1):
+        g = pdmod.PD(prob)
+        g.set_tuning(lanes_per_node=lanes, wall_pass=wp)
+        g.set_counting(True)
+        assert g.step(200, check=False) == 0
+        out[wp] = g.get_state()
+        cnt[wp] = g.counters()
+    for key in ("ux", "uy", "vx", "vy", "ax", "ay"):
+        assert np.array_equal(out[0][key], out[1][key]), key
+    assert np.array_equal(out[0]["broken"], out[1]["broken"])
+    assert cnt[0] == cnt[1]
+    assert cnt[1]["inter"] > 0 and cnt[1]["self_"] > 0 and cnt[1]["broken"] > 0
+    assert cnt[1]["wall"] == 0
 
 
 @pytest.mark.parametrize("seed,lanes", [(11, 4), (12, 4), (11, 1), (12, 2)])

@@ -1,6 +1,7 @@
 """The wall pass (tuning wall_pass = 1): the wall forces (Sec. 4.5) of the
-nodes near a wall evaluated in a launch of their own before each list-mode
-step, the step kernel reading them.  Beds pressed into a corner of the floor
+nodes near a wall and the contact forces of the nodes with candidates
+evaluated in a launch of their own before each list-mode step, the step
+kernel reading them.  Beds pressed into a corner of the floor
 and the left wall and into the top wall moving down at 2 m/s, against the
 oracle (trajectories to 1e-9 through list rebuilds, among them those the
 moving wall forces), and against the same run with the walls inside the step
@@ -96,7 +97,7 @@ def test_wall_pass_kernel_timing(pdmod):
     g.set_tuning(lanes_per_node=1, wall_pass=1)
     g.step(5)
     kt = g.time_kernels(64)
-    assert kt["walls"][1] > 0 and kt["walls"][0] > 0.0
+    assert kt["pass"][1] > 0 and kt["pass"][0] > 0.0
     assert kt["force"][1] > 0 and kt["force"][0] > 0.0
     g.set_tuning(wall_pass=0)
-    assert g.time_kernels(64)["walls"][1] == 0
+    assert g.time_kernels(64)["pass"][1] == 0
