@@ -181,7 +181,13 @@ void barrier_segments(const double *xy, const int *vert_off, int l0, int l1, dou
                     const double wx = e.ax - px, wy = e.ay - py;
                     const double t = (wx * sy - wy * sx) / den;
                     const double u = (wx * ny - wy * nx) / den;
-                    if (t > 0.0 && u >= 0.0 && u <= 1.0 && t < tbest) tbest = t;
+                    // a ray that meets the boundary at a vertex stops there: in a
+                    // regular polygon of an even vertex count (a ring's hole) each
+                    // cusp's ray runs through the opposite vertex, where rounding
+                    // can leave u just outside both adjacent edges, and the ray
+                    // would run on through the material behind
+                    constexpr double kEnd = 1e-9;
+                    if (t > 0.0 && u >= -kEnd && u <= 1.0 + kEnd && t < tbest) tbest = t;
                 }
                 // start a hair outside the vertex: a bond through the vertex itself
                 // touches the closed domain and is kept

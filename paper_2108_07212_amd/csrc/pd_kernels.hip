@@ -1003,7 +1003,10 @@ __device__ __forceinline__ void bond_forces(const DevArgs &a, const MatConst &mc
 // 4) the nodes of the cells sub, sub + 4, sub + 8 of the 3 x 3
 // neighbourhood.  Pairs closer than R_c act; an intact bond replaces contact
 // between nodes of one particle.
-template <typename R, bool LIST, bool adv, int LPN = 4>
+// SOLO: one thread takes lane `sub`'s share by itself (callers that loop
+// over sub on one thread), so the node's lanes are not a quad to exchange
+// with: candidates are then taken one by one.
+template <typename R, bool LIST, bool adv, int LPN = 4, bool SOLO = false>
 __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst &mc, int i,
                                                int sub, int pi, int ag, double xi, double yi,
                                                double pxi, double pyi, double vxi, double vyi,
@@ -1019,6 +1022,30 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
         // pairs within R_c, not on which extra candidates the list holds (a
         // superset that depends on when it was built).
         const int nc = nc_pre >= 0 ? nc_pre : a.clist_n[i];
+        if constexpr (SOLO) {
+            for (int q = 0; q < nc; ++q) {
+                const int j = (int)a.clist[(size_t)q * a.N + i];
+                if ((j & (LPN - 1)) != sub) continue;
+                const double xj = a.x[j], yj = a.y[j];
+                const double vxj = a.vx[j], vyj = a.vy[j], Vj = a.vol[j];
+                const int pj = a.part[j];
+                double pxj, pyj, ux, uy;
+                if (adv)
+                    advanced_pos_un(a, j, un, pxj, pyj, ux, uy);
+                else
+                    advanced_pos(a, j, false, pxj, pyj, ux, uy);
+                const double ddx = pxj - pxi, ddy = pyj - pyi;
+                const double r2 = ddx * ddx + ddy * ddy;
+                if (!(r2 < a.Rc2)) continue;
+                if (r2 == 0.0) {
+                    count(a, C_COINC);
+                    continue;
+                }
+                contact_pair_d<R>(a, mc, pj == pi, pj, xi, yi, xj, yj, Vj, ddx, ddy, r2, vxi,
+                                  vyi, vxj, vyj, Vi, mi, fsx, fsy, fnx, fny);
+            }
+            return;
+        }
         constexpr int kPer = 4;
         constexpr int kCB = kPer * LPN;
         static_assert(kCB <= 32, "a batch's mask is one word");
@@ -1061,6 +1088,7 @@ __device__ __forceinline__ void contact_forces(const DevArgs &a, const MatConst 
                     advanced_pos(a, j, false, pxj, pyj, ux, uy);
                 const double ddx = pxj - pxi, ddy = pyj - pyi;
                 const double r2 = ddx * ddx + ddy * ddy;
+                if (!(r2 < a.Rc2)) continue;  // (the same test as the mask's)
                 if (r2 == 0.0) {
                     count(a, C_COINC);
                     continue;
@@ -1448,8 +1476,8 @@ __device__ __forceinline__ ClNode cl_contact_node(const DevArgs &a, int i, long 
     double fwx = 0.0, fwy = 0.0;
 #pragma unroll 1
     for (int sub = 0; sub < 4; ++sub)
-        contact_forces<R, true, true>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi, Vi, mi,
-                                      fsx, fsy, fnx, fny);
+        contact_forces<R, true, true, 4, true>(a, mc, i, sub, pi, ag, xi, yi, pxi, pyi, vxi, vyi,
+                                               Vi, mi, fsx, fsy, fnx, fny);
 #pragma unroll 1
     for (int part = 0; part < 4; ++part)
         wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fwx, fwy, st);

@@ -354,6 +354,42 @@ def test_reduced_gate_fallbacks_match_oracle(setup_bed):
     _compare_states(g, o, 1e-9)
 
 
+def _herded(alpha):
+    """The test bed with each particle translated rigidly (nodes and boundary
+    loops) a fraction alpha of the way toward the bed centre: closure
+    particles touch (about 40 node pairs of different particles within R_c
+    at the start for 0.25, 100 for 0.4)."""
+    prob = bed()
+    cx, cy = prob.x.mean(), prob.y.mean()
+    po, lo, vo = prob.particle_offset, prob.loop_offset, prob.loop_vertex_offset
+    for p in range(prob.n_particles):
+        s = slice(po[p], po[p + 1])
+        dx, dy = -alpha * (prob.x[s].mean() - cx), -alpha * (prob.y[s].mean() - cy)
+        prob.x[s] += dx
+        prob.y[s] += dy
+        v0, v1 = int(vo[lo[p]]), int(vo[lo[p + 1]])
+        prob.loop_xy[2 * v0:2 * v1:2] += dx
+        prob.loop_xy[2 * v0 + 1:2 * v1:2] += dy
+    return prob
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.4])
+@pytest.mark.parametrize("reduced", [False, True])
+def test_closure_with_contact_matches_oracle(setup_bed, alpha, reduced):
+    """Contact between closure particles (their nodes' candidates taken by
+    the closure's own contact evaluation, one thread per node), gate
+    fallbacks under the contact load, then plain-force particles in contact
+    with closure ones, over the first ten steps (before bonds of the
+    particles back under the plain force break: the oracle's closure stepper
+    does not commit breaks)."""
+    g, o, st, off = _run_pair(setup_bed, 10, 1, reduced=reduced, prob=_herded(alpha))
+    assert g.damage()[1] == 0
+    assert o.counters()["inter"] > 0 and len(off) > 0
+    _compare_states(g, o, 1e-9)
+    p, s, act = g.closure_particles()
+    np.testing.assert_array_equal(act.astype(bool), st.active[p])
+
+
 def test_reduced_with_larger_particles_matches_oracle():
     """Particles of 300 nodes, most of whose nodes are not active (only nodes
     near contacts and walls are handled in a step); trajectories (all nodes,

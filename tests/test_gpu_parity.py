@@ -118,6 +118,55 @@ def test_bond_sets_lattice_aligned(pdmod):
     _check_bonds(pdmod.PD(prob), Oracle(prob), "aligned")
 
 
+def _translated(prob, shifts):
+    """Each particle moved rigidly by shifts[p] = (dx, dy), its nodes and its
+    boundary loops alike."""
+    po, lo, vo = prob.particle_offset, prob.loop_offset, prob.loop_vertex_offset
+    for p, (dx, dy) in enumerate(shifts):
+        s = slice(po[p], po[p + 1])
+        prob.x[s] += dx
+        prob.y[s] += dy
+        v0, v1 = int(vo[lo[p]]), int(vo[lo[p + 1]])
+        prob.loop_xy[2 * v0:2 * v1:2] += dx
+        prob.loop_xy[2 * v0 + 1:2 * v1:2] += dy
+    return prob
+
+
+@pytest.mark.parametrize("case", ["toward_centre", "seeded_0", "seeded_1", "seeded_2"])
+def test_bond_sets_translated_particles(pdmod, case):
+    """Bond sets do not depend on where a particle sits.  A ring's hole is a
+    regular polygon of an even vertex count, so each cusp's bisector ray runs
+    through the opposite vertex; at some positions rounding put that vertex
+    just outside both of its edges and the ray ran on through the material
+    behind (104 bonds of one ring lost, first seen with the particles of the
+    closure test bed moved a quarter of the way toward its centre, kept here
+    as a case)."""
+    _say(f"case: bond sets of translated particles, {case}")
+    prob = W.closure_bed(n_per_shape=3, h=0.08e-3, nodes=60, seed=21, wall_speed=0.0, vmax=0.3)
+    P = prob.n_particles
+    if case == "toward_centre":
+        cx, cy = prob.x.mean(), prob.y.mean()
+        po = prob.particle_offset
+        shifts = [(-0.25 * (prob.x[po[p]:po[p + 1]].mean() - cx),
+                   -0.25 * (prob.y[po[p]:po[p + 1]].mean() - cy)) for p in range(P)]
+    else:
+        # seeded shifts of up to 1 mm, each within the room its particle has
+        # in the box (a margin of one contact radius)
+        rng = np.random.default_rng(100 + int(case[-1]))
+        xlo, xhi, ylo, yhi = prob.box[0]
+        m = prob.contact_radius
+        po = prob.particle_offset
+        shifts = []
+        for p in range(P):
+            xs, ys = prob.x[po[p]:po[p + 1]], prob.y[po[p]:po[p + 1]]
+            lx, hx = max(xlo + m - xs.min(), -1e-3), min(xhi - m - xs.max(), 1e-3)
+            ly, hy = max(ylo + m - ys.min(), -1e-3), min(yhi - m - ys.max(), 1e-3)
+            shifts.append((rng.uniform(lx, hx) if lx < hx else 0.0,
+                           rng.uniform(ly, hy) if ly < hy else 0.0))
+    prob = _translated(prob, shifts)
+    _check_bonds(pdmod.PD(prob), Oracle(prob), case)
+
+
 def test_forces_t0_two_disks(pdmod):
     _say("case: forces t0 two disks")
     prob = W.two_disks()
