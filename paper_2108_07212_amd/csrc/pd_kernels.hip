@@ -1850,9 +1850,9 @@ __global__ void k_pass_mark(DevArgs a) {
 }
 
 // The pass before each list-mode step kernel: at the position and velocity
-// the step kernel uses, each listed node's wall force (a thread per node; the
-// four regions summed as the step kernel's four lanes sum them, so the result
-// is the same whatever its lane count), then each listed node's contact
+// the step kernel uses, each listed node's wall force (a quad per node, a
+// lane per wall region, summed as the step kernel's four lanes sum them, so
+// the result is the same whatever its lane count), then each listed node's contact
 // forces over its candidates (LPN lanes per node, the step kernel's lanes and
 // order: the same bits).  A launch past the first stale step of a replay does
 // nothing.
@@ -1867,7 +1867,10 @@ __global__ __launch_bounds__(256) void k_pass(DevArgs a) {
     const long long stride = (long long)(gridDim.x / 2) * blockDim.x;
     const long long tid = (long long)(blockIdx.x / 2) * blockDim.x + threadIdx.x;
     const long long n = (blockIdx.x & 1) ? 0 : (long long)*a.wall_n;
-    for (long long k = tid; k < n; k += stride) {
+    // walls: the four lanes of a quad per listed node, lane r the wall region
+    // r, summed (l0 + l1) + (l2 + l3) as the four-lane step kernel sums them
+    const int r = (int)(threadIdx.x & 3);
+    for (long long k = tid >> 2; k < n; k += stride >> 2) {
         const int i = a.wall_list[k];
         double pxi, pyi, uxi, uyi;
         advanced_pos_un(a, i, un, pxi, pyi, uxi, uyi);
@@ -1877,16 +1880,16 @@ __global__ __launch_bounds__(256) void k_pass(DevArgs a) {
         const double Vi = a.vol[i], mi = mc.rho * Vi;
         const double vxi = a.vx[i], vyi = a.vy[i];
         int st = 0;
-        double fx[4], fy[4];
-#pragma unroll
-        for (int part = 0; part < 4; ++part) {
-            fx[part] = 0.0;
-            fy[part] = 0.0;
-            wall_forces(a, ag, part, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fx[part], fy[part], st);
+        double fx = 0.0, fy = 0.0;
+        wall_forces(a, ag, r, pxi, pyi, vxi, vyi, mi, Vi, mc.Kn, t, fx, fy, st);
+        fx = lanes_sum<4>(fx);
+        fy = lanes_sum<4>(fy);
+        st = lanes_or<4>(st);
+        if (r == 0) {
+            a.wfx[i] = fx;
+            a.wfy[i] = fy;
+            if (st) atomicOr(a.status, st);
         }
-        a.wfx[i] = (fx[0] + fx[1]) + (fx[2] + fx[3]);
-        a.wfy[i] = (fy[0] + fy[1]) + (fy[2] + fy[3]);
-        if (st) atomicOr(a.status, st);
     }
     const long long nc = (blockIdx.x & 1) ? (long long)*a.cont_n : 0;
     const int sub = (int)(threadIdx.x & (LPN - 1));
