@@ -647,6 +647,37 @@ def test_oracle_state_handoff(pdmod):
     assert eu <= TRAJ_TOL and ev <= TRAJ_TOL
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("lanes,wall_pass", [(4, 0), (1, 0), (4, 1), (1, 1)])
+def test_tiny_problems_list_steps(pdmod, n, lanes, wall_pass):
+    """A handful of single-node particles (no bonds) in contact with each
+    other and with the walls, stepped with candidate lists: node counts that
+    fill neither a list-build workgroup (four nodes) nor a SELL slice, with
+    and without the pass, against the oracle."""
+    _say(f"case: tiny problem n={n} lanes={lanes} wall_pass={wall_pass}")
+    h = 1e-4
+    Rc = 0.95 * h
+    L = 12 * Rc
+    rng = np.random.default_rng(40 + n)
+    pts = [(0.6 * Rc, 0.7 * Rc)]
+    while len(pts) < n:  # a chain, each node 0.8 R_c from the last
+        ang = rng.uniform(0.0, 0.5 * math.pi)
+        pts.append((pts[-1][0] + 0.8 * Rc * math.cos(ang), pts[-1][1] + 0.8 * Rc * math.sin(ang)))
+    vel = [tuple(v) for v in rng.uniform(-0.3, 0.3, (n, 2))]
+    prob = W.single_node_particles(pts, vel, h * h, [0, L, 0, L], contact_radius=Rc, h=h,
+                                   friction_mu=0.4, damping_ratio=0.6, dt=1e-8,
+                                   gravity=(0.0, -5000.0))
+    g, o = pdmod.PD(prob), Oracle(prob)
+    g.set_tuning(lanes_per_node=lanes, wall_pass=wall_pass)
+    assert g.tuning()["skin_factor"] > 0
+    eu, ev, sg, so = _traj(g, o, 60)
+    assert eu <= TRAJ_TOL and ev <= TRAJ_TOL, (eu, ev)
+    c = o.counters()
+    assert c["wall"] > 0
+    if n > 1:
+        assert c["inter"] > 0
+
+
 def test_escape_status(pdmod):
     _say("case: escape")
     h = 1e-4
