@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -42,10 +43,15 @@ BYTES_PER_BOND = 4
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2108_07212_amd", "csrc", "pd_kernels.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """First 16 hex digits of the SHA-256 of pd_kernels.hip's code: comments
+    and blank lines taken out, so that a comment edit leaves the traffic
+    records valid and any change to the code does not."""
+    with open(os.path.join(ROOT, "paper_2108_07212_amd", "csrc", "pd_kernels.hip")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    code = "\n".join(ln.rstrip() for ln in src.splitlines() if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def tuning_key(t: dict) -> str:

@@ -392,7 +392,8 @@ hipError_t enqueue_closure(Ctx &c, bool list) {
 }
 
 // list-mode replay: n steps from buffer parity `start`
-// the wall pass runs with candidate lists and the closure off
+// the pass of walls and contact candidates runs with candidate lists and the
+// closure off
 bool wall_pass_on(const Ctx &c) {
     return c.tune.wall_pass && c.tune.skin_factor > 0.0 && !c.cl.mode && c.a.wfx;
 }
@@ -662,7 +663,7 @@ pd_status step_lists(Ctx &c, int64_t n) {
             TRY(closure_check(c));
             c.cl.last_check_step = c.step;
         }
-        // reduced closure and wall pass: the moving top wall may approach a
+        // reduced closure and the pass: the moving top wall may approach a
         // node that is not listed (active, near a wall) by at most half the
         // skin between rebuilds
         int64_t n_wall = 0;

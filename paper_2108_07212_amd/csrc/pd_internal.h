@@ -104,9 +104,10 @@ struct DevArgs {
     // walls
     const double *box;    // [A*4]
     const double *vtop;   // [A]
-    // wall pass (list-mode steps, closure off): the nodes within the list
-    // radius of a wall at the last rebuild, and the wall force the pass
-    // evaluates for each of them before the step kernel reads it
+    // the pass of list-mode steps (tuning wall_pass, closure off): the nodes
+    // within the list radius of a wall at the last rebuild and the wall force
+    // the pass evaluates for each of them before the step kernel reads it;
+    // the nodes with contact candidates and their contact sums
     int *wall_list;                  // [N]
     unsigned long long *wall_n;      // listed nodes
     double *wfx, *wfy;               // [N], valid at listed nodes
@@ -410,8 +411,8 @@ hipError_t launch_cells(const DevArgs &a, int adv, int advance_step, hipStream_t
 int force_lds_cap(int max_win);
 hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, hipStream_t s,
                         bool list = false, int sel = 0, bool wall_pass = false);
-// the wall pass of list-mode steps: its node list at a rebuild, then one
-// launch before each step kernel
+// the pass of walls and contact candidates of list-mode steps: its node
+// lists at a rebuild, then one launch before each step kernel
 hipError_t launch_pass_mark(const DevArgs &a, hipStream_t s);
 hipError_t launch_pass(const DevArgs &a, int precision, hipStream_t s);
 hipError_t launch_cl_contact(const DevArgs &a, int precision, hipStream_t s);

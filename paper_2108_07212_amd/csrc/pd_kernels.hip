@@ -1328,7 +1328,7 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
         }
     }
     if constexpr (LIST && WP) {
-        // the wall pass evaluated this node's wall force before this launch
+        // the pass evaluated this node's wall force before this launch
         // (every node near a wall is on its list until the next rebuild)
         if (sub == 0 && __builtin_expect(near_wall(a, ag, pxi, pyi, t), 0)) {
             fwx = a.wfx[i];
@@ -1819,10 +1819,11 @@ hipError_t launch_rc_mark(const DevArgs &a, uint8_t *act, double t_next, hipStre
 }
 
 // ---------------------------------------------------------------------------
-// the wall pass of list-mode steps (closure off): the walls' code needs more
-// registers than the rest of the step kernel, so for large problems it runs
-// in a launch of its own over the few nodes near a wall and the step kernel,
-// which then reads the result, keeps more wavefronts in flight
+// the pass of list-mode steps (closure off): the code of the walls and of
+// the contact candidates needs more registers than the rest of the step
+// kernel, so for large problems it runs in a launch of its own over the few
+// nodes near a wall or with candidates, and the step kernel, which then
+// reads the results, keeps more wavefronts in flight
 // ---------------------------------------------------------------------------
 // at a list rebuild (positions advanced as the lists were built): every node
 // within the list radius of a wall of its aggregate (the top wall at the time
@@ -2340,7 +2341,7 @@ hipError_t launch_force(const DevArgs &a, int precision, int mode, int lds_cap, 
     if (a.N == 0) return hipSuccess;
     if (sel && !(mode == M_STEP && list && a.cl_on && a.pd_blocks && a.n_pd_blocks))
         return hipErrorInvalidValue;
-    // the wall pass serves list-mode steps of the plain path only
+    // the pass serves list-mode steps of the plain path only
     if (wall_pass && !(mode == M_STEP && list && !sel && !a.cl_on && a.wfx && a.wfy))
         return hipErrorInvalidValue;
     // nodes per workgroup, LPN lanes each (the tuning's lanes for list-mode
