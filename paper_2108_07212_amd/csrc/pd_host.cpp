@@ -115,6 +115,8 @@ MatConst material_constants(const pd_material &m, double Rc, int kn_mode) {
     k.eps = eps;
     k.rho = m.rho;
     k.Kd_self = k.cw / Rc;
+    const double t = eps - 1e-9 * eps;  // as the bond build's threshold
+    k.thr2 = t * t;
     return k;
 }
 
@@ -1593,8 +1595,11 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     TRY(upload(c, &dsegoff, seg_off.data(), P + 1));
     TRY(upload(c, &dthr2, thr2.data(), M));
     TRY(dalloc(c, &drowlen, N));
+    uint8_t *drowfull;
+    TRY(dalloc(c, &drowfull, N));
     BondArgs ba{dx, dy, dpart, dpmat, dpoff, dseg, dsegoff, dthr2, N};
-    HIPCHK(launch_bonds_count(ba, drowlen, c.stream));
+    HIPCHK(launch_bonds_count(ba, drowlen, drowfull, c.stream));
+    a.row_full = drowfull;
     c.h_rowlen.resize(N);
     HIPCHK(hipMemcpyAsync(c.h_rowlen.data(), drowlen, N * sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -1646,6 +1651,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     HIPCHK(hipMemsetAsync(c.ctl, 0, sizeof(Ctx::Ctl), c.stream));
     TRY(dalloc(c, &a.clist_n, N));
     TRY(dalloc(c, &a.brk_log, (size_t)16 * N));
+    TRY(dalloc(c, &a.node_broken, N));
     TRY(dalloc(c, &a.ubx, N));
     TRY(dalloc(c, &a.uby, N));
     TRY(alloc_lists(c, 16));
@@ -1664,6 +1670,7 @@ pd_status pd_setup(const pd_problem *p, pd_ctx **out) {
     a.ax_o = c.Acc[0][0];
     a.ay_o = c.Acc[0][1];
     HIPCHK(launch_force(a, c.precision, M_PROLOGUE, lds_cap(c), c.stream));
+    HIPCHK(launch_node_broken(a, c.stream));  // (the break rule may have broken bonds)
     set_state_ptrs(c, 0);
     HIPCHK(hipStreamSynchronize(c.stream));
     pd_status st = read_status(c);
@@ -1973,6 +1980,7 @@ pd_status pd_set_state(pd_ctx *ctx, const double *ux, const double *uy, const do
         }
         HIPCHK(hipMemcpyAsync(c.a.col, h.data(), c.nslots * sizeof(uint32_t), hipMemcpyHostToDevice,
                               c.stream));
+        HIPCHK(launch_node_broken(c.a, c.stream));
     }
     c.step = step;
     TRY(set_device_step(c));
@@ -2325,6 +2333,7 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     for (int k = 0; k < 6; ++k)
         HIPCHK(hipMemcpyAsync(src[k], save + k * c.N, nb, hipMemcpyDeviceToDevice, c.stream));
     HIPCHK(hipMemcpyAsync(c.a.col, save_col, c.nslots * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
+    HIPCHK(launch_node_broken(c.a, c.stream));
     HIPCHK(hipMemcpyAsync(c.a.counters, cnt_save, sizeof cnt_save, hipMemcpyHostToDevice, c.stream));
     c.cur = cur0;
     c.step = step0;

@@ -59,6 +59,7 @@ struct MatConst {
     double cw, s0, Kn, eps, rho, Kd_self;  // Kd_self = c_w / R_c
     int conic;
     int pad;
+    double thr2;  // the reference-bond test |x_j - x_i|^2 < (eps - 1e-9 eps)^2
 };
 
 // Everything a kernel reads; passed by value.
@@ -127,6 +128,8 @@ struct DevArgs {
     uint32_t *clist;
     int *clist_n;
     uint32_t *brk_log;         // [N][4 lanes][4] partners of the bonds a step broke
+    const uint8_t *row_full;   // [N] the row holds every same-particle node within eps
+    uint8_t *node_broken;      // [N] one of the node's bonds is broken
     float *ubx, *uby;          // displacement at list build
     int maxc;                  // slots per node
     double Rl2;                // list radius squared, (R_c + skin)^2
@@ -399,7 +402,8 @@ void sym_eig(std::vector<double> &A, int n, std::vector<double> &w);
 
 // ---- launch wrappers (pd_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, hipStream_t s);
+hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, uint8_t *row_full, hipStream_t s);
+hipError_t launch_node_broken(const DevArgs &a, hipStream_t s);
 hipError_t launch_bonds_fill(const BondArgs &b, uint32_t *col, const uint32_t *slice_ptr,
                              hipStream_t s);
 hipError_t launch_windows(const DevArgs &a, int *win_lo, int *win_hi, hipStream_t s);

@@ -157,7 +157,9 @@ __device__ bool crosses_barrier(double ax, double ay, double bx, double by, cons
     return false;
 }
 
-__global__ void k_bonds_count_w(BondArgs b, int *rowlen) {
+// row lengths; row_full[i]: the line-of-sight filter left out none of the
+// node's same-particle neighbours within eps
+__global__ void k_bonds_count_w(BondArgs b, int *rowlen, uint8_t *row_full) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.N) return;
     const int p = b.part[i];
@@ -165,17 +167,31 @@ __global__ void k_bonds_count_w(BondArgs b, int *rowlen) {
     const double xi = b.x[i], yi = b.y[i];
     const double rx = b.x[b.poff[p]], ry = b.y[b.poff[p]];  // particle frame origin
     const int s0 = b.seg_off[p], s1 = b.seg_off[p + 1];
-    int n = 0;
+    int n = 0, nall = 0;
     for (int j = b.poff[p]; j < b.poff[p + 1]; ++j) {
         if (j == i) continue;
         const double dx = b.x[j] - xi, dy = b.y[j] - yi;
         const double d2 = dx * dx + dy * dy;
         if (!(d2 < thr2)) continue;
+        ++nall;
         if (s1 > s0 && crosses_barrier(xi - rx, yi - ry, b.x[j] - rx, b.y[j] - ry, b.seg, s0, s1))
             continue;
         ++n;
     }
     rowlen[i] = n;
+    row_full[i] = n == nall ? 1 : 0;
+}
+
+// node_broken[i]: one of the node's bonds is broken (after the bond states
+// were set wholesale: at t = 0, a restored state)
+__global__ void k_node_broken(DevArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const uint32_t base = a.slice_ptr[i / kSlice] + (uint32_t)(i % kSlice);
+    const int n = a.rowlen[i];
+    uint8_t any = 0;
+    for (int k = 0; k < n; ++k) any |= (a.col[base + (uint32_t)k * kSlice] & kBroken) ? 1 : 0;
+    a.node_broken[i] = any;
 }
 
 __global__ void k_bonds_fill_w(BondArgs b, uint32_t *col, const uint32_t *slice_ptr) {
@@ -668,6 +684,13 @@ __global__ __launch_bounds__(64) void k_build_list(DevArgs a) {
     const int ncx = a.agg_ncx[ag], ncy = a.agg_ncy[ag];
     const uint32_t c0 = a.agg_cell0[ag];
     const int xlo = max(cx - 1, 0), xhi = min(cx + 1, ncx - 1);
+    // a node whose row holds every same-particle node within eps and none of
+    // whose bonds is broken has an intact bond to a same-particle node j iff
+    // j passes the reference-bond test (written as the bond build writes it);
+    // other nodes search their row
+    const bool by_ref = a.row_full[ic] && !a.node_broken[ic];
+    const double xr = a.x[ic], yr = a.y[ic];
+    const double thr2 = a.mat[a.pmat[pi]].thr2;
     uint32_t beg[3], cnt[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -702,7 +725,14 @@ __global__ __launch_bounds__(64) void k_build_list(DevArgs a) {
             if ((int)j != i) {
                 const double ddx = a.spx[k] - pxi, ddy = a.spy[k] - pyi;
                 acc = ddx * ddx + ddy * ddy < a.Rl2;
-                if (acc && a.spart[k] == pi) acc = !bonded_intact(a, i, (int)j);
+                if (acc && a.spart[k] == pi) {
+                    if (by_ref) {
+                        const double dx = a.x[j] - xr, dy = a.y[j] - yr;
+                        acc = !(dx * dx + dy * dy < thr2);
+                    } else {
+                        acc = !bonded_intact(a, i, (int)j);
+                    }
+                }
             }
         }
         const unsigned long long bal = __ballot(acc) & gmask;
@@ -1251,6 +1281,10 @@ __device__ __forceinline__ void force_block(const DevArgs &a, int lds_cap, int b
                    : bond_forces<R, MODE, false, LPN>(a, mc, i, sub, lo, S, xi, yi, uxi,
                                                       uyi, Vi, fpx, fpy, nbrk, smx, head, false);
     }
+
+    // a lane that broke one of the node's bonds marks the node (the list
+    // build then searches its row)
+    if (MODE != M_FORCES && nbrk > 0) a.node_broken[i] = 1;
 
     // ---- combine the node's lanes -----------------------------------------------
     fpx = lanes_sum<LPN>(fpx);
@@ -2254,9 +2288,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, hipStream_t s) {
+hipError_t launch_bonds_count(const BondArgs &b, int *rowlen, uint8_t *row_full, hipStream_t s) {
     if (b.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bonds_count_w, dim3(grid_for(b.N, 128)), dim3(128), 0, s, b, rowlen);
+    hipLaunchKernelGGL(k_bonds_count_w, dim3(grid_for(b.N, 128)), dim3(128), 0, s, b, rowlen,
+                       row_full);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_broken(const DevArgs &a, hipStream_t s) {
+    if (a.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_broken, dim3(grid_for(a.N, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
