@@ -149,7 +149,7 @@ def precision_split(pd, W, torch, steps):
     prob = W.jammed_compaction(wall_speed=1.0)
     g = pd.PD(prob, precision=0)
     g.step(20)
-    tun = g.autotune(10)
+    tun = g.autotune(50)
     t0 = time.perf_counter()
     g.step(pre_steps - 20)
     torch.cuda.synchronize()
@@ -619,7 +619,7 @@ def settle_shapes(pd, W, torch, micro_s, every_us):
 
         phi0 = frac(np.zeros(prob.n_nodes))
         g.step(20)
-        tun = g.autotune(10)
+        tun = g.autotune(50)
         every = int(round(every_us * 1e-6 / prob.dt))
         n_chunks = max(1, int(round(micro_s / every_us)))
         ke = []

@@ -217,9 +217,13 @@ pd_status pd_set_counting(pd_ctx *c, int32_t on);
 pd_status pd_get_tuning(const pd_ctx *c, pd_tuning *t);
 pd_status pd_set_tuning(pd_ctx *c, const pd_tuning *t);
 
-/* Autotuner: times steps_per_trial steps for each candidate configuration
- * on a copy of the state (the state is restored afterwards) and keeps the
- * fastest.  chosen may be NULL. */
+/* Autotuner: for each candidate configuration, starting from a copy of the
+ * state and bonds, two warm-up steps and then two windows of steps_per_trial
+ * steps, the shorter window counting; the pass of walls and contact
+ * candidates (wall_pass = 1) is tried on the three fastest list-mode
+ * candidates, and the four fastest of all are timed again over windows of
+ * 3 * steps_per_trial steps; the fastest of those is kept.  The state, bonds
+ * and counters are restored afterwards.  chosen may be NULL. */
 pd_status pd_autotune(pd_ctx *c, int32_t steps_per_trial, pd_tuning *chosen);
 
 /* Kernel timing: runs n_steps steps and records HIP events on the

@@ -2278,53 +2278,86 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     HIPCHK(hipStreamSynchronize(c.stream));
     const pd_tuning base = c.tune;
     pd_tuning best = base;
-    float best_ms = 1e30f;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // One trial: the saved state and bonds back in place, two warm-up steps,
+    // then two windows of n steps; the shorter window counts, so that a list
+    // rebuild or a graph's first instantiation in one window does not decide.
+    auto trial_ms = [&](const pd_tuning &t, int n, float *ms) -> pd_status {
+        TRY(pd_set_tuning(ctx, &t));
+        for (int k = 0; k < 6; ++k)
+            HIPCHK(hipMemcpyAsync(src[k], save + k * c.N, nb, hipMemcpyDeviceToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(c.a.col, save_col, c.nslots * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                              c.stream));
+        HIPCHK(launch_node_broken(c.a, c.stream));
+        c.cur = cur0;
+        c.step = step0;
+        c.list_valid = false;
+        c.last_rebuild_step = step0;
+        TRY(set_device_step(c));
+        TRY(pd_step(ctx, 2));
+        *ms = 1e30f;
+        for (int w = 0; w < 2; ++w) {
+            HIPCHK(hipEventRecord(e0, c.stream));
+            TRY(pd_step(ctx, n));
+            HIPCHK(hipEventRecord(e1, c.stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float m = 0;
+            HIPCHK(hipEventElapsedTime(&m, e0, e1));
+            *ms = std::min(*ms, m);
+        }
+        return PD_OK;
+    };
     const int blocks[3] = {256, 128, 64};
     const int lanes[3] = {4, 2, 1};
     // skin 0 (cell search every step) also tries cells of twice the contact
     // radius: four times fewer cells can take a radix pass off the key sort
     const double skins[5] = {0.0, 0.0, 0.5, 1.0, 2.0};
     const double cells[5] = {1.0, 2.0, 1.0, 1.0, 1.0};
+    std::vector<std::pair<float, pd_tuning>> tried;
+    auto by_time = [](const std::pair<float, pd_tuning> &p, const std::pair<float, pd_tuning> &q) {
+        return p.first < q.first;
+    };
     pd_status result = PD_OK;
     constexpr int kGrid = 3 * 5 * 2 * 3;
-    for (int trial = 0; trial <= kGrid && result == PD_OK; ++trial) {
+    for (int trial = 0; trial < kGrid && result == PD_OK; ++trial) {
+        const int bi = trial / 30, ci = (trial / 6) % 5, li = (trial / 3) % 2, ni = trial % 3;
+        // the lane count matters to the list-mode step only
+        if (skins[ci] == 0.0 && ni > 0) continue;
         pd_tuning t = base;
-        if (trial < kGrid) {
-            const int bi = trial / 30, ci = (trial / 6) % 5, li = (trial / 3) % 2, ni = trial % 3;
-            // the lane count matters to the list-mode step only
-            if (skins[ci] == 0.0 && ni > 0) continue;
-            t.block_nodes = blocks[bi];
-            t.cell_factor = cells[ci];
-            t.skin_factor = skins[ci];
-            t.use_lds = 1 - li;
-            t.lanes_per_node = skins[ci] > 0.0 ? lanes[ni] : 4;
-            t.wall_pass = 0;
-        } else {
-            // last: the best so far with the walls in a pass of their own
-            if (!(best.skin_factor > 0.0)) break;
-            t = best;
-            t.wall_pass = 1;
-        }
-        if ((result = pd_set_tuning(ctx, &t)) != PD_OK) break;
-        // restore and warm up
-        for (int k = 0; k < 6; ++k)
-            HIPCHK(hipMemcpyAsync(src[k], save + k * c.N, nb, hipMemcpyDeviceToDevice, c.stream));
-        c.cur = cur0;
-        c.step = step0;
-        TRY(set_device_step(c));
-        if ((result = pd_step(ctx, 2)) != PD_OK) break;
-        HIPCHK(hipEventRecord(e0, c.stream));
-        if ((result = pd_step(ctx, steps)) != PD_OK) break;
-        HIPCHK(hipEventRecord(e1, c.stream));
-        HIPCHK(hipEventSynchronize(e1));
+        t.block_nodes = blocks[bi];
+        t.cell_factor = cells[ci];
+        t.skin_factor = skins[ci];
+        t.use_lds = 1 - li;
+        t.lanes_per_node = skins[ci] > 0.0 ? lanes[ni] : 4;
+        t.wall_pass = 0;
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if ((result = trial_ms(t, steps, &ms)) == PD_OK) tried.emplace_back(ms, t);
+    }
+    // the pass of walls and contact candidates on the three fastest list-mode
+    // candidates, then the four fastest of all again over windows three times
+    // as long
+    if (result == PD_OK) {
+        std::stable_sort(tried.begin(), tried.end(), by_time);
+        std::vector<std::pair<float, pd_tuning>> with_pass;
+        for (size_t k = 0; k < tried.size() && with_pass.size() < 3 && result == PD_OK; ++k) {
+            if (!(tried[k].second.skin_factor > 0.0)) continue;
+            pd_tuning t = tried[k].second;
+            t.wall_pass = 1;
+            float ms = 0;
+            if ((result = trial_ms(t, steps, &ms)) == PD_OK) with_pass.emplace_back(ms, t);
+        }
+        tried.insert(tried.end(), with_pass.begin(), with_pass.end());
+        std::stable_sort(tried.begin(), tried.end(), by_time);
+    }
+    float best_ms = 1e30f;
+    for (size_t k = 0; k < std::min<size_t>(tried.size(), 4) && result == PD_OK; ++k) {
+        float ms = 0;
+        if ((result = trial_ms(tried[k].second, 3 * steps, &ms)) != PD_OK) break;
         if (ms < best_ms) {
             best_ms = ms;
-            best = t;
+            best = tried[k].second;
         }
     }
     hipEventDestroy(e0);
@@ -2337,6 +2370,7 @@ pd_status pd_autotune(pd_ctx *ctx, int32_t steps, pd_tuning *chosen) {
     HIPCHK(hipMemcpyAsync(c.a.counters, cnt_save, sizeof cnt_save, hipMemcpyHostToDevice, c.stream));
     c.cur = cur0;
     c.step = step0;
+    c.last_rebuild_step = step0;
     c.status = 0;
     HIPCHK(hipMemsetAsync(c.a.status, 0, sizeof(int), c.stream));
     TRY(set_device_step(c));
