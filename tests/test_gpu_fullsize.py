@@ -16,8 +16,10 @@ default tuning).
 * The notched impact at its benchmark resolution, whole against the oracle
   through first contact and the bulk of the fractures.
 * The four jammed shape beds of the settling study, whole against the oracle.
-* The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), FP64 with
-  one lane per node and FP32 forces with two, with the
+* The 64 batched aggregates (6.4 M nodes, 130 M directed bonds), FP64 and
+  FP32 forces each with one lane per node and the pass of walls and contact
+  candidates (the autotuner's pick at this size in both precisions), FP64
+  with one lane and FP32 with two without the pass, with the
   same noise and seeded rigid particle velocities: aggregates never
   interact, so three sampled aggregates (the smallest, the largest, the
   first) are each run by the oracle alone and compared with their slice of
@@ -169,15 +171,20 @@ def test_batched_64_full_size_sampled(pdmod):
     sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0})
     steps = 100
     runs = {}
-    for prec in (W.PREC_FP64, W.PREC_FP32_FORCE):
+    # (precision, lanes per node, the pass of walls and contact candidates):
+    # one lane with the pass is what the autotuner picks at this size in both
+    # precisions; two lanes without it for the FP32-force mode
+    configs = ((W.PREC_FP64, 1, 1), (W.PREC_FP64, 1, 0), (W.PREC_FP32_FORCE, 1, 1),
+               (W.PREC_FP32_FORCE, 2, 0))
+    for prec, lanes, wp in configs:
+        _say(f"  library run: precision {prec}, {lanes} lane(s), pass {wp}")
         g = pdmod.PD(prob, precision=prec)
-        # one lane per node (FP64, the headline's pick at this size) and two
-        g.set_tuning(**BENCH_TUNING, lanes_per_node=1 if prec == W.PREC_FP64 else 2)
-        if prec == W.PREC_FP64:
+        g.set_tuning(**BENCH_TUNING, lanes_per_node=lanes, wall_pass=wp)
+        if prec == W.PREC_FP64 and wp == 0:
             rg, cg = g.bonds()
         g.set_counting(True)
         assert g.step(steps, check=False) == 0
-        runs[prec] = (g.get_state(), g.counters()["inter"])
+        runs[prec, lanes, wp] = (g.get_state(), g.counters()["inter"])
         del g
     for a in sample:
         _say(f"  aggregate {a}: nodes {sizes[a]}")
@@ -189,13 +196,14 @@ def test_batched_64_full_size_sampled(pdmod):
         assert np.array_equal(rg[n0:n1 + 1] - rg[n0], ro), a
         assert o.step(steps) == 0
         so = o.get_state()
-        for prec, tol in ((W.PREC_FP64, 1e-9), (W.PREC_FP32_FORCE, 1e-5)):
-            sg = runs[prec][0]
+        for prec, lanes, wp in configs:
+            tol = 1e-9 if prec == W.PREC_FP64 else 1e-5
+            sg = runs[prec, lanes, wp][0]
             for k in ("ux", "uy", "vx", "vy"):
                 e = _relerr(sg[k][n0:n1], so[k])
-                _say(f"    prec {prec} {k}: {e:.2e}")
-                assert e <= tol, (a, prec, k, e)
-            assert np.array_equal(sg["broken"][cg_slice(rg, n0, n1)], so["broken"]), (a, prec)
+                _say(f"    prec {prec} lanes {lanes} pass {wp} {k}: {e:.2e}")
+                assert e <= tol, (a, prec, lanes, wp, k, e)
+            assert np.array_equal(sg["broken"][cg_slice(rg, n0, n1)], so["broken"]), (a, prec, lanes, wp)
         # FP32 forces at the oracle's final state: the aggregate alone in the
         # library (aggregates never interact), FP32 forces, put at that state
         ga = pdmod.PD(sub, precision=W.PREC_FP32_FORCE)
