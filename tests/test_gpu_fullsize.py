@@ -9,6 +9,12 @@ default tuning).
   from rest every bond force stays exactly zero for many steps): the whole
   problem against the FP64 oracle -- reference bonds and contact sets
   bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
+* The settling bed under the paper's 5 000 m/s^2 (the contact-active
+  leg): the oracle falls for 2 ms (20 100 steps), then ten windows of 100
+  steps, each started by the library from the oracle's state, in the
+  autotuner's tuning there (four lanes per node) and with one lane and the
+  pass: trajectories to 1e-9 and broken bonds bit-exact at each window's
+  end, with list rebuilds and contact inside the windows.
 * The compaction bed of 500 particles from a packed start (the FP32 / FP64
   precision split's workload), whole against the oracle.
 * The closure workload of 2 000 particles, reduced and nodal forms, whole
@@ -89,6 +95,47 @@ def test_settling_100_full_size(pdmod):
     cg_ = g.contacts()
     co_ = o.contacts()
     assert np.array_equal(cg_[0], co_[0]) and np.array_equal(cg_[1], co_[1])
+
+
+# the contact-active leg's tunings: the autotuner's pick there, and one lane
+# per node with the pass
+G5000_TUNINGS = (dict(block_nodes=64, use_lds=1, use_graph=1, skin_factor=1.0, lanes_per_node=4,
+                      wall_pass=0),
+                 dict(block_nodes=128, use_lds=1, use_graph=1, skin_factor=0.5, lanes_per_node=1,
+                      wall_pass=1))
+
+
+def test_settling_g5000_window_full_size(pdmod):
+    _say("case: settling bed under 5000 m/s^2, full size, windows from the oracle at t = 2 ms")
+    prob = W.settling(gravity=-5000.0)
+    o = Oracle(prob, contact_mode=1, n_threads=16)
+    for k in range(10):
+        assert o.step(2010) == 0
+        _say(f"  oracle fall: {(k + 1) * 2010} steps")
+    runs = []
+    for tun in G5000_TUNINGS:
+        g = pdmod.PD(prob)
+        g.set_tuning(**tun)
+        g.set_counting(True)
+        runs.append(g)
+    so = o.get_state()
+    for k in range(10):
+        start = so
+        assert o.step(100) == 0
+        so = o.get_state()
+        for tun, g in zip(G5000_TUNINGS, runs):
+            g.set_state(start)
+            assert g.step(100, check=False) == 0
+            sg = g.get_state()
+            err = max(_relerr(sg[key], so[key]) for key in ("ux", "uy", "vx", "vy"))
+            _say(f"  segment {k}, {tun['lanes_per_node']} lane(s), pass {tun['wall_pass']}: {err:.2e}")
+            assert err <= 1e-9, (k, tun, err)
+            assert np.array_equal(sg["broken"], so["broken"]), (k, tun)
+    for g in runs:
+        # the lists went stale inside the segments, and contact acted
+        assert g.sizes()["list_rebuilds"] > 2 * 10
+        assert g.counters()["inter"] > 0
+    assert o.counters()["inter"] > 0
 
 
 def test_compaction_500_full_size(pdmod):
