@@ -8,7 +8,8 @@ default tuning).
   with seeded nodal noise (displacements of 2 um, velocities of 0.05 m/s;
   from rest every bond force stays exactly zero for many steps): the whole
   problem against the FP64 oracle -- reference bonds and contact sets
-  bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9.
+  bit-exact, per-term forces to 1e-12, a 200-step trajectory to 1e-9 (also
+  in the two tunings the autotuner has picked for the settling leg).
 * The settling bed under the paper's 5 000 m/s^2 (the contact-active
   leg): the oracle falls for 2 ms (20 100 steps), then ten windows of 100
   steps, each started by the library from the oracle's state, in the
@@ -95,6 +96,16 @@ def test_settling_100_full_size(pdmod):
     cg_ = g.contacts()
     co_ = o.contacts()
     assert np.array_equal(cg_[0], co_[0]) and np.array_equal(cg_[1], co_[1])
+    # the settling leg's own picks of the autotuner (four lanes per node)
+    for tun in (dict(block_nodes=64, skin_factor=1.0), dict(block_nodes=128, skin_factor=2.0)):
+        h = pdmod.PD(prob)
+        h.set_tuning(**dict(BENCH_TUNING, **tun), lanes_per_node=4, wall_pass=0)
+        assert h.step(200, check=False) == 0
+        sh = h.get_state()
+        for k in ("ux", "uy", "vx", "vy"):
+            assert _relerr(sh[k], so[k]) <= 1e-9, (tun, k)
+        assert np.array_equal(sh["broken"], so["broken"]), tun
+        del h
 
 
 # the contact-active leg's tunings: the autotuner's pick there, and one lane
