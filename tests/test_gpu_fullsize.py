@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
 benchmark times for each workload (the headline and the batched run: 128
 nodes per workgroup, LDS staging, candidate lists with skin 0.5, graph
-replays of 64 steps; the precision split and the closure: the library's
-default tuning).
+replays of 64 steps; the precision split's bed: two lanes per node, as its
+autotuner picks; its stress case and the closure: the library's default
+tuning).
 
 * The settling bed of 100 particles (30 075 nodes, 594 576 directed bonds),
   with seeded nodal noise (displacements of 2 um, velocities of 0.05 m/s;
@@ -16,8 +17,10 @@ default tuning).
   autotuner's tuning there (four lanes per node) and with one lane and the
   pass: trajectories to 1e-9 and broken bonds bit-exact at each window's
   end, with list rebuilds and contact inside the windows.
-* The compaction bed of 500 particles from a packed start (the FP32 / FP64
-  precision split's workload), whole against the oracle.
+* The FP32 / FP64 precision split's bed (509 particles from the jammed
+  start, 178k nodes) at its start in that leg's tuning, and its stress case
+  (500 particles herded into one another, 245k nodes), whole against the
+  oracle.
 * The closure workload of 2 000 particles, reduced and nodal forms, whole
   against the oracle's closure steppers.
 * The notched impact at its benchmark resolution, whole against the oracle
@@ -149,10 +152,47 @@ def test_settling_g5000_window_full_size(pdmod):
     assert o.counters()["inter"] > 0
 
 
+def test_jammed_compaction_full_size(pdmod):
+    """The precision-split leg's bed (509 particles from the jammed start of
+    Sec. 7.1, 178k nodes, top wall at 1 m/s) at its start, with seeded nodal
+    noise, in that leg's autotuned tuning (two lanes per node): FP64 against
+    the oracle -- bonds bit-exact, per-term forces to 1e-12, 100 steps to
+    1e-9, broken bonds equal; FP32 forces per term to 2e-5."""
+    _say("case: jammed compaction, full size, the precision split's start")
+    prob = W.perturb(W.jammed_compaction(wall_speed=1.0), 10, du=2e-6, dv=0.05)
+    tun = dict(BENCH_TUNING, lanes_per_node=2, wall_pass=0)
+    o = Oracle(prob, contact_mode=1, n_threads=16)
+    g = pdmod.PD(prob, precision=W.PREC_FP64)
+    g.set_tuning(**tun)
+    g32 = pdmod.PD(prob, precision=W.PREC_FP32_FORCE)
+    g32.set_tuning(**tun)
+    rg, cg = g.bonds()
+    ro, co = o.bonds()
+    assert np.array_equal(rg, ro) and np.array_equal(cg, co)
+    for t in TERMS:
+        ox, oy = o.forces(t)
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        if scale == 0.0:
+            continue
+        for gg, tol in ((g, 1e-12), (g32, 2e-5)):
+            gx, gy = gg.forces(t)
+            e = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / scale
+            _say(f"    term {t}: {e:.2e}")
+            assert e <= tol, (t, tol, e)
+    assert np.abs(o.forces(1)[0]).max() > 0.0  # the noise strains the bonds
+    assert g.step(100, check=False) == o.step(100)
+    sg, so = g.get_state(), o.get_state()
+    for k in ("ux", "uy", "vx", "vy"):
+        e = _relerr(sg[k], so[k])
+        _say(f"    {k}: {e:.2e}")
+        assert e <= 1e-9, k
+    assert np.array_equal(sg["broken"], so["broken"])
+
+
 def test_compaction_500_full_size(pdmod):
-    """The precision-split workload (500 particles, about 245k nodes, packed
-    start, top wall at 0.1 m/s) in the benchmark's configuration (the
-    library's default tuning): FP64 against the oracle -- bonds and contact
+    """The precision-split leg's stress case (500 particles, about 245k
+    nodes, herded into one another at t = 0, top wall at 0.1 m/s) in the
+    library's default tuning: FP64 against the oracle -- bonds and contact
     sets bit-exact, per-term forces to 1e-12, 100 steps to 1e-9, broken bonds
     equal.  The FP32-force mode: per-term forces against the oracle to 2e-5
     at the start and at its own final state; its 100-step trajectory to
